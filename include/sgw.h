@@ -1,0 +1,171 @@
+/*
+ * sgw.h -- C-ABI of the MI355X stochastic Galerkin wave solver.
+ *
+ * The library advances the intrusive stochastic Galerkin (SG) discretisation
+ * of the 2-D acoustic wave equation with a log-normal squared wave speed
+ * (Sec. 4, Eq. acous_sto) in time with Newmark average acceleration
+ * (Sec. 2, Eq. K_T, Kuf, fparts, UmCm).  Every time step solves the SG system
+ * by conjugate gradients on the interface Schur complement (Eq. Sto_Schur)
+ * preconditioned by the probabilistic two-level Neumann-Neumann
+ * preconditioner with a corner coarse grid (Sec. 5, Eq. Fcc_2, NNCP2),
+ * the per-step loop of Alg. 1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: 0 = OK, > 0 = warning (the requested work was done),
+ *   < 0 = error (nothing usable was produced).  sgw_last_error() gives text.
+ * - Mesh: the unit square cut into n x n square cells, each cell split along
+ *   the diagonal (i,j)-(i+1,j+1); node (i,j) at (i/n, j/n) has mesh index
+ *   i + (n+1) j; u = 0 on the whole boundary (Sec. 6 setup).
+ * - PCE arrays at the boundary are mode-major ("PCE-major blocks", the
+ *   layout of Eq. GAssembly_Sto): element (mode j, mesh node v) sits at
+ *   [j * (n+1)^2 + v], j = 0..P-1.  Boundary nodes read back as 0 and are
+ *   ignored on input.  The PCE basis is the normalised Hermite chaos of total
+ *   degree <= p_out in L variables, graded then descending-lexicographic.
+ * - where = SGW_HOST or SGW_DEVICE says whether a pointer is host memory or
+ *   device memory of the context's GPU.  The caller owns all memory it
+ *   passes; the library copies what it needs and never keeps a pointer.
+ * - Device memory of a context is obtained from the allocator given at
+ *   create time (PyTorch's caching allocator in the Python binding), or from
+ *   hipMalloc when none is given; sgw_destroy releases it.
+ * - A context is not thread-safe.  Calls that take a stream enqueue on it;
+ *   sgw_step and sgw_factor synchronise that stream before returning (the
+ *   iteration counts decide how much work is enqueued).
+ */
+#ifndef SGW_H
+#define SGW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SGW_OK = 0,
+  SGW_NOT_CONVERGED = 1,   /* warning: a PCG hit max_iter; state advanced */
+  SGW_EINVAL = -1,         /* bad argument */
+  SGW_ESTATE = -2,         /* call order (e.g. step before factor) */
+  SGW_ENOMEM = -3,         /* allocation failed */
+  SGW_ENOTSPD = -4,        /* non-positive pivot in a Cholesky factor */
+  SGW_EBREAKDOWN = -5,     /* PCG breakdown (p'q <= 0) */
+  SGW_ENAN = -6,           /* NaN or Inf in a residual */
+  SGW_EHIP = -7            /* HIP runtime error */
+};
+
+enum { SGW_HOST = 0, SGW_DEVICE = 1 };
+enum { SGW_FP64 = 0, SGW_FP32_IR64 = 1 };
+enum { SGW_GUESS_PREV = 0, SGW_GUESS_NEWMARK = 1, SGW_GUESS_LEARNED = 2 };
+
+/* Problem description.  Fields follow the paper's problem statement:
+ * Eq. CovarKer2D_chapt2 (sigma, bx, by), Eq. KLEchapt2 (L), Eq. c0pce
+ * (p_in: order of the input PCE of c_s), Eq. uPCE (p_out: order of the
+ * output PCE), Eq. K_T (dt, zeta, gamma), Appendix Rayleigh damping
+ * (alpha0, alpha1), Eq. initial_2Dwave (pulse x0, y0, amp, with
+ * alpha = width^2).  The partition is rectilinear: nsx+1 increasing cut
+ * positions in cells along x (first 0, last n), likewise along y. */
+typedef struct sgw_problem_desc {
+  int n;                 /* cells per side */
+  int nsx, nsy;          /* number of subdomain strips along x and y */
+  const int* xsplits;    /* host, nsx+1 cut positions in cells */
+  const int* ysplits;    /* host, nsy+1 cut positions in cells */
+  int L, p_in, p_out;    /* KLE terms, input PCE order, output PCE order */
+  double sigma, bx, by;  /* std. dev. and correlation lengths of g = log c_s */
+  double dt, zeta, gamma;
+  double alpha0, alpha1;
+  double x0, y0, width, amp;   /* initial pulse (used by sgw_set_state(NULL)) */
+  double rtol;           /* outer PCG: ||r|| <= rtol ||G_Gamma||; IR: on the SG residual */
+  int max_iter;          /* outer PCG iteration cap */
+  double inner_rtol;     /* subdomain solves: ||r_s|| <= inner_rtol ||b_s|| */
+  int inner_max_iter;
+  int precision;         /* SGW_FP64 or SGW_FP32_IR64 */
+  int guess;             /* initial interface guess, SGW_GUESS_* */
+} sgw_problem_desc;
+
+/* Optional device allocator.  alloc returns device memory of >= bytes
+ * (256-byte aligned) or NULL; free releases it. */
+typedef struct sgw_allocator {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} sgw_allocator;
+
+/* Per-call statistics (host memory, filled by sgw_step). */
+typedef struct sgw_step_stats {
+  int steps;             /* steps advanced by the call */
+  int outer_iters;       /* total outer PCG iterations */
+  int outer_iters_max;   /* max outer iterations in one step */
+  long long inner_iters; /* total inner iterations (summed over solves) */
+  int inner_solves;      /* number of batched subdomain solves */
+  int ir_sweeps;         /* iterative-refinement sweeps (mixed precision) */
+  double last_rel_res;   /* outer ||r||/||G_Gamma|| of the last solve */
+} sgw_step_stats;
+
+typedef struct sgw_ctx sgw_ctx;
+
+/* Build a context on the current HIP device: mesh, partition into
+ * subdomains (interior, remaining and corner nodes, Sec. 3 and Eq.
+ * uruc_sto), KLE (Eq. KLEchapt2), log-normal PCE coefficients
+ * (Eq. c0pce, LNL0), Hermite triple products (Eq. galerproject_chap2),
+ * SG transient matrices (Eq. K_T_Sto, K_T_Stosub) and the mean-matrix
+ * factors of every subdomain.  Host inputs are copied.  alloc may be NULL.
+ * Errors: SGW_EINVAL (bad sizes / splits), SGW_ENOMEM, SGW_ENOTSPD. */
+int sgw_create(const sgw_problem_desc* d, const sgw_allocator* alloc,
+               sgw_ctx** out);
+
+/* Coarse-grid setup on the device: for every subdomain and every local
+ * corner degree of freedom, the SG Neumann solve that gives the coarse
+ * basis and the local coarse matrix; assembly of F_cc (Eq. Fcc_2) and its
+ * Cholesky factor in FP64.  stream may be 0.  Errors: SGW_ESTATE,
+ * SGW_ENOTSPD, SGW_EHIP. */
+int sgw_factor(sgw_ctx* ctx, void* stream);
+
+/* Set the state (U, V, A), each mode-major [P][(n+1)^2] in memory `where`.
+ * U == NULL: U_0 = pulse in mode 0, zero elsewhere (Eq. initial_2Dwave).
+ * V == NULL: V_0 = 0.  A == NULL: A_0 solved from
+ * (I (x) M) A_0 = -K U_0 - C V_0 (f = 0).  Also used to resume from a
+ * checkpoint taken with sgw_get_state.  Resets the step counter to step. */
+int sgw_set_state(sgw_ctx* ctx, const double* U, const double* V,
+                  const double* A, int where, int step, void* stream);
+
+/* Copy the state out (mode-major [P][(n+1)^2]); any pointer may be NULL. */
+int sgw_get_state(sgw_ctx* ctx, double* U, double* V, double* A, int where,
+                  void* stream);
+
+/* Advance nsteps Newmark steps (Alg. 1 loop body): effective force,
+ * static condensation, interface PCG with the two-level NN preconditioner,
+ * interior recovery, Newmark update.  stats may be NULL.  Returns
+ * SGW_NOT_CONVERGED if any PCG hit its cap (the state still advances), or an
+ * error code. */
+int sgw_step(sgw_ctx* ctx, int nsteps, void* stream, sgw_step_stats* stats);
+
+/* Mean (mode 0) and variance (sum of squares of modes >= 1, normalised
+ * basis) of U over all (n+1)^2 mesh nodes; either pointer may be NULL. */
+int sgw_read_moments(sgw_ctx* ctx, double* mean, double* var, int where,
+                     void* stream);
+
+/* Apply the SG transient operator (Eq. K_T_Sto) to X, both mode-major
+ * [P][(n+1)^2] device arrays: Y = K~ X on the free nodes, 0 on the boundary.
+ * precision selects the FP64 or FP32 kernel (FP32 reads and writes double
+ * arrays but computes in float). */
+int sgw_apply_operator(sgw_ctx* ctx, const double* X, double* Y,
+                       int precision, void* stream);
+
+/* Solve one SG system K~ U = F (Eq. Kuf with the SG operator) with the
+ * full DD-PCG of sgw_step, F and U mode-major [P][(n+1)^2] device arrays;
+ * U holds the initial guess on entry. */
+int sgw_solve(sgw_ctx* ctx, const double* F, double* U, void* stream,
+              sgw_step_stats* stats);
+
+/* Sizes: what = 0 P, 1 number of input PCE terms, 2 free nodes,
+ * 3 interface nodes, 4 corner nodes, 5 subdomains, 6 (n+1)^2. */
+long long sgw_query(const sgw_ctx* ctx, int what);
+
+const char* sgw_last_error(const sgw_ctx* ctx);
+int sgw_destroy(sgw_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGW_H */

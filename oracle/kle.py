@@ -16,7 +16,8 @@ for the exponential kernel on an interval [-a, a] (here a = 1/2 after shifting
 The 2-D kernel is a product of two 1-D kernels, so its eigenpairs are the
 products sigma^2 lambda_m^x lambda_n^y, phi_m^x(x) phi_n^y(y).  They are
 sorted by decreasing eigenvalue, ties broken by (m, n) ascending, and the
-first L are kept.
+first L are kept.  The 1-D product is formed first so that swapped pairs
+(m, n), (n, m) of an isotropic kernel tie exactly.
 """
 
 import math
@@ -74,7 +75,7 @@ def kle_2d(sigma, bx, by, L):
     cand = []
     for m in range(nper):
         for n in range(nper):
-            lam = sigma * sigma * mx[m][1] * my[n][1]
+            lam = sigma * sigma * (mx[m][1] * my[n][1])
             cand.append((-lam, m + 1, n + 1))
     cand.sort()
     out = []

@@ -1,0 +1,239 @@
+"""Python binding of libsgw.so, the MI355X stochastic Galerkin wave solver.
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  PyTorch supplies device memory (through the allocator callback
+handed to ``sgw_create``) and the stream.  The library must have been built
+(``paper_2512_23027_amd.build.build()``); importing the binding on a machine
+without it raises, there is no fallback path.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libsgw.so")
+
+SGW_HOST, SGW_DEVICE = 0, 1
+SGW_FP64, SGW_FP32_IR64 = 0, 1
+SGW_GUESS_PREV, SGW_GUESS_NEWMARK, SGW_GUESS_LEARNED = 0, 1, 2
+SGW_NOT_CONVERGED = 1
+
+ERRORS = {-1: "SGW_EINVAL", -2: "SGW_ESTATE", -3: "SGW_ENOMEM",
+          -4: "SGW_ENOTSPD", -5: "SGW_EBREAKDOWN", -6: "SGW_ENAN",
+          -7: "SGW_EHIP"}
+
+# every symbol include/sgw.h declares
+EXPORTS = ["sgw_create", "sgw_factor", "sgw_set_state", "sgw_get_state",
+           "sgw_step", "sgw_read_moments", "sgw_apply_operator", "sgw_solve",
+           "sgw_query", "sgw_last_error", "sgw_destroy"]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("nsx", ctypes.c_int), ("nsy", ctypes.c_int),
+                ("xsplits", ctypes.POINTER(ctypes.c_int)),
+                ("ysplits", ctypes.POINTER(ctypes.c_int)),
+                ("L", ctypes.c_int), ("p_in", ctypes.c_int), ("p_out", ctypes.c_int),
+                ("sigma", ctypes.c_double), ("bx", ctypes.c_double), ("by", ctypes.c_double),
+                ("dt", ctypes.c_double), ("zeta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("alpha0", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("width", ctypes.c_double), ("amp", ctypes.c_double),
+                ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
+                ("precision", ctypes.c_int), ("guess", ctypes.c_int)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("outer_iters", ctypes.c_int),
+                ("outer_iters_max", ctypes.c_int), ("inner_iters", ctypes.c_longlong),
+                ("inner_solves", ctypes.c_int), ("ir_sweeps", ctypes.c_int),
+                ("last_rel_res", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_LIB = None
+
+
+def lib():
+    """Load libsgw.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError("libsgw.so is not built; run paper_2512_23027_amd.build.build()")
+        L = ctypes.CDLL(LIBPATH)
+        vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.sgw_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(Allocator),
+                                 ctypes.POINTER(vp)]
+        L.sgw_factor.argtypes = [vp, vp]
+        L.sgw_set_state.argtypes = [vp, vp, vp, vp, ip, ip, vp]
+        L.sgw_get_state.argtypes = [vp, vp, vp, vp, ip, vp]
+        L.sgw_step.argtypes = [vp, ip, vp, ctypes.POINTER(StepStats)]
+        L.sgw_read_moments.argtypes = [vp, vp, vp, ip, vp]
+        L.sgw_apply_operator.argtypes = [vp, vp, vp, ip, vp]
+        L.sgw_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(StepStats)]
+        L.sgw_query.argtypes = [vp, ip]
+        L.sgw_query.restype = ctypes.c_longlong
+        L.sgw_last_error.argtypes = [vp]
+        L.sgw_last_error.restype = ctypes.c_char_p
+        L.sgw_destroy.argtypes = [vp]
+        for name in EXPORTS:
+            if name not in ("sgw_query", "sgw_last_error"):
+                getattr(L, name).restype = ip
+        del dp
+        _LIB = L
+    return _LIB
+
+
+class SGWError(RuntimeError):
+    pass
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One SG wave problem on the current CUDA/HIP device.
+
+    ``prm`` is a parameter dict as produced by ``workloads.config``; solver
+    options (rtol, inner_rtol, max_iter, precision, guess) may be given as
+    keyword arguments.
+    """
+
+    def __init__(self, prm, rtol=None, inner_rtol=None, max_iter=1000,
+                 inner_max_iter=1000, precision=SGW_FP64, guess=SGW_GUESS_PREV,
+                 use_torch_allocator=True):
+        import torch
+        self.torch = torch
+        L = lib()
+        self._xs = (ctypes.c_int * len(prm["xsplits"]))(*prm["xsplits"])
+        self._ys = (ctypes.c_int * len(prm["ysplits"]))(*prm["ysplits"])
+        d = ProblemDesc()
+        d.n = prm["n"]
+        d.nsx, d.nsy = len(prm["xsplits"]) - 1, len(prm["ysplits"]) - 1
+        d.xsplits = ctypes.cast(self._xs, ctypes.POINTER(ctypes.c_int))
+        d.ysplits = ctypes.cast(self._ys, ctypes.POINTER(ctypes.c_int))
+        d.L, d.p_in, d.p_out = prm["L"], prm["p_in"], prm["p_out"]
+        d.sigma, d.bx, d.by = prm["sigma"], prm["bx"], prm["by"]
+        d.dt, d.zeta, d.gamma = prm["dt"], prm.get("zeta", 0.25), prm.get("gamma", 0.5)
+        d.alpha0, d.alpha1 = prm.get("alpha0", 0.0), prm.get("alpha1", 0.0)
+        d.x0, d.y0 = prm.get("x0", 0.5), prm.get("y0", 0.5)
+        d.width, d.amp = prm.get("width", 0.05), prm.get("amp", 1.0)
+        d.rtol = rtol if rtol is not None else prm.get("rtol", 1e-8)
+        d.max_iter = max_iter
+        d.inner_rtol = inner_rtol if inner_rtol is not None else 1e-3 * d.rtol
+        d.inner_max_iter = inner_max_iter
+        d.precision, d.guess = precision, guess
+        self.desc = d
+        self._live = {}
+        al = None
+        if use_torch_allocator:
+            dev = torch.cuda.current_device()
+
+            def _alloc(nbytes, user):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda:%d" % dev)
+                p = t.data_ptr()
+                self._live[p] = t
+                return p
+
+            def _free(p, user):
+                self._live.pop(p, None)
+
+            self._afn = ALLOC_FN(_alloc)
+            self._ffn = FREE_FN(_free)
+            al = Allocator(self._afn, self._ffn, None)
+        self.ctx = ctypes.c_void_p()
+        rc = L.sgw_create(ctypes.byref(d), ctypes.byref(al) if al else None,
+                          ctypes.byref(self.ctx))
+        self._check(rc, "sgw_create")
+        self.P = L.sgw_query(self.ctx, 0)
+        self.nk = L.sgw_query(self.ctx, 1)
+        self.nfree = L.sgw_query(self.ctx, 2)
+        self.ninterface = L.sgw_query(self.ctx, 3)
+        self.ncorner = L.sgw_query(self.ctx, 4)
+        self.nsub = L.sgw_query(self.ctx, 5)
+        self.nn = L.sgw_query(self.ctx, 6)
+
+    # -- helpers -----------------------------------------------------------
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def _check(self, rc, what):
+        if rc < 0:
+            msg = lib().sgw_last_error(self.ctx).decode() if self.ctx else ""
+            raise SGWError("%s failed: %s (%s)" % (what, ERRORS.get(rc, rc), msg))
+        return rc
+
+    def _dev(self, t):
+        t = t.to(device="cuda", dtype=self.torch.float64).contiguous()
+        assert t.numel() == self.P * self.nn, "expected a [P][(n+1)^2] array"
+        return t
+
+    # -- API -----------------------------------------------------------------
+    def factor(self):
+        return self._check(lib().sgw_factor(self.ctx, self._stream()), "sgw_factor")
+
+    def set_state(self, U=None, V=None, A=None, step=0):
+        ts = [self._dev(x) if x is not None else None for x in (U, V, A)]
+        return self._check(lib().sgw_set_state(self.ctx, *[_ptr(t) for t in ts], SGW_DEVICE,
+                                               step, self._stream()), "sgw_set_state")
+
+    def get_state(self):
+        out = [self.torch.empty(self.P * self.nn, dtype=self.torch.float64, device="cuda")
+               for _ in range(3)]
+        self._check(lib().sgw_get_state(self.ctx, *[_ptr(t) for t in out], SGW_DEVICE,
+                                        self._stream()), "sgw_get_state")
+        return tuple(t.view(self.P, self.nn) for t in out)
+
+    def step(self, nsteps=1):
+        st = StepStats()
+        rc = lib().sgw_step(self.ctx, nsteps, self._stream(), ctypes.byref(st))
+        self._check(rc, "sgw_step")
+        d = st.as_dict()
+        d["status"] = rc
+        return d
+
+    def moments(self):
+        mean = self.torch.empty(self.nn, dtype=self.torch.float64, device="cuda")
+        var = self.torch.empty(self.nn, dtype=self.torch.float64, device="cuda")
+        self._check(lib().sgw_read_moments(self.ctx, _ptr(mean), _ptr(var), SGW_DEVICE,
+                                           self._stream()), "sgw_read_moments")
+        return mean, var
+
+    def apply_operator(self, X, precision=SGW_FP64):
+        X = self._dev(X)
+        Y = self.torch.empty_like(X)
+        self._check(lib().sgw_apply_operator(self.ctx, _ptr(X), _ptr(Y), precision,
+                                             self._stream()), "sgw_apply_operator")
+        return Y.view(self.P, self.nn)
+
+    def solve(self, F, U0=None):
+        F = self._dev(F)
+        U = self._dev(U0) if U0 is not None else self.torch.zeros_like(F)
+        U = U.clone()
+        st = StepStats()
+        rc = lib().sgw_solve(self.ctx, _ptr(F), _ptr(U), self._stream(), ctypes.byref(st))
+        self._check(rc, "sgw_solve")
+        return U.view(self.P, self.nn), st.as_dict()
+
+    def close(self):
+        if self.ctx:
+            lib().sgw_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,139 @@
+// Launchers of the HIP kernels of the SG wave solver (gfx950).
+// Vectors are mode-major: element (mode j, row r) of a vector with leading
+// dimension ld sits at v[j * ld + r].
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sgw {
+namespace k {
+
+// Galerkin contraction table of the SG operator apply, for one (nk, P,
+// chunk KC, output group GS) choice.  For output group g, k-chunk ch and
+// input mode j: mask bit kk says that coefficient matrix ch*KC+kk meets mode
+// j with some output i of group g; for every set bit, in order, pair_cnt
+// gives the number of (i, c) entries, stored consecutively in ent_i / ent_c.
+struct GTab {
+  int nk = 0, P = 0, KC = 0, GS = 0, ng = 0, nch = 0;
+  const uint32_t* mask = nullptr;    // [ng][nch][P]
+  const int* pair_beg = nullptr;     // [ng][nch][P]
+  const int* ent_beg = nullptr;      // [ng][nch][P]
+  const int* pair_cnt = nullptr;
+  const int* ent_i = nullptr;        // output mode within the group
+  const double* ent_c = nullptr;
+  const float* ent_cf = nullptr;
+};
+
+// Sliced-ELL matrix on the device (see setup.h): col[s*nrows + r],
+// val[(k*W + s)*nrows + r], mval[s*nrows + r].
+template <typename T>
+struct DEll {
+  int nrows = 0, W = 0, nk = 0;
+  const int* col = nullptr;
+  const T* val = nullptr;
+  const T* mval = nullptr;
+};
+
+// y[i][r] = alpha * sum_k sum_j c_kij sum_s K_k[r, s] x[j][col]  (+ beta*y)
+// for rows r in [r0, r0 + nrows) of the matrix.  nbatch vectors with strides.
+template <typename T>
+void sg_apply(const DEll<T>& A, const GTab& g, int r0, int nrows,
+              const T* x, int ldx, T* y, int ldy, T alpha, T beta,
+              int nbatch, long long sx, long long sy, hipStream_t st);
+
+// y[j][r] = beta*y[j][r] + alpha * sum_s M[r, s] x[j][col]  for all P modes.
+template <typename T>
+void mass_apply(const DEll<T>& A, int r0, int nrows, int P, const T* x,
+                int ldx, T* y, int ldy, T alpha, T beta, hipStream_t st);
+
+// Batched supernodal triangular solves with the mean-matrix factor:
+// out = (L L^T)^{-1} rhs for every block and P modes (nbatch vectors).
+struct DFactor {
+  int nb = 0, P = 0;
+  const int *row_off, *lvl_off, *lvl_ptr, *lrow_ptr, *lrow_list, *lrow_sn;
+  const int *sn_beg, *sn_w, *sn_dinv, *lr_ptr, *lr_col, *lc_ptr, *lc_row;
+  const double *lr_val, *lc_val, *dinv;
+  const float *lr_valf, *lc_valf, *dinvf;
+  int max_rows = 0, max_level_rows = 0;
+};
+template <typename T>
+void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
+               int ldo, int nbatch, long long sr, long long so, hipStream_t st);
+
+// Segmented dot products: partial[b * P + j] = sum_{r in block b} a[j][r] b[j][r]
+// (row_off relative to the vectors; a second vector pair is optional).
+template <typename T>
+void seg_dot(int nb, const int* row_off, int P, const T* a, int lda,
+             const T* b, int ldb, double* partial, const T* c, int ldc,
+             const T* d, int ldd, double* partial2, hipStream_t st);
+
+// PCG scalar phase on nb blocks (one workgroup): see kernels.hip.
+void pcg_scalars(int phase, int nb, int P, const double* part,
+                 const double* part2, double* sc, double tol2, int* flags,
+                 hipStream_t st);
+
+// x += alpha_b p ; r -= alpha_b q ; partial[b*P + j] = ||r_bj||^2
+template <typename T>
+void pcg_xr(int nb, const int* row_off, int P, const double* sc, T* x, int ldx,
+            const T* p, int ldp, T* r, int ldr, const T* q, int ldq,
+            double* partial, hipStream_t st);
+// p = z + beta_b p
+template <typename T>
+void pcg_p(int nb, const int* row_off, int P, const double* sc, const T* z,
+           int ldz, T* p, int ldp, hipStream_t st);
+
+// strided copies / fills over [P][n] (dst = a*src, optional type change)
+template <typename TD, typename TS>
+void copy2d(int P, int n, const TS* src, int lds, TD* dst, int ldd, double a,
+            hipStream_t st);
+template <typename T>
+void fill2d(int P, int n, T* dst, int ldd, T v, hipStream_t st);
+// dst = a*x + b*y (elementwise over [P][n])
+template <typename T>
+void axpby2d(int P, int n, double a, const T* x, int ldx, double b, const T* y,
+             int ldy, T* dst, int ldd, hipStream_t st);
+
+// Newmark predictor (Eq. UmCm, UmCm2) and the mass-term vector of the force.
+void newmark_predict(int P, int n, int ld, const double* U, const double* V,
+                     const double* A, double dt, double zeta, double gamma,
+                     double wc, double* Um, double* Uc, double* Wm,
+                     hipStream_t st);
+// Newmark update: A1 = U1/(zeta dt^2) - Um; V1 = V + dt((1-g)A + g A1)
+void newmark_update(int P, int n, int ld, const double* U1, const double* Um,
+                    double* V, double* A, double dt, double zeta, double gamma,
+                    hipStream_t st);
+
+// Interface <-> torn maps (D_s R_s and sum_s R_s^T D_s) and the coarse grid.
+template <typename T>
+void scatter_to_torn(int NT, int P, const int* gidx, const double* w,
+                     const T* r, int ldr, T* bt, int ldt, hipStream_t st);
+template <typename T>
+void gather_from_torn(int nG, int P, const int* gptr, const int* gtorn,
+                      const double* gw, const int* g2c, const T* ut, int ldt,
+                      const T* uc, int ldc, T* z, int ldz, hipStream_t st);
+struct DCoarse {
+  int nC = 0, P = 0, nk = 0, maxc = 0;
+  const int *c_ptr, *c_lc;        // coarse index -> local corners
+  const int *sc_gidx, *sc_coarse;  // local corner -> interface index, coarse index
+  const double* sc_w;
+  const int *cc_ptr, *cc_torn;     // local corner -> torn couplings
+  const double* cc_val;            // [entry][nk]
+  const int *gi_ptr, *gi_k, *gi_j; // Galerkin entries by output mode i
+  const double* gi_v;
+  const double* finv;              // dense inverse of F_cc, [(m,c)][(m',c')]
+  const int *rem_off, *rem_list;   // remaining torn rows per subdomain
+  const int* sc_ptr;               // local corners per subdomain
+  const double* phi;               // coarse basis, per subdomain blocks
+  const long long* phi_off;
+};
+template <typename T>
+void coarse_rhs(const DCoarse& c, const T* r, int ldr, const T* yt, int ldt,
+                double* dc, hipStream_t st);
+void coarse_solve(const DCoarse& c, const double* dc, double* uc, hipStream_t st);
+template <typename T>
+void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt,
+                 hipStream_t st);
+
+}  // namespace k
+}  // namespace sgw

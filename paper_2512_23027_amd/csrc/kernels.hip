@@ -1,0 +1,689 @@
+// HIP kernels of the SG wave solver for gfx950 (CDNA4, wave64).
+//
+// Data layout: every SG vector is mode-major (one contiguous block of rows
+// per PCE mode, Eq. GAssembly_Sto), sparse matrices are sliced ELL with the
+// rows of one slot contiguous.  With one lane per matrix row, every global
+// load of matrix values, column indices and vector entries is coalesced, and
+// the Galerkin contraction over the PCE modes runs in registers and LDS of
+// the lane that owns the row.
+#include "kernels.h"
+
+#include <cstdio>
+
+namespace sgw {
+namespace k {
+
+#define SGW_WAVE 64
+#define SGW_BLOCK 256
+
+static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+template <typename T> __device__ __forceinline__ T fmadd(T a, T b, T c) { return fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// K1: SG operator apply y_i = sum_k sum_j c_kij K_k x_j (Eq. stok / K_T_Sto).
+// One wave = 64 consecutive rows, one lane per row.  The KC coefficient
+// matrices of a chunk live in registers (7 values each); for every input mode
+// j the lane loads its 7 neighbour values of x_j, forms
+// W_kj = sum_s K_k[r,s] x_j[col_s] for the (k, j) pairs the Galerkin tensor
+// needs, and scatters c_kij W_kj into the output modes of its group, held in
+// LDS (one column per lane, no bank conflicts, no atomics).  The loops over
+// j, k and the tensor entries are uniform across the wave; the tensor tables
+// are read through the scalar cache.
+// ---------------------------------------------------------------------------
+template <typename T, int KC>
+__global__ __launch_bounds__(SGW_WAVE) void k_sg_apply(
+    DEll<T> A, GTab g, const T* __restrict__ entc, int r0, int nrows,
+    const T* __restrict__ x, int ldx, T* __restrict__ y, int ldy, T alpha,
+    T beta, long long sx, long long sy) {
+  extern __shared__ unsigned char smem_raw[];
+  T* yl = reinterpret_cast<T*>(smem_raw);
+  const int lane = threadIdx.x;
+  const int rl = blockIdx.x * SGW_WAVE + lane;
+  const int grp = blockIdx.y;
+  x += (long long)blockIdx.z * sx;
+  y += (long long)blockIdx.z * sy;
+  const bool live = rl < nrows;
+  const int r = r0 + (live ? rl : nrows - 1);
+  const int NR = A.nrows;
+  int col[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) col[s] = A.col[(size_t)s * NR + r];
+  const int i0 = grp * g.GS;
+  const int gsz = min(g.GS, g.P - i0);
+  for (int i = 0; i < gsz; ++i) yl[i * SGW_WAVE + lane] = T(0);
+  for (int ch = 0; ch < g.nch; ++ch) {
+    T kr[KC][7];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int kx = ch * KC + kk;
+#pragma unroll
+      for (int s = 0; s < 7; ++s)
+        kr[kk][s] = kx < A.nk ? A.val[((size_t)kx * 7 + s) * NR + r] : T(0);
+    }
+    const int tb = (grp * g.nch + ch) * g.P;
+    for (int j = 0; j < g.P; ++j) {
+      const uint32_t m = g.mask[tb + j];
+      if (!m) continue;
+      const T* xj = x + (size_t)j * ldx;
+      T u[7];
+#pragma unroll
+      for (int s = 0; s < 7; ++s) u[s] = xj[col[s]];
+      int pp = g.pair_beg[tb + j];
+      int e = g.ent_beg[tb + j];
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        if (m & (1u << kk)) {
+          T w = kr[kk][0] * u[0];
+#pragma unroll
+          for (int s = 1; s < 7; ++s) w = fmadd(kr[kk][s], u[s], w);
+          const int cnt = g.pair_cnt[pp++];
+          for (int t = 0; t < cnt; ++t) {
+            T* dst = &yl[g.ent_i[e + t] * SGW_WAVE + lane];
+            *dst = fmadd(entc[e + t], w, *dst);
+          }
+          e += cnt;
+        }
+      }
+    }
+  }
+  if (live) {
+    for (int i = 0; i < gsz; ++i) {
+      T* yp = y + (size_t)(i0 + i) * ldy + r;
+      T v = alpha * yl[i * SGW_WAVE + lane];
+      if (beta != T(0)) v = fmadd(beta, *yp, v);
+      *yp = v;
+    }
+  }
+}
+
+template <typename T>
+void sg_apply(const DEll<T>& A, const GTab& g, int r0, int nrows, const T* x,
+              int ldx, T* y, int ldy, T alpha, T beta, int nbatch,
+              long long sx, long long sy, hipStream_t st) {
+  if (nrows <= 0) return;
+  dim3 grid(ceil_div(nrows, SGW_WAVE), g.ng, nbatch);
+  size_t sh = (size_t)g.GS * SGW_WAVE * sizeof(T);
+  const T* entc = nullptr;
+  if constexpr (sizeof(T) == 8) entc = reinterpret_cast<const T*>(g.ent_c);
+  else entc = reinterpret_cast<const T*>(g.ent_cf);
+  switch (g.KC) {
+    case 4:
+      k_sg_apply<T, 4><<<grid, SGW_WAVE, sh, st>>>(A, g, entc, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy);
+      break;
+    case 8:
+      k_sg_apply<T, 8><<<grid, SGW_WAVE, sh, st>>>(A, g, entc, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy);
+      break;
+    default:
+      k_sg_apply<T, 16><<<grid, SGW_WAVE, sh, st>>>(A, g, entc, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy);
+      break;
+  }
+}
+
+// Deterministic mass apply over all P modes: thread per (row, mode).
+template <typename T>
+__global__ void k_mass_apply(DEll<T> A, int r0, int nrows, int P, const T* __restrict__ x,
+                             int ldx, T* __restrict__ y, int ldy, T alpha, T beta) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nrows * P) return;
+  int j = (int)(t / nrows), r = r0 + (int)(t % nrows);
+  const int NR = A.nrows;
+  T s = T(0);
+#pragma unroll
+  for (int q = 0; q < 7; ++q)
+    s = fmadd(A.mval[(size_t)q * NR + r], x[(size_t)j * ldx + A.col[(size_t)q * NR + r]], s);
+  T* yp = y + (size_t)j * ldy + r;
+  T v = alpha * s;
+  if (beta != T(0)) v = fmadd(beta, *yp, v);
+  *yp = v;
+}
+
+template <typename T>
+void mass_apply(const DEll<T>& A, int r0, int nrows, int P, const T* x, int ldx,
+                T* y, int ldy, T alpha, T beta, hipStream_t st) {
+  long long n = (long long)nrows * P;
+  if (n <= 0) return;
+  k_mass_apply<T><<<ceil_div(n, SGW_BLOCK), SGW_BLOCK, 0, st>>>(A, r0, nrows, P, x, ldx, y, ldy, alpha, beta);
+}
+
+// ---------------------------------------------------------------------------
+// K3: batched supernodal triangular solves with the mean-matrix factor
+// L L^T = K~_0^s (the inner preconditioner I_P (x) K~_0^{-1}).  One workgroup
+// per (subdomain block, tile of Q modes); the right-hand sides of the tile
+// stay in LDS for both sweeps.  Supernodes (nested-dissection sets) are
+// processed level by level; inside a level every row first pulls the
+// contributions of the already-solved supernodes (forward: descendants
+// through the rows of L; backward: ancestors through the columns of L), then
+// the dense inverse of the supernode's diagonal block is applied.  All sums
+// have a fixed order, so the result is bitwise reproducible.
+// ---------------------------------------------------------------------------
+template <typename T, int Q>
+__global__ __launch_bounds__(SGW_BLOCK) void k_tri_solve(
+    DFactor f, const T* __restrict__ lrv, const T* __restrict__ lcv,
+    const T* __restrict__ dv, const T* rhs, int ldr, T* out, int ldo,
+    long long sr, long long so) {
+  extern __shared__ unsigned char smem_raw[];
+  T* X = reinterpret_cast<T*>(smem_raw);
+  T* tmp = X + (size_t)f.max_rows * Q;
+  const int b = blockIdx.x;
+  const int q0 = blockIdx.y * Q;
+  rhs += (long long)blockIdx.z * sr;
+  out += (long long)blockIdx.z * so;
+  const int r0 = f.row_off[b];
+  const int n = f.row_off[b + 1] - r0;
+  const int nq = min(Q, f.P - q0);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < n * Q; idx += SGW_BLOCK) {
+    int r = idx / Q, q = idx - r * Q;
+    X[idx] = q < nq ? rhs[(size_t)(q0 + q) * ldr + r0 + r] : T(0);
+  }
+  __syncthreads();
+  const int lo = f.lvl_off[b];
+  const int nlev = f.lvl_off[b + 1] - lo - 1;
+  const int pb = r0 + b;
+  // forward: L y = b
+  for (int l = nlev - 1; l >= 0; --l) {
+    const int ra = f.lrow_ptr[lo + l], cnt = (f.lrow_ptr[lo + l + 1] - ra) * Q;
+    for (int idx = tid; idx < cnt; idx += SGW_BLOCK) {
+      const int row = f.lrow_list[ra + idx / Q], q = idx % Q;
+      T s = X[row * Q + q];
+      const int e1 = f.lr_ptr[pb + row + 1];
+      for (int e = f.lr_ptr[pb + row]; e < e1; ++e) s = fmadd(-lrv[e], X[f.lr_col[e] * Q + q], s);
+      X[row * Q + q] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < cnt; idx += SGW_BLOCK) {
+      const int li = ra + idx / Q, q = idx % Q;
+      const int row = f.lrow_list[li], sn = f.lrow_sn[li];
+      const int beg = f.sn_beg[sn], w = f.sn_w[sn], a = row - beg;
+      const T* D = dv + f.sn_dinv[sn] + (size_t)a * w;
+      T s = T(0);
+      for (int c = 0; c <= a; ++c) s = fmadd(D[c], X[(beg + c) * Q + q], s);
+      tmp[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < cnt; idx += SGW_BLOCK)
+      X[f.lrow_list[ra + idx / Q] * Q + idx % Q] = tmp[idx];
+    __syncthreads();
+  }
+  // backward: L^T x = y
+  for (int l = 0; l < nlev; ++l) {
+    const int ra = f.lrow_ptr[lo + l], cnt = (f.lrow_ptr[lo + l + 1] - ra) * Q;
+    for (int idx = tid; idx < cnt; idx += SGW_BLOCK) {
+      const int row = f.lrow_list[ra + idx / Q], q = idx % Q;
+      T s = X[row * Q + q];
+      const int e1 = f.lc_ptr[pb + row + 1];
+      for (int e = f.lc_ptr[pb + row]; e < e1; ++e) s = fmadd(-lcv[e], X[f.lc_row[e] * Q + q], s);
+      X[row * Q + q] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < cnt; idx += SGW_BLOCK) {
+      const int li = ra + idx / Q, q = idx % Q;
+      const int row = f.lrow_list[li], sn = f.lrow_sn[li];
+      const int beg = f.sn_beg[sn], w = f.sn_w[sn], a = row - beg;
+      const T* D = dv + f.sn_dinv[sn];
+      T s = T(0);
+      for (int c = a; c < w; ++c) s = fmadd(D[(size_t)c * w + a], X[(beg + c) * Q + q], s);
+      tmp[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < cnt; idx += SGW_BLOCK)
+      X[f.lrow_list[ra + idx / Q] * Q + idx % Q] = tmp[idx];
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n * Q; idx += SGW_BLOCK) {
+    int r = idx / Q, q = idx - r * Q;
+    if (q < nq) out[(size_t)(q0 + q) * ldo + r0 + r] = X[idx];
+  }
+}
+
+template <typename T, int Q>
+static void launch_tri(const DFactor& f, const T* rhs, int ldr, T* out, int ldo,
+                       int nbatch, long long sr, long long so, hipStream_t st) {
+  size_t sh = (size_t)(f.max_rows + f.max_level_rows) * Q * sizeof(T);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_tri_solve<T, Q>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  const T *lrv, *lcv, *dv;
+  if constexpr (sizeof(T) == 8) {
+    lrv = reinterpret_cast<const T*>(f.lr_val);
+    lcv = reinterpret_cast<const T*>(f.lc_val);
+    dv = reinterpret_cast<const T*>(f.dinv);
+  } else {
+    lrv = reinterpret_cast<const T*>(f.lr_valf);
+    lcv = reinterpret_cast<const T*>(f.lc_valf);
+    dv = reinterpret_cast<const T*>(f.dinvf);
+  }
+  dim3 grid(f.nb, ceil_div(f.P, Q), nbatch);
+  k_tri_solve<T, Q><<<grid, SGW_BLOCK, sh, st>>>(f, lrv, lcv, dv, rhs, ldr, out, ldo, sr, so);
+}
+
+template <typename T>
+void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out, int ldo,
+               int nbatch, long long sr, long long so, hipStream_t st) {
+  switch (Q) {
+    case 1: launch_tri<T, 1>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    case 2: launch_tri<T, 2>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    case 4: launch_tri<T, 4>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    case 8: launch_tri<T, 8>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    default: launch_tri<T, 16>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4: segmented reductions, FP64 accumulation, fixed order (wave shuffles
+// then LDS), one workgroup per (block, mode).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += sh[q];
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SGW_BLOCK) void k_seg_dot(
+    const int* row_off, int P, const T* a, int lda, const T* b, int ldb,
+    double* part, const T* c, int ldc, const T* d, int ldd, double* part2) {
+  __shared__ double sh[SGW_BLOCK / 64];
+  const int blk = blockIdx.x, j = blockIdx.y;
+  const int r0 = row_off[blk], r1 = row_off[blk + 1];
+  double s = 0.0, s2 = 0.0;
+  const T* ap = a + (size_t)j * lda;
+  const T* bp = b + (size_t)j * ldb;
+  for (int r = r0 + threadIdx.x; r < r1; r += SGW_BLOCK) s += (double)ap[r] * (double)bp[r];
+  if (part2) {
+    const T* cp = c + (size_t)j * ldc;
+    const T* dp = d + (size_t)j * ldd;
+    for (int r = r0 + threadIdx.x; r < r1; r += SGW_BLOCK) s2 += (double)cp[r] * (double)dp[r];
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blk * P + j] = s;
+  if (part2) {
+    s2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) part2[blk * P + j] = s2;
+  }
+}
+
+template <typename T>
+void seg_dot(int nb, const int* row_off, int P, const T* a, int lda, const T* b,
+             int ldb, double* partial, const T* c, int ldc, const T* d, int ldd,
+             double* partial2, hipStream_t st) {
+  k_seg_dot<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, a, lda, b, ldb, partial, c, ldc, d, ldd, partial2);
+}
+
+// Per-block PCG scalars.  sc[b*8 + ...]: 0 rz, 1 pq, 2 rr, 3 bb, 4 alpha,
+// 5 beta, 6 active, 7 iterations.  flags[0] = active blocks after this
+// phase, flags[1] |= breakdown, flags[2] |= non-finite.
+//   phase 0: rz = sum part, rr = sum part2 (bb = rr when tol2 < 0 is passed
+//            as -tol2), active = rr > tol2 bb
+//   phase 1: pq = sum part; alpha = rz / pq on active blocks (else 0)
+//   phase 2: rr = sum part; active = rr > tol2 bb; iterations++
+//   phase 3: rz' = sum part; beta = rz'/rz; rz = rz'
+//   phase 4: bb = sum part
+__global__ __launch_bounds__(SGW_BLOCK) void k_pcg_scalars(
+    int phase, int nb, int P, const double* part, const double* part2,
+    double* sc, double tol2, int* flags) {
+  __shared__ int nact, brk, bad;
+  if (threadIdx.x == 0) {
+    nact = 0;
+    brk = 0;
+    bad = 0;
+  }
+  __syncthreads();
+  bool set_bb = tol2 < 0.0;
+  double t2 = set_bb ? -tol2 : tol2;
+  for (int b = threadIdx.x; b < nb; b += SGW_BLOCK) {
+    double v = 0.0, v2 = 0.0;
+    for (int j = 0; j < P; ++j) v += part[b * P + j];
+    if (part2)
+      for (int j = 0; j < P; ++j) v2 += part2[b * P + j];
+    double* s = sc + b * 8;
+    int act = s[6] != 0.0;
+    if (phase == 0) {
+      s[0] = v;
+      s[2] = v2;
+      if (set_bb) s[3] = v2;
+      act = (s[3] > 0.0) && (v2 > t2 * s[3]);
+      s[7] = 0.0;
+      if (!isfinite(v) || !isfinite(v2)) atomicOr(&bad, 1);
+    } else if (phase == 1) {
+      s[1] = v;
+      if (act && !(v > 0.0)) {
+        atomicOr(&brk, 1);
+        act = 0;
+      }
+      s[4] = act ? s[0] / v : 0.0;
+      if (!isfinite(v)) atomicOr(&bad, 1);
+    } else if (phase == 2) {
+      s[2] = v;
+      if (act) s[7] += 1.0;
+      act = act && (v > t2 * s[3]);
+      if (!isfinite(v)) atomicOr(&bad, 1);
+    } else if (phase == 3) {
+      s[5] = act ? v / s[0] : 0.0;
+      s[0] = v;
+    } else if (phase == 4) {
+      s[3] = v;
+    }
+    s[6] = act ? 1.0 : 0.0;
+    if (act) atomicAdd(&nact, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    flags[0] = nact;
+    if (phase == 0) {  // a new solve starts with clean error flags
+      flags[1] = brk;
+      flags[2] = bad;
+    } else {
+      if (brk) flags[1] = 1;
+      if (bad) flags[2] = 1;
+    }
+  }
+}
+
+void pcg_scalars(int phase, int nb, int P, const double* part, const double* part2,
+                 double* sc, double tol2, int* flags, hipStream_t st) {
+  k_pcg_scalars<<<1, SGW_BLOCK, 0, st>>>(phase, nb, P, part, part2, sc, tol2, flags);
+}
+
+template <typename T>
+__global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
+    const int* row_off, int P, const double* sc, T* x, int ldx, const T* p, int ldp,
+    T* r, int ldr, const T* q, int ldq, double* part) {
+  __shared__ double sh[SGW_BLOCK / 64];
+  const int blk = blockIdx.x, j = blockIdx.y;
+  const int r0 = row_off[blk], r1 = row_off[blk + 1];
+  const T al = (T)sc[blk * 8 + 4];
+  double s = 0.0;
+  T* xp = x + (size_t)j * ldx;
+  T* rp = r + (size_t)j * ldr;
+  const T* pp = p + (size_t)j * ldp;
+  const T* qp = q + (size_t)j * ldq;
+  for (int i = r0 + threadIdx.x; i < r1; i += SGW_BLOCK) {
+    T rv = rp[i];
+    if (al != T(0)) {
+      xp[i] = fmadd(al, pp[i], xp[i]);
+      rv = fmadd(-al, qp[i], rv);
+      rp[i] = rv;
+    }
+    s += (double)rv * (double)rv;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blk * P + j] = s;
+}
+
+template <typename T>
+void pcg_xr(int nb, const int* row_off, int P, const double* sc, T* x, int ldx,
+            const T* p, int ldp, T* r, int ldr, const T* q, int ldq,
+            double* partial, hipStream_t st) {
+  k_pcg_xr<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, sc, x, ldx, p, ldp, r, ldr, q, ldq, partial);
+}
+
+template <typename T>
+__global__ __launch_bounds__(SGW_BLOCK) void k_pcg_p(const int* row_off, const double* sc,
+                                                    const T* z, int ldz, T* p, int ldp) {
+  const int blk = blockIdx.x, j = blockIdx.y;
+  const int r0 = row_off[blk], r1 = row_off[blk + 1];
+  if (sc[blk * 8 + 6] == 0.0) return;
+  const T be = (T)sc[blk * 8 + 5];
+  const T* zp = z + (size_t)j * ldz;
+  T* pp = p + (size_t)j * ldp;
+  for (int i = r0 + threadIdx.x; i < r1; i += SGW_BLOCK) pp[i] = fmadd(be, pp[i], zp[i]);
+}
+
+template <typename T>
+void pcg_p(int nb, const int* row_off, int P, const double* sc, const T* z, int ldz,
+           T* p, int ldp, hipStream_t st) {
+  k_pcg_p<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, sc, z, ldz, p, ldp);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers over mode-major [P][n] arrays.
+// ---------------------------------------------------------------------------
+template <typename TD, typename TS>
+__global__ void k_copy2d(int P, int n, const TS* src, int lds, TD* dst, int ldd, double a) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)P * n) return;
+  int j = (int)(t / n), r = (int)(t % n);
+  dst[(size_t)j * ldd + r] = (TD)(a * (double)src[(size_t)j * lds + r]);
+}
+template <typename TD, typename TS>
+void copy2d(int P, int n, const TS* src, int lds, TD* dst, int ldd, double a, hipStream_t st) {
+  long long N = (long long)P * n;
+  if (N > 0) k_copy2d<TD, TS><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(P, n, src, lds, dst, ldd, a);
+}
+
+template <typename T>
+__global__ void k_fill2d(int P, int n, T* dst, int ldd, T v) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)P * n) return;
+  int j = (int)(t / n), r = (int)(t % n);
+  dst[(size_t)j * ldd + r] = v;
+}
+template <typename T>
+void fill2d(int P, int n, T* dst, int ldd, T v, hipStream_t st) {
+  long long N = (long long)P * n;
+  if (N > 0) k_fill2d<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(P, n, dst, ldd, v);
+}
+
+template <typename T>
+__global__ void k_axpby2d(int P, int n, double a, const T* x, int ldx, double b,
+                          const T* y, int ldy, T* dst, int ldd) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)P * n) return;
+  int j = (int)(t / n), r = (int)(t % n);
+  double v = a * (double)x[(size_t)j * ldx + r] + b * (double)y[(size_t)j * ldy + r];
+  dst[(size_t)j * ldd + r] = (T)v;
+}
+template <typename T>
+void axpby2d(int P, int n, double a, const T* x, int ldx, double b, const T* y,
+             int ldy, T* dst, int ldd, hipStream_t st) {
+  long long N = (long long)P * n;
+  if (N > 0) k_axpby2d<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(P, n, a, x, ldx, b, y, ldy, dst, ldd);
+}
+
+// ---------------------------------------------------------------------------
+// K7: Newmark predictor (Eq. UmCm, UmCm2) and update (Sec. 2).
+// Wm = Um + wc Uc is the vector the mass matrix multiplies in the effective
+// force (Eq. fparts with Rayleigh damping).
+// ---------------------------------------------------------------------------
+__global__ void k_newmark_predict(long long N, const double* U, const double* V,
+                                  const double* A, double dt, double zeta, double gamma,
+                                  double wc, double* Um, double* Uc, double* Wm) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  double um = (U[t] + dt * V[t]) / (zeta * dt * dt) + (1.0 - 2.0 * zeta) * A[t] / (2.0 * zeta);
+  double uc = gamma * dt * um - V[t] - (1.0 - gamma) * dt * A[t];
+  Um[t] = um;
+  Uc[t] = uc;
+  Wm[t] = um + wc * uc;
+}
+void newmark_predict(int P, int n, int ld, const double* U, const double* V,
+                     const double* A, double dt, double zeta, double gamma, double wc,
+                     double* Um, double* Uc, double* Wm, hipStream_t st) {
+  long long N = (long long)P * ld;
+  (void)n;
+  k_newmark_predict<<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(N, U, V, A, dt, zeta, gamma, wc, Um, Uc, Wm);
+}
+
+__global__ void k_newmark_update(long long N, const double* U1, const double* Um,
+                                 double* V, double* A, double dt, double zeta, double gamma) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  double a1 = U1[t] / (zeta * dt * dt) - Um[t];
+  V[t] = V[t] + dt * ((1.0 - gamma) * A[t] + gamma * a1);
+  A[t] = a1;
+}
+void newmark_update(int P, int n, int ld, const double* U1, const double* Um, double* V,
+                    double* A, double dt, double zeta, double gamma, hipStream_t st) {
+  long long N = (long long)P * ld;
+  (void)n;
+  k_newmark_update<<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(N, U1, Um, V, A, dt, zeta, gamma);
+}
+
+// ---------------------------------------------------------------------------
+// K6: interface restriction with partition-of-unity weights (D_s R_s,
+// Eq. det_scaling) into the torn Neumann vectors, and the weighted
+// owner-computes gather sum_s R_s^T D_s back to the interface (Eq. ugb).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_scatter_to_torn(int NT, int P, const int* gidx, const double* w,
+                                  const T* r, int ldr, T* bt, int ldt) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)NT * P) return;
+  int j = (int)(t / NT), row = (int)(t % NT);
+  int g = gidx[row];
+  bt[(size_t)j * ldt + row] = g >= 0 ? (T)(w[row] * (double)r[(size_t)j * ldr + g]) : T(0);
+}
+template <typename T>
+void scatter_to_torn(int NT, int P, const int* gidx, const double* w, const T* r,
+                     int ldr, T* bt, int ldt, hipStream_t st) {
+  long long N = (long long)NT * P;
+  k_scatter_to_torn<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(NT, P, gidx, w, r, ldr, bt, ldt);
+}
+
+template <typename T>
+__global__ void k_gather_from_torn(int nG, int P, const int* gptr, const int* gtorn,
+                                   const double* gw, const int* g2c, const T* ut, int ldt,
+                                   const T* uc, int ldc, T* z, int ldz) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nG * P) return;
+  int j = (int)(t / nG), g = (int)(t % nG);
+  double s = 0.0;
+  int c = g2c[g];
+  if (c >= 0) {
+    s = (double)uc[(size_t)j * ldc + c];
+  } else {
+    for (int e = gptr[g]; e < gptr[g + 1]; ++e) s += gw[e] * (double)ut[(size_t)j * ldt + gtorn[e]];
+  }
+  z[(size_t)j * ldz + g] = (T)s;
+}
+template <typename T>
+void gather_from_torn(int nG, int P, const int* gptr, const int* gtorn, const double* gw,
+                      const int* g2c, const T* ut, int ldt, const T* uc, int ldc, T* z,
+                      int ldz, hipStream_t st) {
+  long long N = (long long)nG * P;
+  k_gather_from_torn<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(nG, P, gptr, gtorn, gw, g2c, ut, ldt, uc, ldc, z, ldz);
+}
+
+// ---------------------------------------------------------------------------
+// K5: coarse grid (Eq. Fcc_2, NNCP2).  d_c = sum_s B_c^T (D_s r_c - K~^s_{c,(ir)} y^s)
+// with y^s the Neumann solution; u_c = F_cc^{-1} d_c with the FP64 inverse;
+// the lift adds the coarse basis Phi_s u_c^s on the remaining rows.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_coarse_rhs(DCoarse c, const T* r, int ldr, const T* yt, int ldt, double* dc) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)c.nC * c.P) return;
+  int m = (int)(t / c.nC), ci = (int)(t % c.nC);
+  double s = 0.0;
+  for (int q = c.c_ptr[ci]; q < c.c_ptr[ci + 1]; ++q) {
+    int lc = c.c_lc[q];
+    s += c.sc_w[lc] * (double)r[(size_t)m * ldr + c.sc_gidx[lc]];
+    for (int e = c.cc_ptr[lc]; e < c.cc_ptr[lc + 1]; ++e) {
+      const int row = c.cc_torn[e];
+      const double* kv = c.cc_val + (size_t)e * c.nk;
+      double acc = 0.0;
+      for (int g = c.gi_ptr[m]; g < c.gi_ptr[m + 1]; ++g)
+        acc += c.gi_v[g] * kv[c.gi_k[g]] * (double)yt[(size_t)c.gi_j[g] * ldt + row];
+      s -= acc;
+    }
+  }
+  dc[(size_t)m * c.nC + ci] = s;
+}
+template <typename T>
+void coarse_rhs(const DCoarse& c, const T* r, int ldr, const T* yt, int ldt, double* dc,
+                hipStream_t st) {
+  long long N = (long long)c.nC * c.P;
+  if (N > 0) k_coarse_rhs<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(c, r, ldr, yt, ldt, dc);
+}
+
+// u_c = F_cc^{-1} d_c; the inverse is symmetric, so thread `row` reads the
+// column finv[col*n + row] and the loads of a wave are contiguous.
+__global__ void k_coarse_solve(int n, const double* finv, const double* dc, double* uc) {
+  int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int col = 0; col < n; ++col) s += finv[(size_t)col * n + row] * dc[col];
+  uc[row] = s;
+}
+void coarse_solve(const DCoarse& c, const double* dc, double* uc, hipStream_t st) {
+  int n = c.nC * c.P;
+  if (n > 0) k_coarse_solve<<<ceil_div(n, SGW_BLOCK), SGW_BLOCK, 0, st>>>(n, c.finv, dc, uc);
+}
+
+// ut[j][rem] += sum_{m, lc} Phi_s[(m, lc)][(j, tr)] uc[m][coarse(lc)]
+template <typename T>
+__global__ void k_coarse_lift(DCoarse c, const double* uc, T* ut, int ldt) {
+  const int s = blockIdx.x;
+  const int nrem = c.rem_off[s + 1] - c.rem_off[s];
+  const int lc0 = c.sc_ptr[s], ncs = c.sc_ptr[s + 1] - lc0;
+  if (ncs == 0) return;
+  const long long nout = (long long)c.P * nrem;
+  const double* ph = c.phi + c.phi_off[s];
+  for (long long o = (long long)blockIdx.y * blockDim.x + threadIdx.x; o < nout;
+       o += (long long)gridDim.y * blockDim.x) {
+    int j = (int)(o / nrem), tr = (int)(o % nrem);
+    double acc = 0.0;
+    for (int m = 0; m < c.P; ++m)
+      for (int l = 0; l < ncs; ++l)
+        acc += ph[((size_t)m * ncs + l) * nout + o] * uc[(size_t)m * c.nC + c.sc_coarse[lc0 + l]];
+    T* dst = ut + (size_t)j * ldt + c.rem_list[c.rem_off[s] + tr];
+    *dst = (T)((double)*dst + acc);
+  }
+}
+template <typename T>
+void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt, hipStream_t st) {
+  if (c.nC == 0) return;
+  k_coarse_lift<T><<<dim3(nsub, 8), SGW_BLOCK, 0, st>>>(c, uc, ut, ldt);
+}
+
+// explicit instantiations
+#define SGW_INST(T)                                                                          \
+  template void sg_apply<T>(const DEll<T>&, const GTab&, int, int, const T*, int, T*, int, T, \
+                            T, int, long long, long long, hipStream_t);                     \
+  template void mass_apply<T>(const DEll<T>&, int, int, int, const T*, int, T*, int, T, T,   \
+                              hipStream_t);                                                  \
+  template void tri_solve<T>(const DFactor&, int, const T*, int, T*, int, int, long long,    \
+                             long long, hipStream_t);                                        \
+  template void seg_dot<T>(int, const int*, int, const T*, int, const T*, int, double*,     \
+                           const T*, int, const T*, int, double*, hipStream_t);             \
+  template void pcg_xr<T>(int, const int*, int, const double*, T*, int, const T*, int, T*,  \
+                          int, const T*, int, double*, hipStream_t);                         \
+  template void pcg_p<T>(int, const int*, int, const double*, const T*, int, T*, int,       \
+                         hipStream_t);                                                       \
+  template void fill2d<T>(int, int, T*, int, T, hipStream_t);                               \
+  template void axpby2d<T>(int, int, double, const T*, int, double, const T*, int, T*, int, \
+                           hipStream_t);                                                     \
+  template void scatter_to_torn<T>(int, int, const int*, const double*, const T*, int, T*,  \
+                                   int, hipStream_t);                                        \
+  template void gather_from_torn<T>(int, int, const int*, const int*, const double*,        \
+                                    const int*, const T*, int, const T*, int, T*, int,       \
+                                    hipStream_t);                                            \
+  template void coarse_rhs<T>(const DCoarse&, const T*, int, const T*, int, double*,        \
+                              hipStream_t);                                                  \
+  template void coarse_lift<T>(const DCoarse&, int, const double*, T*, int, hipStream_t);
+SGW_INST(double)
+SGW_INST(float)
+template void copy2d<double, double>(int, int, const double*, int, double*, int, double, hipStream_t);
+template void copy2d<float, double>(int, int, const double*, int, float*, int, double, hipStream_t);
+template void copy2d<double, float>(int, int, const float*, int, double*, int, double, hipStream_t);
+template void copy2d<float, float>(int, int, const float*, int, float*, int, double, hipStream_t);
+
+}  // namespace k
+}  // namespace sgw

@@ -1,0 +1,1023 @@
+// C-ABI and orchestration of the SG wave solver on one MI355X.
+//
+// One time step (Alg. 1 loop body, SG form of Sec. 5):
+//   H1  Newmark predictor and effective force F~ = (I(x)M) Um + C Uc
+//   H2  static condensation: Dirichlet solves per subdomain, G = F_G - K_GI x_I
+//   H3  interface initial guess
+//   H4  PCG on S U_G = G with the two-level Neumann-Neumann preconditioner
+//   H5  interior recovery (Dirichlet solves)
+//   H6  Newmark update
+// The subdomain solves with the SG-coupled matrices (H8) run as batched
+// block-PCG with the mean-matrix preconditioner I_P (x) (K~_0^s)^{-1}.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "setup.h"
+#include "sgw.h"
+
+using namespace sgw;
+
+namespace {
+
+struct Sys {  // batched block-diagonal SG system (Dirichlet or Neumann)
+  int nrows = 0, nb = 0, Q = 8;
+  k::DEll<double> A;
+  k::DFactor F;
+  const int* row_off = nullptr;  // device
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+};
+
+}  // namespace
+
+struct sgw_ctx {
+  Host h;
+  sgw_allocator al{};
+  bool has_al = false;
+  std::vector<void*> mem;
+  std::string err;
+  int dev = 0;
+  int P = 0, nk = 0, NF = 0, nI = 0, nG = 0, nC = 0, NT = 0, nsub = 0, nn = 0;
+  k::GTab gt;
+  k::DEll<double> G;
+  Sys D, N;
+  k::DCoarse co;
+  double *U = nullptr, *V = nullptr, *A = nullptr, *Um = nullptr, *Uc = nullptr,
+         *Wm = nullptr, *F = nullptr, *X = nullptr, *R = nullptr, *Z = nullptr,
+         *Pw = nullptr, *Qw = nullptr, *T1 = nullptr, *Gv = nullptr, *Tt = nullptr,
+         *Yt = nullptr, *meshbuf = nullptr, *meshbuf2 = nullptr;
+  double *part = nullptr, *part2 = nullptr, *sc = nullptr, *dc = nullptr, *uc = nullptr;
+  int* flags = nullptr;
+  int* hflags = nullptr;
+  const int* goff = nullptr;   // {0, nG}: rows relative to an interface-part pointer
+  const int* alloff = nullptr; // {0, NF}
+  const int* dd2mesh = nullptr;
+  const double* mdiag = nullptr;
+  // interface <-> torn maps
+  const int *torn_gidx = nullptr, *gam_ptr = nullptr, *gam_torn = nullptr, *g2c = nullptr;
+  const double *torn_w = nullptr, *gam_w = nullptr;
+  int maxc = 0;
+  std::vector<int> rem_off_h, rem_list_h;
+  std::vector<long long> phi_off_h;
+  double* phi = nullptr;
+  double* fs = nullptr;   // local coarse matrices during factor
+  bool factored = false, has_state = false;
+  long long stepno = 0;
+  // per-call statistics
+  long long inner_its = 0;
+  int inner_solves = 0;
+  int status_warn = 0;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+#define HIPCHK(x)                                                         \
+  do {                                                                    \
+    hipError_t e_ = (x);                                                  \
+    if (e_ != hipSuccess) {                                               \
+      c->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " \
+               + #x;                                                      \
+      return SGW_EHIP;                                                    \
+    }                                                                     \
+  } while (0)
+
+static void* dalloc_bytes(sgw_ctx* c, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  void* p = nullptr;
+  if (c->has_al) {
+    p = c->al.alloc(bytes, c->al.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) {
+    c->mem.push_back(p);
+    (void)hipMemset(p, 0, bytes);  // no kernel ever sees uninitialised memory
+  }
+  return p;
+}
+
+template <class T>
+static T* dalloc(sgw_ctx* c, size_t n) {
+  return reinterpret_cast<T*>(dalloc_bytes(c, n * sizeof(T)));
+}
+
+template <class T>
+static T* upload(sgw_ctx* c, const std::vector<T>& v) {
+  T* d = dalloc<T>(c, v.size());
+  if (d && !v.empty()) hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return d;
+}
+
+static std::vector<float> to_f(const std::vector<double>& v) {
+  return std::vector<float>(v.begin(), v.end());
+}
+
+// Galerkin contraction table for the SG apply kernel (see kernels.h).
+static int build_gtab(sgw_ctx* c, int KC, int GS) {
+  const Galerkin& g = c->h.g;
+  k::GTab t;
+  t.nk = g.nk;
+  t.P = g.P;
+  t.KC = KC;
+  t.GS = GS;
+  t.ng = (g.P + GS - 1) / GS;
+  t.nch = (g.nk + KC - 1) / KC;
+  std::map<std::pair<int, int>, std::vector<std::pair<int, double>>> byKJ;
+  for (size_t e = 0; e < g.v.size(); ++e) byKJ[{g.k[e], g.j[e]}].push_back({g.i[e], g.v[e]});
+  std::vector<uint32_t> mask;
+  std::vector<int> pbeg, ebeg, pcnt, ei;
+  std::vector<double> ec;
+  for (int grp = 0; grp < t.ng; ++grp)
+    for (int ch = 0; ch < t.nch; ++ch)
+      for (int j = 0; j < g.P; ++j) {
+        uint32_t m = 0;
+        pbeg.push_back((int)pcnt.size());
+        ebeg.push_back((int)ei.size());
+        for (int kk = 0; kk < KC; ++kk) {
+          int kx = ch * KC + kk;
+          if (kx >= g.nk) break;
+          auto it = byKJ.find({kx, j});
+          if (it == byKJ.end()) continue;
+          int cnt = 0;
+          for (auto& iv : it->second)
+            if (iv.first >= grp * GS && iv.first < (grp + 1) * GS) {
+              ei.push_back(iv.first - grp * GS);
+              ec.push_back(iv.second);
+              ++cnt;
+            }
+          if (cnt) {
+            m |= 1u << kk;
+            pcnt.push_back(cnt);
+          }
+        }
+        mask.push_back(m);
+      }
+  t.mask = upload(c, mask);
+  t.pair_beg = upload(c, pbeg);
+  t.ent_beg = upload(c, ebeg);
+  t.pair_cnt = upload(c, pcnt);
+  t.ent_i = upload(c, ei);
+  t.ent_c = upload(c, ec);
+  t.ent_cf = upload(c, to_f(ec));
+  c->gt = t;
+  return 0;
+}
+
+static k::DEll<double> upload_ell(sgw_ctx* c, const Ell& E) {
+  k::DEll<double> d;
+  d.nrows = E.nrows;
+  d.W = E.W;
+  d.nk = E.nk;
+  d.col = upload(c, E.col);
+  d.val = upload(c, E.val);
+  d.mval = upload(c, E.mval);
+  return d;
+}
+
+static k::DFactor upload_factor(sgw_ctx* c, const Factor& f) {
+  k::DFactor d;
+  d.nb = f.nb;
+  d.P = c->P;
+  d.row_off = upload(c, f.row_off);
+  d.lvl_off = upload(c, f.lvl_off);
+  d.lvl_ptr = upload(c, f.lvl_ptr);
+  d.lrow_ptr = upload(c, f.lrow_ptr);
+  d.lrow_list = upload(c, f.lrow_list);
+  d.lrow_sn = upload(c, f.lrow_sn);
+  d.sn_beg = upload(c, f.sn_beg);
+  d.sn_w = upload(c, f.sn_w);
+  d.sn_dinv = upload(c, f.sn_dinv);
+  d.lr_ptr = upload(c, f.lr_ptr);
+  d.lr_col = upload(c, f.lr_col);
+  d.lc_ptr = upload(c, f.lc_ptr);
+  d.lc_row = upload(c, f.lc_row);
+  d.lr_val = upload(c, f.lr_val);
+  d.lc_val = upload(c, f.lc_val);
+  d.dinv = upload(c, f.dinv);
+  d.lr_valf = upload(c, to_f(f.lr_val));
+  d.lc_valf = upload(c, to_f(f.lc_val));
+  d.dinvf = upload(c, to_f(f.dinv));
+  d.max_rows = f.max_rows;
+  d.max_level_rows = f.max_level_rows;
+  return d;
+}
+
+static int pick_q(const Factor& f, int P) {
+  // largest mode tile whose two LDS arrays fit in 64 KiB (two workgroups/CU)
+  int best = 1;
+  for (int q : {2, 4, 8, 16}) {
+    size_t bytes = (size_t)(f.max_rows + f.max_level_rows) * q * sizeof(double);
+    if (bytes <= 64 * 1024 && q <= std::max(1, P)) best = q;
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------------------
+// H8: batched subdomain SG solves.  PCG per block with x0 = 0 and the
+// preconditioner I_P (x) (L L^T)^{-1}; stops when every block has
+// ||r_s|| <= tol ||b_s||.  Converged blocks are frozen (alpha = 0).
+// ---------------------------------------------------------------------------
+static int inner_solve(sgw_ctx* c, Sys& S, const double* b, int ldb, double* out,
+                       int ldo, double tol, int maxit, hipStream_t st) {
+  const int P = c->P, n = S.nrows, nb = S.nb;
+  k::copy2d<double, double>(P, n, b, ldb, S.r, n, 1.0, st);
+  k::fill2d<double>(P, n, S.x, n, 0.0, st);
+  k::tri_solve<double>(S.F, S.Q, S.r, n, S.z, n, 1, 0, 0, st);
+  k::copy2d<double, double>(P, n, S.z, n, S.p, n, 1.0, st);
+  k::seg_dot<double>(nb, S.row_off, P, S.r, n, S.z, n, c->part, S.r, n, S.r, n, c->part2, st);
+  k::pcg_scalars(0, nb, P, c->part, c->part2, c->sc, -(tol * tol), c->flags, st);
+  HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int it = 0, rc = 0;
+  int nact = c->hflags[0];
+  while (nact > 0) {
+    if (it >= maxit) {
+      rc = SGW_NOT_CONVERGED;
+      break;
+    }
+    k::sg_apply<double>(S.A, c->gt, 0, n, S.p, n, S.q, n, 1.0, 0.0, 1, 0, 0, st);
+    k::seg_dot<double>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
+    k::pcg_scalars(1, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
+    k::pcg_xr<double>(nb, S.row_off, P, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part, st);
+    k::pcg_scalars(2, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
+    HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ++it;
+    nact = c->hflags[0];
+    if (c->hflags[1]) {
+      c->err = "breakdown (p'q <= 0) in a subdomain solve";
+      return SGW_EBREAKDOWN;
+    }
+    if (c->hflags[2]) {
+      c->err = "non-finite residual in a subdomain solve";
+      return SGW_ENAN;
+    }
+    if (nact == 0) break;
+    k::tri_solve<double>(S.F, S.Q, S.r, n, S.z, n, 1, 0, 0, st);
+    k::seg_dot<double>(nb, S.row_off, P, S.r, n, S.z, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
+    k::pcg_scalars(3, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
+    k::pcg_p<double>(nb, S.row_off, P, c->sc, S.z, n, S.p, n, st);
+  }
+  k::copy2d<double, double>(P, n, S.x, n, out, ldo, 1.0, st);
+  c->inner_its += it;
+  c->inner_solves += 1;
+  return rc;
+}
+
+// q_G = S p_G (Eq. Sto_Schur): harmonic extension of p into the interiors
+// (Dirichlet solves) and the interface rows of the global operator.  w and q
+// are full [P][NF] arrays: p is w's interface part, the interior part of w is
+// overwritten with the extension, the result goes to q's interface rows.
+static int schur_apply(sgw_ctx* c, double* w, double* q, hipStream_t st) {
+  const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
+  const sgw_problem_desc& d = c->h.d;
+  k::fill2d<double>(P, nI, w, NF, 0.0, st);
+  k::sg_apply<double>(c->G, c->gt, 0, nI, w, NF, c->T1, NF, -1.0, 0.0, 1, 0, 0, st);
+  int rc = inner_solve(c, c->D, c->T1, NF, w, NF, d.inner_rtol, d.inner_max_iter, st);
+  if (rc < 0) return rc;
+  k::sg_apply<double>(c->G, c->gt, nI, nG, w, NF, q, NF, 1.0, 0.0, 1, 0, 0, st);
+  return rc;
+}
+
+
+// z_G = M_NNC^{-1} r_G (Eq. NNCP2).  The local residuals D_s R_s r on the
+// remaining nodes drive one batched Neumann solve (corners held at zero);
+// the coarse right-hand side d_c = sum_s B_c^T (D_s r_c - K~^s_{c,(ir)} y^s)
+// gives u_c = F_cc^{-1} d_c; the remaining values get the coarse basis term
+// Phi_s u_c^s (the second Neumann solve of Eq. urs, precomputed), and the
+// weighted gather sum_s R_s^T D_s (...) assembles z (Eq. ugb).
+static int precond(sgw_ctx* c, const double* r, double* z, hipStream_t st) {
+  const int P = c->P, NF = c->NF, NT = c->NT, nG = c->nG;
+  const sgw_problem_desc& d = c->h.d;
+  k::scatter_to_torn<double>(NT, P, c->torn_gidx, c->torn_w, r, NF, c->Tt, NT, st);
+  int rc = inner_solve(c, c->N, c->Tt, NT, c->Yt, NT, d.inner_rtol, d.inner_max_iter, st);
+  if (rc < 0) return rc;
+  if (c->nC > 0) {
+    k::coarse_rhs<double>(c->co, r, NF, c->Yt, NT, c->dc, st);
+    k::coarse_solve(c->co, c->dc, c->uc, st);
+    k::coarse_lift<double>(c->co, c->nsub, c->uc, c->Yt, NT, st);
+  }
+  k::gather_from_torn<double>(nG, P, c->gam_ptr, c->gam_torn, c->gam_w, c->g2c, c->Yt, NT,
+                              c->uc, c->nC, z, NF, st);
+  return rc;
+}
+
+// Global dot over the interface rows (one block), FP64, fixed order.
+static int gdot(sgw_ctx* c, const double* a, const double* b, double& out, hipStream_t st) {
+  k::seg_dot<double>(1, c->goff, c->P, a, c->NF, b, c->NF, c->part, nullptr, 0, nullptr, 0,
+                     nullptr, st);
+  std::vector<double> h(c->P);
+  HIPCHK(hipMemcpyAsync(h.data(), c->part, c->P * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double s = 0.0;
+  for (double v : h) s += v;
+  out = s;
+  return 0;
+}
+
+// One SG system K~ U = F on the DD numbering (F, X global [P][NF]); X holds
+// the interface initial guess on entry and the full solution on exit.
+static int dd_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st,
+                    int& outer_its, double& relres) {
+  const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
+  const sgw_problem_desc& d = c->h.d;
+  int warn = 0, rc;
+  // H2: condensation G = F_G - K~_GI K~_II^{-1} F_I
+  rc = inner_solve(c, c->D, F, NF, c->T1, NF, d.inner_rtol, d.inner_max_iter, st);
+  if (rc < 0) return rc;
+  warn |= rc;
+  k::fill2d<double>(P, nG, c->T1 + nI, NF, 0.0, st);
+  k::copy2d<double, double>(P, nG, F + nI, NF, c->Gv + nI, NF, 1.0, st);
+  k::sg_apply<double>(c->G, c->gt, nI, nG, c->T1, NF, c->Gv, NF, -1.0, 1.0, 1, 0, 0, st);
+  double gg;
+  if ((rc = gdot(c, c->Gv + nI, c->Gv + nI, gg, st))) return rc;
+  // H3/H4: PCG on S U_G = G, initial guess in X's interface part
+  double* x = X + nI;
+  double* r = c->R + nI;
+  double* z = c->Z + nI;
+  double* p = c->Pw + nI;
+  double* q = c->Qw + nI;
+  k::copy2d<double, double>(P, nG, x, NF, p, NF, 1.0, st);
+  if ((rc = schur_apply(c, c->Pw, c->Qw, st)) < 0) return rc;
+  warn |= rc;
+  k::axpby2d<double>(P, nG, 1.0, c->Gv + nI, NF, -1.0, q, NF, r, NF, st);
+  if ((rc = precond(c, r, z, st)) < 0) return rc;
+  warn |= rc;
+  k::copy2d<double, double>(P, nG, z, NF, p, NF, 1.0, st);
+  double rz, rr;
+  if ((rc = gdot(c, r, z, rz, st))) return rc;
+  if ((rc = gdot(c, r, r, rr, st))) return rc;
+  const double stop2 = d.rtol * d.rtol * gg;
+  int it = 0;
+  while (rr > stop2 && gg > 0.0) {
+    if (it >= d.max_iter) {
+      warn = SGW_NOT_CONVERGED;
+      break;
+    }
+    if ((rc = schur_apply(c, c->Pw, c->Qw, st)) < 0) return rc;
+    warn |= rc;
+    double pq;
+    if ((rc = gdot(c, p, q, pq, st))) return rc;
+    if (!(pq > 0.0)) {
+      c->err = "breakdown (p'Sp <= 0) in the interface PCG";
+      return std::isfinite(pq) ? SGW_EBREAKDOWN : SGW_ENAN;
+    }
+    double al = rz / pq;
+    k::axpby2d<double>(P, nG, 1.0, x, NF, al, p, NF, x, NF, st);
+    k::axpby2d<double>(P, nG, 1.0, r, NF, -al, q, NF, r, NF, st);
+    ++it;
+    if ((rc = gdot(c, r, r, rr, st))) return rc;
+    if (!std::isfinite(rr)) {
+      c->err = "non-finite interface residual";
+      return SGW_ENAN;
+    }
+    if (rr <= stop2) break;
+    if ((rc = precond(c, r, z, st)) < 0) return rc;
+    warn |= rc;
+    double rzn;
+    if ((rc = gdot(c, r, z, rzn, st))) return rc;
+    k::axpby2d<double>(P, nG, 1.0, z, NF, rzn / rz, p, NF, p, NF, st);
+    rz = rzn;
+  }
+  outer_its = it;
+  relres = gg > 0.0 ? std::sqrt(rr / gg) : 0.0;
+  // H5: interior recovery U_I = K~_II^{-1} (F_I - K~_IG U_G)
+  k::fill2d<double>(P, nI, X, NF, 0.0, st);
+  k::copy2d<double, double>(P, nI, F, NF, c->T1, NF, 1.0, st);
+  k::sg_apply<double>(c->G, c->gt, 0, nI, X, NF, c->T1, NF, -1.0, 1.0, 1, 0, 0, st);
+  rc = inner_solve(c, c->D, c->T1, NF, X, NF, d.inner_rtol, d.inner_max_iter, st);
+  if (rc < 0) return rc;
+  warn |= rc;
+  return warn ? SGW_NOT_CONVERGED : 0;
+}
+
+// ---------------------------------------------------------------------------
+// mesh-node <-> DD-numbering conversions and moments
+// ---------------------------------------------------------------------------
+__global__ void k_mesh_to_dd(int P, int NF, int nn, const int* dd2mesh, const double* src,
+                             double* dst) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)P * NF) return;
+  int j = (int)(t / NF), dd = (int)(t % NF);
+  dst[(size_t)j * NF + dd] = src[(size_t)j * nn + dd2mesh[dd]];
+}
+__global__ void k_dd_to_mesh(int P, int NF, int nn, const int* dd2mesh, const double* src,
+                             double* dst) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)P * NF) return;
+  int j = (int)(t / NF), dd = (int)(t % NF);
+  dst[(size_t)j * nn + dd2mesh[dd]] = src[(size_t)j * NF + dd];
+}
+// H10: mean = mode 0, var = sum_{j>=1} u_j^2 (normalised basis)
+__global__ void k_moments(int P, int NF, const int* dd2mesh, const double* U, double* mean,
+                          double* var) {
+  int dd = blockIdx.x * blockDim.x + threadIdx.x;
+  if (dd >= NF) return;
+  double v = 0.0;
+  for (int j = 1; j < P; ++j) {
+    double u = U[(size_t)j * NF + dd];
+    v += u * u;
+  }
+  int m = dd2mesh[dd];
+  if (mean) mean[m] = U[dd];
+  if (var) var[m] = v;
+}
+__global__ void k_diag_scale(long long N, int NF, const double* diag, const double* r, double* z) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  z[t] = r[t] / diag[t % NF];
+}
+
+static int to_dd(sgw_ctx* c, const double* src, int where, double* dst, hipStream_t st) {
+  const size_t bytes = (size_t)c->P * c->nn * sizeof(double);
+  const double* s = src;
+  if (where == SGW_HOST) {
+    HIPCHK(hipMemcpyAsync(c->meshbuf, src, bytes, hipMemcpyHostToDevice, st));
+    s = c->meshbuf;
+  }
+  long long N = (long long)c->P * c->NF;
+  k_mesh_to_dd<<<(int)((N + 255) / 256), 256, 0, st>>>(c->P, c->NF, c->nn, c->dd2mesh, s, dst);
+  return 0;
+}
+
+static int from_dd(sgw_ctx* c, const double* src, double* dst, int where, hipStream_t st) {
+  const size_t bytes = (size_t)c->P * c->nn * sizeof(double);
+  double* t = where == SGW_HOST ? c->meshbuf : dst;
+  HIPCHK(hipMemsetAsync(t, 0, bytes, st));
+  long long N = (long long)c->P * c->NF;
+  k_dd_to_mesh<<<(int)((N + 255) / 256), 256, 0, st>>>(c->P, c->NF, c->nn, c->dd2mesh, src, t);
+  if (where == SGW_HOST) {
+    HIPCHK(hipMemcpyAsync(dst, t, bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return 0;
+}
+
+// (I (x) M) A = rhs by Jacobi-preconditioned CG over all modes (set-up only).
+static int mass_solve(sgw_ctx* c, const double* rhs, double* out, hipStream_t st) {
+  const int P = c->P, NF = c->NF;
+  const long long N = (long long)P * NF;
+  double* r = c->R;
+  double* z = c->Z;
+  double* p = c->Pw;
+  double* q = c->Qw;
+  k::fill2d<double>(P, NF, out, NF, 0.0, st);
+  k::copy2d<double, double>(P, NF, rhs, NF, r, NF, 1.0, st);
+  auto dot = [&](const double* a, const double* b, double& v) -> int {
+    k::seg_dot<double>(1, c->alloff, P, a, NF, b, NF, c->part, nullptr, 0, nullptr, 0, nullptr, st);
+    std::vector<double> h(P);
+    HIPCHK(hipMemcpyAsync(h.data(), c->part, P * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    v = 0.0;
+    for (double x : h) v += x;
+    return 0;
+  };
+  int rc;
+  double bb, rz, rr;
+  if ((rc = dot(r, r, bb))) return rc;
+  if (bb == 0.0) return 0;
+  k_diag_scale<<<(int)((N + 255) / 256), 256, 0, st>>>(N, NF, c->mdiag, r, z);
+  k::copy2d<double, double>(P, NF, z, NF, p, NF, 1.0, st);
+  if ((rc = dot(r, z, rz))) return rc;
+  rr = bb;
+  for (int it = 0; it < 500 && rr > 1e-30 * bb; ++it) {
+    k::mass_apply<double>(c->G, 0, NF, P, p, NF, q, NF, 1.0, 0.0, st);
+    double pq;
+    if ((rc = dot(p, q, pq))) return rc;
+    double al = rz / pq;
+    k::axpby2d<double>(P, NF, 1.0, out, NF, al, p, NF, out, NF, st);
+    k::axpby2d<double>(P, NF, 1.0, r, NF, -al, q, NF, r, NF, st);
+    if ((rc = dot(r, r, rr))) return rc;
+    k_diag_scale<<<(int)((N + 255) / 256), 256, 0, st>>>(N, NF, c->mdiag, r, z);
+    double rzn;
+    if ((rc = dot(r, z, rzn))) return rc;
+    k::axpby2d<double>(P, NF, 1.0, z, NF, rzn / rz, p, NF, p, NF, st);
+    rz = rzn;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// coarse set-up kernels: for local corner slot lcl and mode m, the right-hand
+// side -K~^s_{(ir),c} e_(c,m) of every subdomain that has that corner, and,
+// from the Neumann solution x, the coarse basis Phi_s[:, (m,lcl)] (remaining
+// rows) and the local coarse-matrix column
+// F^s[(m',lc'), (m,lcl)] = K~^s_cc + K~^s_{c',(ir)} x  (Eq. Fcc_2 with
+// S_cc - S_cr S_rr^{-1} S_rc written as one Neumann solve).
+// ---------------------------------------------------------------------------
+__global__ void k_basis_rhs(k::DCoarse co, int lcl, int m, double* bt, int ldt) {
+  int s = blockIdx.x;
+  int ncs = co.sc_ptr[s + 1] - co.sc_ptr[s];
+  if (lcl >= ncs) return;
+  int lc = co.sc_ptr[s] + lcl;
+  int ne = co.cc_ptr[lc + 1] - co.cc_ptr[lc];
+  for (int t = threadIdx.x; t < ne * co.P; t += blockDim.x) {
+    int e = co.cc_ptr[lc] + t / co.P, j = t % co.P;
+    const double* kv = co.cc_val + (size_t)e * co.nk;
+    double acc = 0.0;
+    for (int g = co.gi_ptr[j]; g < co.gi_ptr[j + 1]; ++g)
+      if (co.gi_j[g] == m) acc += co.gi_v[g] * kv[co.gi_k[g]];
+    bt[(size_t)j * ldt + co.cc_torn[e]] = -acc;
+  }
+}
+
+__global__ void k_basis_store(k::DCoarse co, int lcl, int m, const double* xt, int ldt,
+                              double* fs) {
+  int s = blockIdx.x;
+  int lc0 = co.sc_ptr[s], ncs = co.sc_ptr[s + 1] - lc0;
+  if (lcl >= ncs) return;
+  int nrem = co.rem_off[s + 1] - co.rem_off[s];
+  long long nout = (long long)co.P * nrem;
+  double* ph = const_cast<double*>(co.phi) + co.phi_off[s] + ((size_t)m * ncs + lcl) * nout;
+  for (long long o = threadIdx.x; o < nout; o += blockDim.x) {
+    int j = (int)(o / nrem), tr = (int)(o % nrem);
+    ph[o] = xt[(size_t)j * ldt + co.rem_list[co.rem_off[s] + tr]];
+  }
+  const int MP = co.maxc * co.P;
+  double* F = fs + (size_t)s * MP * MP;
+  for (int t = threadIdx.x; t < ncs * co.P; t += blockDim.x) {
+    int l2 = t / co.P, m2 = t % co.P;
+    int lc = lc0 + l2;
+    double v = 0.0;  // the K~^s_cc term is added on the host
+    for (int e = co.cc_ptr[lc]; e < co.cc_ptr[lc + 1]; ++e) {
+      const double* kv = co.cc_val + (size_t)e * co.nk;
+      int row = co.cc_torn[e];
+      for (int g = co.gi_ptr[m2]; g < co.gi_ptr[m2 + 1]; ++g)
+        v += co.gi_v[g] * kv[co.gi_k[g]] * xt[(size_t)co.gi_j[g] * ldt + row];
+    }
+    F[(size_t)(m2 * co.maxc + l2) * MP + (m * co.maxc + lcl)] = v;
+  }
+}
+
+// dense SPD inverse on the host: Cholesky, then L^{-1}, then L^{-T} L^{-1}
+static bool spd_inverse(std::vector<double>& A, int n) {
+  for (int j = 0; j < n; ++j) {
+    double dsum = A[(size_t)j * n + j];
+    for (int k2 = 0; k2 < j; ++k2) dsum -= A[(size_t)j * n + k2] * A[(size_t)j * n + k2];
+    if (!(dsum > 0.0)) return false;
+    double djj = std::sqrt(dsum);
+    A[(size_t)j * n + j] = djj;
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[(size_t)i * n + j];
+      const double* ai = &A[(size_t)i * n];
+      const double* aj = &A[(size_t)j * n];
+      for (int k2 = 0; k2 < j; ++k2) s -= ai[k2] * aj[k2];
+      A[(size_t)i * n + j] = s / djj;
+    }
+  }
+  // Linv (lower) in place of L
+  std::vector<double> Li((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    Li[(size_t)j * n + j] = 1.0 / A[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int k2 = j; k2 < i; ++k2) s -= A[(size_t)i * n + k2] * Li[(size_t)k2 * n + j];
+      Li[(size_t)i * n + j] = s / A[(size_t)i * n + i];
+    }
+  }
+  // Ainv = Li^T Li
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (int k2 = i; k2 < n; ++k2) s += Li[(size_t)k2 * n + i] * Li[(size_t)k2 * n + j];
+      A[(size_t)i * n + j] = s;
+      A[(size_t)j * n + i] = s;
+    }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* sgw_last_error(const sgw_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+long long sgw_query(const sgw_ctx* c, int what) {
+  if (!c) return -1;
+  switch (what) {
+    case 0: return c->P;
+    case 1: return c->nk;
+    case 2: return c->NF;
+    case 3: return c->nG;
+    case 4: return c->nC;
+    case 5: return c->nsub;
+    case 6: return c->nn;
+    default: return -1;
+  }
+}
+
+int sgw_destroy(sgw_ctx* c) {
+  if (!c) return 0;
+  hipDeviceSynchronize();
+  for (void* p : c->mem) {
+    if (c->has_al) c->al.free(p, c->al.user);
+    else hipFree(p);
+  }
+  if (c->hflags) hipHostFree(c->hflags);
+  delete c;
+  return 0;
+}
+
+int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out) {
+  if (!d || !out) return SGW_EINVAL;
+  *out = nullptr;
+  sgw_ctx* c = new sgw_ctx();
+  if (al && al->alloc && al->free) {
+    c->al = *al;
+    c->has_al = true;
+  }
+  hipGetDevice(&c->dev);
+  sgw_problem_desc dd = *d;
+  if (dd.zeta == 0.0) dd.zeta = 0.25;
+  if (dd.gamma == 0.0) dd.gamma = 0.5;
+  if (dd.max_iter <= 0) dd.max_iter = 1000;
+  if (dd.inner_max_iter <= 0) dd.inner_max_iter = 1000;
+  if (!(dd.rtol > 0)) dd.rtol = 1e-8;
+  if (!(dd.inner_rtol > 0)) dd.inner_rtol = 1e-3 * dd.rtol;
+  int rc = build_host(dd, c->h, c->err);
+  if (rc) {
+    *out = c;
+    return rc;
+  }
+  Host& h = c->h;
+  c->P = h.g.P;
+  c->nk = h.g.nk;
+  c->NF = h.NF;
+  c->nI = h.nI;
+  c->nG = h.nG;
+  c->nC = h.nC;
+  c->NT = h.NT;
+  c->nsub = h.nsub;
+  c->nn = h.nn;
+  const int P = c->P;
+  int GS = (P + ((P + 47) / 48) - 1) / ((P + 47) / 48);
+  build_gtab(c, 8, GS);
+  c->G = upload_ell(c, h.glob);
+  c->D.A = upload_ell(c, h.dir);
+  c->N.A = upload_ell(c, h.neu);
+  c->D.F = upload_factor(c, h.fD);
+  c->N.F = upload_factor(c, h.fN);
+  c->D.nrows = h.nI;
+  c->D.nb = h.nsub;
+  c->D.row_off = c->D.F.row_off;
+  c->D.Q = pick_q(h.fD, P);
+  c->N.nrows = h.NT;
+  c->N.nb = h.nsub;
+  c->N.row_off = c->N.F.row_off;
+  c->N.Q = pick_q(h.fN, P);
+  for (Sys* S : {&c->D, &c->N}) {
+    size_t n = (size_t)P * S->nrows;
+    S->x = dalloc<double>(c, n);
+    S->r = dalloc<double>(c, n);
+    S->z = dalloc<double>(c, n);
+    S->p = dalloc<double>(c, n);
+    S->q = dalloc<double>(c, n);
+  }
+  size_t nv = (size_t)P * h.NF;
+  for (double** v : {&c->U, &c->V, &c->A, &c->Um, &c->Uc, &c->Wm, &c->F, &c->X, &c->R, &c->Z,
+                     &c->Pw, &c->Qw, &c->T1, &c->Gv})
+    *v = dalloc<double>(c, nv);
+  c->Tt = dalloc<double>(c, (size_t)P * h.NT);
+  c->Yt = dalloc<double>(c, (size_t)P * h.NT);
+  c->meshbuf = dalloc<double>(c, (size_t)std::max(P, 2) * h.nn);
+  c->meshbuf2 = dalloc<double>(c, (size_t)P * h.nn);
+  int nbmax = std::max(1, h.nsub);
+  c->part = dalloc<double>(c, (size_t)nbmax * P);
+  c->part2 = dalloc<double>(c, (size_t)nbmax * P);
+  c->sc = dalloc<double>(c, (size_t)nbmax * 8);
+  c->flags = dalloc<int>(c, 4);
+  c->goff = upload(c, std::vector<int>{0, h.nG});  // rows of the interface part
+  c->alloff = upload(c, std::vector<int>{0, h.NF});
+  c->dd2mesh = upload(c, h.dd2mesh);
+  std::vector<double> md(h.NF);
+  for (int r = 0; r < h.NF; ++r) md[r] = h.glob.mval[r];  // slot 0 = diagonal
+  c->mdiag = upload(c, md);
+  c->torn_gidx = upload(c, h.torn_gidx);
+  c->torn_w = upload(c, h.torn_w);
+  c->gam_ptr = upload(c, h.gam_ptr);
+  c->gam_torn = upload(c, h.gam_torn);
+  c->gam_w = upload(c, h.gam_w);
+  c->g2c = upload(c, h.g2c.empty() ? std::vector<int>{-1} : h.g2c);
+  // coarse structures
+  k::DCoarse& co = c->co;
+  co.nC = h.nC;
+  co.P = P;
+  co.nk = c->nk;
+  for (int s = 0; s < h.nsub; ++s) c->maxc = std::max(c->maxc, h.sc_ptr[s + 1] - h.sc_ptr[s]);
+  co.maxc = c->maxc;
+  std::vector<std::vector<int>> cl(h.nC);
+  for (size_t lc = 0; lc < h.sc_coarse.size(); ++lc) cl[h.sc_coarse[lc]].push_back((int)lc);
+  std::vector<int> c_ptr{0}, c_lc;
+  for (auto& v : cl) {
+    c_lc.insert(c_lc.end(), v.begin(), v.end());
+    c_ptr.push_back((int)c_lc.size());
+  }
+  co.c_ptr = upload(c, c_ptr);
+  co.c_lc = upload(c, c_lc);
+  co.sc_gidx = upload(c, h.sc_gidx);
+  co.sc_coarse = upload(c, h.sc_coarse);
+  co.sc_w = upload(c, h.sc_w);
+  co.sc_ptr = upload(c, h.sc_ptr);
+  co.cc_ptr = upload(c, h.cc_ptr);
+  co.cc_torn = upload(c, h.cc_torn);
+  co.cc_val = upload(c, h.cc_val);
+  {
+    std::vector<std::vector<int>> byi(P);
+    for (size_t e = 0; e < h.g.v.size(); ++e) byi[h.g.i[e]].push_back((int)e);
+    std::vector<int> gp{0}, gk, gj;
+    std::vector<double> gv;
+    for (int i = 0; i < P; ++i) {
+      for (int e : byi[i]) {
+        gk.push_back(h.g.k[e]);
+        gj.push_back(h.g.j[e]);
+        gv.push_back(h.g.v[e]);
+      }
+      gp.push_back((int)gk.size());
+    }
+    co.gi_ptr = upload(c, gp);
+    co.gi_k = upload(c, gk);
+    co.gi_j = upload(c, gj);
+    co.gi_v = upload(c, gv);
+  }
+  c->rem_off_h.assign(1, 0);
+  c->phi_off_h.assign(1, 0);
+  for (int s = 0; s < h.nsub; ++s) {
+    for (int t = h.Toff[s]; t < h.Toff[s + 1]; ++t)
+      if (h.torn_gidx[t] >= 0) c->rem_list_h.push_back(t);
+    c->rem_off_h.push_back((int)c->rem_list_h.size());
+    long long nrem = c->rem_off_h[s + 1] - c->rem_off_h[s];
+    int ncs = h.sc_ptr[s + 1] - h.sc_ptr[s];
+    c->phi_off_h.push_back(c->phi_off_h.back() + (long long)P * ncs * P * nrem);
+  }
+  co.rem_off = upload(c, c->rem_off_h);
+  co.rem_list = upload(c, c->rem_list_h.empty() ? std::vector<int>{0} : c->rem_list_h);
+  co.phi_off = upload(c, c->phi_off_h);
+  c->phi = dalloc<double>(c, (size_t)std::max<long long>(1, c->phi_off_h.back()));
+  co.phi = c->phi;
+  c->dc = dalloc<double>(c, (size_t)std::max(1, h.nC * P));
+  c->uc = dalloc<double>(c, (size_t)std::max(1, h.nC * P));
+  if (hipHostMalloc((void**)&c->hflags, 16 * sizeof(int)) != hipSuccess) {
+    c->err = "pinned allocation failed";
+    *out = c;
+    return SGW_ENOMEM;
+  }
+  for (void* p : c->mem)
+    if (!p) {
+      c->err = "device allocation failed";
+      *out = c;
+      return SGW_ENOMEM;
+    }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    c->err = "device error during upload";
+    *out = c;
+    return SGW_EHIP;
+  }
+  *out = c;
+  return 0;
+}
+
+int sgw_factor(sgw_ctx* c, void* stream) {
+  if (!c) return SGW_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Host& h = c->h;
+  const int P = c->P, NT = c->NT;
+  if (c->nC > 0) {
+    const int MP = c->maxc * P;
+    c->fs = dalloc<double>(c, (size_t)c->nsub * MP * MP);
+    if (!c->fs) {
+      c->err = "device allocation failed (coarse set-up)";
+      return SGW_ENOMEM;
+    }
+    HIPCHK(hipMemsetAsync(c->fs, 0, (size_t)c->nsub * MP * MP * sizeof(double), st));
+    const double tol = std::min(1e-12, c->h.d.inner_rtol);
+    for (int lcl = 0; lcl < c->maxc; ++lcl)
+      for (int m = 0; m < P; ++m) {
+        k::fill2d<double>(P, NT, c->Tt, NT, 0.0, st);
+        k_basis_rhs<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->Tt, NT);
+        int rc = inner_solve(c, c->N, c->Tt, NT, c->Yt, NT, tol, c->h.d.inner_max_iter, st);
+        if (rc < 0) return rc;
+        k_basis_store<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->Yt, NT, c->fs);
+      }
+    std::vector<double> fs((size_t)c->nsub * MP * MP);
+    HIPCHK(hipMemcpyAsync(fs.data(), c->fs, fs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int n = c->nC * P;
+    std::vector<double> F((size_t)n * n, 0.0);
+    for (int s = 0; s < c->nsub; ++s) {
+      int lc0 = h.sc_ptr[s], ncs = h.sc_ptr[s + 1] - lc0;
+      const double* Fs = &fs[(size_t)s * MP * MP];
+      for (int l2 = 0; l2 < ncs; ++l2)
+        for (int m2 = 0; m2 < P; ++m2)
+          for (int l1 = 0; l1 < ncs; ++l1)
+            for (int m1 = 0; m1 < P; ++m1) {
+              double v = Fs[(size_t)(m2 * c->maxc + l2) * MP + (m1 * c->maxc + l1)];
+              if (l2 == l1) {  // K~^s_cc: corners couple only to themselves
+                for (size_t e = 0; e < h.g.v.size(); ++e)
+                  if (h.g.i[e] == m2 && h.g.j[e] == m1)
+                    v += h.g.v[e] * h.cself[(size_t)(lc0 + l2) * c->nk + h.g.k[e]];
+              }
+              int r = m2 * c->nC + h.sc_coarse[lc0 + l2];
+              int q = m1 * c->nC + h.sc_coarse[lc0 + l1];
+              F[(size_t)r * n + q] += v;
+            }
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j) {
+        double a = 0.5 * (F[(size_t)i * n + j] + F[(size_t)j * n + i]);
+        F[(size_t)i * n + j] = a;
+        F[(size_t)j * n + i] = a;
+      }
+    if (!spd_inverse(F, n)) {
+      c->err = "coarse matrix F_cc is not positive definite";
+      return SGW_ENOTSPD;
+    }
+    double* finv = upload(c, F);
+    if (!finv) {
+      c->err = "device allocation failed (coarse inverse)";
+      return SGW_ENOMEM;
+    }
+    c->co.finv = finv;
+  }
+  c->factored = true;
+  return 0;
+}
+
+int sgw_set_state(sgw_ctx* c, const double* U, const double* V, const double* A, int where,
+                  int step, void* stream) {
+  if (!c) return SGW_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Host& h = c->h;
+  const int P = c->P, NF = c->NF;
+  const sgw_problem_desc& d = h.d;
+  if (U) {
+    to_dd(c, U, where, c->U, st);
+  } else {
+    std::vector<double> u0((size_t)P * c->nn, 0.0);
+    for (int v = 0; v < c->nn; ++v) {
+      double x = (v % (h.n + 1)) / (double)h.n, y = (v / (h.n + 1)) / (double)h.n;
+      double r2 = (x - d.x0) * (x - d.x0) + (y - d.y0) * (y - d.y0);
+      u0[v] = d.amp * std::exp(-r2 / (d.width * d.width));
+    }
+    HIPCHK(hipMemcpyAsync(c->meshbuf2, u0.data(), u0.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    to_dd(c, c->meshbuf2, SGW_DEVICE, c->U, st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (V) to_dd(c, V, where, c->V, st);
+  else k::fill2d<double>(P, NF, c->V, NF, 0.0, st);
+  if (A) {
+    to_dd(c, A, where, c->A, st);
+  } else {
+    // (I(x)M) A = -(K U + C V); K = (K~ - a_m I(x)M)/s_k, C = a0 I(x)M + a1 K
+    const double s = h.s_k, am = h.a_m, a0 = d.alpha0, a1 = d.alpha1;
+    k::axpby2d<double>(P, NF, 1.0, c->U, NF, a1, c->V, NF, c->Wm, NF, st);
+    k::sg_apply<double>(c->G, c->gt, 0, NF, c->Wm, NF, c->F, NF, -1.0 / s, 0.0, 1, 0, 0, st);
+    k::mass_apply<double>(c->G, 0, NF, P, c->Wm, NF, c->F, NF, am / s, 1.0, st);
+    k::mass_apply<double>(c->G, 0, NF, P, c->V, NF, c->F, NF, -a0, 1.0, st);
+    int rc = mass_solve(c, c->F, c->A, st);
+    if (rc) return rc;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  c->stepno = step;
+  c->has_state = true;
+  return 0;
+}
+
+int sgw_get_state(sgw_ctx* c, double* U, double* V, double* A, int where, void* stream) {
+  if (!c) return SGW_EINVAL;
+  if (!c->has_state) {
+    c->err = "no state";
+    return SGW_ESTATE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (U && (rc = from_dd(c, c->U, U, where, st))) return rc;
+  if (V && (rc = from_dd(c, c->V, V, where, st))) return rc;
+  if (A && (rc = from_dd(c, c->A, A, where, st))) return rc;
+  return 0;
+}
+
+int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
+  if (!c) return SGW_EINVAL;
+  if (!c->factored || !c->has_state) {
+    c->err = "sgw_step needs sgw_factor and sgw_set_state first";
+    return SGW_ESTATE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const Host& h = c->h;
+  const sgw_problem_desc& d = h.d;
+  const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
+  sgw_step_stats s{};
+  c->inner_its = 0;
+  c->inner_solves = 0;
+  int warn = 0;
+  for (int n = 0; n < nsteps; ++n) {
+    // H1: predictor and effective force F~ = M (Um + wc Uc) + (a1/s) K~ Uc
+    const double wc = d.alpha0 - d.alpha1 * h.a_m / h.s_k;
+    k::newmark_predict(P, NF, NF, c->U, c->V, c->A, d.dt, d.zeta, d.gamma, wc, c->Um, c->Uc,
+                       c->Wm, st);
+    k::mass_apply<double>(c->G, 0, NF, P, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
+    if (d.alpha1 != 0.0)
+      k::sg_apply<double>(c->G, c->gt, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0, 1, 0,
+                          0, st);
+    // H3: initial interface guess
+    if (d.guess == SGW_GUESS_NEWMARK) {
+      // U + dt V + dt^2/2 A on the interface
+      k::axpby2d<double>(P, nG, 1.0, c->U + nI, NF, d.dt, c->V + nI, NF, c->X + nI, NF, st);
+      k::axpby2d<double>(P, nG, 1.0, c->X + nI, NF, 0.5 * d.dt * d.dt, c->A + nI, NF,
+                         c->X + nI, NF, st);
+    } else {
+      k::copy2d<double, double>(P, nG, c->U + nI, NF, c->X + nI, NF, 1.0, st);
+    }
+    int its = 0;
+    double rel = 0.0;
+    int rc = dd_solve(c, c->F, c->X, st, its, rel);
+    if (rc < 0) return rc;
+    warn |= rc;
+    // H6: Newmark update
+    k::newmark_update(P, NF, NF, c->X, c->Um, c->V, c->A, d.dt, d.zeta, d.gamma, st);
+    std::swap(c->U, c->X);
+    s.steps++;
+    s.outer_iters += its;
+    s.outer_iters_max = std::max(s.outer_iters_max, its);
+    s.last_rel_res = rel;
+    c->stepno++;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  s.inner_iters = c->inner_its;
+  s.inner_solves = c->inner_solves;
+  if (stats) *stats = s;
+  return warn ? SGW_NOT_CONVERGED : 0;
+}
+
+int sgw_solve(sgw_ctx* c, const double* F, double* U, void* stream, sgw_step_stats* stats) {
+  if (!c || !F || !U) return SGW_EINVAL;
+  if (!c->factored) {
+    c->err = "sgw_solve needs sgw_factor first";
+    return SGW_ESTATE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  c->inner_its = 0;
+  c->inner_solves = 0;
+  to_dd(c, F, SGW_DEVICE, c->Wm, st);
+  to_dd(c, U, SGW_DEVICE, c->X, st);
+  int its = 0;
+  double rel = 0.0;
+  int rc = dd_solve(c, c->Wm, c->X, st, its, rel);
+  if (rc < 0) return rc;
+  int rc2 = from_dd(c, c->X, U, SGW_DEVICE, st);
+  if (rc2) return rc2;
+  HIPCHK(hipStreamSynchronize(st));
+  if (stats) {
+    sgw_step_stats s{};
+    s.outer_iters = its;
+    s.outer_iters_max = its;
+    s.inner_iters = c->inner_its;
+    s.inner_solves = c->inner_solves;
+    s.last_rel_res = rel;
+    *stats = s;
+  }
+  return rc;
+}
+
+int sgw_read_moments(sgw_ctx* c, double* mean, double* var, int where, void* stream) {
+  if (!c) return SGW_EINVAL;
+  if (!c->has_state) {
+    c->err = "no state";
+    return SGW_ESTATE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = (size_t)c->nn * sizeof(double);
+  double* dm = where == SGW_HOST ? c->meshbuf : mean;
+  double* dv = where == SGW_HOST ? c->meshbuf + c->nn : var;
+  if (dm) HIPCHK(hipMemsetAsync(dm, 0, bytes, st));
+  if (dv) HIPCHK(hipMemsetAsync(dv, 0, bytes, st));
+  k_moments<<<(c->NF + 255) / 256, 256, 0, st>>>(c->P, c->NF, c->dd2mesh, c->U,
+                                                 mean ? dm : nullptr, var ? dv : nullptr);
+  if (where == SGW_HOST) {
+    if (mean) HIPCHK(hipMemcpyAsync(mean, dm, bytes, hipMemcpyDeviceToHost, st));
+    if (var) HIPCHK(hipMemcpyAsync(var, dv, bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return 0;
+}
+
+int sgw_apply_operator(sgw_ctx* c, const double* X, double* Y, int precision, void* stream) {
+  if (!c || !X || !Y) return SGW_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  to_dd(c, X, SGW_DEVICE, c->Wm, st);
+  (void)precision;
+  k::sg_apply<double>(c->G, c->gt, 0, c->NF, c->Wm, c->NF, c->F, c->NF, 1.0, 0.0, 1, 0, 0, st);
+  return from_dd(c, c->F, Y, SGW_DEVICE, st);
+}
+
+}  // extern "C"
