@@ -81,6 +81,8 @@ typedef struct sgw_problem_desc {
   int inner_max_iter;
   int precision;         /* SGW_FP64 or SGW_FP32_IR64 */
   int guess;             /* initial interface guess, SGW_GUESS_* */
+  double precond_rtol;   /* Neumann solves inside the preconditioner (<= 0: inner_rtol);
+                            the interface PCG is the flexible (Polak-Ribiere) variant */
 } sgw_problem_desc;
 
 /* Optional device allocator.  alloc returns device memory of >= bytes
@@ -157,6 +159,30 @@ int sgw_apply_operator(sgw_ctx* ctx, const double* X, double* Y,
  * U holds the initial guess on entry. */
 int sgw_solve(sgw_ctx* ctx, const double* F, double* U, void* stream,
               sgw_step_stats* stats);
+
+/* Kernel timing (tracing).  enable != 0 records a HIP event pair around
+ * every launch of the SG operator apply (kind 0) and of the batched
+ * subdomain triangular solves (kind 1) on the launch stream, and clears the
+ * counters; enable == 0 stops recording.  Adds one event record per launch. */
+int sgw_profile(sgw_ctx* ctx, int enable);
+
+/* Launches, total kernel milliseconds and total algorithmic bytes of a kind
+ * since the last sgw_profile call.  Bytes per SG-apply row:
+ * 7 (M+1) values + 7 column indices + P inputs + P outputs (+ P when the
+ * output is accumulated), 8-byte values; per triangular-solve launch: the
+ * right-hand sides in and out plus the factor's values and indices. */
+int sgw_profile_read(sgw_ctx* ctx, int kind, long long* launches, double* ms,
+                     double* bytes);
+
+/* Autotuner (tile shapes picked on the context's own data): times the
+ * batched triangular solves for every feasible mode tile Q = 1..8 on the
+ * Dirichlet and the Neumann systems and the SG apply with the unrolled
+ * Galerkin tensor against the table-driven one, and keeps the fastest for
+ * later calls.  report (may be NULL) receives up to nreport values, in
+ * microseconds per launch: [0..7] Dirichlet solve with Q = 1..8, [8..15]
+ * Neumann solve with Q = 1..8 (-1: not feasible), [16] unrolled SG apply,
+ * [17] table-driven SG apply.  Enqueues on stream and waits for it. */
+int sgw_autotune(sgw_ctx* ctx, void* stream, double* report, int nreport);
 
 /* Sizes: what = 0 P, 1 number of input PCE terms, 2 free nodes,
  * 3 interface nodes, 4 corner nodes, 5 subdomains, 6 (n+1)^2. */

@@ -25,7 +25,8 @@ ERRORS = {-1: "SGW_EINVAL", -2: "SGW_ESTATE", -3: "SGW_ENOMEM",
 # every symbol include/sgw.h declares
 EXPORTS = ["sgw_create", "sgw_factor", "sgw_set_state", "sgw_get_state",
            "sgw_step", "sgw_read_moments", "sgw_apply_operator", "sgw_solve",
-           "sgw_query", "sgw_last_error", "sgw_destroy"]
+           "sgw_query", "sgw_last_error", "sgw_destroy", "sgw_profile",
+           "sgw_profile_read", "sgw_autotune"]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -40,7 +41,8 @@ class ProblemDesc(ctypes.Structure):
                 ("width", ctypes.c_double), ("amp", ctypes.c_double),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
-                ("precision", ctypes.c_int), ("guess", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("guess", ctypes.c_int),
+                ("precond_rtol", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -86,6 +88,11 @@ def lib():
         L.sgw_last_error.argtypes = [vp]
         L.sgw_last_error.restype = ctypes.c_char_p
         L.sgw_destroy.argtypes = [vp]
+        L.sgw_profile.argtypes = [vp, ip]
+        L.sgw_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ip]
+        L.sgw_profile_read.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong),
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTS:
             if name not in ("sgw_query", "sgw_last_error"):
                 getattr(L, name).restype = ip
@@ -112,7 +119,7 @@ class Solver:
 
     def __init__(self, prm, rtol=None, inner_rtol=None, max_iter=1000,
                  inner_max_iter=1000, precision=SGW_FP64, guess=SGW_GUESS_PREV,
-                 use_torch_allocator=True):
+                 precond_rtol=None, use_torch_allocator=True):
         import torch
         self.torch = torch
         L = lib()
@@ -134,6 +141,7 @@ class Solver:
         d.inner_rtol = inner_rtol if inner_rtol is not None else 1e-3 * d.rtol
         d.inner_max_iter = inner_max_iter
         d.precision, d.guess = precision, guess
+        d.precond_rtol = precond_rtol if precond_rtol is not None else 0.0
         self.desc = d
         self._live = {}
         al = None
@@ -225,6 +233,26 @@ class Solver:
         rc = lib().sgw_solve(self.ctx, _ptr(F), _ptr(U), self._stream(), ctypes.byref(st))
         self._check(rc, "sgw_solve")
         return U.view(self.P, self.nn), st.as_dict()
+
+    def profile(self, enable=True):
+        """Start (clear) or stop the per-launch kernel timing."""
+        return self._check(lib().sgw_profile(self.ctx, int(enable)), "sgw_profile")
+
+    def profile_read(self, kind):
+        """(launches, ms, algorithmic bytes) of kind 0 = SG apply,
+        1 = subdomain triangular solves."""
+        n, ms, b = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        self._check(lib().sgw_profile_read(self.ctx, kind, ctypes.byref(n), ctypes.byref(ms),
+                                           ctypes.byref(b)), "sgw_profile_read")
+        return n.value, ms.value, b.value
+
+    def autotune(self):
+        """Pick the fastest launch shapes; returns the timing report (us)."""
+        rep = (ctypes.c_double * 18)()
+        self._check(lib().sgw_autotune(self.ctx, self._stream(), rep, 18), "sgw_autotune")
+        r = list(rep)
+        return {"tri_dirichlet_us_by_Q": r[0:8], "tri_neumann_us_by_Q": r[8:16],
+                "sg_apply_unrolled_us": r[16], "sg_apply_table_us": r[17]}
 
     def close(self):
         if self.ctx:

@@ -21,6 +21,9 @@ FLAGS = [
 def build(verbose=False):
     """Compile every source into libsgw.so (always rebuilds)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    sys.path.insert(0, ROOT)
+    from paper_2512_23027_amd import gen_k1
+    gen_k1.generate()
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src + ".o")

@@ -16,6 +16,8 @@ namespace k {
 // gives the number of (i, c) entries, stored consecutively in ent_i / ent_c.
 struct GTab {
   int nk = 0, P = 0, KC = 0, GS = 0, ng = 0, nch = 0;
+  int L = -1, p_in = -1, p_out = -1;  // basis, for the specialised kernels
+  bool use_spec = true;              // false: always the table-driven kernel
   const uint32_t* mask = nullptr;    // [ng][nch][P]
   const int* pair_beg = nullptr;     // [ng][nch][P]
   const int* ent_beg = nullptr;      // [ng][nch][P]
@@ -53,10 +55,13 @@ struct DFactor {
   int nb = 0, P = 0;
   const int *row_off, *lvl_off, *lvl_ptr, *lrow_ptr, *lrow_list, *lrow_sn;
   const int *sn_beg, *sn_w, *sn_dinv, *lr_ptr, *lr_col, *lc_ptr, *lc_row;
-  const double *lr_val, *lc_val, *dinv;
-  const float *lr_valf, *lc_valf, *dinvf;
-  int max_rows = 0, max_level_rows = 0;
+  const int *lvl_gf, *lvl_gb;  // lanes per row in the pull phases (0: no entries)
+  const double *lr_val, *lc_val, *dinv, *dinvT;  // dinv row-major, dinvT column-major
+  const float *lr_valf, *lc_valf, *dinvf, *dinvTf;
+  int max_rows = 0, max_level_rows = 0, max_sn = 0, max_levels = 0, max_lvl_d = 0;
 };
+template <typename T>
+size_t tri_lds_bytes(const DFactor& f, int Q);
 template <typename T>
 void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
                int ldo, int nbatch, long long sr, long long so, hipStream_t st);

@@ -15,10 +15,40 @@ namespace k {
 
 #define SGW_WAVE 64
 #define SGW_BLOCK 256
+// triangular solves: threads per workgroup and rows per thread in the
+// diagonal phase (levels may hold up to TRI_TPB * TRI_RPT rows)
+#define TRI_TPB 1024
+#define TRI_RPT 2
+#define TRI_DPT 8   // inverse-block values per thread loaded ahead of the pull phase
 
 static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 template <typename T> __device__ __forceinline__ T fmadd(T a, T b, T c) { return fma(a, b, c); }
+
+// Raw buffer access: 128-bit resource (base address, no stride, no range
+// limit) with a per-lane 32-bit byte offset and a wave-uniform byte offset.
+typedef unsigned int sgw_u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xffffffffu,
+                                           0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ int buf_load<int>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+template <typename T> __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(sgw_u32x2, v), r, voff, soff, 0);
+}
+template <> __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
 
 // ---------------------------------------------------------------------------
 // K1: SG operator apply y_i = sum_k sum_j c_kij K_k x_j (Eq. stok / K_T_Sto).
@@ -97,11 +127,17 @@ __global__ __launch_bounds__(SGW_WAVE) void k_sg_apply(
   }
 }
 
+// Kernels with the Galerkin tensor of a fixed basis unrolled (gen_k1.py).
+#include "k1_spec.inc"
+
 template <typename T>
 void sg_apply(const DEll<T>& A, const GTab& g, int r0, int nrows, const T* x,
               int ldx, T* y, int ldy, T alpha, T beta, int nbatch,
               long long sx, long long sy, hipStream_t st) {
   if (nrows <= 0) return;
+  if (g.use_spec && sg_apply_specialised<T>(g.L, g.p_in, g.p_out, A, r0, nrows, x, ldx, y, ldy,
+                                            alpha, beta, nbatch, sx, sy, st))
+    return;
   dim3 grid(ceil_div(nrows, SGW_WAVE), g.ng, nbatch);
   size_t sh = (size_t)g.GS * SGW_WAVE * sizeof(T);
   const T* entc = nullptr;
@@ -150,21 +186,42 @@ void mass_apply(const DEll<T>& A, int r0, int nrows, int P, const T* x, int ldx,
 // K3: batched supernodal triangular solves with the mean-matrix factor
 // L L^T = K~_0^s (the inner preconditioner I_P (x) K~_0^{-1}).  One workgroup
 // per (subdomain block, tile of Q modes); the right-hand sides of the tile
-// stay in LDS for both sweeps.  Supernodes (nested-dissection sets) are
-// processed level by level; inside a level every row first pulls the
-// contributions of the already-solved supernodes (forward: descendants
-// through the rows of L; backward: ancestors through the columns of L), then
-// the dense inverse of the supernode's diagonal block is applied.  All sums
-// have a fixed order, so the result is bitwise reproducible.
+// stay in LDS (row-major, Q values per row) for both sweeps.  Supernodes
+// (nested-dissection sets) are processed level by level:
+//  * pull phase, one thread per row, all Q modes in registers: the row takes
+//    the contributions of the already-solved supernodes (forward: its
+//    descendants through the rows of L; backward: its ancestors through the
+//    columns of L);
+//  * diagonal phase, one wave per supernode, one lane per row: the dense
+//    inverse of the supernode's diagonal block is applied in place.  All
+//    lanes of the wave read the block before any lane writes it, so no
+//    workgroup barrier or scratch copy is needed.  The inverse is stored
+//    column-major for the forward and row-major for the backward sweep, so
+//    the lanes of a wave read it contiguously.
+// Every sum has a fixed order: the result is bitwise reproducible.
 // ---------------------------------------------------------------------------
 template <typename T, int Q>
-__global__ __launch_bounds__(SGW_BLOCK) void k_tri_solve(
+__global__ __launch_bounds__(TRI_TPB) void k_tri_solve(
     DFactor f, const T* __restrict__ lrv, const T* __restrict__ lcv,
-    const T* __restrict__ dv, const T* rhs, int ldr, T* out, int ldo,
-    long long sr, long long so) {
+    const T* __restrict__ dr, const T* __restrict__ dc, const T* rhs, int ldr,
+    T* out, int ldo, long long sr, long long so) {
   extern __shared__ unsigned char smem_raw[];
+  // LDS: right-hand sides; the dense inverse blocks of the current level;
+  // the block's level lists, entry pointers and supernode table, so that
+  // every index the sweeps need is one LDS read
   T* X = reinterpret_cast<T*>(smem_raw);
-  T* tmp = X + (size_t)f.max_rows * Q;
+  T* Dst = X + (size_t)f.max_rows * Q;
+  int* s_row = reinterpret_cast<int*>(Dst + f.max_lvl_d);
+  int* s_sn = s_row + f.max_rows;
+  int* s_lr = s_sn + f.max_rows;
+  int* s_lc = s_lr + f.max_rows + 1;
+  int* s_beg = s_lc + f.max_rows + 1;
+  int* s_w = s_beg + f.max_sn;
+  int* s_dv = s_w + f.max_sn;
+  int* s_lrow = s_dv + f.max_sn;             // level -> first position
+  int* s_lsn = s_lrow + f.max_levels + 1;     // level -> first supernode
+  int* s_gf = s_lsn + f.max_levels + 1;
+  int* s_gb = s_gf + f.max_levels + 1;
   const int b = blockIdx.x;
   const int q0 = blockIdx.y * Q;
   rhs += (long long)blockIdx.z * sr;
@@ -173,92 +230,174 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_tri_solve(
   const int n = f.row_off[b + 1] - r0;
   const int nq = min(Q, f.P - q0);
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < n * Q; idx += SGW_BLOCK) {
-    int r = idx / Q, q = idx - r * Q;
-    X[idx] = q < nq ? rhs[(size_t)(q0 + q) * ldr + r0 + r] : T(0);
-  }
-  __syncthreads();
   const int lo = f.lvl_off[b];
   const int nlev = f.lvl_off[b + 1] - lo - 1;
-  const int pb = r0 + b;
-  // forward: L y = b
-  for (int l = nlev - 1; l >= 0; --l) {
-    const int ra = f.lrow_ptr[lo + l], cnt = (f.lrow_ptr[lo + l + 1] - ra) * Q;
-    for (int idx = tid; idx < cnt; idx += SGW_BLOCK) {
-      const int row = f.lrow_list[ra + idx / Q], q = idx % Q;
-      T s = X[row * Q + q];
-      const int e1 = f.lr_ptr[pb + row + 1];
-      for (int e = f.lr_ptr[pb + row]; e < e1; ++e) s = fmadd(-lrv[e], X[f.lr_col[e] * Q + q], s);
-      X[row * Q + q] = s;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < cnt; idx += SGW_BLOCK) {
-      const int li = ra + idx / Q, q = idx % Q;
-      const int row = f.lrow_list[li], sn = f.lrow_sn[li];
-      const int beg = f.sn_beg[sn], w = f.sn_w[sn], a = row - beg;
-      const T* D = dv + f.sn_dinv[sn] + (size_t)a * w;
-      T s = T(0);
-      for (int c = 0; c <= a; ++c) s = fmadd(D[c], X[(beg + c) * Q + q], s);
-      tmp[idx] = s;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < cnt; idx += SGW_BLOCK)
-      X[f.lrow_list[ra + idx / Q] * Q + idx % Q] = tmp[idx];
-    __syncthreads();
+  const int p0 = f.lrow_ptr[lo];
+  const int sn0 = f.lvl_ptr[lo];
+  const int nsn = f.lvl_ptr[lo + nlev] - sn0;
+  for (int i = tid; i < n; i += TRI_TPB) {
+    s_row[i] = f.lrow_list[p0 + i];
+    s_sn[i] = f.lrow_sn[p0 + i] - sn0;
   }
-  // backward: L^T x = y
-  for (int l = 0; l < nlev; ++l) {
-    const int ra = f.lrow_ptr[lo + l], cnt = (f.lrow_ptr[lo + l + 1] - ra) * Q;
-    for (int idx = tid; idx < cnt; idx += SGW_BLOCK) {
-      const int row = f.lrow_list[ra + idx / Q], q = idx % Q;
-      T s = X[row * Q + q];
-      const int e1 = f.lc_ptr[pb + row + 1];
-      for (int e = f.lc_ptr[pb + row]; e < e1; ++e) s = fmadd(-lcv[e], X[f.lc_row[e] * Q + q], s);
-      X[row * Q + q] = s;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < cnt; idx += SGW_BLOCK) {
-      const int li = ra + idx / Q, q = idx % Q;
-      const int row = f.lrow_list[li], sn = f.lrow_sn[li];
-      const int beg = f.sn_beg[sn], w = f.sn_w[sn], a = row - beg;
-      const T* D = dv + f.sn_dinv[sn];
-      T s = T(0);
-      for (int c = a; c < w; ++c) s = fmadd(D[(size_t)c * w + a], X[(beg + c) * Q + q], s);
-      tmp[idx] = s;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < cnt; idx += SGW_BLOCK)
-      X[f.lrow_list[ra + idx / Q] * Q + idx % Q] = tmp[idx];
-    __syncthreads();
+  for (int i = tid; i <= n; i += TRI_TPB) {
+    s_lr[i] = f.lr_ptr[p0 + i];
+    s_lc[i] = f.lc_ptr[p0 + i];
   }
-  for (int idx = tid; idx < n * Q; idx += SGW_BLOCK) {
-    int r = idx / Q, q = idx - r * Q;
-    if (q < nq) out[(size_t)(q0 + q) * ldo + r0 + r] = X[idx];
+  for (int i = tid; i < nsn; i += TRI_TPB) {
+    s_beg[i] = f.sn_beg[sn0 + i];
+    s_w[i] = f.sn_w[sn0 + i];
+    s_dv[i] = f.sn_dinv[sn0 + i];
   }
+  for (int i = tid; i <= nlev; i += TRI_TPB) {
+    s_lrow[i] = f.lrow_ptr[lo + i] - p0;
+    s_lsn[i] = f.lvl_ptr[lo + i] - sn0;
+    s_gf[i] = f.lvl_gf[lo + i];
+    s_gb[i] = f.lvl_gb[lo + i];
+  }
+  // coalesced load: consecutive threads take consecutive rows of one mode
+  for (int idx = tid; idx < n * Q; idx += TRI_TPB) {
+    int q = idx / n, r = idx - q * n;
+    X[r * Q + q] = q < nq ? rhs[(size_t)(q0 + q) * ldr + r0 + r] : T(0);
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    const bool fwd = sweep == 0;
+    const int* sp = fwd ? s_lr : s_lc;
+    const int* eidx = fwd ? f.lr_col : f.lc_row;
+    const T* eval = fwd ? lrv : lcv;
+    const T* dmat = fwd ? dc : dr;
+    const int* sg = fwd ? s_gf : s_gb;
+    for (int it = 0; it < nlev; ++it) {
+      const int l = fwd ? nlev - 1 - it : it;
+      const int ra = s_lrow[l], nr = s_lrow[l + 1] - ra;
+      const int snA = s_lsn[l], snB = s_lsn[l + 1];
+      // the inverse blocks of this level are contiguous: start their loads
+      // now, store them to LDS after the pull phase
+      const int d0 = snA < snB ? s_dv[snA] : 0;
+      const int nd = snA < snB ? s_dv[snB - 1] + s_w[snB - 1] * s_w[snB - 1] - d0 : 0;
+      T dreg[TRI_DPT];
+#pragma unroll
+      for (int t = 0; t < TRI_DPT; ++t) {
+        const int j = tid + t * TRI_TPB;
+        dreg[t] = j < nd ? dmat[(size_t)d0 + j] : T(0);
+      }
+      // pull phase: G consecutive lanes share one row (G divides 64); each
+      // lane reads up to 8 of its entries at once, then a fixed xor-shuffle
+      // tree adds the G partial sums
+      const int G = sg[l];
+      if (G > 0) {
+        for (int idx = tid; idx < nr * G; idx += TRI_TPB) {
+          const int li = ra + idx / G, sub = idx & (G - 1);
+          const int row = s_row[li];
+          const int e1 = sp[li + 1];
+          T acc[Q];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) acc[q] = T(0);
+          for (int e = sp[li] + sub; e < e1; e += 8 * G) {
+            int ci[8];
+            T cv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int ee = e + t * G;
+              const bool ok = ee < e1;
+              ci[t] = ok ? eidx[ee] * Q : 0;
+              cv[t] = ok ? eval[ee] : T(0);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+              for (int q = 0; q < Q; ++q) acc[q] = fmadd(cv[t], X[ci[t] + q], acc[q]);
+          }
+          for (int off = G >> 1; off > 0; off >>= 1)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q] += __shfl_xor(acc[q], off, 64);
+          if (sub == 0)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) X[row * Q + q] -= acc[q];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TRI_DPT; ++t) {
+        const int j = tid + t * TRI_TPB;
+        if (j < nd) Dst[j] = dreg[t];
+      }
+      for (int j = tid + TRI_DPT * TRI_TPB; j < nd; j += TRI_TPB) Dst[j] = dmat[(size_t)d0 + j];
+      __syncthreads();
+      // diagonal phase: one thread per row of the level (at most TRI_RPT
+      // rows per thread) applies its row of the supernode's dense inverse
+      // from LDS; results wait in registers until every thread has read the
+      // level's rows, then overwrite them
+      T res[TRI_RPT][Q];
+#pragma unroll
+      for (int k2 = 0; k2 < TRI_RPT; ++k2) {
+        const int idx = tid + k2 * TRI_TPB;
+        if (idx < nr) {
+          const int li = ra + idx, row = s_row[li], sn = s_sn[li];
+          const int beg = s_beg[sn], w = s_w[sn], a = row - beg;
+          const T* D = Dst + (s_dv[sn] - d0);
+          T acc[Q];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) acc[q] = T(0);
+          for (int c = 0; c < w; ++c) {
+            const T dv = D[c * w + a];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q] = fmadd(dv, X[(beg + c) * Q + q], acc[q]);
+          }
+#pragma unroll
+          for (int q = 0; q < Q; ++q) res[k2][q] = acc[q];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k2 = 0; k2 < TRI_RPT; ++k2) {
+        const int idx = tid + k2 * TRI_TPB;
+        if (idx < nr) {
+          const int row = s_row[ra + idx];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) X[row * Q + q] = res[k2][q];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // coalesced store
+  for (int idx = tid; idx < n * Q; idx += TRI_TPB) {
+    int q = idx / n, r = idx - q * n;
+    if (q < nq) out[(size_t)(q0 + q) * ldo + r0 + r] = X[r * Q + q];
+  }
+}
+
+// LDS bytes of one triangular-solve workgroup with Q modes
+template <typename T>
+size_t tri_lds_bytes(const DFactor& f, int Q) {
+  return ((size_t)f.max_rows * Q + (size_t)f.max_lvl_d) * sizeof(T) +
+         sizeof(int) * (4 * (size_t)f.max_rows + 2 + 3 * (size_t)f.max_sn + 4 * ((size_t)f.max_levels + 1));
 }
 
 template <typename T, int Q>
 static void launch_tri(const DFactor& f, const T* rhs, int ldr, T* out, int ldo,
                        int nbatch, long long sr, long long so, hipStream_t st) {
-  size_t sh = (size_t)(f.max_rows + f.max_level_rows) * Q * sizeof(T);
+  size_t sh = tri_lds_bytes<T>(f, Q);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_tri_solve<T, Q>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  const T *lrv, *lcv, *dv;
+  const T *lrv, *lcv, *dr, *dc;
   if constexpr (sizeof(T) == 8) {
     lrv = reinterpret_cast<const T*>(f.lr_val);
     lcv = reinterpret_cast<const T*>(f.lc_val);
-    dv = reinterpret_cast<const T*>(f.dinv);
+    dr = reinterpret_cast<const T*>(f.dinv);
+    dc = reinterpret_cast<const T*>(f.dinvT);
   } else {
     lrv = reinterpret_cast<const T*>(f.lr_valf);
     lcv = reinterpret_cast<const T*>(f.lc_valf);
-    dv = reinterpret_cast<const T*>(f.dinvf);
+    dr = reinterpret_cast<const T*>(f.dinvf);
+    dc = reinterpret_cast<const T*>(f.dinvTf);
   }
   dim3 grid(f.nb, ceil_div(f.P, Q), nbatch);
-  k_tri_solve<T, Q><<<grid, SGW_BLOCK, sh, st>>>(f, lrv, lcv, dv, rhs, ldr, out, ldo, sr, so);
+  k_tri_solve<T, Q><<<grid, TRI_TPB, sh, st>>>(f, lrv, lcv, dr, dc, rhs, ldr, out, ldo, sr, so);
 }
 
 template <typename T>
@@ -267,9 +406,12 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out, int ldo,
   switch (Q) {
     case 1: launch_tri<T, 1>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
     case 2: launch_tri<T, 2>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    case 3: launch_tri<T, 3>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
     case 4: launch_tri<T, 4>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
-    case 8: launch_tri<T, 8>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
-    default: launch_tri<T, 16>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    case 5: launch_tri<T, 5>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    case 6: launch_tri<T, 6>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    case 7: launch_tri<T, 7>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
+    default: launch_tri<T, 8>(f, rhs, ldr, out, ldo, nbatch, sr, so, st); break;
   }
 }
 
@@ -654,6 +796,8 @@ void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt, h
 }
 
 // explicit instantiations
+template size_t tri_lds_bytes<double>(const DFactor&, int);
+template size_t tri_lds_bytes<float>(const DFactor&, int);
 #define SGW_INST(T)                                                                          \
   template void sg_apply<T>(const DEll<T>&, const GTab&, int, int, const T*, int, T*, int, T, \
                             T, int, long long, long long, hipStream_t);                     \

@@ -313,11 +313,13 @@ static void append_factor(Factor& f, const CSC& L, const std::vector<SN>& sns) {
                    [&](int a, int b) { return sns[a].level < sns[b].level; });
   int sn0 = (int)f.sn_beg.size();
   f.lvl_off.push_back((int)f.lvl_ptr.size() + nlev + 1);
-  std::vector<int> lvcount(nlev, 0), lvrows(nlev, 0);
+  std::vector<int> lvcount(nlev, 0), lvrows(nlev, 0), lvd(nlev, 0);
   for (auto& s : sns) {
     lvcount[s.level]++;
     lvrows[s.level] += s.w;
+    lvd[s.level] += s.w * s.w;
   }
+  for (int l = 0; l < nlev; ++l) f.max_lvl_d = std::max(f.max_lvl_d, lvd[l]);
   int acc = sn0;
   for (int l = 0; l < nlev; ++l) {
     f.lvl_ptr.push_back(acc);
@@ -365,29 +367,69 @@ static void append_factor(Factor& f, const CSC& L, const std::vector<SN>& sns) {
       }
     }
     f.dinv.insert(f.dinv.end(), Inv.begin(), Inv.end());
+    for (int c = 0; c < w; ++c)
+      for (int r = 0; r < w; ++r) f.dinvT.push_back(Inv[r * w + c]);
   }
-  // off-diagonal entries: rows outside the column's supernode
-  std::vector<std::vector<std::pair<int, double>>> byrow(n);
-  int base_lc = (int)f.lc_row.size();
-  (void)base_lc;
+  // off-diagonal entries (rows outside the column's supernode), stored in
+  // the order of the level lists: position li of the block owns
+  // [lr_ptr[li], lr_ptr[li+1]) (its row of L) and [lc_ptr[li], lc_ptr[li+1])
+  // (its column of L); indices are block-local rows.
+  std::vector<std::vector<std::pair<int, double>>> byrow(n), bycol(n);
   for (int c = 0; c < n; ++c) {
     const SN& q = sns[sn_of[c]];
     for (int t = L.p[c] + 1; t < L.p[c + 1]; ++t) {
       int r = L.i[t];
       if (r >= q.beg + q.w) {
-        f.lc_row.push_back(r);
-        f.lc_val.push_back(L.x[t]);
+        bycol[c].push_back({r, L.x[t]});
         byrow[r].push_back({c, L.x[t]});
       }
     }
-    f.lc_ptr.push_back((int)f.lc_row.size());
   }
-  for (int r = 0; r < n; ++r) {
-    for (auto& e : byrow[r]) {
-      f.lr_col.push_back(e.first);
-      f.lr_val.push_back(e.second);
+  for (int s : ordsn)
+    for (int r = sns[s].beg; r < sns[s].beg + sns[s].w; ++r) {
+      for (auto& e : byrow[r]) {
+        f.lr_col.push_back(e.first);
+        f.lr_val.push_back(e.second);
+      }
+      f.lr_ptr.push_back((int)f.lr_col.size());
+      for (auto& e : bycol[r]) {
+        f.lc_row.push_back(e.first);
+        f.lc_val.push_back(e.second);
+      }
+      f.lc_ptr.push_back((int)f.lc_row.size());
     }
-    f.lr_ptr.push_back((int)f.lr_col.size());
+  f.max_sn = std::max(f.max_sn, (int)sns.size());
+  // lanes per row for the pull phases of each level: a power of two that
+  // leaves about four entries per lane for the longest row (0: no entries)
+  {
+    std::vector<int> mr(nlev, 0), mc(nlev, 0);
+    for (size_t s = 0; s < sns.size(); ++s)
+      for (int r = sns[s].beg; r < sns[s].beg + sns[s].w; ++r) {
+        mr[sns[s].level] = std::max(mr[sns[s].level], (int)byrow[r].size());
+        mc[sns[s].level] = std::max(mc[sns[s].level], (int)bycol[r].size());
+      }
+    // lanes per row: the power of two G that minimises the dependent load
+    // rounds ceil(rows G / 1024) * ceil(longest row / (8 G)) of a 1024-thread
+    // workgroup issuing eight entry loads per lane at a time
+    auto lanes_for = [](int rows, int m) {
+      if (m == 0) return 0;
+      int best = 1;
+      long long bestr = -1;
+      for (int g = 1; g <= 64; g *= 2) {
+        long long r = ((long long)rows * g + 1023) / 1024 * ((m + 8 * g - 1) / (8 * g));
+        if (bestr < 0 || r < bestr) {
+          bestr = r;
+          best = g;
+        }
+      }
+      return best;
+    };
+    for (int l = 0; l < nlev; ++l) {
+      f.lvl_gf.push_back(lanes_for(lvrows[l], mr[l]));
+      f.lvl_gb.push_back(lanes_for(lvrows[l], mc[l]));
+    }
+    f.lvl_gf.push_back(0);  // keeps the same indexing as lvl_ptr
+    f.lvl_gb.push_back(0);
   }
   f.nb++;
 }
@@ -704,8 +746,8 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
     F = Factor();
     F.row_off.assign(1, 0);
     F.lvl_off.assign(1, 0);
-    F.lr_ptr.clear();
-    F.lc_ptr.clear();
+    F.lr_ptr.assign(1, 0);
+    F.lc_ptr.assign(1, 0);
     std::vector<int> lr0, lc0;
     for (int s = 0; s < h.nsub; ++s) {
       int r0 = off[s], nb = off[s + 1] - off[s];
@@ -719,9 +761,6 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
         }
       CSC L;
       if (!cholesky(nb, A, L)) return false;
-      // lc_ptr / lr_ptr are per row with a leading 0 per block
-      F.lc_ptr.push_back((int)F.lc_row.size());
-      F.lr_ptr.push_back((int)F.lr_col.size());
       append_factor(F, L, sns[s]);
     }
     return true;

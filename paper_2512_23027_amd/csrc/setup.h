@@ -47,13 +47,19 @@ struct Factor {
   std::vector<int> lvl_ptr;            // supernode ranges per level
   std::vector<int> lrow_ptr;           // row ranges per level (same indexing)
   std::vector<int> lrow_list, lrow_sn; // local rows of each level, their supernode
+  std::vector<int> lvl_gf, lvl_gb;     // lanes per row of the forward/backward pulls
   std::vector<int> sn_beg, sn_w, sn_dinv;  // local first row, width, dinv offset
-  std::vector<int> lr_ptr, lr_col;     // off-diagonal L by rows (local cols)
+  // off-diagonal L by level-list position (global positions, one pointer
+  // array over all blocks): row entries (local columns) and column entries
+  // (local rows)
+  std::vector<int> lr_ptr, lr_col;
   std::vector<double> lr_val;
-  std::vector<int> lc_ptr, lc_row;     // off-diagonal L by columns (local rows)
+  std::vector<int> lc_ptr, lc_row;
   std::vector<double> lc_val;
   std::vector<double> dinv;            // dense w x w inverse blocks, row-major
-  int max_rows = 0, max_level_rows = 0, max_w = 0, max_levels = 0;
+  std::vector<double> dinvT;           // the same blocks column-major
+  int max_rows = 0, max_level_rows = 0, max_w = 0, max_levels = 0, max_sn = 0;
+  int max_lvl_d = 0;                   // largest sum of w^2 over one level
   long long nnz_l = 0;
 };
 

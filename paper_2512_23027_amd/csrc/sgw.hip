@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -29,6 +30,8 @@ namespace {
 
 struct Sys {  // batched block-diagonal SG system (Dirichlet or Neumann)
   int nrows = 0, nb = 0, Q = 8;
+  int last_its[2] = {0, 0};     // previous iteration counts (tight / loose tolerance)
+  double loose_tol = 1e300;     // tolerances >= this use the second count
   k::DEll<double> A;
   k::DFactor F;
   const int* row_off = nullptr;  // device
@@ -51,7 +54,7 @@ struct sgw_ctx {
   k::DCoarse co;
   double *U = nullptr, *V = nullptr, *A = nullptr, *Um = nullptr, *Uc = nullptr,
          *Wm = nullptr, *F = nullptr, *X = nullptr, *R = nullptr, *Z = nullptr,
-         *Pw = nullptr, *Qw = nullptr, *T1 = nullptr, *Gv = nullptr, *Tt = nullptr,
+         *Zp = nullptr, *Pw = nullptr, *Qw = nullptr, *T1 = nullptr, *Gv = nullptr, *Tt = nullptr,
          *Yt = nullptr, *meshbuf = nullptr, *meshbuf2 = nullptr;
   double *part = nullptr, *part2 = nullptr, *sc = nullptr, *dc = nullptr, *uc = nullptr;
   int* flags = nullptr;
@@ -70,6 +73,15 @@ struct sgw_ctx {
   double* fs = nullptr;   // local coarse matrices during factor
   bool factored = false, has_state = false;
   long long stepno = 0;
+  // kernel timing: event pairs around SG-apply (kind 0) and triangular-solve
+  // (kind 1) launches; launches, milliseconds and algorithmic bytes per kind
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  struct Pend { int a, kind; double bytes; };
+  std::vector<Pend> pend;
+  long long pcnt[2] = {0, 0};
+  double pms[2] = {0, 0}, pbytes[2] = {0, 0};
+  double factor_bytes_D = 0, factor_bytes_N = 0;
   // per-call statistics
   long long inner_its = 0;
   int inner_solves = 0;
@@ -130,6 +142,11 @@ static int build_gtab(sgw_ctx* c, int KC, int GS) {
   t.GS = GS;
   t.ng = (g.P + GS - 1) / GS;
   t.nch = (g.nk + KC - 1) / KC;
+  t.L = g.L;
+  t.p_in = g.p_in;
+  t.p_out = g.p_out;
+  const char* env = getenv("SGW_K1_GENERIC");
+  t.use_spec = !(env && env[0] == '1');
   std::map<std::pair<int, int>, std::vector<std::pair<int, double>>> byKJ;
   for (size_t e = 0; e < g.v.size(); ++e) byKJ[{g.k[e], g.j[e]}].push_back({g.i[e], g.v[e]});
   std::vector<uint32_t> mask;
@@ -192,6 +209,8 @@ static k::DFactor upload_factor(sgw_ctx* c, const Factor& f) {
   d.lrow_ptr = upload(c, f.lrow_ptr);
   d.lrow_list = upload(c, f.lrow_list);
   d.lrow_sn = upload(c, f.lrow_sn);
+  d.lvl_gf = upload(c, f.lvl_gf);
+  d.lvl_gb = upload(c, f.lvl_gb);
   d.sn_beg = upload(c, f.sn_beg);
   d.sn_w = upload(c, f.sn_w);
   d.sn_dinv = upload(c, f.sn_dinv);
@@ -202,22 +221,80 @@ static k::DFactor upload_factor(sgw_ctx* c, const Factor& f) {
   d.lr_val = upload(c, f.lr_val);
   d.lc_val = upload(c, f.lc_val);
   d.dinv = upload(c, f.dinv);
+  d.dinvT = upload(c, f.dinvT);
+  d.dinvTf = upload(c, to_f(f.dinvT));
   d.lr_valf = upload(c, to_f(f.lr_val));
   d.lc_valf = upload(c, to_f(f.lc_val));
   d.dinvf = upload(c, to_f(f.dinv));
   d.max_rows = f.max_rows;
   d.max_level_rows = f.max_level_rows;
+  d.max_sn = f.max_sn;
+  d.max_levels = f.max_levels;
+  d.max_lvl_d = f.max_lvl_d;
   return d;
 }
 
-static int pick_q(const Factor& f, int P) {
-  // largest mode tile whose two LDS arrays fit in 64 KiB (two workgroups/CU)
-  int best = 1;
-  for (int q : {2, 4, 8, 16}) {
-    size_t bytes = (size_t)(f.max_rows + f.max_level_rows) * q * sizeof(double);
-    if (bytes <= 64 * 1024 && q <= std::max(1, P)) best = q;
+static int pick_q(const k::DFactor& f, int P) {
+  // modes per workgroup: at most 8, spread evenly over the tiles, and the
+  // workgroup's LDS (right-hand sides + index tables) within 150 KiB
+  int ntiles = (P + 7) / 8;
+  int q = (P + ntiles - 1) / ntiles;
+  while (q > 1 && k::tri_lds_bytes<double>(f, q) > 150 * 1024) --q;
+  return q;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing (sgw_profile): a HIP event pair around each timed launch,
+// harvested at the host synchronisation points the solver has anyway.
+// ---------------------------------------------------------------------------
+static int prof_begin(sgw_ctx* c, hipStream_t st) {
+  if (!c->prof) return -1;
+  int a = (int)c->pend.size() * 2;
+  while ((int)c->ev.size() < a + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    c->ev.push_back(e);
   }
-  return best;
+  (void)hipEventRecord(c->ev[a], st);
+  return a;
+}
+static void prof_end(sgw_ctx* c, int a, int kind, double bytes, hipStream_t st) {
+  if (a < 0) return;
+  (void)hipEventRecord(c->ev[a + 1], st);
+  c->pend.push_back({a, kind, bytes});
+}
+static void prof_harvest(sgw_ctx* c) {
+  if (c->pend.empty()) return;
+  for (auto& p : c->pend) {
+    float ms = 0.f;
+    if (hipEventSynchronize(c->ev[p.a + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, c->ev[p.a], c->ev[p.a + 1]) == hipSuccess) {
+      c->pcnt[p.kind] += 1;
+      c->pms[p.kind] += ms;
+      c->pbytes[p.kind] += p.bytes;
+    }
+  }
+  c->pend.clear();
+}
+
+// K1 wrapper: algorithmic bytes per row = 7 (M+1) values + 7 column indices
+// + P inputs + P outputs (+ P when the output is accumulated).
+static void K1(sgw_ctx* c, const k::DEll<double>& A, int r0, int nrows, const double* x, int ldx,
+               double* y, int ldy, double alpha, double beta, hipStream_t st) {
+  int a = prof_begin(c, st);
+  k::sg_apply<double>(A, c->gt, r0, nrows, x, ldx, y, ldy, alpha, beta, 1, 0, 0, st);
+  const double w = 8.0;
+  double per_row = 7.0 * c->nk * w + 7.0 * 4.0 + 2.0 * c->P * w + (beta != 0.0 ? c->P * w : 0.0);
+  prof_end(c, a, 0, per_row * nrows, st);
+}
+
+// K3 wrapper: algorithmic bytes = right-hand sides in and out + the factor.
+static void K3(sgw_ctx* c, Sys& S, const double* rhs, int ldr, double* out, int ldo,
+               hipStream_t st) {
+  int a = prof_begin(c, st);
+  k::tri_solve<double>(S.F, S.Q, rhs, ldr, out, ldo, 1, 0, 0, st);
+  double fb = (&S == &c->D) ? c->factor_bytes_D : c->factor_bytes_N;
+  prof_end(c, a, 1, 2.0 * 8.0 * c->P * S.nrows + fb, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -228,45 +305,56 @@ static int pick_q(const Factor& f, int P) {
 static int inner_solve(sgw_ctx* c, Sys& S, const double* b, int ldb, double* out,
                        int ldo, double tol, int maxit, hipStream_t st) {
   const int P = c->P, n = S.nrows, nb = S.nb;
+  // iterations of the previous solve of this system at this tolerance: the
+  // host checks convergence only from one iteration before that count on
+  // (converged blocks are frozen on the device, extra iterations are no-ops)
+  int& predicted = S.last_its[tol >= S.loose_tol ? 1 : 0];
   k::copy2d<double, double>(P, n, b, ldb, S.r, n, 1.0, st);
   k::fill2d<double>(P, n, S.x, n, 0.0, st);
-  k::tri_solve<double>(S.F, S.Q, S.r, n, S.z, n, 1, 0, 0, st);
+  K3(c, S, S.r, n, S.z, n, st);
   k::copy2d<double, double>(P, n, S.z, n, S.p, n, 1.0, st);
   k::seg_dot<double>(nb, S.row_off, P, S.r, n, S.z, n, c->part, S.r, n, S.r, n, c->part2, st);
   k::pcg_scalars(0, nb, P, c->part, c->part2, c->sc, -(tol * tol), c->flags, st);
-  HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
   int it = 0, rc = 0;
-  int nact = c->hflags[0];
+  int nact = 1;
+  if (predicted <= 1) {
+    HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    nact = c->hflags[0];
+  }
   while (nact > 0) {
     if (it >= maxit) {
       rc = SGW_NOT_CONVERGED;
       break;
     }
-    k::sg_apply<double>(S.A, c->gt, 0, n, S.p, n, S.q, n, 1.0, 0.0, 1, 0, 0, st);
+    K1(c, S.A, 0, n, S.p, n, S.q, n, 1.0, 0.0, st);
     k::seg_dot<double>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
     k::pcg_scalars(1, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
     k::pcg_xr<double>(nb, S.row_off, P, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part, st);
     k::pcg_scalars(2, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
-    HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
     ++it;
-    nact = c->hflags[0];
-    if (c->hflags[1]) {
-      c->err = "breakdown (p'q <= 0) in a subdomain solve";
-      return SGW_EBREAKDOWN;
+    if (it + 1 >= predicted || it >= maxit) {
+      HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      prof_harvest(c);
+      nact = c->hflags[0];
+      if (c->hflags[1]) {
+        c->err = "breakdown (p'q <= 0) in a subdomain solve";
+        return SGW_EBREAKDOWN;
+      }
+      if (c->hflags[2]) {
+        c->err = "non-finite residual in a subdomain solve";
+        return SGW_ENAN;
+      }
+      if (nact == 0) break;
     }
-    if (c->hflags[2]) {
-      c->err = "non-finite residual in a subdomain solve";
-      return SGW_ENAN;
-    }
-    if (nact == 0) break;
-    k::tri_solve<double>(S.F, S.Q, S.r, n, S.z, n, 1, 0, 0, st);
+    K3(c, S, S.r, n, S.z, n, st);
     k::seg_dot<double>(nb, S.row_off, P, S.r, n, S.z, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
     k::pcg_scalars(3, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
     k::pcg_p<double>(nb, S.row_off, P, c->sc, S.z, n, S.p, n, st);
   }
   k::copy2d<double, double>(P, n, S.x, n, out, ldo, 1.0, st);
+  predicted = it;
   c->inner_its += it;
   c->inner_solves += 1;
   return rc;
@@ -280,10 +368,10 @@ static int schur_apply(sgw_ctx* c, double* w, double* q, hipStream_t st) {
   const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
   const sgw_problem_desc& d = c->h.d;
   k::fill2d<double>(P, nI, w, NF, 0.0, st);
-  k::sg_apply<double>(c->G, c->gt, 0, nI, w, NF, c->T1, NF, -1.0, 0.0, 1, 0, 0, st);
+  K1(c, c->G, 0, nI, w, NF, c->T1, NF, -1.0, 0.0, st);
   int rc = inner_solve(c, c->D, c->T1, NF, w, NF, d.inner_rtol, d.inner_max_iter, st);
   if (rc < 0) return rc;
-  k::sg_apply<double>(c->G, c->gt, nI, nG, w, NF, q, NF, 1.0, 0.0, 1, 0, 0, st);
+  K1(c, c->G, nI, nG, w, NF, q, NF, 1.0, 0.0, st);
   return rc;
 }
 
@@ -298,7 +386,7 @@ static int precond(sgw_ctx* c, const double* r, double* z, hipStream_t st) {
   const int P = c->P, NF = c->NF, NT = c->NT, nG = c->nG;
   const sgw_problem_desc& d = c->h.d;
   k::scatter_to_torn<double>(NT, P, c->torn_gidx, c->torn_w, r, NF, c->Tt, NT, st);
-  int rc = inner_solve(c, c->N, c->Tt, NT, c->Yt, NT, d.inner_rtol, d.inner_max_iter, st);
+  int rc = inner_solve(c, c->N, c->Tt, NT, c->Yt, NT, d.precond_rtol, d.inner_max_iter, st);
   if (rc < 0) return rc;
   if (c->nC > 0) {
     k::coarse_rhs<double>(c->co, r, NF, c->Yt, NT, c->dc, st);
@@ -317,6 +405,7 @@ static int gdot(sgw_ctx* c, const double* a, const double* b, double& out, hipSt
   std::vector<double> h(c->P);
   HIPCHK(hipMemcpyAsync(h.data(), c->part, c->P * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  prof_harvest(c);
   double s = 0.0;
   for (double v : h) s += v;
   out = s;
@@ -336,7 +425,7 @@ static int dd_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st,
   warn |= rc;
   k::fill2d<double>(P, nG, c->T1 + nI, NF, 0.0, st);
   k::copy2d<double, double>(P, nG, F + nI, NF, c->Gv + nI, NF, 1.0, st);
-  k::sg_apply<double>(c->G, c->gt, nI, nG, c->T1, NF, c->Gv, NF, -1.0, 1.0, 1, 0, 0, st);
+  K1(c, c->G, nI, nG, c->T1, NF, c->Gv, NF, -1.0, 1.0, st);
   double gg;
   if ((rc = gdot(c, c->Gv + nI, c->Gv + nI, gg, st))) return rc;
   // H3/H4: PCG on S U_G = G, initial guess in X's interface part
@@ -356,6 +445,10 @@ static int dd_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st,
   if ((rc = gdot(c, r, z, rz, st))) return rc;
   if ((rc = gdot(c, r, r, rr, st))) return rc;
   const double stop2 = d.rtol * d.rtol * gg;
+  // flexible CG (Polak-Ribiere beta): the preconditioner's Neumann solves run
+  // to precond_rtol, so M^{-1} may vary slightly between iterations; with an
+  // exact preconditioner this is the classic PCG recurrence
+  double* zp = c->Zp + nI;
   int it = 0;
   while (rr > stop2 && gg > 0.0) {
     if (it >= d.max_iter) {
@@ -380,11 +473,13 @@ static int dd_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st,
       return SGW_ENAN;
     }
     if (rr <= stop2) break;
+    k::copy2d<double, double>(P, nG, z, NF, zp, NF, 1.0, st);
     if ((rc = precond(c, r, z, st)) < 0) return rc;
     warn |= rc;
-    double rzn;
+    double rzn, rzo;
     if ((rc = gdot(c, r, z, rzn, st))) return rc;
-    k::axpby2d<double>(P, nG, 1.0, z, NF, rzn / rz, p, NF, p, NF, st);
+    if ((rc = gdot(c, r, zp, rzo, st))) return rc;
+    k::axpby2d<double>(P, nG, 1.0, z, NF, (rzn - rzo) / rz, p, NF, p, NF, st);
     rz = rzn;
   }
   outer_its = it;
@@ -392,7 +487,7 @@ static int dd_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st,
   // H5: interior recovery U_I = K~_II^{-1} (F_I - K~_IG U_G)
   k::fill2d<double>(P, nI, X, NF, 0.0, st);
   k::copy2d<double, double>(P, nI, F, NF, c->T1, NF, 1.0, st);
-  k::sg_apply<double>(c->G, c->gt, 0, nI, X, NF, c->T1, NF, -1.0, 1.0, 1, 0, 0, st);
+  K1(c, c->G, 0, nI, X, NF, c->T1, NF, -1.0, 1.0, st);
   rc = inner_solve(c, c->D, c->T1, NF, X, NF, d.inner_rtol, d.inner_max_iter, st);
   if (rc < 0) return rc;
   warn |= rc;
@@ -615,9 +710,98 @@ long long sgw_query(const sgw_ctx* c, int what) {
   }
 }
 
+int sgw_profile(sgw_ctx* c, int enable) {
+  if (!c) return SGW_EINVAL;
+  prof_harvest(c);
+  c->prof = enable != 0;
+  for (int k2 = 0; k2 < 2; ++k2) {
+    c->pcnt[k2] = 0;
+    c->pms[k2] = 0.0;
+    c->pbytes[k2] = 0.0;
+  }
+  return 0;
+}
+
+int sgw_profile_read(sgw_ctx* c, int kind, long long* launches, double* ms, double* bytes) {
+  if (!c || kind < 0 || kind > 1) return SGW_EINVAL;
+  prof_harvest(c);
+  if (launches) *launches = c->pcnt[kind];
+  if (ms) *ms = c->pms[kind];
+  if (bytes) *bytes = c->pbytes[kind];
+  return 0;
+}
+
+// Autotuner: times the candidate launch shapes on the context's own data and
+// keeps the fastest (mode tile of the triangular solves per system, SG-apply
+// kernel with the unrolled tensor vs the table-driven one).
+int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
+  if (!c) return SGW_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  std::vector<double> rep(18, -1.0);
+  const int reps = 10;
+  auto time_it = [&](auto&& fn) -> double {
+    fn();
+    fn();
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps; ++i) fn();
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return 1e3 * ms / reps;  // microseconds per launch
+  };
+  Sys* sys[2] = {&c->D, &c->N};
+  for (int si = 0; si < 2; ++si) {
+    Sys& S = *sys[si];
+    k::fill2d<double>(c->P, S.nrows, S.r, S.nrows, 1.0, st);
+    double best = 1e300;
+    int bestq = S.Q;
+    for (int q = 1; q <= 8; ++q) {
+      if (q > c->P || k::tri_lds_bytes<double>(S.F, q) > 150 * 1024) continue;
+      double us = time_it([&] {
+        k::tri_solve<double>(S.F, q, S.r, S.nrows, S.z, S.nrows, 1, 0, 0, st);
+      });
+      rep[si * 8 + q - 1] = us;
+      if (us < best) {
+        best = us;
+        bestq = q;
+      }
+    }
+    S.Q = bestq;
+  }
+  {
+    Sys& S = c->D;
+    bool keep = c->gt.use_spec;
+    double us[2];
+    for (int v = 0; v < 2; ++v) {
+      c->gt.use_spec = v == 0;
+      us[v] = time_it([&] {
+        k::sg_apply<double>(S.A, c->gt, 0, S.nrows, S.r, S.nrows, S.q, S.nrows, 1.0, 0.0, 1, 0, 0, st);
+      });
+    }
+    rep[16] = us[0];
+    rep[17] = us[1];
+    c->gt.use_spec = keep && us[0] <= us[1];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (hipGetLastError() != hipSuccess) {
+    c->err = "kernel launch failed during autotuning";
+    return SGW_EHIP;
+  }
+  if (report)
+    for (int i = 0; i < nreport && i < 18; ++i) report[i] = rep[i];
+  return 0;
+}
+
 int sgw_destroy(sgw_ctx* c) {
   if (!c) return 0;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
+  prof_harvest(c);
+  for (auto e : c->ev) (void)hipEventDestroy(e);
   for (void* p : c->mem) {
     if (c->has_al) c->al.free(p, c->al.user);
     else hipFree(p);
@@ -643,6 +827,7 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   if (dd.inner_max_iter <= 0) dd.inner_max_iter = 1000;
   if (!(dd.rtol > 0)) dd.rtol = 1e-8;
   if (!(dd.inner_rtol > 0)) dd.inner_rtol = 1e-3 * dd.rtol;
+  if (!(dd.precond_rtol > 0)) dd.precond_rtol = dd.inner_rtol;
   int rc = build_host(dd, c->h, c->err);
   if (rc) {
     *out = c;
@@ -666,14 +851,26 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   c->N.A = upload_ell(c, h.neu);
   c->D.F = upload_factor(c, h.fD);
   c->N.F = upload_factor(c, h.fN);
+  auto fbytes = [](const Factor& f) {
+    return 8.0 * (f.lr_val.size() + f.lc_val.size() + f.dinv.size() + f.dinvT.size()) +
+           4.0 * (f.lr_col.size() + f.lc_row.size() + f.lr_ptr.size() + f.lc_ptr.size());
+  };
+  c->factor_bytes_D = fbytes(h.fD);
+  c->factor_bytes_N = fbytes(h.fN);
   c->D.nrows = h.nI;
   c->D.nb = h.nsub;
   c->D.row_off = c->D.F.row_off;
-  c->D.Q = pick_q(h.fD, P);
+  c->D.Q = pick_q(c->D.F, P);
+  if (h.fD.max_level_rows > 2048 || h.fN.max_level_rows > 2048) {
+    c->err = "a nested-dissection level holds more than 2048 rows";
+    *out = c;
+    return SGW_EINVAL;
+  }
+  if (dd.precond_rtol > dd.inner_rtol) c->N.loose_tol = dd.precond_rtol;
   c->N.nrows = h.NT;
   c->N.nb = h.nsub;
   c->N.row_off = c->N.F.row_off;
-  c->N.Q = pick_q(h.fN, P);
+  c->N.Q = pick_q(c->N.F, P);
   for (Sys* S : {&c->D, &c->N}) {
     size_t n = (size_t)P * S->nrows;
     S->x = dalloc<double>(c, n);
@@ -684,7 +881,7 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   }
   size_t nv = (size_t)P * h.NF;
   for (double** v : {&c->U, &c->V, &c->A, &c->Um, &c->Uc, &c->Wm, &c->F, &c->X, &c->R, &c->Z,
-                     &c->Pw, &c->Qw, &c->T1, &c->Gv})
+                     &c->Zp, &c->Pw, &c->Qw, &c->T1, &c->Gv})
     *v = dalloc<double>(c, nv);
   c->Tt = dalloc<double>(c, (size_t)P * h.NT);
   c->Yt = dalloc<double>(c, (size_t)P * h.NT);
@@ -927,8 +1124,7 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
                        c->Wm, st);
     k::mass_apply<double>(c->G, 0, NF, P, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
     if (d.alpha1 != 0.0)
-      k::sg_apply<double>(c->G, c->gt, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0, 1, 0,
-                          0, st);
+      K1(c, c->G, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0, st);
     // H3: initial interface guess
     if (d.guess == SGW_GUESS_NEWMARK) {
       // U + dt V + dt^2/2 A on the interface
@@ -953,6 +1149,7 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
     c->stepno++;
   }
   HIPCHK(hipStreamSynchronize(st));
+  prof_harvest(c);
   s.inner_iters = c->inner_its;
   s.inner_solves = c->inner_solves;
   if (stats) *stats = s;

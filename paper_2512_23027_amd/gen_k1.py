@@ -1,0 +1,235 @@
+"""Generate the specialised SG-apply kernels (csrc/k1_spec.inc).
+
+For a fixed Hermite chaos (L variables, input order p_in, output order p_out)
+the sparsity of the Galerkin tensor c_kij = <psi_k psi_i psi_j> and its values
+are known before run time.  This script writes one HIP kernel per such basis
+in which the whole contraction y_i = sum_k sum_j c_kij (K_k x_j) is unrolled:
+the output modes of a lane's row live in registers and every tensor value is
+an immediate, so the inner loop has no table lookups and no LDS traffic.
+
+Layout and launch are those of the generic kernel (kernels.hip): one lane per
+matrix row, sliced-ELL values val[(k*7 + s)*nrows + r], mode-major vectors.
+All memory accesses are buffer loads/stores: a 32-bit per-lane offset (the
+row, or a neighbour column) plus a scalar offset (the coefficient matrix and
+slot, or the mode), so no 64-bit address is kept per load.
+The coefficient matrices are split into up to four chunks, one per wave of a
+workgroup, so four waves share the 64 rows of a workgroup (registers per lane:
+14 KC for the chunk, 2 G for G outputs of a group, 28 for the neighbour
+values of the current and the next mode); the partial outputs are added in a
+fixed order through LDS.
+
+Run:  python -m paper_2512_23027_amd.gen_k1   (build.py runs it)
+"""
+
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(HERE, "csrc", "k1_spec.inc")
+
+# (L, p_in, p_out): the bases of the shipped workloads
+BASES = [(2, 2, 2), (4, 2, 3), (6, 2, 3)]
+MAX_GROUP = 42         # output modes per kernel (register budget)
+MAX_WAVES = 4          # waves per workgroup, one per chunk of coefficient matrices
+
+
+def _graded(L, p):
+    out = []
+
+    def rec(pos, rem, a):
+        if pos == L - 1:
+            out.append(tuple(a + [rem]))
+            return
+        for v in range(rem, -1, -1):
+            rec(pos + 1, rem - v, a + [v])
+
+    for deg in range(p + 1):
+        rec(0, deg, [])
+    return out
+
+
+def _fact(n):
+    f = 1.0
+    for i in range(2, n + 1):
+        f *= i
+    return f
+
+
+def _binom(n, r):
+    b = 1.0
+    for i in range(1, r + 1):
+        b = b * (n - r + i) / i
+    return b
+
+
+def _triple1(a, b, c):
+    """<psi_a psi_b psi_c>, normalised 1-D Hermite, from the linearisation
+    He_a He_b = sum_r C(a,r) C(b,r) r! He_{a+b-2r}."""
+    twice = a + b - c
+    if twice < 0 or twice % 2:
+        return 0.0
+    r = twice // 2
+    if r > min(a, b):
+        return 0.0
+    e = _binom(a, r) * _binom(b, r) * _fact(r) * _fact(c)
+    return e / math.sqrt(_fact(a) * _fact(b) * _fact(c))
+
+
+def entries(L, p_in, p_out):
+    kin, out = _graded(L, p_in), _graded(L, p_out)
+    ent = []
+    for k, ak in enumerate(kin):
+        for i, ai in enumerate(out):
+            for j, aj in enumerate(out):
+                v = 1.0
+                for d in range(L):
+                    v *= _triple1(ak[d], ai[d], aj[d])
+                    if v == 0.0:
+                        break
+                if v != 0.0:
+                    ent.append((k, i, j, v))
+    return len(kin), len(out), ent
+
+
+def kernel_source(L, p_in, p_out):
+    """One kernel per output group; a workgroup = 64 rows x NCH waves, wave w
+    contracting coefficient matrices of chunk w.  The partial outputs of the
+    waves are added in a fixed order through LDS by wave 0."""
+    nk, P, ent = entries(L, p_in, p_out)
+    ngroups = (P + MAX_GROUP - 1) // MAX_GROUP
+    G = (P + ngroups - 1) // ngroups
+    nch = min(MAX_WAVES, nk)
+    KC = (nk + nch - 1) // nch
+    nch = (nk + KC - 1) // KC
+    name = "k1_L%d_%d_%d" % (L, p_in, p_out)
+    lines = []
+    tables = []
+    for g in range(ngroups):
+        i0, i1 = g * G, min(P, (g + 1) * G)
+        gs = i1 - i0
+        lines.append("template <typename T>")
+        lines.append("__global__ __launch_bounds__(%d, 2) void %s_g%d(DEll<T> A, int r0, int nrows, "
+                     "const T* __restrict__ x, int ldx, T* __restrict__ y, int ldy, T alpha, "
+                     "T beta, long long sx, long long sy) {" % (64 * nch, name, g))
+        if nch > 1:
+            lines.append("  __shared__ T part[%d][%d][64];" % (nch - 1, gs))
+        lines.append("  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;")
+        lines.append("  const int rl = blockIdx.x * 64 + lane;")
+        lines.append("  x += (long long)blockIdx.z * sx;")
+        lines.append("  y += (long long)blockIdx.z * sy;")
+        lines.append("  const bool live = rl < nrows;")
+        lines.append("  const int r = r0 + (live ? rl : nrows - 1);")
+        lines.append("  const int NR = A.nrows;")
+        # buffer resources: per-lane 32-bit offsets, per-mode scalar offsets
+        lines.append("  const auto rc = buf_rsrc(A.col), rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y);")
+        lines.append("  const int rb = r * (int)sizeof(T);")
+        for q in range(7):
+            lines.append("  const int c%d = buf_load<int>(rc, r * 4, %d * NR * 4) * (int)sizeof(T);" % (q, q))
+        for i in range(i0, i1):
+            lines.append("  T y%d = T(0);" % i)
+        for ch in range(nch):
+            k0, k1 = ch * KC, min(nk, (ch + 1) * KC)
+            mine = [e for e in ent if k0 <= e[0] < k1 and i0 <= e[1] < i1]
+            js = [j for j in range(P) if any(e[2] == j for e in mine)]
+            if not js:
+                continue
+            jt = "%s_g%d_c%d_modes" % (name, g, ch)
+            tables.append("__device__ const int %s[%d] = {%s};" % (jt, len(js), ", ".join(map(str, js))))
+            lines.append("  if (wv == %d) {  // coefficient matrices %d..%d" % (ch, k0, k1 - 1))
+            for k in range(k0, k1):
+                for q in range(7):
+                    lines.append("    const T k%d_%d = buf_load<T>(rv, rb, %d * NR * (int)sizeof(T));"
+                                 % (k, q, k * 7 + q))
+            # A runtime loop over the modes of this chunk with one switch case
+            # per mode keeps every mode's contraction in its own basic block,
+            # so the register live ranges stay those of one mode; the 7
+            # neighbour values of the next mode are loaded before the switch
+            # (software pipelining).
+            for q in range(7):
+                lines.append("    T n%d = buf_load<T>(rx, c%d, %d * ldx * (int)sizeof(T));" % (q, q, js[0]))
+            lines.append("#pragma clang loop unroll(disable)")
+            lines.append("    for (int t = 0; t < %d; ++t) {" % len(js))
+            for q in range(7):
+                lines.append("      const T u%d = n%d;" % (q, q))
+            lines.append("      if (t + 1 < %d) {" % len(js))
+            lines.append("        const int so = %s[t + 1] * ldx * (int)sizeof(T);" % jt)
+            for q in range(7):
+                lines.append("        n%d = buf_load<T>(rx, c%d, so);" % (q, q))
+            lines.append("      }")
+            lines.append("      switch (t) {")
+            for t, j in enumerate(js):
+                lines.append("        case %d: {  // mode %d" % (t, j))
+                for k in sorted({e[0] for e in mine if e[2] == j}):
+                    expr = "k%d_0 * u0" % k
+                    for q in range(1, 7):
+                        expr = "fma(k%d_%d, u%d, %s)" % (k, q, q, expr)
+                    lines.append("          { const T w = %s;" % expr)
+                    for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
+                        lines.append("            y%d = fma(T(%.17g), w, y%d);" % (i, v, i))
+                    lines.append("          }")
+                lines.append("        } break;")
+            lines.append("        default: break;")
+            lines.append("      }")
+            lines.append("    }")
+            lines.append("  }")
+        if nch > 1:
+            lines.append("  if (wv > 0) {")
+            for i in range(i0, i1):
+                lines.append("    part[wv - 1][%d][lane] = y%d;" % (i - i0, i))
+            lines.append("  }")
+            lines.append("  __syncthreads();")
+            lines.append("  if (wv != 0) return;")
+            for i in range(i0, i1):
+                lines.append("  y%d = %s;" % (i, " + ".join(["y%d" % i] + ["part[%d][%d][lane]" % (w, i - i0)
+                                                                       for w in range(nch - 1)])))
+        lines.append("  if (live) {")
+        for i in range(i0, i1):
+            lines.append("    { T v = alpha * y%d; if (beta != T(0)) v = fma(beta, buf_load<T>(ry, rb, %d * ldy * (int)sizeof(T)), v);"
+                         " buf_store<T>(v, ry, rb, %d * ldy * (int)sizeof(T)); }" % (i, i, i))
+        lines.append("  }")
+        lines.append("}")
+        lines.append("")
+    # dispatcher
+    lines.append("template <typename T>")
+    lines.append("static void %s_launch(const DEll<T>& A, int r0, int nrows, const T* x, int ldx, T* y, "
+                 "int ldy, T alpha, T beta, int nbatch, long long sx, long long sy, hipStream_t st) {"
+                 % name)
+    lines.append("  dim3 grid((nrows + 63) / 64, 1, nbatch);")
+    for g in range(ngroups):
+        lines.append("  %s_g%d<T><<<grid, %d, 0, st>>>(A, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy);"
+                     % (name, g, 64 * nch))
+    lines.append("}")
+    lines.append("")
+    return "\n".join(tables + [""] + lines), name, nk, P, len(ent)
+
+
+def generate():
+    parts = ["// Generated by gen_k1.py -- specialised SG-apply kernels, do not edit.",
+             "// Bases (L, p_in, p_out): " + ", ".join(str(b) for b in BASES), ""]
+    disp = ["template <typename T>",
+            "static bool sg_apply_specialised(int L, int p_in, int p_out, const DEll<T>& A, int r0, "
+            "int nrows, const T* x, int ldx, T* y, int ldy, T alpha, T beta, int nbatch, "
+            "long long sx, long long sy, hipStream_t st) {"]
+    for (L, pi, po) in BASES:
+        src, name, nk, P, nnz = kernel_source(L, pi, po)
+        parts.append("// L=%d p_in=%d p_out=%d: %d coefficient matrices, P=%d, %d tensor entries"
+                     % (L, pi, po, nk, P, nnz))
+        parts.append(src)
+        disp.append("  if (L == %d && p_in == %d && p_out == %d) {" % (L, pi, po))
+        disp.append("    %s_launch<T>(A, r0, nrows, x, ldx, y, ldy, alpha, beta, nbatch, sx, sy, st);"
+                    % name)
+        disp.append("    return true;")
+        disp.append("  }")
+    disp.append("  return false;")
+    disp.append("}")
+    parts.extend(disp)
+    text = "\n".join(parts) + "\n"
+    old = open(OUT).read() if os.path.exists(OUT) else None
+    if old != text:
+        with open(OUT, "w") as f:
+            f.write(text)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(generate())
