@@ -116,7 +116,7 @@ void scatter_to_torn(int NT, int P, const int* gidx, const double* w,
 template <typename T>
 void gather_from_torn(int nG, int P, const int* gptr, const int* gtorn,
                       const double* gw, const int* g2c, const T* ut, int ldt,
-                      const T* uc, int ldc, T* z, int ldz, hipStream_t st);
+                      const double* uc, int ldc, T* z, int ldz, hipStream_t st);
 struct DCoarse {
   int nC = 0, P = 0, nk = 0, maxc = 0;
   const int *c_ptr, *c_lc;        // coarse index -> local corners

@@ -702,7 +702,7 @@ void scatter_to_torn(int NT, int P, const int* gidx, const double* w, const T* r
 template <typename T>
 __global__ void k_gather_from_torn(int nG, int P, const int* gptr, const int* gtorn,
                                    const double* gw, const int* g2c, const T* ut, int ldt,
-                                   const T* uc, int ldc, T* z, int ldz) {
+                                   const double* uc, int ldc, T* z, int ldz) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)nG * P) return;
   int j = (int)(t / nG), g = (int)(t % nG);
@@ -717,7 +717,7 @@ __global__ void k_gather_from_torn(int nG, int P, const int* gptr, const int* gt
 }
 template <typename T>
 void gather_from_torn(int nG, int P, const int* gptr, const int* gtorn, const double* gw,
-                      const int* g2c, const T* ut, int ldt, const T* uc, int ldc, T* z,
+                      const int* g2c, const T* ut, int ldt, const double* uc, int ldc, T* z,
                       int ldz, hipStream_t st) {
   long long N = (long long)nG * P;
   k_gather_from_torn<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(nG, P, gptr, gtorn, gw, g2c, ut, ldt, uc, ldc, z, ldz);
@@ -817,7 +817,7 @@ template size_t tri_lds_bytes<float>(const DFactor&, int);
   template void scatter_to_torn<T>(int, int, const int*, const double*, const T*, int, T*,  \
                                    int, hipStream_t);                                        \
   template void gather_from_torn<T>(int, int, const int*, const int*, const double*,        \
-                                    const int*, const T*, int, const T*, int, T*, int,       \
+                                    const int*, const T*, int, const double*, int, T*, int,  \
                                     hipStream_t);                                            \
   template void coarse_rhs<T>(const DCoarse&, const T*, int, const T*, int, double*,        \
                               hipStream_t);                                                  \

@@ -26,16 +26,43 @@
 
 using namespace sgw;
 
+// Refinement path (SGW_FP32_IR64): tolerances of each FP32 DD solve and the
+// sweep cap of the FP64 refinement loop.
+static const double kIrOuterRtol = 1e-5;    // interface PCG, relative to ||G||
+static const double kIrInnerRtol = 1e-6;    // Dirichlet solves (the operator)
+static const double kIrPrecondRtol = 1e-3;  // Neumann solves (the preconditioner)
+static const int kIrMaxSweeps = 8;
+
 namespace {
 
-struct Sys {  // batched block-diagonal SG system (Dirichlet or Neumann)
+template <typename T>
+struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   int nrows = 0, nb = 0, Q = 8;
   int last_its[2] = {0, 0};     // previous iteration counts (tight / loose tolerance)
   double loose_tol = 1e300;     // tolerances >= this use the second count
-  k::DEll<double> A;
+  k::DEll<T> A;
   k::DFactor F;
   const int* row_off = nullptr;  // device
-  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+};
+
+// Everything one precision of the DD solve needs: the global operator, the
+// Dirichlet and Neumann systems, the interface PCG vectors (full [P][NF]
+// arrays, interface part at offset nI) and the torn Neumann buffers.
+template <typename T>
+struct PrecT {
+  bool ready = false;
+  k::DEll<T> G;
+  SysT<T> D, N;
+  T *X = nullptr, *R = nullptr, *Z = nullptr, *Zp = nullptr, *Pw = nullptr, *Qw = nullptr,
+    *T1 = nullptr, *Gv = nullptr, *Tt = nullptr, *Yt = nullptr;
+  T *Fb = nullptr, *Xb = nullptr;  // right-hand side and correction of a refinement sweep
+};
+
+// tolerances of one DD solve
+struct Tols {
+  double rtol, inner, precond;
+  int max_iter, inner_max_iter;
 };
 
 }  // namespace
@@ -49,13 +76,11 @@ struct sgw_ctx {
   int dev = 0;
   int P = 0, nk = 0, NF = 0, nI = 0, nG = 0, nC = 0, NT = 0, nsub = 0, nn = 0;
   k::GTab gt;
-  k::DEll<double> G;
-  Sys D, N;
+  PrecT<double> d64;
+  PrecT<float> f32;
   k::DCoarse co;
   double *U = nullptr, *V = nullptr, *A = nullptr, *Um = nullptr, *Uc = nullptr,
-         *Wm = nullptr, *F = nullptr, *X = nullptr, *R = nullptr, *Z = nullptr,
-         *Zp = nullptr, *Pw = nullptr, *Qw = nullptr, *T1 = nullptr, *Gv = nullptr, *Tt = nullptr,
-         *Yt = nullptr, *meshbuf = nullptr, *meshbuf2 = nullptr;
+         *Wm = nullptr, *F = nullptr, *meshbuf = nullptr, *meshbuf2 = nullptr;
   double *part = nullptr, *part2 = nullptr, *sc = nullptr, *dc = nullptr, *uc = nullptr;
   int* flags = nullptr;
   int* hflags = nullptr;
@@ -188,17 +213,6 @@ static int build_gtab(sgw_ctx* c, int KC, int GS) {
   return 0;
 }
 
-static k::DEll<double> upload_ell(sgw_ctx* c, const Ell& E) {
-  k::DEll<double> d;
-  d.nrows = E.nrows;
-  d.W = E.W;
-  d.nk = E.nk;
-  d.col = upload(c, E.col);
-  d.val = upload(c, E.val);
-  d.mval = upload(c, E.mval);
-  return d;
-}
-
 static k::DFactor upload_factor(sgw_ctx* c, const Factor& f) {
   k::DFactor d;
   d.nb = f.nb;
@@ -232,15 +246,6 @@ static k::DFactor upload_factor(sgw_ctx* c, const Factor& f) {
   d.max_levels = f.max_levels;
   d.max_lvl_d = f.max_lvl_d;
   return d;
-}
-
-static int pick_q(const k::DFactor& f, int P) {
-  // modes per workgroup: at most 8, spread evenly over the tiles, and the
-  // workgroup's LDS (right-hand sides + index tables) within 150 KiB
-  int ntiles = (P + 7) / 8;
-  int q = (P + ntiles - 1) / ntiles;
-  while (q > 1 && k::tri_lds_bytes<double>(f, q) > 150 * 1024) --q;
-  return q;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,41 +284,44 @@ static void prof_harvest(sgw_ctx* c) {
 
 // K1 wrapper: algorithmic bytes per row = 7 (M+1) values + 7 column indices
 // + P inputs + P outputs (+ P when the output is accumulated).
-static void K1(sgw_ctx* c, const k::DEll<double>& A, int r0, int nrows, const double* x, int ldx,
-               double* y, int ldy, double alpha, double beta, hipStream_t st) {
+template <typename T>
+static void K1(sgw_ctx* c, const k::DEll<T>& A, int r0, int nrows, const T* x, int ldx, T* y,
+               int ldy, double alpha, double beta, hipStream_t st) {
   int a = prof_begin(c, st);
-  k::sg_apply<double>(A, c->gt, r0, nrows, x, ldx, y, ldy, alpha, beta, 1, 0, 0, st);
-  const double w = 8.0;
+  k::sg_apply<T>(A, c->gt, r0, nrows, x, ldx, y, ldy, (T)alpha, (T)beta, 1, 0, 0, st);
+  const double w = sizeof(T);
   double per_row = 7.0 * c->nk * w + 7.0 * 4.0 + 2.0 * c->P * w + (beta != 0.0 ? c->P * w : 0.0);
   prof_end(c, a, 0, per_row * nrows, st);
 }
 
 // K3 wrapper: algorithmic bytes = right-hand sides in and out + the factor.
-static void K3(sgw_ctx* c, Sys& S, const double* rhs, int ldr, double* out, int ldo,
+template <typename T>
+static void K3(sgw_ctx* c, SysT<T>& S, bool neumann, const T* rhs, int ldr, T* out, int ldo,
                hipStream_t st) {
   int a = prof_begin(c, st);
-  k::tri_solve<double>(S.F, S.Q, rhs, ldr, out, ldo, 1, 0, 0, st);
-  double fb = (&S == &c->D) ? c->factor_bytes_D : c->factor_bytes_N;
-  prof_end(c, a, 1, 2.0 * 8.0 * c->P * S.nrows + fb, st);
+  k::tri_solve<T>(S.F, S.Q, rhs, ldr, out, ldo, 1, 0, 0, st);
+  double fb = (neumann ? c->factor_bytes_N : c->factor_bytes_D) * (sizeof(T) / 8.0);
+  prof_end(c, a, 1, 2.0 * sizeof(T) * c->P * S.nrows + fb, st);
 }
 
 // ---------------------------------------------------------------------------
 // H8: batched subdomain SG solves.  PCG per block with x0 = 0 and the
 // preconditioner I_P (x) (L L^T)^{-1}; stops when every block has
-// ||r_s|| <= tol ||b_s||.  Converged blocks are frozen (alpha = 0).
+// ||r_s|| <= tol ||b_s||.  Converged blocks are frozen (alpha = 0).  The
+// iteration count of the previous solve of the same system and tolerance
+// class tells the host when to start checking convergence: extra iterations
+// of frozen blocks change nothing.
 // ---------------------------------------------------------------------------
-static int inner_solve(sgw_ctx* c, Sys& S, const double* b, int ldb, double* out,
+template <typename T>
+static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb, T* out,
                        int ldo, double tol, int maxit, hipStream_t st) {
   const int P = c->P, n = S.nrows, nb = S.nb;
-  // iterations of the previous solve of this system at this tolerance: the
-  // host checks convergence only from one iteration before that count on
-  // (converged blocks are frozen on the device, extra iterations are no-ops)
   int& predicted = S.last_its[tol >= S.loose_tol ? 1 : 0];
-  k::copy2d<double, double>(P, n, b, ldb, S.r, n, 1.0, st);
-  k::fill2d<double>(P, n, S.x, n, 0.0, st);
-  K3(c, S, S.r, n, S.z, n, st);
-  k::copy2d<double, double>(P, n, S.z, n, S.p, n, 1.0, st);
-  k::seg_dot<double>(nb, S.row_off, P, S.r, n, S.z, n, c->part, S.r, n, S.r, n, c->part2, st);
+  k::copy2d<T, T>(P, n, b, ldb, S.r, n, 1.0, st);
+  k::fill2d<T>(P, n, S.x, n, T(0), st);
+  K3<T>(c, S, neumann, S.r, n, S.z, n, st);
+  k::copy2d<T, T>(P, n, S.z, n, S.p, n, 1.0, st);
+  k::seg_dot<T>(nb, S.row_off, P, S.r, n, S.z, n, c->part, S.r, n, S.r, n, c->part2, st);
   k::pcg_scalars(0, nb, P, c->part, c->part2, c->sc, -(tol * tol), c->flags, st);
   int it = 0, rc = 0;
   int nact = 1;
@@ -327,10 +335,10 @@ static int inner_solve(sgw_ctx* c, Sys& S, const double* b, int ldb, double* out
       rc = SGW_NOT_CONVERGED;
       break;
     }
-    K1(c, S.A, 0, n, S.p, n, S.q, n, 1.0, 0.0, st);
-    k::seg_dot<double>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
+    K1<T>(c, S.A, 0, n, S.p, n, S.q, n, 1.0, 0.0, st);
+    k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
     k::pcg_scalars(1, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
-    k::pcg_xr<double>(nb, S.row_off, P, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part, st);
+    k::pcg_xr<T>(nb, S.row_off, P, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part, st);
     k::pcg_scalars(2, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
     ++it;
     if (it + 1 >= predicted || it >= maxit) {
@@ -348,12 +356,12 @@ static int inner_solve(sgw_ctx* c, Sys& S, const double* b, int ldb, double* out
       }
       if (nact == 0) break;
     }
-    K3(c, S, S.r, n, S.z, n, st);
-    k::seg_dot<double>(nb, S.row_off, P, S.r, n, S.z, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
+    K3<T>(c, S, neumann, S.r, n, S.z, n, st);
+    k::seg_dot<T>(nb, S.row_off, P, S.r, n, S.z, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
     k::pcg_scalars(3, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
-    k::pcg_p<double>(nb, S.row_off, P, c->sc, S.z, n, S.p, n, st);
+    k::pcg_p<T>(nb, S.row_off, P, c->sc, S.z, n, S.p, n, st);
   }
-  k::copy2d<double, double>(P, n, S.x, n, out, ldo, 1.0, st);
+  k::copy2d<T, T>(P, n, S.x, n, out, ldo, 1.0, st);
   predicted = it;
   c->inner_its += it;
   c->inner_solves += 1;
@@ -364,44 +372,44 @@ static int inner_solve(sgw_ctx* c, Sys& S, const double* b, int ldb, double* out
 // (Dirichlet solves) and the interface rows of the global operator.  w and q
 // are full [P][NF] arrays: p is w's interface part, the interior part of w is
 // overwritten with the extension, the result goes to q's interface rows.
-static int schur_apply(sgw_ctx* c, double* w, double* q, hipStream_t st) {
+template <typename T>
+static int schur_apply(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, T* w, T* q, hipStream_t st) {
   const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
-  const sgw_problem_desc& d = c->h.d;
-  k::fill2d<double>(P, nI, w, NF, 0.0, st);
-  K1(c, c->G, 0, nI, w, NF, c->T1, NF, -1.0, 0.0, st);
-  int rc = inner_solve(c, c->D, c->T1, NF, w, NF, d.inner_rtol, d.inner_max_iter, st);
+  k::fill2d<T>(P, nI, w, NF, T(0), st);
+  K1<T>(c, pr.G, 0, nI, w, NF, pr.T1, NF, -1.0, 0.0, st);
+  int rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, w, NF, tl.inner, tl.inner_max_iter, st);
   if (rc < 0) return rc;
-  K1(c, c->G, nI, nG, w, NF, q, NF, 1.0, 0.0, st);
+  K1<T>(c, pr.G, nI, nG, w, NF, q, NF, 1.0, 0.0, st);
   return rc;
 }
-
 
 // z_G = M_NNC^{-1} r_G (Eq. NNCP2).  The local residuals D_s R_s r on the
 // remaining nodes drive one batched Neumann solve (corners held at zero);
 // the coarse right-hand side d_c = sum_s B_c^T (D_s r_c - K~^s_{c,(ir)} y^s)
-// gives u_c = F_cc^{-1} d_c; the remaining values get the coarse basis term
-// Phi_s u_c^s (the second Neumann solve of Eq. urs, precomputed), and the
-// weighted gather sum_s R_s^T D_s (...) assembles z (Eq. ugb).
-static int precond(sgw_ctx* c, const double* r, double* z, hipStream_t st) {
+// gives u_c = F_cc^{-1} d_c (FP64); the remaining values get the coarse basis
+// term Phi_s u_c^s (the second Neumann solve of Eq. urs, precomputed), and
+// the weighted gather sum_s R_s^T D_s (...) assembles z (Eq. ugb).
+template <typename T>
+static int precond(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* r, T* z, hipStream_t st) {
   const int P = c->P, NF = c->NF, NT = c->NT, nG = c->nG;
-  const sgw_problem_desc& d = c->h.d;
-  k::scatter_to_torn<double>(NT, P, c->torn_gidx, c->torn_w, r, NF, c->Tt, NT, st);
-  int rc = inner_solve(c, c->N, c->Tt, NT, c->Yt, NT, d.precond_rtol, d.inner_max_iter, st);
+  k::scatter_to_torn<T>(NT, P, c->torn_gidx, c->torn_w, r, NF, pr.Tt, NT, st);
+  int rc = inner_solve<T>(c, pr.N, true, pr.Tt, NT, pr.Yt, NT, tl.precond, tl.inner_max_iter, st);
   if (rc < 0) return rc;
   if (c->nC > 0) {
-    k::coarse_rhs<double>(c->co, r, NF, c->Yt, NT, c->dc, st);
+    k::coarse_rhs<T>(c->co, r, NF, pr.Yt, NT, c->dc, st);
     k::coarse_solve(c->co, c->dc, c->uc, st);
-    k::coarse_lift<double>(c->co, c->nsub, c->uc, c->Yt, NT, st);
+    k::coarse_lift<T>(c->co, c->nsub, c->uc, pr.Yt, NT, st);
   }
-  k::gather_from_torn<double>(nG, P, c->gam_ptr, c->gam_torn, c->gam_w, c->g2c, c->Yt, NT,
-                              c->uc, c->nC, z, NF, st);
+  k::gather_from_torn<T>(nG, P, c->gam_ptr, c->gam_torn, c->gam_w, c->g2c, pr.Yt, NT, c->uc,
+                         c->nC, z, NF, st);
   return rc;
 }
 
-// Global dot over the interface rows (one block), FP64, fixed order.
-static int gdot(sgw_ctx* c, const double* a, const double* b, double& out, hipStream_t st) {
-  k::seg_dot<double>(1, c->goff, c->P, a, c->NF, b, c->NF, c->part, nullptr, 0, nullptr, 0,
-                     nullptr, st);
+// Dot product over the interface rows (one block), FP64 sums, fixed order.
+template <typename T>
+static int gdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st) {
+  k::seg_dot<T>(1, c->goff, c->P, a, c->NF, b, c->NF, c->part, nullptr, 0, nullptr, 0, nullptr,
+                st);
   std::vector<double> h(c->P);
   HIPCHK(hipMemcpyAsync(h.data(), c->part, c->P * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -412,83 +420,84 @@ static int gdot(sgw_ctx* c, const double* a, const double* b, double& out, hipSt
   return 0;
 }
 
-// One SG system K~ U = F on the DD numbering (F, X global [P][NF]); X holds
-// the interface initial guess on entry and the full solution on exit.
-static int dd_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st,
+// One SG system K~ U = F on the DD numbering (F, X full [P][NF] arrays of
+// this precision); X holds the interface initial guess on entry and the full
+// solution on exit.
+template <typename T>
+static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, hipStream_t st,
                     int& outer_its, double& relres) {
   const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
-  const sgw_problem_desc& d = c->h.d;
   int warn = 0, rc;
   // H2: condensation G = F_G - K~_GI K~_II^{-1} F_I
-  rc = inner_solve(c, c->D, F, NF, c->T1, NF, d.inner_rtol, d.inner_max_iter, st);
+  rc = inner_solve<T>(c, pr.D, false, F, NF, pr.T1, NF, tl.inner, tl.inner_max_iter, st);
   if (rc < 0) return rc;
   warn |= rc;
-  k::fill2d<double>(P, nG, c->T1 + nI, NF, 0.0, st);
-  k::copy2d<double, double>(P, nG, F + nI, NF, c->Gv + nI, NF, 1.0, st);
-  K1(c, c->G, nI, nG, c->T1, NF, c->Gv, NF, -1.0, 1.0, st);
+  k::fill2d<T>(P, nG, pr.T1 + nI, NF, T(0), st);
+  k::copy2d<T, T>(P, nG, F + nI, NF, pr.Gv + nI, NF, 1.0, st);
+  K1<T>(c, pr.G, nI, nG, pr.T1, NF, pr.Gv, NF, -1.0, 1.0, st);
   double gg;
-  if ((rc = gdot(c, c->Gv + nI, c->Gv + nI, gg, st))) return rc;
+  if ((rc = gdot<T>(c, pr.Gv + nI, pr.Gv + nI, gg, st))) return rc;
   // H3/H4: PCG on S U_G = G, initial guess in X's interface part
-  double* x = X + nI;
-  double* r = c->R + nI;
-  double* z = c->Z + nI;
-  double* p = c->Pw + nI;
-  double* q = c->Qw + nI;
-  k::copy2d<double, double>(P, nG, x, NF, p, NF, 1.0, st);
-  if ((rc = schur_apply(c, c->Pw, c->Qw, st)) < 0) return rc;
+  T* x = X + nI;
+  T* r = pr.R + nI;
+  T* z = pr.Z + nI;
+  T* zp = pr.Zp + nI;
+  T* p = pr.Pw + nI;
+  T* q = pr.Qw + nI;
+  k::copy2d<T, T>(P, nG, x, NF, p, NF, 1.0, st);
+  if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
   warn |= rc;
-  k::axpby2d<double>(P, nG, 1.0, c->Gv + nI, NF, -1.0, q, NF, r, NF, st);
-  if ((rc = precond(c, r, z, st)) < 0) return rc;
+  k::axpby2d<T>(P, nG, 1.0, pr.Gv + nI, NF, -1.0, q, NF, r, NF, st);
+  if ((rc = precond<T>(c, pr, tl, r, z, st)) < 0) return rc;
   warn |= rc;
-  k::copy2d<double, double>(P, nG, z, NF, p, NF, 1.0, st);
+  k::copy2d<T, T>(P, nG, z, NF, p, NF, 1.0, st);
   double rz, rr;
-  if ((rc = gdot(c, r, z, rz, st))) return rc;
-  if ((rc = gdot(c, r, r, rr, st))) return rc;
-  const double stop2 = d.rtol * d.rtol * gg;
+  if ((rc = gdot<T>(c, r, z, rz, st))) return rc;
+  if ((rc = gdot<T>(c, r, r, rr, st))) return rc;
+  const double stop2 = tl.rtol * tl.rtol * gg;
   // flexible CG (Polak-Ribiere beta): the preconditioner's Neumann solves run
-  // to precond_rtol, so M^{-1} may vary slightly between iterations; with an
-  // exact preconditioner this is the classic PCG recurrence
-  double* zp = c->Zp + nI;
+  // to their own tolerance, so M^{-1} may vary slightly between iterations;
+  // with an exact preconditioner this is the classic PCG recurrence
   int it = 0;
   while (rr > stop2 && gg > 0.0) {
-    if (it >= d.max_iter) {
+    if (it >= tl.max_iter) {
       warn = SGW_NOT_CONVERGED;
       break;
     }
-    if ((rc = schur_apply(c, c->Pw, c->Qw, st)) < 0) return rc;
+    if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
     warn |= rc;
     double pq;
-    if ((rc = gdot(c, p, q, pq, st))) return rc;
+    if ((rc = gdot<T>(c, p, q, pq, st))) return rc;
     if (!(pq > 0.0)) {
       c->err = "breakdown (p'Sp <= 0) in the interface PCG";
       return std::isfinite(pq) ? SGW_EBREAKDOWN : SGW_ENAN;
     }
     double al = rz / pq;
-    k::axpby2d<double>(P, nG, 1.0, x, NF, al, p, NF, x, NF, st);
-    k::axpby2d<double>(P, nG, 1.0, r, NF, -al, q, NF, r, NF, st);
+    k::axpby2d<T>(P, nG, 1.0, x, NF, al, p, NF, x, NF, st);
+    k::axpby2d<T>(P, nG, 1.0, r, NF, -al, q, NF, r, NF, st);
     ++it;
-    if ((rc = gdot(c, r, r, rr, st))) return rc;
+    if ((rc = gdot<T>(c, r, r, rr, st))) return rc;
     if (!std::isfinite(rr)) {
       c->err = "non-finite interface residual";
       return SGW_ENAN;
     }
     if (rr <= stop2) break;
-    k::copy2d<double, double>(P, nG, z, NF, zp, NF, 1.0, st);
-    if ((rc = precond(c, r, z, st)) < 0) return rc;
+    k::copy2d<T, T>(P, nG, z, NF, zp, NF, 1.0, st);
+    if ((rc = precond<T>(c, pr, tl, r, z, st)) < 0) return rc;
     warn |= rc;
     double rzn, rzo;
-    if ((rc = gdot(c, r, z, rzn, st))) return rc;
-    if ((rc = gdot(c, r, zp, rzo, st))) return rc;
-    k::axpby2d<double>(P, nG, 1.0, z, NF, (rzn - rzo) / rz, p, NF, p, NF, st);
+    if ((rc = gdot<T>(c, r, z, rzn, st))) return rc;
+    if ((rc = gdot<T>(c, r, zp, rzo, st))) return rc;
+    k::axpby2d<T>(P, nG, 1.0, z, NF, (rzn - rzo) / rz, p, NF, p, NF, st);
     rz = rzn;
   }
   outer_its = it;
   relres = gg > 0.0 ? std::sqrt(rr / gg) : 0.0;
   // H5: interior recovery U_I = K~_II^{-1} (F_I - K~_IG U_G)
-  k::fill2d<double>(P, nI, X, NF, 0.0, st);
-  k::copy2d<double, double>(P, nI, F, NF, c->T1, NF, 1.0, st);
-  K1(c, c->G, 0, nI, X, NF, c->T1, NF, -1.0, 1.0, st);
-  rc = inner_solve(c, c->D, c->T1, NF, X, NF, d.inner_rtol, d.inner_max_iter, st);
+  k::fill2d<T>(P, nI, X, NF, T(0), st);
+  k::copy2d<T, T>(P, nI, F, NF, pr.T1, NF, 1.0, st);
+  K1<T>(c, pr.G, 0, nI, X, NF, pr.T1, NF, -1.0, 1.0, st);
+  rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, X, NF, tl.inner, tl.inner_max_iter, st);
   if (rc < 0) return rc;
   warn |= rc;
   return warn ? SGW_NOT_CONVERGED : 0;
@@ -560,10 +569,10 @@ static int from_dd(sgw_ctx* c, const double* src, double* dst, int where, hipStr
 static int mass_solve(sgw_ctx* c, const double* rhs, double* out, hipStream_t st) {
   const int P = c->P, NF = c->NF;
   const long long N = (long long)P * NF;
-  double* r = c->R;
-  double* z = c->Z;
-  double* p = c->Pw;
-  double* q = c->Qw;
+  double* r = c->d64.R;
+  double* z = c->d64.Z;
+  double* p = c->d64.Pw;
+  double* q = c->d64.Qw;
   k::fill2d<double>(P, NF, out, NF, 0.0, st);
   k::copy2d<double, double>(P, NF, rhs, NF, r, NF, 1.0, st);
   auto dot = [&](const double* a, const double* b, double& v) -> int {
@@ -584,7 +593,7 @@ static int mass_solve(sgw_ctx* c, const double* rhs, double* out, hipStream_t st
   if ((rc = dot(r, z, rz))) return rc;
   rr = bb;
   for (int it = 0; it < 500 && rr > 1e-30 * bb; ++it) {
-    k::mass_apply<double>(c->G, 0, NF, P, p, NF, q, NF, 1.0, 0.0, st);
+    k::mass_apply<double>(c->d64.G, 0, NF, P, p, NF, q, NF, 1.0, 0.0, st);
     double pq;
     if ((rc = dot(p, q, pq))) return rc;
     double al = rz / pq;
@@ -689,6 +698,174 @@ static bool spd_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
+
+// Device state of one precision: operator values (FP32 copies for the
+// refinement path), system workspaces and interface vectors.
+template <typename T>
+static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
+  const Host& h = c->h;
+  const int P = c->P;
+  auto ell = [&](const Ell& E) {
+    k::DEll<T> d;
+    d.nrows = E.nrows;
+    d.W = E.W;
+    d.nk = E.nk;
+    d.col = upload(c, E.col);
+    if constexpr (sizeof(T) == 8) {
+      d.val = upload(c, E.val);
+      d.mval = upload(c, E.mval);
+    } else {
+      d.val = upload(c, to_f(E.val));
+      d.mval = upload(c, to_f(E.mval));
+    }
+    return d;
+  };
+  pr.G = ell(h.glob);
+  pr.D.A = ell(h.dir);
+  pr.N.A = ell(h.neu);
+  if constexpr (sizeof(T) == 8) {
+    pr.D.F = upload_factor(c, h.fD);
+    pr.N.F = upload_factor(c, h.fN);
+  } else {
+    pr.D.F = c->d64.D.F;  // one factor upload holds both precisions
+    pr.N.F = c->d64.N.F;
+  }
+  pr.D.nrows = h.nI;
+  pr.D.nb = h.nsub;
+  pr.D.row_off = pr.D.F.row_off;
+  pr.N.nrows = h.NT;
+  pr.N.nb = h.nsub;
+  pr.N.row_off = pr.N.F.row_off;
+  auto pickq = [&](const k::DFactor& f) {
+    int ntiles = (P + 7) / 8;
+    int q = (P + ntiles - 1) / ntiles;
+    while (q > 1 && k::tri_lds_bytes<T>(f, q) > 150 * 1024) --q;
+    return q;
+  };
+  pr.D.Q = pickq(pr.D.F);
+  pr.N.Q = pickq(pr.N.F);
+  const sgw_problem_desc& d = h.d;
+  double loose = refine ? kIrPrecondRtol : d.precond_rtol;
+  double tight = refine ? kIrInnerRtol : d.inner_rtol;
+  if (loose > tight) pr.N.loose_tol = loose;
+  for (SysT<T>* S : {&pr.D, &pr.N}) {
+    size_t n = (size_t)P * S->nrows;
+    S->x = dalloc<T>(c, n);
+    S->r = dalloc<T>(c, n);
+    S->z = dalloc<T>(c, n);
+    S->p = dalloc<T>(c, n);
+    S->q = dalloc<T>(c, n);
+  }
+  size_t nv = (size_t)P * h.NF;
+  for (T** v : {&pr.X, &pr.R, &pr.Z, &pr.Zp, &pr.Pw, &pr.Qw, &pr.T1, &pr.Gv}) *v = dalloc<T>(c, nv);
+  if (refine) {
+    pr.Fb = dalloc<T>(c, nv);
+    pr.Xb = dalloc<T>(c, nv);
+  }
+  pr.Tt = dalloc<T>(c, (size_t)P * h.NT);
+  pr.Yt = dalloc<T>(c, (size_t)P * h.NT);
+  pr.ready = true;
+}
+
+// X64 += (double) D32 over [P][NF]
+__global__ void k_add_f32(long long N, double* x, const float* d) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) x[t] += (double)d[t];
+}
+
+// Dot product over all rows of full [P][NF] arrays (FP64 sums)
+template <typename T>
+static int fdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st) {
+  k::seg_dot<T>(1, c->alloff, c->P, a, c->NF, b, c->NF, c->part, nullptr, 0, nullptr, 0,
+                nullptr, st);
+  std::vector<double> h(c->P);
+  HIPCHK(hipMemcpyAsync(h.data(), c->part, c->P * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double s = 0.0;
+  for (double v : h) s += v;
+  out = s;
+  return 0;
+}
+
+// H7: FP64 iterative refinement around the FP32 DD-PCG.  The residual
+// R = F - K~ X and the update X += D are FP64 on the global SG system; each
+// correction K~ D = R is solved by the whole DD method in FP32 (coarse grid
+// FP64) to the relative tolerances below.  Stops when ||R|| <= rtol ||F||.
+static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int& outer_total,
+                    int& sweeps, double& relres) {
+  const sgw_problem_desc& d = c->h.d;
+  const int P = c->P, NF = c->NF;
+  PrecT<float>& pr = c->f32;
+  double* R = c->d64.R;
+  Tols tl{kIrOuterRtol, kIrInnerRtol, kIrPrecondRtol, d.max_iter, d.inner_max_iter};
+  double ff;
+  int rc = fdot<double>(c, F, F, ff, st);
+  if (rc) return rc;
+  int warn = 0;
+  outer_total = 0;
+  sweeps = 0;
+  for (;;) {
+    k::copy2d<double, double>(P, NF, F, NF, R, NF, 1.0, st);
+    K1<double>(c, c->d64.G, 0, NF, X, NF, R, NF, -1.0, 1.0, st);
+    double rr;
+    if ((rc = fdot<double>(c, R, R, rr, st))) return rc;
+    relres = ff > 0.0 ? std::sqrt(rr / ff) : 0.0;
+    if (!std::isfinite(rr)) {
+      c->err = "non-finite refinement residual";
+      return SGW_ENAN;
+    }
+    if (rr <= d.rtol * d.rtol * ff) break;
+    if (sweeps >= kIrMaxSweeps) {
+      warn = SGW_NOT_CONVERGED;
+      break;
+    }
+    k::copy2d<float, double>(P, NF, R, NF, pr.Fb, NF, 1.0, st);
+    k::fill2d<float>(P, NF, pr.Xb, NF, 0.0f, st);
+    int its = 0;
+    double rel32 = 0.0;
+    rc = dd_solve<float>(c, pr, tl, pr.Fb, pr.Xb, st, its, rel32);
+    if (rc < 0) return rc;
+    warn |= rc;
+    outer_total += its;
+    long long N = (long long)P * NF;
+    k_add_f32<<<(int)((N + 255) / 256), 256, 0, st>>>(N, X, pr.Xb);
+    ++sweeps;
+  }
+  return warn ? SGW_NOT_CONVERGED : 0;
+}
+
+
+// Every device array a kernel may touch must exist before create returns
+// (a missing allocation is reported instead of reaching a kernel).
+template <typename T>
+static bool prec_complete(const PrecT<T>& pr, bool refine) {
+  const void* ps[] = {pr.G.col, pr.G.val, pr.G.mval, pr.D.A.col, pr.D.A.val, pr.N.A.col,
+                      pr.N.A.val, pr.D.x, pr.D.r, pr.D.z, pr.D.p, pr.D.q, pr.N.x, pr.N.r,
+                      pr.N.z, pr.N.p, pr.N.q, pr.X, pr.R, pr.Z, pr.Zp, pr.Pw, pr.Qw, pr.T1,
+                      pr.Gv, pr.Tt, pr.Yt, pr.D.row_off, pr.N.row_off};
+  for (const void* p : ps)
+    if (!p) return false;
+  return !refine || (pr.Fb && pr.Xb);
+}
+
+static bool check_pointers(sgw_ctx* c) {
+  const void* ps[] = {c->U, c->V, c->A, c->Um, c->Uc, c->Wm, c->F, c->meshbuf, c->meshbuf2,
+                      c->part, c->part2, c->sc, c->flags, c->goff, c->alloff, c->dd2mesh,
+                      c->mdiag, c->torn_gidx, c->torn_w, c->gam_ptr, c->gam_torn, c->gam_w,
+                      c->g2c, c->dc, c->uc, c->phi, c->gt.mask, c->gt.pair_beg, c->gt.ent_beg,
+                      c->gt.pair_cnt, c->gt.ent_i, c->gt.ent_c, c->gt.ent_cf};
+  for (const void* p : ps)
+    if (!p) {
+      c->err = "internal error: a device array was not allocated";
+      return false;
+    }
+  if (!prec_complete(c->d64, false) ||
+      (c->h.d.precision == SGW_FP32_IR64 && !prec_complete(c->f32, true))) {
+    c->err = "internal error: a device array of a solver precision was not allocated";
+    return false;
+  }
+  return true;
+}
 // ---------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------
@@ -753,9 +930,9 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
     (void)hipEventElapsedTime(&ms, e0, e1);
     return 1e3 * ms / reps;  // microseconds per launch
   };
-  Sys* sys[2] = {&c->D, &c->N};
+  SysT<double>* sys[2] = {&c->d64.D, &c->d64.N};
   for (int si = 0; si < 2; ++si) {
-    Sys& S = *sys[si];
+    SysT<double>& S = *sys[si];
     k::fill2d<double>(c->P, S.nrows, S.r, S.nrows, 1.0, st);
     double best = 1e300;
     int bestq = S.Q;
@@ -772,8 +949,28 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
     }
     S.Q = bestq;
   }
+  if (c->f32.ready) {
+    SysT<float>* sys32[2] = {&c->f32.D, &c->f32.N};
+    for (int si = 0; si < 2; ++si) {
+      SysT<float>& S = *sys32[si];
+      k::fill2d<float>(c->P, S.nrows, S.r, S.nrows, 1.0f, st);
+      double best = 1e300;
+      int bestq = S.Q;
+      for (int q = 1; q <= 8; ++q) {
+        if (q > c->P || k::tri_lds_bytes<float>(S.F, q) > 150 * 1024) continue;
+        double us = time_it([&] {
+          k::tri_solve<float>(S.F, q, S.r, S.nrows, S.z, S.nrows, 1, 0, 0, st);
+        });
+        if (us < best) {
+          best = us;
+          bestq = q;
+        }
+      }
+      S.Q = bestq;
+    }
+  }
   {
-    Sys& S = c->D;
+    SysT<double>& S = c->d64.D;
     bool keep = c->gt.use_spec;
     double us[2];
     for (int v = 0; v < 2; ++v) {
@@ -846,45 +1043,24 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   const int P = c->P;
   int GS = (P + ((P + 47) / 48) - 1) / ((P + 47) / 48);
   build_gtab(c, 8, GS);
-  c->G = upload_ell(c, h.glob);
-  c->D.A = upload_ell(c, h.dir);
-  c->N.A = upload_ell(c, h.neu);
-  c->D.F = upload_factor(c, h.fD);
-  c->N.F = upload_factor(c, h.fN);
   auto fbytes = [](const Factor& f) {
     return 8.0 * (f.lr_val.size() + f.lc_val.size() + f.dinv.size() + f.dinvT.size()) +
            4.0 * (f.lr_col.size() + f.lc_row.size() + f.lr_ptr.size() + f.lc_ptr.size());
   };
   c->factor_bytes_D = fbytes(h.fD);
   c->factor_bytes_N = fbytes(h.fN);
-  c->D.nrows = h.nI;
-  c->D.nb = h.nsub;
-  c->D.row_off = c->D.F.row_off;
-  c->D.Q = pick_q(c->D.F, P);
   if (h.fD.max_level_rows > 2048 || h.fN.max_level_rows > 2048) {
     c->err = "a nested-dissection level holds more than 2048 rows";
     *out = c;
     return SGW_EINVAL;
   }
-  if (dd.precond_rtol > dd.inner_rtol) c->N.loose_tol = dd.precond_rtol;
-  c->N.nrows = h.NT;
-  c->N.nb = h.nsub;
-  c->N.row_off = c->N.F.row_off;
-  c->N.Q = pick_q(c->N.F, P);
-  for (Sys* S : {&c->D, &c->N}) {
-    size_t n = (size_t)P * S->nrows;
-    S->x = dalloc<double>(c, n);
-    S->r = dalloc<double>(c, n);
-    S->z = dalloc<double>(c, n);
-    S->p = dalloc<double>(c, n);
-    S->q = dalloc<double>(c, n);
+  setup_prec<double>(c, c->d64, false);
+  if (dd.precision == SGW_FP32_IR64) setup_prec<float>(c, c->f32, true);
+  {
+    size_t nv = (size_t)P * h.NF;
+    for (double** v : {&c->U, &c->V, &c->A, &c->Um, &c->Uc, &c->Wm, &c->F})
+      *v = dalloc<double>(c, nv);
   }
-  size_t nv = (size_t)P * h.NF;
-  for (double** v : {&c->U, &c->V, &c->A, &c->Um, &c->Uc, &c->Wm, &c->F, &c->X, &c->R, &c->Z,
-                     &c->Zp, &c->Pw, &c->Qw, &c->T1, &c->Gv})
-    *v = dalloc<double>(c, nv);
-  c->Tt = dalloc<double>(c, (size_t)P * h.NT);
-  c->Yt = dalloc<double>(c, (size_t)P * h.NT);
   c->meshbuf = dalloc<double>(c, (size_t)std::max(P, 2) * h.nn);
   c->meshbuf2 = dalloc<double>(c, (size_t)P * h.nn);
   int nbmax = std::max(1, h.nsub);
@@ -973,6 +1149,10 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
       *out = c;
       return SGW_ENOMEM;
     }
+  if (!check_pointers(c)) {
+    *out = c;
+    return SGW_ENOMEM;
+  }
   if (hipDeviceSynchronize() != hipSuccess) {
     c->err = "device error during upload";
     *out = c;
@@ -998,11 +1178,12 @@ int sgw_factor(sgw_ctx* c, void* stream) {
     const double tol = std::min(1e-12, c->h.d.inner_rtol);
     for (int lcl = 0; lcl < c->maxc; ++lcl)
       for (int m = 0; m < P; ++m) {
-        k::fill2d<double>(P, NT, c->Tt, NT, 0.0, st);
-        k_basis_rhs<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->Tt, NT);
-        int rc = inner_solve(c, c->N, c->Tt, NT, c->Yt, NT, tol, c->h.d.inner_max_iter, st);
+        k::fill2d<double>(P, NT, c->d64.Tt, NT, 0.0, st);
+        k_basis_rhs<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->d64.Tt, NT);
+        int rc = inner_solve<double>(c, c->d64.N, true, c->d64.Tt, NT, c->d64.Yt, NT, tol,
+                                     c->h.d.inner_max_iter, st);
         if (rc < 0) return rc;
-        k_basis_store<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->Yt, NT, c->fs);
+        k_basis_store<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->d64.Yt, NT, c->fs);
       }
     std::vector<double> fs((size_t)c->nsub * MP * MP);
     HIPCHK(hipMemcpyAsync(fs.data(), c->fs, fs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1077,9 +1258,9 @@ int sgw_set_state(sgw_ctx* c, const double* U, const double* V, const double* A,
     // (I(x)M) A = -(K U + C V); K = (K~ - a_m I(x)M)/s_k, C = a0 I(x)M + a1 K
     const double s = h.s_k, am = h.a_m, a0 = d.alpha0, a1 = d.alpha1;
     k::axpby2d<double>(P, NF, 1.0, c->U, NF, a1, c->V, NF, c->Wm, NF, st);
-    k::sg_apply<double>(c->G, c->gt, 0, NF, c->Wm, NF, c->F, NF, -1.0 / s, 0.0, 1, 0, 0, st);
-    k::mass_apply<double>(c->G, 0, NF, P, c->Wm, NF, c->F, NF, am / s, 1.0, st);
-    k::mass_apply<double>(c->G, 0, NF, P, c->V, NF, c->F, NF, -a0, 1.0, st);
+    k::sg_apply<double>(c->d64.G, c->gt, 0, NF, c->Wm, NF, c->F, NF, -1.0 / s, 0.0, 1, 0, 0, st);
+    k::mass_apply<double>(c->d64.G, 0, NF, P, c->Wm, NF, c->F, NF, am / s, 1.0, st);
+    k::mass_apply<double>(c->d64.G, 0, NF, P, c->V, NF, c->F, NF, -a0, 1.0, st);
     int rc = mass_solve(c, c->F, c->A, st);
     if (rc) return rc;
   }
@@ -1122,26 +1303,39 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
     const double wc = d.alpha0 - d.alpha1 * h.a_m / h.s_k;
     k::newmark_predict(P, NF, NF, c->U, c->V, c->A, d.dt, d.zeta, d.gamma, wc, c->Um, c->Uc,
                        c->Wm, st);
-    k::mass_apply<double>(c->G, 0, NF, P, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
+    k::mass_apply<double>(c->d64.G, 0, NF, P, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
     if (d.alpha1 != 0.0)
-      K1(c, c->G, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0, st);
+      K1<double>(c, c->d64.G, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0, st);
     // H3: initial interface guess
     if (d.guess == SGW_GUESS_NEWMARK) {
       // U + dt V + dt^2/2 A on the interface
-      k::axpby2d<double>(P, nG, 1.0, c->U + nI, NF, d.dt, c->V + nI, NF, c->X + nI, NF, st);
-      k::axpby2d<double>(P, nG, 1.0, c->X + nI, NF, 0.5 * d.dt * d.dt, c->A + nI, NF,
-                         c->X + nI, NF, st);
+      k::axpby2d<double>(P, nG, 1.0, c->U + nI, NF, d.dt, c->V + nI, NF, c->d64.X + nI, NF, st);
+      k::axpby2d<double>(P, nG, 1.0, c->d64.X + nI, NF, 0.5 * d.dt * d.dt, c->A + nI, NF,
+                         c->d64.X + nI, NF, st);
     } else {
-      k::copy2d<double, double>(P, nG, c->U + nI, NF, c->X + nI, NF, 1.0, st);
+      k::copy2d<double, double>(P, nG, c->U + nI, NF, c->d64.X + nI, NF, 1.0, st);
     }
-    int its = 0;
+    int its = 0, sweeps = 0;
     double rel = 0.0;
-    int rc = dd_solve(c, c->F, c->X, st, its, rel);
+    int rc;
+    if (d.precision == SGW_FP32_IR64) {
+      // the refinement starts from the whole previous (or extrapolated) state
+      k::copy2d<double, double>(P, nI, c->U, NF, c->d64.X, NF, 1.0, st);
+      if (d.guess == SGW_GUESS_NEWMARK) {
+        k::axpby2d<double>(P, nI, 1.0, c->U, NF, d.dt, c->V, NF, c->d64.X, NF, st);
+        k::axpby2d<double>(P, nI, 1.0, c->d64.X, NF, 0.5 * d.dt * d.dt, c->A, NF, c->d64.X, NF, st);
+      }
+      rc = ir_solve(c, c->F, c->d64.X, st, its, sweeps, rel);
+      s.ir_sweeps += sweeps;
+    } else {
+      Tols tl{d.rtol, d.inner_rtol, d.precond_rtol, d.max_iter, d.inner_max_iter};
+      rc = dd_solve<double>(c, c->d64, tl, c->F, c->d64.X, st, its, rel);
+    }
     if (rc < 0) return rc;
     warn |= rc;
     // H6: Newmark update
-    k::newmark_update(P, NF, NF, c->X, c->Um, c->V, c->A, d.dt, d.zeta, d.gamma, st);
-    std::swap(c->U, c->X);
+    k::newmark_update(P, NF, NF, c->d64.X, c->Um, c->V, c->A, d.dt, d.zeta, d.gamma, st);
+    std::swap(c->U, c->d64.X);
     s.steps++;
     s.outer_iters += its;
     s.outer_iters_max = std::max(s.outer_iters_max, its);
@@ -1166,12 +1360,14 @@ int sgw_solve(sgw_ctx* c, const double* F, double* U, void* stream, sgw_step_sta
   c->inner_its = 0;
   c->inner_solves = 0;
   to_dd(c, F, SGW_DEVICE, c->Wm, st);
-  to_dd(c, U, SGW_DEVICE, c->X, st);
+  to_dd(c, U, SGW_DEVICE, c->d64.X, st);
   int its = 0;
   double rel = 0.0;
-  int rc = dd_solve(c, c->Wm, c->X, st, its, rel);
+  const sgw_problem_desc& d = c->h.d;
+  Tols tl{d.rtol, d.inner_rtol, d.precond_rtol, d.max_iter, d.inner_max_iter};
+  int rc = dd_solve<double>(c, c->d64, tl, c->Wm, c->d64.X, st, its, rel);
   if (rc < 0) return rc;
-  int rc2 = from_dd(c, c->X, U, SGW_DEVICE, st);
+  int rc2 = from_dd(c, c->d64.X, U, SGW_DEVICE, st);
   if (rc2) return rc2;
   HIPCHK(hipStreamSynchronize(st));
   if (stats) {
@@ -1211,9 +1407,19 @@ int sgw_read_moments(sgw_ctx* c, double* mean, double* var, int where, void* str
 int sgw_apply_operator(sgw_ctx* c, const double* X, double* Y, int precision, void* stream) {
   if (!c || !X || !Y) return SGW_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  const int P = c->P, NF = c->NF;
   to_dd(c, X, SGW_DEVICE, c->Wm, st);
-  (void)precision;
-  k::sg_apply<double>(c->G, c->gt, 0, c->NF, c->Wm, c->NF, c->F, c->NF, 1.0, 0.0, 1, 0, 0, st);
+  if (precision == SGW_FP32_IR64) {
+    if (!c->f32.ready) {
+      c->err = "the FP32 operator exists only for precision SGW_FP32_IR64";
+      return SGW_ESTATE;
+    }
+    k::copy2d<float, double>(P, NF, c->Wm, NF, c->f32.Fb, NF, 1.0, st);
+    K1<float>(c, c->f32.G, 0, NF, c->f32.Fb, NF, c->f32.Xb, NF, 1.0, 0.0, st);
+    k::copy2d<double, float>(P, NF, c->f32.Xb, NF, c->F, NF, 1.0, st);
+  } else {
+    K1<double>(c, c->d64.G, 0, NF, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
+  }
   return from_dd(c, c->F, Y, SGW_DEVICE, st);
 }
 
