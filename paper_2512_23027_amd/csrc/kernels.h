@@ -75,8 +75,8 @@ void seg_dot(int nb, const int* row_off, int P, const T* a, int lda,
 
 // PCG scalar phase on nb blocks (one workgroup): see kernels.hip.
 void pcg_scalars(int phase, int nb, int P, const double* part,
-                 const double* part2, double* sc, double tol2, int* flags,
-                 hipStream_t st);
+                 const double* part2, double* sc, double tol2, double negl,
+                 int* flags, hipStream_t st);
 
 // x += alpha_b p ; r -= alpha_b q ; partial[b*P + j] = ||r_bj||^2
 template <typename T>

@@ -468,19 +468,34 @@ void seg_dot(int nb, const int* row_off, int P, const T* a, int lda, const T* b,
   k_seg_dot<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, a, lda, b, ldb, partial, c, ldc, d, ldd, partial2);
 }
 
-// Per-block PCG scalars.  sc[b*8 + ...]: 0 rz, 1 pq, 2 rr, 3 bb, 4 alpha,
-// 5 beta, 6 active, 7 iterations.  flags[0] = active blocks after this
-// phase, flags[1] |= breakdown, flags[2] |= non-finite.
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double m = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, sh[q]);
+  return m;
+}
+
+// Per-block scalars of the batched PCG, one workgroup for all blocks.
+// sc[b*8 + ...]: 0 rz, 1 pq, 2 rr, 3 bb, 4 alpha, 5 beta, 6 active,
+// 7 iterations.  flags[0] = active blocks after this phase, flags[1] |=
+// breakdown, flags[2] |= non-finite.
 //   phase 0: rz = sum part, rr = sum part2 (bb = rr when tol2 < 0 is passed
-//            as -tol2), active = rr > tol2 bb
+//            as -tol2); active = bb > negl * max_b bb and rr > tol2 bb, so a
+//            block whose right-hand side is negligible within the batch
+//            (negl > 0) keeps x = 0 -- in FP32 such blocks would underflow
 //   phase 1: pq = sum part; alpha = rz / pq on active blocks (else 0)
 //   phase 2: rr = sum part; active = rr > tol2 bb; iterations++
 //   phase 3: rz' = sum part; beta = rz'/rz; rz = rz'
 //   phase 4: bb = sum part
 __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_scalars(
     int phase, int nb, int P, const double* part, const double* part2,
-    double* sc, double tol2, int* flags) {
+    double* sc, double tol2, double negl, int* flags) {
   __shared__ int nact, brk, bad;
+  __shared__ double shm[SGW_BLOCK / 64];
   if (threadIdx.x == 0) {
     nact = 0;
     brk = 0;
@@ -489,38 +504,50 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_scalars(
   __syncthreads();
   bool set_bb = tol2 < 0.0;
   double t2 = set_bb ? -tol2 : tol2;
-  for (int b = threadIdx.x; b < nb; b += SGW_BLOCK) {
-    double v = 0.0, v2 = 0.0;
-    for (int j = 0; j < P; ++j) v += part[b * P + j];
-    if (part2)
-      for (int j = 0; j < P; ++j) v2 += part2[b * P + j];
-    double* s = sc + b * 8;
-    int act = s[6] != 0.0;
-    if (phase == 0) {
+  double floor_bb = 0.0;
+  if (phase == 0) {
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nb; b += SGW_BLOCK) {
+      double v = 0.0, v2 = 0.0;
+      for (int j = 0; j < P; ++j) v += part[b * P + j];
+      if (part2)
+        for (int j = 0; j < P; ++j) v2 += part2[b * P + j];
+      double* s = sc + b * 8;
       s[0] = v;
       s[2] = v2;
       if (set_bb) s[3] = v2;
-      act = (s[3] > 0.0) && (v2 > t2 * s[3]);
       s[7] = 0.0;
       if (!isfinite(v) || !isfinite(v2)) atomicOr(&bad, 1);
-    } else if (phase == 1) {
-      s[1] = v;
-      if (act && !(v > 0.0)) {
-        atomicOr(&brk, 1);
-        act = 0;
+      if (isfinite(s[3])) m = fmax(m, s[3]);
+    }
+    floor_bb = negl * block_max(m, shm);
+  }
+  for (int b = threadIdx.x; b < nb; b += SGW_BLOCK) {
+    double* s = sc + b * 8;
+    int act = s[6] != 0.0;
+    if (phase == 0) {
+      act = (s[3] > floor_bb) && (s[2] > t2 * s[3]);
+    } else {
+      double v = 0.0;
+      for (int j = 0; j < P; ++j) v += part[b * P + j];
+      if (!isfinite(v)) atomicOr(&bad, 1);
+      if (phase == 1) {
+        s[1] = v;
+        if (act && !(v > 0.0)) {
+          atomicOr(&brk, 1);
+          act = 0;
+        }
+        s[4] = act ? s[0] / v : 0.0;
+      } else if (phase == 2) {
+        s[2] = v;
+        if (act) s[7] += 1.0;
+        act = act && (v > t2 * s[3]);
+      } else if (phase == 3) {
+        s[5] = act ? v / s[0] : 0.0;
+        s[0] = v;
+      } else if (phase == 4) {
+        s[3] = v;
       }
-      s[4] = act ? s[0] / v : 0.0;
-      if (!isfinite(v)) atomicOr(&bad, 1);
-    } else if (phase == 2) {
-      s[2] = v;
-      if (act) s[7] += 1.0;
-      act = act && (v > t2 * s[3]);
-      if (!isfinite(v)) atomicOr(&bad, 1);
-    } else if (phase == 3) {
-      s[5] = act ? v / s[0] : 0.0;
-      s[0] = v;
-    } else if (phase == 4) {
-      s[3] = v;
     }
     s[6] = act ? 1.0 : 0.0;
     if (act) atomicAdd(&nact, 1);
@@ -539,8 +566,8 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_scalars(
 }
 
 void pcg_scalars(int phase, int nb, int P, const double* part, const double* part2,
-                 double* sc, double tol2, int* flags, hipStream_t st) {
-  k_pcg_scalars<<<1, SGW_BLOCK, 0, st>>>(phase, nb, P, part, part2, sc, tol2, flags);
+                 double* sc, double tol2, double negl, int* flags, hipStream_t st) {
+  k_pcg_scalars<<<1, SGW_BLOCK, 0, st>>>(phase, nb, P, part, part2, sc, tol2, negl, flags);
 }
 
 template <typename T>

@@ -149,7 +149,9 @@ static T* dalloc(sgw_ctx* c, size_t n) {
 template <class T>
 static T* upload(sgw_ctx* c, const std::vector<T>& v) {
   T* d = dalloc<T>(c, v.size());
-  if (d && !v.empty()) hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (d && !v.empty() &&
+      hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return nullptr;  // reported by the completeness check of sgw_create
   return d;
 }
 
@@ -312,6 +314,12 @@ static void K3(sgw_ctx* c, SysT<T>& S, bool neumann, const T* rhs, int ldr, T* o
 // class tells the host when to start checking convergence: extra iterations
 // of frozen blocks change nothing.
 // ---------------------------------------------------------------------------
+// Relative size (squared norms) below which a block's right-hand side is
+// negligible within its batch: FP64 solves every nonzero block, FP32 leaves
+// blocks 1e-10 below the largest at zero (their values can underflow FP32).
+template <typename T> struct NegligibleBlock { static constexpr double value = 0.0; };
+template <> struct NegligibleBlock<float> { static constexpr double value = 1e-20; };
+
 template <typename T>
 static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb, T* out,
                        int ldo, double tol, int maxit, hipStream_t st) {
@@ -322,7 +330,8 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
   K3<T>(c, S, neumann, S.r, n, S.z, n, st);
   k::copy2d<T, T>(P, n, S.z, n, S.p, n, 1.0, st);
   k::seg_dot<T>(nb, S.row_off, P, S.r, n, S.z, n, c->part, S.r, n, S.r, n, c->part2, st);
-  k::pcg_scalars(0, nb, P, c->part, c->part2, c->sc, -(tol * tol), c->flags, st);
+  k::pcg_scalars(0, nb, P, c->part, c->part2, c->sc, -(tol * tol), NegligibleBlock<T>::value,
+                 c->flags, st);
   int it = 0, rc = 0;
   int nact = 1;
   if (predicted <= 1) {
@@ -337,9 +346,9 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
     }
     K1<T>(c, S.A, 0, n, S.p, n, S.q, n, 1.0, 0.0, st);
     k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
-    k::pcg_scalars(1, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
+    k::pcg_scalars(1, nb, P, c->part, nullptr, c->sc, tol * tol, 0.0, c->flags, st);
     k::pcg_xr<T>(nb, S.row_off, P, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part, st);
-    k::pcg_scalars(2, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
+    k::pcg_scalars(2, nb, P, c->part, nullptr, c->sc, tol * tol, 0.0, c->flags, st);
     ++it;
     if (it + 1 >= predicted || it >= maxit) {
       HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -358,7 +367,7 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
     }
     K3<T>(c, S, neumann, S.r, n, S.z, n, st);
     k::seg_dot<T>(nb, S.row_off, P, S.r, n, S.z, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
-    k::pcg_scalars(3, nb, P, c->part, nullptr, c->sc, tol * tol, c->flags, st);
+    k::pcg_scalars(3, nb, P, c->part, nullptr, c->sc, tol * tol, 0.0, c->flags, st);
     k::pcg_p<T>(nb, S.row_off, P, c->sc, S.z, n, S.p, n, st);
   }
   k::copy2d<T, T>(P, n, S.x, n, out, ldo, 1.0, st);
@@ -768,9 +777,9 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
 }
 
 // X64 += (double) D32 over [P][NF]
-__global__ void k_add_f32(long long N, double* x, const float* d) {
+__global__ void k_add_f32(long long N, double* x, const float* d, double scale) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < N) x[t] += (double)d[t];
+  if (t < N) x[t] += scale * (double)d[t];
 }
 
 // Dot product over all rows of full [P][NF] arrays (FP64 sums)
@@ -819,7 +828,10 @@ static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int&
       warn = SGW_NOT_CONVERGED;
       break;
     }
-    k::copy2d<float, double>(P, NF, R, NF, pr.Fb, NF, 1.0, st);
+    // the correction equation is solved for the residual scaled to unit RMS,
+    // which keeps the FP32 values away from the ends of their range
+    const double scale = std::sqrt(rr / ((double)P * NF));
+    k::copy2d<float, double>(P, NF, R, NF, pr.Fb, NF, 1.0 / scale, st);
     k::fill2d<float>(P, NF, pr.Xb, NF, 0.0f, st);
     int its = 0;
     double rel32 = 0.0;
@@ -828,7 +840,7 @@ static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int&
     warn |= rc;
     outer_total += its;
     long long N = (long long)P * NF;
-    k_add_f32<<<(int)((N + 255) / 256), 256, 0, st>>>(N, X, pr.Xb);
+    k_add_f32<<<(int)((N + 255) / 256), 256, 0, st>>>(N, X, pr.Xb, scale);
     ++sweeps;
   }
   return warn ? SGW_NOT_CONVERGED : 0;
@@ -1001,9 +1013,9 @@ int sgw_destroy(sgw_ctx* c) {
   for (auto e : c->ev) (void)hipEventDestroy(e);
   for (void* p : c->mem) {
     if (c->has_al) c->al.free(p, c->al.user);
-    else hipFree(p);
+    else (void)hipFree(p);
   }
-  if (c->hflags) hipHostFree(c->hflags);
+  if (c->hflags) (void)hipHostFree(c->hflags);
   delete c;
   return 0;
 }
@@ -1016,7 +1028,10 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     c->al = *al;
     c->has_al = true;
   }
-  hipGetDevice(&c->dev);
+  if (hipGetDevice(&c->dev) != hipSuccess) {
+    delete c;
+    return SGW_EHIP;
+  }
   sgw_problem_desc dd = *d;
   if (dd.zeta == 0.0) dd.zeta = 0.25;
   if (dd.gamma == 0.0) dd.gamma = 0.5;
