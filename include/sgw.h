@@ -57,6 +57,7 @@ enum {
 enum { SGW_HOST = 0, SGW_DEVICE = 1 };
 enum { SGW_FP64 = 0, SGW_FP32_IR64 = 1 };
 enum { SGW_GUESS_PREV = 0, SGW_GUESS_NEWMARK = 1, SGW_GUESS_LEARNED = 2 };
+enum { SGW_INNER_CHOLESKY = 0, SGW_INNER_CHEBYSHEV = 1 };
 
 /* Problem description.  Fields follow the paper's problem statement:
  * Eq. CovarKer2D_chapt2 (sigma, bx, by), Eq. KLEchapt2 (L), Eq. c0pce
@@ -83,6 +84,12 @@ typedef struct sgw_problem_desc {
   int guess;             /* initial interface guess, SGW_GUESS_* */
   double precond_rtol;   /* Neumann solves inside the preconditioner (<= 0: inner_rtol);
                             the interface PCG is the flexible (Polak-Ribiere) variant */
+  int inner_prec;        /* preconditioner I_P (x) (K~_0^s)^-1 of the subdomain SG PCG:
+                            SGW_INNER_CHOLESKY applies the mean-matrix inverse exactly
+                            (supernodal Cholesky factors), SGW_INNER_CHEBYSHEV
+                            approximates it by a Chebyshev polynomial in the
+                            Jacobi-scaled mean matrix (blocks of <= 4096 rows) */
+  int cheb_degree;       /* degree of that polynomial (<= 0: 4; at most 64) */
 } sgw_problem_desc;
 
 /* Optional device allocator.  alloc returns device memory of >= bytes
@@ -161,27 +168,35 @@ int sgw_solve(sgw_ctx* ctx, const double* F, double* U, void* stream,
               sgw_step_stats* stats);
 
 /* Kernel timing (tracing).  enable != 0 records a HIP event pair around
- * every launch of the SG operator apply (kind 0) and of the batched
- * subdomain triangular solves (kind 1) on the launch stream, and clears the
- * counters; enable == 0 stops recording.  Adds one event record per launch. */
+ * every launch of the SG operator apply (kind 0), of the batched subdomain
+ * triangular solves (kind 1) and of the Chebyshev preconditioner (kind 2)
+ * on the launch stream, and clears the counters; enable == 0 stops
+ * recording.  Adds two event records per timed launch. */
 int sgw_profile(sgw_ctx* ctx, int enable);
 
 /* Launches, total kernel milliseconds and total algorithmic bytes of a kind
  * since the last sgw_profile call.  Bytes per SG-apply row:
  * 7 (M+1) values + 7 column indices + P inputs + P outputs (+ P when the
- * output is accumulated), 8-byte values; per triangular-solve launch: the
- * right-hand sides in and out plus the factor's values and indices. */
+ * output is accumulated), 8-byte values (4-byte in FP32 launches); per
+ * triangular-solve launch: the right-hand sides in and out plus the
+ * factor's values and indices; per Chebyshev launch: the right-hand sides
+ * in and out plus the mean matrix's values and column indices. */
 int sgw_profile_read(sgw_ctx* ctx, int kind, long long* launches, double* ms,
                      double* bytes);
 
 /* Autotuner (tile shapes picked on the context's own data): times the
- * batched triangular solves for every feasible mode tile Q = 1..8 on the
- * Dirichlet and the Neumann systems and the SG apply with the unrolled
+ * subdomain preconditioner kernels for every feasible mode tile Q = 1..8 on
+ * the Dirichlet and the Neumann systems, and the SG apply with the unrolled
  * Galerkin tensor against the table-driven one, and keeps the fastest for
  * later calls.  report (may be NULL) receives up to nreport values, in
- * microseconds per launch: [0..7] Dirichlet solve with Q = 1..8, [8..15]
- * Neumann solve with Q = 1..8 (-1: not feasible), [16] unrolled SG apply,
- * [17] table-driven SG apply.  Enqueues on stream and waits for it. */
+ * microseconds per launch (-1: not feasible or not used):
+ *   [0..7]   FP64 Dirichlet triangular solve, Q = 1..8
+ *   [8..15]  FP64 Neumann triangular solve
+ *   [16]     FP64 unrolled SG apply     [17] FP64 table-driven SG apply
+ *   [18..25] FP64 Dirichlet Chebyshev   [26..33] FP64 Neumann Chebyshev
+ *   [34..41] FP32 Dirichlet triangular  [42..49] FP32 Neumann triangular
+ *   [50..57] FP32 Dirichlet Chebyshev   [58..65] FP32 Neumann Chebyshev
+ * Enqueues on stream and waits for it. */
 int sgw_autotune(sgw_ctx* ctx, void* stream, double* report, int nreport);
 
 /* Sizes: what = 0 P, 1 number of input PCE terms, 2 free nodes,

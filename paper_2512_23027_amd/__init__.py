@@ -16,6 +16,7 @@ LIBPATH = os.path.join(HERE, "libsgw.so")
 SGW_HOST, SGW_DEVICE = 0, 1
 SGW_FP64, SGW_FP32_IR64 = 0, 1
 SGW_GUESS_PREV, SGW_GUESS_NEWMARK, SGW_GUESS_LEARNED = 0, 1, 2
+SGW_INNER_CHOLESKY, SGW_INNER_CHEBYSHEV = 0, 1
 SGW_NOT_CONVERGED = 1
 
 ERRORS = {-1: "SGW_EINVAL", -2: "SGW_ESTATE", -3: "SGW_ENOMEM",
@@ -42,7 +43,8 @@ class ProblemDesc(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int),
-                ("precond_rtol", ctypes.c_double)]
+                ("precond_rtol", ctypes.c_double), ("inner_prec", ctypes.c_int),
+                ("cheb_degree", ctypes.c_int)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -114,12 +116,15 @@ class Solver:
 
     ``prm`` is a parameter dict as produced by ``workloads.config``; solver
     options (rtol, inner_rtol, max_iter, precision, guess) may be given as
-    keyword arguments.
+    keyword arguments.  inner_prec selects the subdomain preconditioner
+    (SGW_INNER_CHOLESKY: exact mean-matrix solve, SGW_INNER_CHEBYSHEV:
+    Chebyshev polynomial of degree cheb_degree).
     """
 
     def __init__(self, prm, rtol=None, inner_rtol=None, max_iter=1000,
                  inner_max_iter=1000, precision=SGW_FP64, guess=SGW_GUESS_PREV,
-                 precond_rtol=None, use_torch_allocator=True):
+                 precond_rtol=None, inner_prec=SGW_INNER_CHOLESKY, cheb_degree=0,
+                 use_torch_allocator=True):
         import torch
         self.torch = torch
         L = lib()
@@ -142,6 +147,7 @@ class Solver:
         d.inner_max_iter = inner_max_iter
         d.precision, d.guess = precision, guess
         d.precond_rtol = precond_rtol if precond_rtol is not None else 0.0
+        d.inner_prec, d.cheb_degree = inner_prec, cheb_degree
         self.desc = d
         self._live = {}
         al = None
@@ -234,13 +240,16 @@ class Solver:
         self._check(rc, "sgw_solve")
         return U.view(self.P, self.nn), st.as_dict()
 
-    def profile(self, enable=True):
-        """Start (clear) or stop the per-launch kernel timing."""
-        return self._check(lib().sgw_profile(self.ctx, int(enable)), "sgw_profile")
+    def profile(self, enable=True, every=1):
+        """Start (clear) or stop the per-launch kernel timing; with every > 1
+        only every n-th launch of each kind is timed."""
+        return self._check(lib().sgw_profile(self.ctx, int(every) if enable else 0),
+                           "sgw_profile")
 
     def profile_read(self, kind):
-        """(launches, ms, algorithmic bytes) of kind 0 = SG apply,
-        1 = subdomain triangular solves."""
+        """(launches, ms, algorithmic bytes) of the timed launches of kind
+        0 = SG apply, 1 = subdomain triangular solves, 2 = Chebyshev
+        preconditioner."""
         n, ms, b = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
         self._check(lib().sgw_profile_read(self.ctx, kind, ctypes.byref(n), ctypes.byref(ms),
                                            ctypes.byref(b)), "sgw_profile_read")
@@ -248,11 +257,17 @@ class Solver:
 
     def autotune(self):
         """Pick the fastest launch shapes; returns the timing report (us)."""
-        rep = (ctypes.c_double * 18)()
-        self._check(lib().sgw_autotune(self.ctx, self._stream(), rep, 18), "sgw_autotune")
+        rep = (ctypes.c_double * 66)()
+        self._check(lib().sgw_autotune(self.ctx, self._stream(), rep, 66), "sgw_autotune")
         r = list(rep)
-        return {"tri_dirichlet_us_by_Q": r[0:8], "tri_neumann_us_by_Q": r[8:16],
-                "sg_apply_unrolled_us": r[16], "sg_apply_table_us": r[17]}
+        out = {"fp64": {"tri_dirichlet_us_by_Q": r[0:8], "tri_neumann_us_by_Q": r[8:16],
+                        "cheb_dirichlet_us_by_Q": r[18:26], "cheb_neumann_us_by_Q": r[26:34]},
+               "fp32": {"tri_dirichlet_us_by_Q": r[34:42], "tri_neumann_us_by_Q": r[42:50],
+                        "cheb_dirichlet_us_by_Q": r[50:58], "cheb_neumann_us_by_Q": r[58:66]},
+               "sg_apply_unrolled_us": r[16], "sg_apply_table_us": r[17]}
+        for prec in ("fp64", "fp32"):  # keep only what was timed
+            out[prec] = {k: v for k, v in out[prec].items() if max(v) > 0}
+        return out
 
     def close(self):
         if self.ctx:

@@ -66,6 +66,21 @@ template <typename T>
 void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
                int ldo, int nbatch, long long sr, long long so, hipStream_t st);
 
+// Chebyshev polynomial preconditioner (degree deg, Q modes per workgroup) on
+// the blocks of A's mean matrix; iv[2b], iv[2b+1] = spectral interval of
+// block b.  Writes z and part[b*P + j] = r_j'z_j (part2 = r_j'r_j if not
+// null).  Returns -1 (nothing launched) if Q, deg or the block size is out
+// of range (max_rows <= 4096, Q * max_rows * sizeof(T) <= 150 KiB).
+template <typename T>
+size_t cheb_lds_bytes(int max_rows, int Q);
+// Once per process before the first cheb_apply: allows the kernels the full
+// 160 KiB of LDS.  0 on success, -1 on a HIP error.
+int cheb_prepare();
+template <typename T>
+int cheb_apply(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P, int deg,
+               int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
+               double* part2, hipStream_t st);
+
 // Segmented dot products: partial[b * P + j] = sum_{r in block b} a[j][r] b[j][r]
 // (row_off relative to the vectors; a second vector pair is optional).
 template <typename T>
@@ -130,8 +145,12 @@ struct DCoarse {
   const int *rem_off, *rem_list;   // remaining torn rows per subdomain
   const int* sc_ptr;               // local corners per subdomain
   const double* phi;               // coarse basis, per subdomain blocks
+  const float* phif;               // its FP32 copy (FP32 solver only)
   const long long* phi_off;
+  int max_rem = 0;                 // largest number of remaining rows
 };
+// local coarse unknowns (P x corners) of one subdomain held in LDS by the lift
+#define SGW_MAX_COARSE_LOCAL 4096
 template <typename T>
 void coarse_rhs(const DCoarse& c, const T* r, int ldr, const T* yt, int ldt,
                 double* dc, hipStream_t st);

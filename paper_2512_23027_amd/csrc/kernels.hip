@@ -751,79 +751,322 @@ void gather_from_torn(int nG, int P, const int* gptr, const int* gtorn, const do
 }
 
 // ---------------------------------------------------------------------------
+// K3c: Chebyshev polynomial preconditioner, the alternative to the exact
+// mean-matrix solve of K3.  Per block b it returns z = p(D^{-1} A0) D^{-1} r,
+// the result of `deg` steps of the Chebyshev iteration for A0 z = r with
+// Jacobi scaling D = diag(A0) on the block's spectral interval [lo, hi]
+// (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 12.1),
+// started from z = 0.  A0 is the mean matrix (coefficient slot k = 0).
+// The result is SPD in r whenever the scaled spectrum lies in (0, lo + hi).
+// One workgroup per (block, tile of Q modes): the block's rows stay in the
+// workgroup for all steps, the search direction goes through LDS, the rest
+// lives in registers (RPT rows per thread).  Also writes the partial sums
+// part[b*P + j] = r_j'z_j over the block (and part2 = r_j'r_j if given), in a
+// fixed order.
+// ---------------------------------------------------------------------------
+#define CHEB_TPB 1024
+
+template <typename T, int Q, int RPT>
+__global__ __launch_bounds__(CHEB_TPB) void k_cheb(
+    DEll<T> A, const int* __restrict__ row_off, const double* __restrict__ iv, int P, int deg,
+    const T* __restrict__ r, int ldr, T* __restrict__ z, int ldz, double* __restrict__ part,
+    double* __restrict__ part2) {
+  // all LDS is dynamic (so the launch may use up to the whole 160 KiB):
+  // the reduction slots, then the current search direction [Q][n]
+  extern __shared__ unsigned char smem_raw[];
+  double(*red)[CHEB_TPB / 64][Q] = reinterpret_cast<double(*)[CHEB_TPB / 64][Q]>(smem_raw);
+  T* Dk = reinterpret_cast<T*>(smem_raw + sizeof(double) * 2 * (CHEB_TPB / 64) * Q);
+  const int b = blockIdx.x, j0 = blockIdx.y * Q;
+  const int r0 = row_off[b], n = row_off[b + 1] - r0;
+  const int NR = A.nrows;
+  const double lo = iv[2 * b], hi = iv[2 * b + 1];
+  const double theta = 0.5 * (hi + lo);
+  const double delta = fmax(0.5 * (hi - lo), 1e-3 * theta);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  int lc[RPT][7];
+  T av[RPT][7], dinv[RPT];
+  T res[RPT][Q], zz[RPT][Q], dd[RPT][Q];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int i = threadIdx.x + t * CHEB_TPB;
+    const bool live = i < n;
+#pragma unroll
+    for (int sl = 0; sl < 7; ++sl) {
+      const size_t o = (size_t)sl * NR + r0 + (live ? i : 0);
+      lc[t][sl] = live ? A.col[o] - r0 : 0;
+      av[t][sl] = live ? A.val[o] : T(0);
+    }
+    dinv[t] = live ? T(1) / av[t][0] : T(0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = j0 + q;
+      const T v = (live && j < P) ? r[(size_t)j * ldr + r0 + i] : T(0);
+      res[t][q] = v;
+      zz[t][q] = T(0);
+      dd[t][q] = dinv[t] * v * (T)(1.0 / theta);
+    }
+  }
+  for (int k = 0; k < deg; ++k) {
+#pragma unroll
+    for (int t = 0; t < RPT; ++t)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) zz[t][q] += dd[t][q];
+    if (k + 1 == deg) break;
+    __syncthreads();  // every read of the previous direction is done
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int i = threadIdx.x + t * CHEB_TPB;
+      if (i < n)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Dk[q * n + i] = dd[t][q];
+    }
+    __syncthreads();
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    const T c1 = (T)(rn * rho), c2 = (T)(2.0 * rn / delta);
+    rho = rn;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int i = threadIdx.x + t * CHEB_TPB;
+      if (i >= n) continue;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        T ad = av[t][0] * Dk[q * n + lc[t][0]];
+#pragma unroll
+        for (int sl = 1; sl < 7; ++sl) ad = fmadd(av[t][sl], Dk[q * n + lc[t][sl]], ad);
+        res[t][q] -= ad;
+        dd[t][q] = fmadd(c1, dd[t][q], c2 * dinv[t] * res[t][q]);
+      }
+    }
+  }
+  // store z; partial sums of r'z and r'r
+  double srz[Q], srr[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) srz[q] = srr[q] = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int i = threadIdx.x + t * CHEB_TPB;
+    if (i >= n) continue;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = j0 + q;
+      if (j >= P) continue;
+      z[(size_t)j * ldz + r0 + i] = zz[t][q];
+      const double rv = (double)r[(size_t)j * ldr + r0 + i];
+      srz[q] += rv * (double)zz[t][q];
+      srr[q] += rv * rv;
+    }
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const double a = wave_sum(srz[q]);
+    const double bq = part2 ? wave_sum(srr[q]) : 0.0;
+    if (lane == 0) {
+      red[0][w][q] = a;
+      red[1][w][q] = bq;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < Q && j0 + (int)threadIdx.x < P) {
+    const int q = threadIdx.x;
+    double a = 0.0, bq = 0.0;
+    for (int v = 0; v < CHEB_TPB / 64; ++v) {
+      a += red[0][v][q];
+      bq += red[1][v][q];
+    }
+    part[(size_t)b * P + j0 + q] = a;
+    if (part2) part2[(size_t)b * P + j0 + q] = bq;
+  }
+}
+
+template <typename T>
+size_t cheb_lds_bytes(int max_rows, int Q) {
+  return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + (size_t)max_rows * Q * sizeof(T);
+}
+
+template <typename T, int Q, int RPT>
+static void launch_cheb(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P,
+                        int deg, int max_rows, const T* r, int ldr, T* z, int ldz,
+                        double* part, double* part2, hipStream_t st) {
+  dim3 grid(nb, ceil_div(P, Q));
+  k_cheb<T, Q, RPT><<<grid, CHEB_TPB, cheb_lds_bytes<T>(max_rows, Q), st>>>(
+      A, row_off, iv, P, deg, r, ldr, z, ldz, part, part2);
+}
+
+template <typename T, int RPT>
+static void cheb_q(int Q, const DEll<T>& A, const int* row_off, const double* iv, int nb, int P,
+                   int deg, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
+                   double* part2, hipStream_t st) {
+  switch (Q) {
+#define SGW_CHEB_CASE(q)                                                                      \
+  case q:                                                                                    \
+    launch_cheb<T, q, RPT>(A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, \
+                           st);                                                              \
+    break;
+    SGW_CHEB_CASE(1)
+    SGW_CHEB_CASE(2)
+    SGW_CHEB_CASE(3)
+    SGW_CHEB_CASE(4)
+    SGW_CHEB_CASE(5)
+    SGW_CHEB_CASE(6)
+    SGW_CHEB_CASE(7)
+    default:
+    SGW_CHEB_CASE(8)
+#undef SGW_CHEB_CASE
+  }
+}
+
+// The kernels have no static LDS, so the whole 160 KiB may be dynamic; the
+// attribute is set once for every instantiation before the first launch.
+template <typename T, int RPT>
+static bool cheb_attr_rpt() {
+  bool ok = true;
+#define SGW_CHEB_ATTR(q)                                                                \
+  ok = ok && hipFuncSetAttribute((const void*)k_cheb<T, q, RPT>,                         \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == \
+                 hipSuccess;
+  SGW_CHEB_ATTR(1)
+  SGW_CHEB_ATTR(2)
+  SGW_CHEB_ATTR(3)
+  SGW_CHEB_ATTR(4)
+  SGW_CHEB_ATTR(5)
+  SGW_CHEB_ATTR(6)
+  SGW_CHEB_ATTR(7)
+  SGW_CHEB_ATTR(8)
+#undef SGW_CHEB_ATTR
+  return ok;
+}
+int cheb_prepare() {
+  bool ok = cheb_attr_rpt<double, 1>() && cheb_attr_rpt<double, 2>() &&
+            cheb_attr_rpt<double, 4>() && cheb_attr_rpt<float, 1>() &&
+            cheb_attr_rpt<float, 2>() && cheb_attr_rpt<float, 4>();
+  return ok ? 0 : -1;
+}
+
+template <typename T>
+int cheb_apply(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P, int deg,
+               int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
+               double* part2, hipStream_t st) {
+  if (Q < 1 || Q > 8 || deg < 1 || max_rows < 1 || max_rows > 4 * CHEB_TPB ||
+      cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024)
+    return -1;
+  if (max_rows <= CHEB_TPB)
+    cheb_q<T, 1>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, st);
+  else if (max_rows <= 2 * CHEB_TPB)
+    cheb_q<T, 2>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, st);
+  else
+    cheb_q<T, 4>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, st);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // K5: coarse grid (Eq. Fcc_2, NNCP2).  d_c = sum_s B_c^T (D_s r_c - K~^s_{c,(ir)} y^s)
 // with y^s the Neumann solution; u_c = F_cc^{-1} d_c with the FP64 inverse;
 // the lift adds the coarse basis Phi_s u_c^s on the remaining rows.
 // ---------------------------------------------------------------------------
+// d_c[m][ci]: one wave per coarse unknown (mode m, corner ci); the lanes
+// share the Galerkin entries of output mode m.
 template <typename T>
-__global__ void k_coarse_rhs(DCoarse c, const T* r, int ldr, const T* yt, int ldt, double* dc) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(SGW_BLOCK) void k_coarse_rhs(DCoarse c, const T* r, int ldr,
+                                                         const T* yt, int ldt, double* dc) {
+  const long long t = (long long)blockIdx.x * (SGW_BLOCK / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (t >= (long long)c.nC * c.P) return;
-  int m = (int)(t / c.nC), ci = (int)(t % c.nC);
+  const int m = (int)(t / c.nC), ci = (int)(t % c.nC);
+  const int g0 = c.gi_ptr[m], g1 = c.gi_ptr[m + 1];
   double s = 0.0;
   for (int q = c.c_ptr[ci]; q < c.c_ptr[ci + 1]; ++q) {
-    int lc = c.c_lc[q];
-    s += c.sc_w[lc] * (double)r[(size_t)m * ldr + c.sc_gidx[lc]];
+    const int lc = c.c_lc[q];
+    if (lane == 0) s += c.sc_w[lc] * (double)r[(size_t)m * ldr + c.sc_gidx[lc]];
     for (int e = c.cc_ptr[lc]; e < c.cc_ptr[lc + 1]; ++e) {
       const int row = c.cc_torn[e];
       const double* kv = c.cc_val + (size_t)e * c.nk;
-      double acc = 0.0;
-      for (int g = c.gi_ptr[m]; g < c.gi_ptr[m + 1]; ++g)
-        acc += c.gi_v[g] * kv[c.gi_k[g]] * (double)yt[(size_t)c.gi_j[g] * ldt + row];
-      s -= acc;
+      for (int g = g0 + lane; g < g1; g += 64)
+        s -= c.gi_v[g] * kv[c.gi_k[g]] * (double)yt[(size_t)c.gi_j[g] * ldt + row];
     }
   }
-  dc[(size_t)m * c.nC + ci] = s;
+  s = wave_sum(s);
+  if (lane == 0) dc[(size_t)m * c.nC + ci] = s;
 }
 template <typename T>
 void coarse_rhs(const DCoarse& c, const T* r, int ldr, const T* yt, int ldt, double* dc,
                 hipStream_t st) {
   long long N = (long long)c.nC * c.P;
-  if (N > 0) k_coarse_rhs<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(c, r, ldr, yt, ldt, dc);
+  const int wpb = SGW_BLOCK / 64;
+  if (N > 0)
+    k_coarse_rhs<T><<<(int)((N + wpb - 1) / wpb), SGW_BLOCK, 0, st>>>(c, r, ldr, yt, ldt, dc);
 }
 
-// u_c = F_cc^{-1} d_c; the inverse is symmetric, so thread `row` reads the
-// column finv[col*n + row] and the loads of a wave are contiguous.
-__global__ void k_coarse_solve(int n, const double* finv, const double* dc, double* uc) {
-  int row = blockIdx.x * blockDim.x + threadIdx.x;
+// u_c = F_cc^{-1} d_c: one wave per row; the inverse is symmetric and stored
+// densely, so row `row` is read contiguously by the lanes.
+__global__ __launch_bounds__(SGW_BLOCK) void k_coarse_solve(int n, const double* finv,
+                                                           const double* dc, double* uc) {
+  const int row = blockIdx.x * (SGW_BLOCK / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (row >= n) return;
+  const double* fr = finv + (size_t)row * n;
   double s = 0.0;
-  for (int col = 0; col < n; ++col) s += finv[(size_t)col * n + row] * dc[col];
-  uc[row] = s;
+  for (int col = lane; col < n; col += 64) s += fr[col] * dc[col];
+  s = wave_sum(s);
+  if (lane == 0) uc[row] = s;
 }
 void coarse_solve(const DCoarse& c, const double* dc, double* uc, hipStream_t st) {
   int n = c.nC * c.P;
-  if (n > 0) k_coarse_solve<<<ceil_div(n, SGW_BLOCK), SGW_BLOCK, 0, st>>>(n, c.finv, dc, uc);
+  const int wpb = SGW_BLOCK / 64;
+  if (n > 0) k_coarse_solve<<<(n + wpb - 1) / wpb, SGW_BLOCK, 0, st>>>(n, c.finv, dc, uc);
 }
 
-// ut[j][rem] += sum_{m, lc} Phi_s[(m, lc)][(j, tr)] uc[m][coarse(lc)]
+// ut[j][rem] += sum_{m, lc} Phi_s[(m, lc)][(j, tr)] uc[m][coarse(lc)]: the
+// subdomain's coarse values go to LDS, each thread owns one output and
+// streams its column of Phi_s (contiguous across the threads).  The FP32
+// path reads an FP32 copy of Phi.
 template <typename T>
-__global__ void k_coarse_lift(DCoarse c, const double* uc, T* ut, int ldt) {
+__global__ __launch_bounds__(SGW_BLOCK) void k_coarse_lift(DCoarse c, const double* uc, T* ut,
+                                                          int ldt) {
+  __shared__ double ucl[SGW_MAX_COARSE_LOCAL];
   const int s = blockIdx.x;
   const int nrem = c.rem_off[s + 1] - c.rem_off[s];
   const int lc0 = c.sc_ptr[s], ncs = c.sc_ptr[s + 1] - lc0;
   if (ncs == 0) return;
+  const int nq = c.P * ncs;
+  for (int q = threadIdx.x; q < nq; q += SGW_BLOCK)
+    ucl[q] = uc[(size_t)(q / ncs) * c.nC + c.sc_coarse[lc0 + q % ncs]];
+  __syncthreads();
   const long long nout = (long long)c.P * nrem;
-  const double* ph = c.phi + c.phi_off[s];
-  for (long long o = (long long)blockIdx.y * blockDim.x + threadIdx.x; o < nout;
-       o += (long long)gridDim.y * blockDim.x) {
-    int j = (int)(o / nrem), tr = (int)(o % nrem);
-    double acc = 0.0;
-    for (int m = 0; m < c.P; ++m)
-      for (int l = 0; l < ncs; ++l)
-        acc += ph[((size_t)m * ncs + l) * nout + o] * uc[(size_t)m * c.nC + c.sc_coarse[lc0 + l]];
-    T* dst = ut + (size_t)j * ldt + c.rem_list[c.rem_off[s] + tr];
-    *dst = (T)((double)*dst + acc);
+  const long long o = (long long)blockIdx.y * SGW_BLOCK + threadIdx.x;
+  if (o >= nout) return;
+  double acc = 0.0;
+  if constexpr (sizeof(T) == 4) {
+    const float* ph = c.phif + c.phi_off[s] + o;
+#pragma unroll 8
+    for (int q = 0; q < nq; ++q) acc += (double)ph[(size_t)q * nout] * ucl[q];
+  } else {
+    const double* ph = c.phi + c.phi_off[s] + o;
+#pragma unroll 8
+    for (int q = 0; q < nq; ++q) acc += ph[(size_t)q * nout] * ucl[q];
   }
+  const int j = (int)(o / nrem), tr = (int)(o % nrem);
+  T* dst = ut + (size_t)j * ldt + c.rem_list[c.rem_off[s] + tr];
+  *dst = (T)((double)*dst + acc);
 }
 template <typename T>
 void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt, hipStream_t st) {
   if (c.nC == 0) return;
-  k_coarse_lift<T><<<dim3(nsub, 8), SGW_BLOCK, 0, st>>>(c, uc, ut, ldt);
+  const int gy = (int)((c.P * (long long)c.max_rem + SGW_BLOCK - 1) / SGW_BLOCK);
+  k_coarse_lift<T><<<dim3(nsub, std::max(gy, 1)), SGW_BLOCK, 0, st>>>(c, uc, ut, ldt);
 }
 
 // explicit instantiations
 template size_t tri_lds_bytes<double>(const DFactor&, int);
+template size_t cheb_lds_bytes<double>(int, int);
+template size_t cheb_lds_bytes<float>(int, int);
+template int cheb_apply<double>(const DEll<double>&, const int*, const double*, int, int, int,
+                                int, int, const double*, int, double*, int, double*, double*,
+                                hipStream_t);
+template int cheb_apply<float>(const DEll<float>&, const int*, const double*, int, int, int,
+                               int, int, const float*, int, float*, int, double*, double*,
+                               hipStream_t);
 template size_t tri_lds_bytes<float>(const DFactor&, int);
 #define SGW_INST(T)                                                                          \
   template void sg_apply<T>(const DEll<T>&, const GTab&, int, int, const T*, int, T*, int, T, \

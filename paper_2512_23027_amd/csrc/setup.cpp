@@ -437,6 +437,107 @@ static void append_factor(Factor& f, const CSC& L, const std::vector<SN>& sns) {
 // ---------------------------------------------------------------------------
 // Problem build.
 // ---------------------------------------------------------------------------
+// Spectral interval [lo, hi] of the Jacobi-scaled mean matrix
+// D^{-1/2} K~_0 D^{-1/2} of every block [off[b], off[b+1]) of E (k = 0
+// values, slot 0 = diagonal).  hi: the smaller of the Gershgorin bound and
+// 1.05 x the largest Ritz value; lo: the smallest Ritz value of a 60-step
+// Lanczos run (the Chebyshev preconditioner built from them is SPD for any
+// spectrum inside (0, lo + hi), which these bounds always contain).
+// Returns false if a block has a non-positive diagonal or couples to a row
+// outside itself.
+static bool cheb_bounds(const Ell& E, const std::vector<int>& off, std::vector<double>& out) {
+  const int nb = (int)off.size() - 1, W = E.W, NR = E.nrows;
+  out.assign(2 * (size_t)nb, 0.0);
+  for (int b = 0; b < nb; ++b) {
+    const int r0 = off[b], n = off[b + 1] - r0;
+    if (n <= 0) continue;
+    std::vector<double> isd(n);
+    for (int r = 0; r < n; ++r) {
+      const size_t o = (size_t)r0 + r;
+      if (E.col[o] != r0 + r || !(E.val[o] > 0.0)) return false;
+      isd[r] = 1.0 / std::sqrt(E.val[o]);
+    }
+    double gersh = 0.0;
+    for (int r = 0; r < n; ++r) {
+      double s = 0.0;
+      for (int sl = 0; sl < W; ++sl) {
+        const size_t o = (size_t)sl * NR + r0 + r;
+        const int c = E.col[o] - r0;
+        if (c < 0 || c >= n) return false;
+        s += std::fabs(E.val[o]) * isd[r] * isd[c];
+      }
+      gersh = std::max(gersh, s);
+    }
+    auto matvec = [&](const std::vector<double>& x, std::vector<double>& y) {
+      for (int r = 0; r < n; ++r) {
+        double s = 0.0;
+        for (int sl = 0; sl < W; ++sl) {
+          const size_t o = (size_t)sl * NR + r0 + r;
+          const int c = E.col[o] - r0;
+          s += E.val[o] * isd[r] * isd[c] * x[c];
+        }
+        y[r] = s;
+      }
+    };
+    // Lanczos with full reorthogonalisation (n ~ 1e3, m = 60)
+    const int m = std::min(n, 60);
+    std::vector<std::vector<double>> V;
+    std::vector<double> al, be;
+    std::vector<double> v(n), w(n);
+    double nv = 0.0;
+    for (int r = 0; r < n; ++r) {
+      v[r] = 1.0 + 0.25 * std::sin(0.7 * r + 0.3 * b);
+      nv += v[r] * v[r];
+    }
+    for (auto& x : v) x /= std::sqrt(nv);
+    for (int it = 0; it < m; ++it) {
+      V.push_back(v);
+      matvec(v, w);
+      double a = 0.0;
+      for (int r = 0; r < n; ++r) a += w[r] * v[r];
+      al.push_back(a);
+      for (const auto& u : V) {
+        double d = 0.0;
+        for (int r = 0; r < n; ++r) d += w[r] * u[r];
+        for (int r = 0; r < n; ++r) w[r] -= d * u[r];
+      }
+      double bnorm = 0.0;
+      for (double x : w) bnorm += x * x;
+      bnorm = std::sqrt(bnorm);
+      if (it + 1 == m || bnorm < 1e-12) break;
+      be.push_back(bnorm);
+      for (int r = 0; r < n; ++r) v[r] = w[r] / bnorm;
+    }
+    // extreme eigenvalues of the tridiagonal matrix by Sturm bisection
+    const int k = (int)al.size();
+    auto count_below = [&](double x) {
+      int cnt = 0;
+      double q = al[0] - x;
+      if (q < 0) ++cnt;
+      for (int i = 1; i < k; ++i) {
+        if (q == 0.0) q = 1e-300;
+        q = al[i] - x - be[i - 1] * be[i - 1] / q;
+        if (q < 0) ++cnt;
+      }
+      return cnt;
+    };
+    auto kth = [&](int idx) {  // idx-th smallest (0-based)
+      double lo = -1.0, hi = gersh + 1.0;
+      for (int t = 0; t < 200; ++t) {
+        double mid = 0.5 * (lo + hi);
+        if (count_below(mid) > idx) hi = mid;
+        else lo = mid;
+      }
+      return 0.5 * (lo + hi);
+    };
+    double tmin = kth(0), tmax = kth(k - 1);
+    if (!(tmin > 0.0)) return false;
+    out[2 * (size_t)b] = tmin;
+    out[2 * (size_t)b + 1] = std::min(gersh, 1.05 * tmax);
+  }
+  return true;
+}
+
 int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
   h.d = d;
   const int n = d.n;
@@ -738,6 +839,12 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
       h.gam_w.push_back(c.second);
     }
     h.gam_ptr.push_back((int)h.gam_torn.size());
+  }
+
+  // ----- spectral interval of every block for the Chebyshev preconditioner
+  if (!cheb_bounds(h.dir, h.Ioff, h.chebD) || !cheb_bounds(h.neu, h.Toff, h.chebN)) {
+    err = "a subdomain block couples outside itself or has a non-positive diagonal";
+    return SGW_ENOTSPD;
   }
 
   // ----- mean-matrix factors (Dirichlet: interior; Neumann: torn) -----

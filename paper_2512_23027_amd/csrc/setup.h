@@ -77,6 +77,8 @@ struct Host {
   std::vector<int> torn2dd;            // torn (Neumann) row -> dd index
   Ell glob, dir, neu;
   Factor fD, fN;
+  // Chebyshev interval (lo, hi) of the Jacobi-scaled mean matrix per block
+  std::vector<double> chebD, chebN;
   // D_s R_s: for every torn row, interface index (or -1) and weight 1/mult
   std::vector<int> torn_gidx;
   std::vector<double> torn_w;

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -38,6 +39,8 @@ namespace {
 template <typename T>
 struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   int nrows = 0, nb = 0, Q = 8;
+  int cq = 8, max_block_rows = 0;     // Chebyshev mode tile, largest block
+  const double* cheb_iv = nullptr;    // device, [nb][2] spectral intervals
   int last_its[2] = {0, 0};     // previous iteration counts (tight / loose tolerance)
   double loose_tol = 1e300;     // tolerances >= this use the second count
   k::DEll<T> A;
@@ -95,17 +98,23 @@ struct sgw_ctx {
   std::vector<int> rem_off_h, rem_list_h;
   std::vector<long long> phi_off_h;
   double* phi = nullptr;
+  float* phif = nullptr;
   double* fs = nullptr;   // local coarse matrices during factor
   bool factored = false, has_state = false;
   long long stepno = 0;
-  // kernel timing: event pairs around SG-apply (kind 0) and triangular-solve
-  // (kind 1) launches; launches, milliseconds and algorithmic bytes per kind
+  // kernel timing: event pairs around SG-apply (kind 0), triangular-solve
+  // (kind 1) and Chebyshev (kind 2) launches, every prof_every-th launch of
+  // a kind; launches, milliseconds and algorithmic bytes per kind
   bool prof = false;
+  int prof_every = 1;
+  long long pseen[3] = {0, 0, 0};
   std::vector<hipEvent_t> ev;
   struct Pend { int a, kind; double bytes; };
   std::vector<Pend> pend;
-  long long pcnt[2] = {0, 0};
-  double pms[2] = {0, 0}, pbytes[2] = {0, 0};
+  long long pcnt[3] = {0, 0, 0};
+  double pms[3] = {0, 0, 0}, pbytes[3] = {0, 0, 0};
+  // subdomain preconditioner: SGW_INNER_* and the Chebyshev degree
+  int inner_prec = SGW_INNER_CHOLESKY, cheb_deg = 4;
   double factor_bytes_D = 0, factor_bytes_N = 0;
   // per-call statistics
   long long inner_its = 0;
@@ -254,8 +263,9 @@ static k::DFactor upload_factor(sgw_ctx* c, const Factor& f) {
 // kernel timing (sgw_profile): a HIP event pair around each timed launch,
 // harvested at the host synchronisation points the solver has anyway.
 // ---------------------------------------------------------------------------
-static int prof_begin(sgw_ctx* c, hipStream_t st) {
+static int prof_begin(sgw_ctx* c, int kind, hipStream_t st) {
   if (!c->prof) return -1;
+  if (c->pseen[kind]++ % c->prof_every != 0) return -1;
   int a = (int)c->pend.size() * 2;
   while ((int)c->ev.size() < a + 2) {
     hipEvent_t e;
@@ -289,7 +299,7 @@ static void prof_harvest(sgw_ctx* c) {
 template <typename T>
 static void K1(sgw_ctx* c, const k::DEll<T>& A, int r0, int nrows, const T* x, int ldx, T* y,
                int ldy, double alpha, double beta, hipStream_t st) {
-  int a = prof_begin(c, st);
+  int a = prof_begin(c, 0, st);
   k::sg_apply<T>(A, c->gt, r0, nrows, x, ldx, y, ldy, (T)alpha, (T)beta, 1, 0, 0, st);
   const double w = sizeof(T);
   double per_row = 7.0 * c->nk * w + 7.0 * 4.0 + 2.0 * c->P * w + (beta != 0.0 ? c->P * w : 0.0);
@@ -300,10 +310,31 @@ static void K1(sgw_ctx* c, const k::DEll<T>& A, int r0, int nrows, const T* x, i
 template <typename T>
 static void K3(sgw_ctx* c, SysT<T>& S, bool neumann, const T* rhs, int ldr, T* out, int ldo,
                hipStream_t st) {
-  int a = prof_begin(c, st);
+  int a = prof_begin(c, 1, st);
   k::tri_solve<T>(S.F, S.Q, rhs, ldr, out, ldo, 1, 0, 0, st);
   double fb = (neumann ? c->factor_bytes_N : c->factor_bytes_D) * (sizeof(T) / 8.0);
   prof_end(c, a, 1, 2.0 * sizeof(T) * c->P * S.nrows + fb, st);
+}
+
+// Subdomain preconditioner z = (I_P (x) (K~_0^s)^{-1}) r on the system's
+// [P][nrows] vectors r, z, followed by the partial sums part[b*P + j] =
+// r_j'z_j (and part2 = r_j'r_j if not null).  Exact (K3 + K4) or Chebyshev
+// (K3c, one fused launch; algorithmic bytes: r in, z out, the mean
+// matrix's values and column indices).
+template <typename T>
+static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, double* part2,
+                        hipStream_t st) {
+  const int P = c->P, n = S.nrows;
+  if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
+    int a = prof_begin(c, 2, st);
+    (void)k::cheb_apply<T>(S.A, S.row_off, S.cheb_iv, S.nb, P, c->cheb_deg, S.cq,
+                           S.max_block_rows, S.r, n, S.z, n, part, part2, st);
+    prof_end(c, a, 2, 2.0 * sizeof(T) * P * n + 7.0 * (sizeof(T) + 4.0) * n, st);
+    return;
+  }
+  K3<T>(c, S, neumann, S.r, n, S.z, n, st);
+  k::seg_dot<T>(S.nb, S.row_off, P, S.r, n, S.z, n, part, part2 ? S.r : nullptr, n,
+                part2 ? S.r : nullptr, n, part2, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,9 +358,8 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
   int& predicted = S.last_its[tol >= S.loose_tol ? 1 : 0];
   k::copy2d<T, T>(P, n, b, ldb, S.r, n, 1.0, st);
   k::fill2d<T>(P, n, S.x, n, T(0), st);
-  K3<T>(c, S, neumann, S.r, n, S.z, n, st);
+  precond_dot<T>(c, S, neumann, c->part, c->part2, st);
   k::copy2d<T, T>(P, n, S.z, n, S.p, n, 1.0, st);
-  k::seg_dot<T>(nb, S.row_off, P, S.r, n, S.z, n, c->part, S.r, n, S.r, n, c->part2, st);
   k::pcg_scalars(0, nb, P, c->part, c->part2, c->sc, -(tol * tol), NegligibleBlock<T>::value,
                  c->flags, st);
   int it = 0, rc = 0;
@@ -365,8 +395,7 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
       }
       if (nact == 0) break;
     }
-    K3<T>(c, S, neumann, S.r, n, S.z, n, st);
-    k::seg_dot<T>(nb, S.row_off, P, S.r, n, S.z, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
+    precond_dot<T>(c, S, neumann, c->part, nullptr, st);
     k::pcg_scalars(3, nb, P, c->part, nullptr, c->sc, tol * tol, 0.0, c->flags, st);
     k::pcg_p<T>(nb, S.row_off, P, c->sc, S.z, n, S.p, n, st);
   }
@@ -753,6 +782,28 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
   };
   pr.D.Q = pickq(pr.D.F);
   pr.N.Q = pickq(pr.N.F);
+  // Chebyshev preconditioner: spectral intervals (shared by both
+  // precisions), largest block, default mode tile
+  if constexpr (sizeof(T) == 8) {
+    pr.D.cheb_iv = upload(c, h.chebD);
+    pr.N.cheb_iv = upload(c, h.chebN);
+  } else {
+    pr.D.cheb_iv = c->d64.D.cheb_iv;
+    pr.N.cheb_iv = c->d64.N.cheb_iv;
+  }
+  auto maxblk = [&](const std::vector<int>& off) {
+    int m = 0;
+    for (size_t b = 0; b + 1 < off.size(); ++b) m = std::max(m, off[b + 1] - off[b]);
+    return m;
+  };
+  pr.D.max_block_rows = maxblk(h.Ioff);
+  pr.N.max_block_rows = maxblk(h.Toff);
+  for (SysT<T>* S : {&pr.D, &pr.N}) {
+    int ntiles = (P + 7) / 8;
+    int q = (P + ntiles - 1) / ntiles;
+    while (q > 1 && k::cheb_lds_bytes<T>(S->max_block_rows, q) > 150 * 1024) --q;
+    S->cq = q;
+  }
   const sgw_problem_desc& d = h.d;
   double loose = refine ? kIrPrecondRtol : d.precond_rtol;
   double tight = refine ? kIrInnerRtol : d.inner_rtol;
@@ -872,7 +923,7 @@ static bool check_pointers(sgw_ctx* c) {
       return false;
     }
   if (!prec_complete(c->d64, false) ||
-      (c->h.d.precision == SGW_FP32_IR64 && !prec_complete(c->f32, true))) {
+      (c->h.d.precision == SGW_FP32_IR64 && (!prec_complete(c->f32, true) || !c->phif))) {
     c->err = "internal error: a device array of a solver precision was not allocated";
     return false;
   }
@@ -900,19 +951,21 @@ long long sgw_query(const sgw_ctx* c, int what) {
 }
 
 int sgw_profile(sgw_ctx* c, int enable) {
-  if (!c) return SGW_EINVAL;
+  if (!c || enable < 0) return SGW_EINVAL;
   prof_harvest(c);
   c->prof = enable != 0;
-  for (int k2 = 0; k2 < 2; ++k2) {
+  c->prof_every = std::max(1, enable);
+  for (int k2 = 0; k2 < 3; ++k2) {
     c->pcnt[k2] = 0;
     c->pms[k2] = 0.0;
     c->pbytes[k2] = 0.0;
+    c->pseen[k2] = 0;
   }
   return 0;
 }
 
 int sgw_profile_read(sgw_ctx* c, int kind, long long* launches, double* ms, double* bytes) {
-  if (!c || kind < 0 || kind > 1) return SGW_EINVAL;
+  if (!c || kind < 0 || kind > 2) return SGW_EINVAL;
   prof_harvest(c);
   if (launches) *launches = c->pcnt[kind];
   if (ms) *ms = c->pms[kind];
@@ -924,12 +977,13 @@ int sgw_profile_read(sgw_ctx* c, int kind, long long* launches, double* ms, doub
 // keeps the fastest (mode tile of the triangular solves per system, SG-apply
 // kernel with the unrolled tensor vs the table-driven one).
 int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
-  if (!c) return SGW_EINVAL;
+  if (!c || nreport < 0) return SGW_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  std::vector<double> rep(18, -1.0);
+  const int kReport = 66;
+  std::vector<double> rep(kReport, -1.0);
   const int reps = 10;
   auto time_it = [&](auto&& fn) -> double {
     fn();
@@ -942,37 +996,37 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
     (void)hipEventElapsedTime(&ms, e0, e1);
     return 1e3 * ms / reps;  // microseconds per launch
   };
-  SysT<double>* sys[2] = {&c->d64.D, &c->d64.N};
-  for (int si = 0; si < 2; ++si) {
-    SysT<double>& S = *sys[si];
-    k::fill2d<double>(c->P, S.nrows, S.r, S.nrows, 1.0, st);
+  // mode tiles of one system: triangular solve (report at tri) and Chebyshev
+  // (report at cheb); the preconditioner the context uses decides which one
+  // is timed
+  auto tune_sys = [&](auto& S, int tri, int cheb) {
+    using T = std::remove_reference_t<decltype(*S.r)>;
+    k::fill2d<T>(c->P, S.nrows, S.r, S.nrows, T(1), st);
     double best = 1e300;
-    int bestq = S.Q;
-    for (int q = 1; q <= 8; ++q) {
-      if (q > c->P || k::tri_lds_bytes<double>(S.F, q) > 150 * 1024) continue;
-      double us = time_it([&] {
-        k::tri_solve<double>(S.F, q, S.r, S.nrows, S.z, S.nrows, 1, 0, 0, st);
-      });
-      rep[si * 8 + q - 1] = us;
-      if (us < best) {
-        best = us;
-        bestq = q;
+    if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
+      int bestq = S.cq;
+      for (int q = 1; q <= 8; ++q) {
+        if (q > c->P || k::cheb_lds_bytes<T>(S.max_block_rows, q) > 150 * 1024) continue;
+        double us = time_it([&] {
+          (void)k::cheb_apply<T>(S.A, S.row_off, S.cheb_iv, S.nb, c->P, c->cheb_deg, q,
+                                 S.max_block_rows, S.r, S.nrows, S.z, S.nrows, c->part,
+                                 c->part2, st);
+        });
+        rep[cheb + q - 1] = us;
+        if (us < best) {
+          best = us;
+          bestq = q;
+        }
       }
-    }
-    S.Q = bestq;
-  }
-  if (c->f32.ready) {
-    SysT<float>* sys32[2] = {&c->f32.D, &c->f32.N};
-    for (int si = 0; si < 2; ++si) {
-      SysT<float>& S = *sys32[si];
-      k::fill2d<float>(c->P, S.nrows, S.r, S.nrows, 1.0f, st);
-      double best = 1e300;
+      S.cq = bestq;
+    } else {
       int bestq = S.Q;
       for (int q = 1; q <= 8; ++q) {
-        if (q > c->P || k::tri_lds_bytes<float>(S.F, q) > 150 * 1024) continue;
+        if (q > c->P || k::tri_lds_bytes<T>(S.F, q) > 150 * 1024) continue;
         double us = time_it([&] {
-          k::tri_solve<float>(S.F, q, S.r, S.nrows, S.z, S.nrows, 1, 0, 0, st);
+          k::tri_solve<T>(S.F, q, S.r, S.nrows, S.z, S.nrows, 1, 0, 0, st);
         });
+        rep[tri + q - 1] = us;
         if (us < best) {
           best = us;
           bestq = q;
@@ -980,6 +1034,12 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
       }
       S.Q = bestq;
     }
+  };
+  tune_sys(c->d64.D, 0, 18);
+  tune_sys(c->d64.N, 8, 26);
+  if (c->f32.ready) {
+    tune_sys(c->f32.D, 34, 50);
+    tune_sys(c->f32.N, 42, 58);
   }
   {
     SysT<double>& S = c->d64.D;
@@ -1002,7 +1062,7 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
     return SGW_EHIP;
   }
   if (report)
-    for (int i = 0; i < nreport && i < 18; ++i) report[i] = rep[i];
+    for (int i = 0; i < nreport && i < kReport; ++i) report[i] = rep[i];
   return 0;
 }
 
@@ -1028,10 +1088,6 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     c->al = *al;
     c->has_al = true;
   }
-  if (hipGetDevice(&c->dev) != hipSuccess) {
-    delete c;
-    return SGW_EHIP;
-  }
   sgw_problem_desc dd = *d;
   if (dd.zeta == 0.0) dd.zeta = 0.25;
   if (dd.gamma == 0.0) dd.gamma = 0.5;
@@ -1040,10 +1096,24 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   if (!(dd.rtol > 0)) dd.rtol = 1e-8;
   if (!(dd.inner_rtol > 0)) dd.inner_rtol = 1e-3 * dd.rtol;
   if (!(dd.precond_rtol > 0)) dd.precond_rtol = dd.inner_rtol;
-  int rc = build_host(dd, c->h, c->err);
+  if (dd.cheb_degree <= 0) dd.cheb_degree = 4;
+  if ((dd.inner_prec != SGW_INNER_CHOLESKY && dd.inner_prec != SGW_INNER_CHEBYSHEV) ||
+      dd.cheb_degree > 64 || (dd.precision != SGW_FP64 && dd.precision != SGW_FP32_IR64)) {
+    c->err = "inner_prec, cheb_degree or precision out of range";
+    *out = c;
+    return SGW_EINVAL;
+  }
+  c->inner_prec = dd.inner_prec;
+  c->cheb_deg = dd.cheb_degree;
+  int rc = build_host(dd, c->h, c->err);  // host-side validation and set-up
   if (rc) {
     *out = c;
     return rc;
+  }
+  if (hipGetDevice(&c->dev) != hipSuccess) {
+    c->err = "no HIP device";
+    *out = c;
+    return SGW_EHIP;
   }
   Host& h = c->h;
   c->P = h.g.P;
@@ -1071,6 +1141,18 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   }
   setup_prec<double>(c, c->d64, false);
   if (dd.precision == SGW_FP32_IR64) setup_prec<float>(c, c->f32, true);
+  if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
+    if (std::max(c->d64.D.max_block_rows, c->d64.N.max_block_rows) > 4096) {
+      c->err = "a subdomain block has more than 4096 rows (Chebyshev preconditioner limit)";
+      *out = c;
+      return SGW_EINVAL;
+    }
+    if (k::cheb_prepare() != 0) {
+      c->err = "hipFuncSetAttribute failed for the Chebyshev kernels";
+      *out = c;
+      return SGW_EHIP;
+    }
+  }
   {
     size_t nv = (size_t)P * h.NF;
     for (double** v : {&c->U, &c->V, &c->A, &c->Um, &c->Uc, &c->Wm, &c->F})
@@ -1102,6 +1184,11 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   co.nk = c->nk;
   for (int s = 0; s < h.nsub; ++s) c->maxc = std::max(c->maxc, h.sc_ptr[s + 1] - h.sc_ptr[s]);
   co.maxc = c->maxc;
+  if ((long long)c->maxc * P > SGW_MAX_COARSE_LOCAL) {
+    c->err = "too many coarse unknowns per subdomain (corners x P above 4096)";
+    *out = c;
+    return SGW_EINVAL;
+  }
   std::vector<std::vector<int>> cl(h.nC);
   for (size_t lc = 0; lc < h.sc_coarse.size(); ++lc) cl[h.sc_coarse[lc]].push_back((int)lc);
   std::vector<int> c_ptr{0}, c_lc;
@@ -1151,6 +1238,13 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   co.phi_off = upload(c, c->phi_off_h);
   c->phi = dalloc<double>(c, (size_t)std::max<long long>(1, c->phi_off_h.back()));
   co.phi = c->phi;
+  if (dd.precision == SGW_FP32_IR64) {
+    c->phif = dalloc<float>(c, (size_t)std::max<long long>(1, c->phi_off_h.back()));
+    co.phif = c->phif;
+  }
+  co.max_rem = 0;
+  for (int s = 0; s < h.nsub; ++s)
+    co.max_rem = std::max(co.max_rem, c->rem_off_h[s + 1] - c->rem_off_h[s]);
   c->dc = dalloc<double>(c, (size_t)std::max(1, h.nC * P));
   c->uc = dalloc<double>(c, (size_t)std::max(1, h.nC * P));
   if (hipHostMalloc((void**)&c->hflags, 16 * sizeof(int)) != hipSuccess) {
@@ -1239,6 +1333,15 @@ int sgw_factor(sgw_ctx* c, void* stream) {
       return SGW_ENOMEM;
     }
     c->co.finv = finv;
+    if (c->phif) {  // the FP32 solver's copy of the coarse basis
+      const long long tot = c->phi_off_h.back();
+      if (tot > 0x7fffffffLL) {
+        c->err = "coarse basis too large for the FP32 copy";
+        return SGW_EINVAL;
+      }
+      k::copy2d<float, double>(1, (int)tot, c->phi, (int)tot, c->phif, (int)tot, 1.0, st);
+      HIPCHK(hipStreamSynchronize(st));
+    }
   }
   c->factored = true;
   return 0;

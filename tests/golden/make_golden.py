@@ -3,7 +3,7 @@
 Calls only ``oracle/`` (and the seeded workload definitions).  For the
 256x256, P = 35 workload it runs the oracle (CG with the mean-matrix
 preconditioner to 1e-14 per step) and stores, at the recorded steps, the mean
-and standard-deviation fields on the sub-grid of every 8th mesh node in each
+and standard-deviation fields on the sub-grid of every 16th mesh node in each
 direction, plus the full-field L2 norms.  Output: cfg2_oracle.txt (text).
 
 Usage: python tests/golden/make_golden.py [nsteps]
@@ -21,7 +21,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import workloads  # noqa: E402
 from oracle.sg import SGProblem  # noqa: E402
 
-STRIDE = 8
+STRIDE = 16
 
 
 def subgrid(n):
@@ -38,7 +38,7 @@ def main():
     out_path = os.path.join(HERE, "cfg2_oracle.txt")
     U, V, A = pr.initial_state()
     lines = ["# oracle reference for cfg2 (256x256, P=35, dt 1e-3), written by make_golden.py",
-             "# sub-grid: mesh nodes (8i, 8j); per recorded step: 'step s norm_mean norm_std'",
+             "# sub-grid: mesh nodes (16i, 16j); per recorded step: 'step s norm_mean norm_std'",
              "# then one line per sub-grid node: 'mean std'"]
     t0 = time.time()
     for s in range(1, nsteps + 1):

@@ -82,3 +82,15 @@ def test_null_arguments(L):
     assert L.sgw_create(None, None, None) == -1
     assert L.sgw_step(None, 1, None, None) == -1
     assert L.sgw_query(None, 0) == -1
+
+
+@pytest.mark.parametrize("field,value", [("inner_prec", 7), ("cheb_degree", 65),
+                                         ("precision", 3)])
+def test_create_rejects_bad_solver_options(L, field, value):
+    d, keep = _desc()
+    setattr(d, field, value)
+    ctx = ctypes.c_void_p()
+    rc = L.sgw_create(ctypes.byref(d), None, ctypes.byref(ctx))
+    assert rc == -1
+    assert "out of range" in L.sgw_last_error(ctx).decode()
+    L.sgw_destroy(ctx)

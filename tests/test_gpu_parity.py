@@ -114,24 +114,38 @@ def test_initial_acceleration_matches_oracle(sgw):
     s.close()
 
 
-def test_cfg1_trajectory_fp64(sgw):
+INNER = [0, 1]  # SGW_INNER_CHOLESKY, SGW_INNER_CHEBYSHEV
+
+
+@pytest.mark.parametrize("inner", INNER)
+def test_cfg1_trajectory_fp64(sgw, inner):
     prm = workloads.config("cfg1")
-    (em, es), stats = _trajectory(sgw, prm, 100, 1e-12)
+    (em, es), stats = _trajectory(sgw, prm, 100, 1e-12, inner_prec=inner)
     assert em < 1e-10 and es < 1e-10, (em, es)
     assert all(st["status"] == 0 for st in stats)
 
 
-def test_uneven_ragged_partition(sgw):
+@pytest.mark.parametrize("inner", INNER)
+def test_uneven_ragged_partition(sgw, inner):
     prm = workloads.config("cfg1", n=37, xsplits=[0, 13, 37], ysplits=[0, 11, 25, 37],
                            x0=0.4, y0=0.6)
-    (em, es), _ = _trajectory(sgw, prm, 20, 1e-12)
+    (em, es), _ = _trajectory(sgw, prm, 20, 1e-12, inner_prec=inner)
     assert em < 1e-10 and es < 1e-10, (em, es)
 
 
-def test_p35_small_mesh(sgw):
+@pytest.mark.parametrize("inner", INNER)
+def test_p35_small_mesh(sgw, inner):
     prm = workloads.config("cfg2", n=64, xsplits=workloads.uniform_splits(64, 4),
                            ysplits=workloads.uniform_splits(64, 4), dt=0.004)
-    (em, es), _ = _trajectory(sgw, prm, 10, 1e-12, every=5)
+    (em, es), _ = _trajectory(sgw, prm, 10, 1e-12, every=5, inner_prec=inner)
+    assert em < 1e-10 and es < 1e-10, (em, es)
+
+
+@pytest.mark.parametrize("deg", [1, 2, 9])
+def test_chebyshev_degrees(sgw, deg):
+    """Any degree gives an SPD preconditioner: the solution is the same."""
+    prm = workloads.config("cfg1")
+    (em, es), _ = _trajectory(sgw, prm, 20, 1e-12, inner_prec=1, cheb_degree=deg)
     assert em < 1e-10 and es < 1e-10, (em, es)
 
 
@@ -201,15 +215,16 @@ def test_sg_apply_fp32_kernel(sgw):
     s.close()
 
 
+@pytest.mark.parametrize("inner", INNER)
 @pytest.mark.parametrize("name,over,nsteps,every", [
     ("cfg1", {}, 100, 10),
     ("cfg2", dict(n=64, xsplits=[0, 16, 32, 48, 64], ysplits=[0, 16, 32, 48, 64], dt=0.004), 10, 5),
 ])
-def test_mixed_precision_trajectory(sgw, name, over, nsteps, every):
-    """FP32 DD-PCG inside FP64 refinement: the benchmark spec's bound 1e-6 on the
-    mean and standard deviation (refinement tolerance 1e-10)."""
+def test_mixed_precision_trajectory(sgw, name, over, nsteps, every, inner):
+    """FP32 DD-PCG inside FP64 refinement: the bound 1e-6 on the mean and
+    standard deviation (refinement tolerance 1e-10)."""
     prm = workloads.config(name, **over)
     (em, es), stats = _trajectory(sgw, prm, nsteps, 1e-10, every=every,
-                                  precision=sgw.SGW_FP32_IR64)
+                                  precision=sgw.SGW_FP32_IR64, inner_prec=inner)
     assert em < 1e-6 and es < 1e-6, (em, es)
     assert all(st["ir_sweeps"] >= st["steps"] for st in stats)
