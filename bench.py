@@ -103,10 +103,10 @@ def solver_settings(precision="mixed"):
         # at ~2e-6 relative error on this path; 1e-9 keeps it below 1e-6
         return dict(precision=sgw.SGW_FP64, guess=sgw.SGW_GUESS_PREV, rtol=1e-9,
                     inner_rtol=1e-12, precond_rtol=1e-4, inner_prec=sgw.SGW_INNER_CHEBYSHEV,
-                    cheb_degree=6)
+                    cheb_degree=8)
     return dict(precision=sgw.SGW_FP32_IR64, guess=sgw.SGW_GUESS_NEWMARK, rtol=1e-8,
                 inner_rtol=1e-11, precond_rtol=1e-4, inner_prec=sgw.SGW_INNER_CHEBYSHEV,
-                cheb_degree=6)
+                cheb_degree=8)
 
 
 def copy_calibration(nbytes=1 << 30, reps=10):

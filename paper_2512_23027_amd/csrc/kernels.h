@@ -69,8 +69,10 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
 // Chebyshev polynomial preconditioner (degree deg, Q modes per workgroup) on
 // the blocks of A's mean matrix; iv[2b], iv[2b+1] = spectral interval of
 // block b.  Writes z and part[b*P + j] = r_j'z_j (part2 = r_j'r_j if not
-// null).  Returns -1 (nothing launched) if Q, deg or the block size is out
-// of range (max_rows <= 4096, Q * max_rows * sizeof(T) <= 150 KiB).
+// null).  With sc != null it first does the PCG stopping test of iteration
+// par (r'r from rrpart, see pcg_test) and skips converged blocks.  Returns
+// -1 (nothing launched) if Q, deg or the block size is out of range
+// (max_rows <= 4096, Q * max_rows * sizeof(T) <= 150 KiB).
 template <typename T>
 size_t cheb_lds_bytes(int max_rows, int Q);
 // Once per process before the first cheb_apply: allows the kernels the full
@@ -79,7 +81,8 @@ int cheb_prepare();
 template <typename T>
 int cheb_apply(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
-               double* part2, hipStream_t st);
+               double* part2, double* sc, int par, double tol2, const double* rrpart,
+               int* flags, hipStream_t st);
 
 // Segmented dot products: partial[b * P + j] = sum_{r in block b} a[j][r] b[j][r]
 // (row_off relative to the vectors; a second vector pair is optional).
@@ -88,20 +91,24 @@ void seg_dot(int nb, const int* row_off, int P, const T* a, int lda,
              const T* b, int ldb, double* partial, const T* c, int ldc,
              const T* d, int ldd, double* partial2, hipStream_t st);
 
-// PCG scalar phase on nb blocks (one workgroup): see kernels.hip.
-void pcg_scalars(int phase, int nb, int P, const double* part,
-                 const double* part2, double* sc, double tol2, double negl,
-                 int* flags, hipStream_t st);
-
-// x += alpha_b p ; r -= alpha_b q ; partial[b*P + j] = ||r_bj||^2
+// Batched block PCG bookkeeping (per-block scalars sc[b*8], parity slots
+// by iteration index, see kernels.hip).
+// start: r'z (part), r'r = b'b (part2), initial stopping test
+void pcg_start(int nb, int P, const double* part, const double* part2, double* sc,
+               double tol2, double negl, int* flags, hipStream_t st);
+// x += alpha_b p ; r -= alpha_b q with alpha_b = r'z / p'q (p'q from part);
+// part2[b*P + j] = ||r_bj||^2
 template <typename T>
-void pcg_xr(int nb, const int* row_off, int P, const double* sc, T* x, int ldx,
-            const T* p, int ldp, T* r, int ldr, const T* q, int ldq,
-            double* partial, hipStream_t st);
-// p = z + beta_b p
+void pcg_xr(int nb, const int* row_off, int P, int par, const double* sc, T* x, int ldx,
+            const T* p, int ldp, T* r, int ldr, const T* q, int ldq, const double* part,
+            double* part2, int* flags, hipStream_t st);
+// stopping test of iteration par from part2 (exact-preconditioner path)
+void pcg_test(int nb, int P, int par, const double* part2, double* sc, double tol2,
+              int* flags, hipStream_t st);
+// p = z + beta_b p with beta_b = (r'z from part) / (previous r'z)
 template <typename T>
-void pcg_p(int nb, const int* row_off, int P, const double* sc, const T* z,
-           int ldz, T* p, int ldp, hipStream_t st);
+void pcg_p(int nb, const int* row_off, int P, int par, double* sc, const double* part,
+           const T* z, int ldz, T* p, int ldp, hipStream_t st);
 
 // strided copies / fills over [P][n] (dst = a*src, optional type change)
 template <typename TD, typename TS>

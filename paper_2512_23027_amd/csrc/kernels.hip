@@ -468,6 +468,20 @@ void seg_dot(int nb, const int* row_off, int P, const T* a, int lda, const T* b,
   k_seg_dot<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, a, lda, b, ldb, partial, c, ldc, d, ldd, partial2);
 }
 
+// ---------------------------------------------------------------------------
+// Batched block PCG bookkeeping.  Every block b of the batch runs its own PCG
+// (own step lengths, own stopping test); the per-block scalars live in
+// sc[b*8 + ...]:
+//   0, 1  r'z of iterations with even / odd index (parity slots)
+//   2, 3  active flag (1.0 / 0.0) of even / odd iterations
+//   4     b'b (squared norm of the right-hand side)
+// Iteration `it` (parity p = it & 1) reads the p slots and writes the 1-p
+// slots, so the workgroups of one block that read a scalar never race with
+// the one that writes its successor.  Partial sums over (block, mode) come
+// from the vector kernels: part = p'q, then r'z; part2 = r'r.
+// flags[0] = number of active blocks after the last test, flags[1] |=
+// breakdown (p'q <= 0 on an active block), flags[2] |= non-finite value.
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ double block_max(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -479,147 +493,162 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return m;
 }
 
-// Per-block scalars of the batched PCG, one workgroup for all blocks.
-// sc[b*8 + ...]: 0 rz, 1 pq, 2 rr, 3 bb, 4 alpha, 5 beta, 6 active,
-// 7 iterations.  flags[0] = active blocks after this phase, flags[1] |=
-// breakdown, flags[2] |= non-finite.
-//   phase 0: rz = sum part, rr = sum part2 (bb = rr when tol2 < 0 is passed
-//            as -tol2); active = bb > negl * max_b bb and rr > tol2 bb, so a
-//            block whose right-hand side is negligible within the batch
-//            (negl > 0) keeps x = 0 -- in FP32 such blocks would underflow
-//   phase 1: pq = sum part; alpha = rz / pq on active blocks (else 0)
-//   phase 2: rr = sum part; active = rr > tol2 bb; iterations++
-//   phase 3: rz' = sum part; beta = rz'/rz; rz = rz'
-//   phase 4: bb = sum part
-__global__ __launch_bounds__(SGW_BLOCK) void k_pcg_scalars(
-    int phase, int nb, int P, const double* part, const double* part2,
-    double* sc, double tol2, double negl, int* flags) {
-  __shared__ int nact, brk, bad;
+__device__ __forceinline__ double sum_modes(const double* part, int b, int P) {
+  double v = 0.0;
+  for (int j = 0; j < P; ++j) v += part[(size_t)b * P + j];
+  return v;
+}
+
+// Start of a solve (x0 = 0, r = b, z = M r): r'z into the even slot, b'b = r'r,
+// active = b'b > negl * max_b b'b and r'r > tol2 b'b.  A block whose
+// right-hand side is negligible within the batch (negl > 0) keeps x = 0 -- in
+// FP32 such blocks would underflow.  One workgroup for all blocks.
+__global__ __launch_bounds__(SGW_BLOCK) void k_pcg_start(int nb, int P, const double* part,
+                                                        const double* part2, double* sc,
+                                                        double tol2, double negl, int* flags) {
+  __shared__ int nact, bad;
   __shared__ double shm[SGW_BLOCK / 64];
   if (threadIdx.x == 0) {
     nact = 0;
-    brk = 0;
     bad = 0;
   }
   __syncthreads();
-  bool set_bb = tol2 < 0.0;
-  double t2 = set_bb ? -tol2 : tol2;
-  double floor_bb = 0.0;
-  if (phase == 0) {
-    double m = 0.0;
-    for (int b = threadIdx.x; b < nb; b += SGW_BLOCK) {
-      double v = 0.0, v2 = 0.0;
-      for (int j = 0; j < P; ++j) v += part[b * P + j];
-      if (part2)
-        for (int j = 0; j < P; ++j) v2 += part2[b * P + j];
-      double* s = sc + b * 8;
-      s[0] = v;
-      s[2] = v2;
-      if (set_bb) s[3] = v2;
-      s[7] = 0.0;
-      if (!isfinite(v) || !isfinite(v2)) atomicOr(&bad, 1);
-      if (isfinite(s[3])) m = fmax(m, s[3]);
-    }
-    floor_bb = negl * block_max(m, shm);
-  }
+  double m = 0.0;
   for (int b = threadIdx.x; b < nb; b += SGW_BLOCK) {
-    double* s = sc + b * 8;
-    int act = s[6] != 0.0;
-    if (phase == 0) {
-      act = (s[3] > floor_bb) && (s[2] > t2 * s[3]);
-    } else {
-      double v = 0.0;
-      for (int j = 0; j < P; ++j) v += part[b * P + j];
-      if (!isfinite(v)) atomicOr(&bad, 1);
-      if (phase == 1) {
-        s[1] = v;
-        if (act && !(v > 0.0)) {
-          atomicOr(&brk, 1);
-          act = 0;
-        }
-        s[4] = act ? s[0] / v : 0.0;
-      } else if (phase == 2) {
-        s[2] = v;
-        if (act) s[7] += 1.0;
-        act = act && (v > t2 * s[3]);
-      } else if (phase == 3) {
-        s[5] = act ? v / s[0] : 0.0;
-        s[0] = v;
-      } else if (phase == 4) {
-        s[3] = v;
-      }
-    }
-    s[6] = act ? 1.0 : 0.0;
+    const double rz = sum_modes(part, b, P), rr = sum_modes(part2, b, P);
+    double* s = sc + (size_t)b * 8;
+    s[0] = rz;
+    s[4] = rr;
+    if (!isfinite(rz) || !isfinite(rr)) atomicOr(&bad, 1);
+    if (isfinite(rr)) m = fmax(m, rr);
+  }
+  const double floor_bb = negl * block_max(m, shm);
+  for (int b = threadIdx.x; b < nb; b += SGW_BLOCK) {
+    double* s = sc + (size_t)b * 8;
+    const bool act = s[4] > floor_bb && s[4] > tol2 * s[4] && s[4] > 0.0;
+    s[2] = act ? 1.0 : 0.0;
     if (act) atomicAdd(&nact, 1);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     flags[0] = nact;
-    if (phase == 0) {  // a new solve starts with clean error flags
-      flags[1] = brk;
-      flags[2] = bad;
-    } else {
-      if (brk) flags[1] = 1;
-      if (bad) flags[2] = 1;
-    }
+    flags[1] = 0;
+    flags[2] = bad;
   }
 }
 
-void pcg_scalars(int phase, int nb, int P, const double* part, const double* part2,
-                 double* sc, double tol2, double negl, int* flags, hipStream_t st) {
-  k_pcg_scalars<<<1, SGW_BLOCK, 0, st>>>(phase, nb, P, part, part2, sc, tol2, negl, flags);
+void pcg_start(int nb, int P, const double* part, const double* part2, double* sc, double tol2,
+               double negl, int* flags, hipStream_t st) {
+  k_pcg_start<<<1, SGW_BLOCK, 0, st>>>(nb, P, part, part2, sc, tol2, negl, flags);
 }
 
+// x += alpha p, r -= alpha q on the active blocks, alpha = r'z / p'q of the
+// block (p'q summed from part); writes part2 = r'r per (block, mode) for every
+// block.  Workgroup (0, 0) clears the active counter for the test that follows.
 template <typename T>
 __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
-    const int* row_off, int P, const double* sc, T* x, int ldx, const T* p, int ldp,
-    T* r, int ldr, const T* q, int ldq, double* part) {
+    const int* row_off, int P, int par, const double* sc, T* x, int ldx, const T* p, int ldp,
+    T* r, int ldr, const T* q, int ldq, const double* part, double* part2, int* flags) {
   __shared__ double sh[SGW_BLOCK / 64];
   const int blk = blockIdx.x, j = blockIdx.y;
   const int r0 = row_off[blk], r1 = row_off[blk + 1];
-  const T al = (T)sc[blk * 8 + 4];
-  double s = 0.0;
+  const double* s = sc + (size_t)blk * 8;
+  const bool act = s[2 + par] != 0.0;
+  double al = 0.0;
+  if (act) {
+    const double pq = sum_modes(part, blk, P);
+    if (pq > 0.0) {
+      al = s[par] / pq;
+    } else if (j == 0 && threadIdx.x == 0) {
+      if (isfinite(pq)) atomicOr(&flags[1], 1);
+      else atomicOr(&flags[2], 1);
+    }
+  }
+  if (blk == 0 && j == 0 && threadIdx.x == 0) flags[0] = 0;
+  const T alt = (T)al;
+  double acc = 0.0;
   T* xp = x + (size_t)j * ldx;
   T* rp = r + (size_t)j * ldr;
   const T* pp = p + (size_t)j * ldp;
   const T* qp = q + (size_t)j * ldq;
   for (int i = r0 + threadIdx.x; i < r1; i += SGW_BLOCK) {
     T rv = rp[i];
-    if (al != T(0)) {
-      xp[i] = fmadd(al, pp[i], xp[i]);
-      rv = fmadd(-al, qp[i], rv);
+    if (al != 0.0) {
+      xp[i] = fmadd(alt, pp[i], xp[i]);
+      rv = fmadd(-alt, qp[i], rv);
       rp[i] = rv;
     }
-    s += (double)rv * (double)rv;
+    acc += (double)rv * (double)rv;
   }
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[blk * P + j] = s;
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part2[(size_t)blk * P + j] = acc;
 }
 
 template <typename T>
-void pcg_xr(int nb, const int* row_off, int P, const double* sc, T* x, int ldx,
-            const T* p, int ldp, T* r, int ldr, const T* q, int ldq,
-            double* partial, hipStream_t st) {
-  k_pcg_xr<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, sc, x, ldx, p, ldp, r, ldr, q, ldq, partial);
+void pcg_xr(int nb, const int* row_off, int P, int par, const double* sc, T* x, int ldx,
+            const T* p, int ldp, T* r, int ldr, const T* q, int ldq, const double* part,
+            double* part2, int* flags, hipStream_t st) {
+  k_pcg_xr<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, par, sc, x, ldx, p, ldp, r, ldr,
+                                                 q, ldq, part, part2, flags);
 }
 
+// Stopping test of iteration par (used with the exact preconditioner; the
+// Chebyshev kernel does the same test itself): active' = active and
+// r'r > tol2 b'b, written to the other parity slot and counted in flags[0].
+__global__ __launch_bounds__(SGW_BLOCK) void k_pcg_test(int nb, int P, int par,
+                                                       const double* part2, double* sc,
+                                                       double tol2, int* flags) {
+  __shared__ int nact, bad;
+  if (threadIdx.x == 0) {
+    nact = 0;
+    bad = 0;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += SGW_BLOCK) {
+    double* s = sc + (size_t)b * 8;
+    const double rr = sum_modes(part2, b, P);
+    if (!isfinite(rr)) atomicOr(&bad, 1);
+    const bool act = s[2 + par] != 0.0 && rr > tol2 * s[4];
+    s[3 - par] = act ? 1.0 : 0.0;
+    if (act) atomicAdd(&nact, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    flags[0] = nact;
+    if (bad) flags[2] = 1;
+  }
+}
+
+void pcg_test(int nb, int P, int par, const double* part2, double* sc, double tol2, int* flags,
+              hipStream_t st) {
+  k_pcg_test<<<1, SGW_BLOCK, 0, st>>>(nb, P, par, part2, sc, tol2, flags);
+}
+
+// p = z + beta p on the blocks still active after the test of iteration par,
+// beta = (new r'z from part) / (old r'z); workgroup (b, 0) stores the new r'z
+// in the other parity slot.
 template <typename T>
-__global__ __launch_bounds__(SGW_BLOCK) void k_pcg_p(const int* row_off, const double* sc,
-                                                    const T* z, int ldz, T* p, int ldp) {
+__global__ __launch_bounds__(SGW_BLOCK) void k_pcg_p(const int* row_off, int P, int par,
+                                                    double* sc, const double* part, const T* z,
+                                                    int ldz, T* p, int ldp) {
   const int blk = blockIdx.x, j = blockIdx.y;
+  double* s = sc + (size_t)blk * 8;
+  if (s[3 - par] == 0.0) return;
+  const double rz = sum_modes(part, blk, P);
+  const T be = (T)(rz / s[par]);
+  if (j == 0 && threadIdx.x == 0) s[1 - par] = rz;
   const int r0 = row_off[blk], r1 = row_off[blk + 1];
-  if (sc[blk * 8 + 6] == 0.0) return;
-  const T be = (T)sc[blk * 8 + 5];
   const T* zp = z + (size_t)j * ldz;
   T* pp = p + (size_t)j * ldp;
   for (int i = r0 + threadIdx.x; i < r1; i += SGW_BLOCK) pp[i] = fmadd(be, pp[i], zp[i]);
 }
 
 template <typename T>
-void pcg_p(int nb, const int* row_off, int P, const double* sc, const T* z, int ldz,
-           T* p, int ldp, hipStream_t st) {
-  k_pcg_p<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, sc, z, ldz, p, ldp);
+void pcg_p(int nb, const int* row_off, int P, int par, double* sc, const double* part,
+           const T* z, int ldz, T* p, int ldp, hipStream_t st) {
+  k_pcg_p<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, par, sc, part, z, ldz, p, ldp);
 }
+
 
 // ---------------------------------------------------------------------------
 // Elementwise helpers over mode-major [P][n] arrays.
@@ -770,13 +799,24 @@ template <typename T, int Q, int RPT>
 __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     DEll<T> A, const int* __restrict__ row_off, const double* __restrict__ iv, int P, int deg,
     const T* __restrict__ r, int ldr, T* __restrict__ z, int ldz, double* __restrict__ part,
-    double* __restrict__ part2) {
+    double* __restrict__ part2, double* sc, int par, double tol2, const double* rrpart,
+    int* flags) {
   // all LDS is dynamic (so the launch may use up to the whole 160 KiB):
   // the reduction slots, then the current search direction [Q][n]
   extern __shared__ unsigned char smem_raw[];
   double(*red)[CHEB_TPB / 64][Q] = reinterpret_cast<double(*)[CHEB_TPB / 64][Q]>(smem_raw);
   T* Dk = reinterpret_cast<T*>(smem_raw + sizeof(double) * 2 * (CHEB_TPB / 64) * Q);
   const int b = blockIdx.x, j0 = blockIdx.y * Q;
+  if (sc) {  // stopping test of PCG iteration par, fused (see k_pcg_test)
+    const double rr = sum_modes(rrpart, b, P);
+    const bool act = sc[(size_t)b * 8 + 2 + par] != 0.0 && rr > tol2 * sc[(size_t)b * 8 + 4];
+    if (blockIdx.y == 0 && threadIdx.x == 0) {
+      sc[(size_t)b * 8 + 3 - par] = act ? 1.0 : 0.0;
+      if (act) atomicAdd(&flags[0], 1);
+      if (!isfinite(rr)) atomicOr(&flags[2], 1);
+    }
+    if (!act) return;  // converged block: its z and r'z are not used again
+  }
   const int r0 = row_off[b], n = row_off[b + 1] - r0;
   const int NR = A.nrows;
   const double lo = iv[2 * b], hi = iv[2 * b + 1];
@@ -885,24 +925,33 @@ size_t cheb_lds_bytes(int max_rows, int Q) {
   return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + (size_t)max_rows * Q * sizeof(T);
 }
 
+struct ChebTest {  // optional fused stopping test (sc == nullptr: none)
+  double* sc;
+  int par;
+  double tol2;
+  const double* rrpart;
+  int* flags;
+};
+
 template <typename T, int Q, int RPT>
 static void launch_cheb(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P,
                         int deg, int max_rows, const T* r, int ldr, T* z, int ldz,
-                        double* part, double* part2, hipStream_t st) {
+                        double* part, double* part2, const ChebTest& t, hipStream_t st) {
   dim3 grid(nb, ceil_div(P, Q));
   k_cheb<T, Q, RPT><<<grid, CHEB_TPB, cheb_lds_bytes<T>(max_rows, Q), st>>>(
-      A, row_off, iv, P, deg, r, ldr, z, ldz, part, part2);
+      A, row_off, iv, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par, t.tol2, t.rrpart,
+      t.flags);
 }
 
 template <typename T, int RPT>
 static void cheb_q(int Q, const DEll<T>& A, const int* row_off, const double* iv, int nb, int P,
                    int deg, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
-                   double* part2, hipStream_t st) {
+                   double* part2, const ChebTest& t, hipStream_t st) {
   switch (Q) {
 #define SGW_CHEB_CASE(q)                                                                      \
   case q:                                                                                    \
     launch_cheb<T, q, RPT>(A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, \
-                           st);                                                              \
+                           t, st);                                                           \
     break;
     SGW_CHEB_CASE(1)
     SGW_CHEB_CASE(2)
@@ -947,16 +996,18 @@ int cheb_prepare() {
 template <typename T>
 int cheb_apply(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
-               double* part2, hipStream_t st) {
+               double* part2, double* sc, int par, double tol2, const double* rrpart,
+               int* flags, hipStream_t st) {
   if (Q < 1 || Q > 8 || deg < 1 || max_rows < 1 || max_rows > 4 * CHEB_TPB ||
-      cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024)
+      cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024 || (sc && (!rrpart || !flags)))
     return -1;
+  const ChebTest t{sc, par, tol2, rrpart, flags};
   if (max_rows <= CHEB_TPB)
-    cheb_q<T, 1>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, st);
+    cheb_q<T, 1>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, t, st);
   else if (max_rows <= 2 * CHEB_TPB)
-    cheb_q<T, 2>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, st);
+    cheb_q<T, 2>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, t, st);
   else
-    cheb_q<T, 4>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, st);
+    cheb_q<T, 4>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, t, st);
   return 0;
 }
 
@@ -1063,10 +1114,10 @@ template size_t cheb_lds_bytes<double>(int, int);
 template size_t cheb_lds_bytes<float>(int, int);
 template int cheb_apply<double>(const DEll<double>&, const int*, const double*, int, int, int,
                                 int, int, const double*, int, double*, int, double*, double*,
-                                hipStream_t);
+                                double*, int, double, const double*, int*, hipStream_t);
 template int cheb_apply<float>(const DEll<float>&, const int*, const double*, int, int, int,
                                int, int, const float*, int, float*, int, double*, double*,
-                               hipStream_t);
+                               double*, int, double, const double*, int*, hipStream_t);
 template size_t tri_lds_bytes<float>(const DFactor&, int);
 #define SGW_INST(T)                                                                          \
   template void sg_apply<T>(const DEll<T>&, const GTab&, int, int, const T*, int, T*, int, T, \
@@ -1077,10 +1128,11 @@ template size_t tri_lds_bytes<float>(const DFactor&, int);
                              long long, hipStream_t);                                        \
   template void seg_dot<T>(int, const int*, int, const T*, int, const T*, int, double*,     \
                            const T*, int, const T*, int, double*, hipStream_t);             \
-  template void pcg_xr<T>(int, const int*, int, const double*, T*, int, const T*, int, T*,  \
-                          int, const T*, int, double*, hipStream_t);                         \
-  template void pcg_p<T>(int, const int*, int, const double*, const T*, int, T*, int,       \
-                         hipStream_t);                                                       \
+  template void pcg_xr<T>(int, const int*, int, int, const double*, T*, int, const T*, int, \
+                          T*, int, const T*, int, const double*, double*, int*,            \
+                          hipStream_t);                                                      \
+  template void pcg_p<T>(int, const int*, int, int, double*, const double*, const T*, int,  \
+                         T*, int, hipStream_t);                                              \
   template void fill2d<T>(int, int, T*, int, T, hipStream_t);                               \
   template void axpby2d<T>(int, int, double, const T*, int, double, const T*, int, T*, int, \
                            hipStream_t);                                                     \

@@ -320,18 +320,23 @@ static void K3(sgw_ctx* c, SysT<T>& S, bool neumann, const T* rhs, int ldr, T* o
 // [P][nrows] vectors r, z, followed by the partial sums part[b*P + j] =
 // r_j'z_j (and part2 = r_j'r_j if not null).  Exact (K3 + K4) or Chebyshev
 // (K3c, one fused launch; algorithmic bytes: r in, z out, the mean
-// matrix's values and column indices).
+// matrix's values and column indices).  test_par >= 0 first runs the PCG
+// stopping test of that iteration (fused into K3c, which then skips the
+// converged blocks).
 template <typename T>
 static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, double* part2,
-                        hipStream_t st) {
+                        int test_par, double tol2, hipStream_t st) {
   const int P = c->P, n = S.nrows;
   if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
     int a = prof_begin(c, 2, st);
     (void)k::cheb_apply<T>(S.A, S.row_off, S.cheb_iv, S.nb, P, c->cheb_deg, S.cq,
-                           S.max_block_rows, S.r, n, S.z, n, part, part2, st);
+                           S.max_block_rows, S.r, n, S.z, n, part, part2,
+                           test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
+                           c->part2, c->flags, st);
     prof_end(c, a, 2, 2.0 * sizeof(T) * P * n + 7.0 * (sizeof(T) + 4.0) * n, st);
     return;
   }
+  if (test_par >= 0) k::pcg_test(S.nb, P, test_par, c->part2, c->sc, tol2, c->flags, st);
   K3<T>(c, S, neumann, S.r, n, S.z, n, st);
   k::seg_dot<T>(S.nb, S.row_off, P, S.r, n, S.z, n, part, part2 ? S.r : nullptr, n,
                 part2 ? S.r : nullptr, n, part2, st);
@@ -339,11 +344,13 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
 
 // ---------------------------------------------------------------------------
 // H8: batched subdomain SG solves.  PCG per block with x0 = 0 and the
-// preconditioner I_P (x) (L L^T)^{-1}; stops when every block has
-// ||r_s|| <= tol ||b_s||.  Converged blocks are frozen (alpha = 0).  The
-// iteration count of the previous solve of the same system and tolerance
-// class tells the host when to start checking convergence: extra iterations
-// of frozen blocks change nothing.
+// preconditioner I_P (x) (K~_0^s)^{-1} (exact or Chebyshev); block b stops
+// when ||r_b|| <= tol ||b_b||, converged blocks are frozen (alpha = 0).  Per
+// iteration: SG apply (K1), p'q partial sums (K4), x/r update with the step
+// lengths computed in place, preconditioner with the stopping test, p update
+// with beta computed in place.  The iteration count of the previous solve of
+// the same system and tolerance class tells the host when to start reading
+// the active count: extra iterations of frozen blocks change nothing.
 // ---------------------------------------------------------------------------
 // Relative size (squared norms) below which a block's right-hand side is
 // negligible within its batch: FP64 solves every nonzero block, FP32 leaves
@@ -355,30 +362,35 @@ template <typename T>
 static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb, T* out,
                        int ldo, double tol, int maxit, hipStream_t st) {
   const int P = c->P, n = S.nrows, nb = S.nb;
+  const double tol2 = tol * tol;
   int& predicted = S.last_its[tol >= S.loose_tol ? 1 : 0];
   k::copy2d<T, T>(P, n, b, ldb, S.r, n, 1.0, st);
   k::fill2d<T>(P, n, S.x, n, T(0), st);
-  precond_dot<T>(c, S, neumann, c->part, c->part2, st);
+  precond_dot<T>(c, S, neumann, c->part, c->part2, -1, 0.0, st);
   k::copy2d<T, T>(P, n, S.z, n, S.p, n, 1.0, st);
-  k::pcg_scalars(0, nb, P, c->part, c->part2, c->sc, -(tol * tol), NegligibleBlock<T>::value,
-                 c->flags, st);
+  k::pcg_start(nb, P, c->part, c->part2, c->sc, tol2, NegligibleBlock<T>::value, c->flags, st);
   int it = 0, rc = 0;
   int nact = 1;
   if (predicted <= 1) {
     HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     nact = c->hflags[0];
+    if (c->hflags[2]) {
+      c->err = "non-finite residual in a subdomain solve";
+      return SGW_ENAN;
+    }
   }
   while (nact > 0) {
     if (it >= maxit) {
       rc = SGW_NOT_CONVERGED;
       break;
     }
+    const int par = it & 1;
     K1<T>(c, S.A, 0, n, S.p, n, S.q, n, 1.0, 0.0, st);
     k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
-    k::pcg_scalars(1, nb, P, c->part, nullptr, c->sc, tol * tol, 0.0, c->flags, st);
-    k::pcg_xr<T>(nb, S.row_off, P, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part, st);
-    k::pcg_scalars(2, nb, P, c->part, nullptr, c->sc, tol * tol, 0.0, c->flags, st);
+    k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part,
+                 c->part2, c->flags, st);
+    precond_dot<T>(c, S, neumann, c->part, nullptr, par, tol2, st);
     ++it;
     if (it + 1 >= predicted || it >= maxit) {
       HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -395,9 +407,7 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
       }
       if (nact == 0) break;
     }
-    precond_dot<T>(c, S, neumann, c->part, nullptr, st);
-    k::pcg_scalars(3, nb, P, c->part, nullptr, c->sc, tol * tol, 0.0, c->flags, st);
-    k::pcg_p<T>(nb, S.row_off, P, c->sc, S.z, n, S.p, n, st);
+    k::pcg_p<T>(nb, S.row_off, P, par, c->sc, c->part, S.z, n, S.p, n, st);
   }
   k::copy2d<T, T>(P, n, S.x, n, out, ldo, 1.0, st);
   predicted = it;
@@ -1010,7 +1020,7 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
         double us = time_it([&] {
           (void)k::cheb_apply<T>(S.A, S.row_off, S.cheb_iv, S.nb, c->P, c->cheb_deg, q,
                                  S.max_block_rows, S.r, S.nrows, S.z, S.nrows, c->part,
-                                 c->part2, st);
+                                 c->part2, nullptr, 0, 0.0, nullptr, nullptr, st);
         });
         rep[cheb + q - 1] = us;
         if (us < best) {
