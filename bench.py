@@ -41,15 +41,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SG-DD-PCG time-steps/s at ≤1e-6 rel err vs FP64 oracle; PCG iters/step; GB/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {0: "k_sg_apply (SG operator apply, K1)",
-                1: "k_tri_solve (batched supernodal triangular solves, K3)",
-                2: "k_cheb (Chebyshev subdomain preconditioner, K3c)"}
+KERNEL_NAMES = {0: "k1 SG operator apply, FP64 (K1)",
+                1: "k_tri_solve batched supernodal triangular solves, FP64 (K3)",
+                2: "k_cheb Chebyshev subdomain preconditioner, FP64 (K3c)",
+                3: "k1 SG operator apply, FP32 (K1)",
+                4: "k_tri_solve batched supernodal triangular solves, FP32 (K3)",
+                5: "k_cheb Chebyshev subdomain preconditioner, FP32 (K3c)"}
+PROFILE_EVERY = 5    # time every 5th launch of each kind (event records cost time)
+
+
+KERNEL_SOURCES = {0: ("k1_spec.inc",), 3: ("k1_spec.inc",)}  # others: kernels.hip
+
+
+def kernel_sources_digest(kernel_kind):
+    """sha256 over the source file(s) of a kernel kind (the generated SG-apply
+    kernels, or kernels.hip): HBM counters recorded for other sources are
+    stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES.get(kernel_kind, ("kernels.hip",)):
+        h.update(open(os.path.join(ROOT, "paper_2512_23027_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def traffic_from_profiles(kernel_kind):
     """HBM bytes per launch measured by rocprofv3 counters, if recorded for
-    the current kernel source (profiles/traffic_*.txt), else None."""
-    import hashlib
+    the current kernel sources (profiles/traffic_*.txt), else None."""
     path = os.path.join(ROOT, "profiles", "traffic_k%d_cfg2.txt" % kernel_kind)
     if not os.path.exists(path):
         return None
@@ -58,8 +75,7 @@ def traffic_from_profiles(kernel_kind):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    src = open(os.path.join(ROOT, "paper_2512_23027_amd", "csrc", "kernels.hip"), "rb").read()
-    if vals.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+    if vals.get("kernel_sources_sha256") != kernel_sources_digest(kernel_kind):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -143,13 +159,17 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--print-kernel-digest", type=int, default=None, metavar="KIND")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.print_kernel_digest is not None:
+        print(kernel_sources_digest(args.print_kernel_digest))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the domain decomposition would shard by subdomain blocks; see DESIGN.md)",
+              "(the domain decomposition would shard by blocks of subdomains)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -184,12 +204,12 @@ def main():
         if e:
             errors.append(e)
     torch.cuda.synchronize()
-    s.profile(True)
+    s.profile(True, every=PROFILE_EVERY)
     t1 = time.perf_counter()
     st = s.step(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
-    prof = {k: s.profile_read(k) for k in (0, 1, 2)}
+    prof = {k: s.profile_read(k) for k in range(6)}
     s.profile(False)
     e = golden_errors(warm + args.steps, *moments())
     if e:
@@ -230,11 +250,14 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "launches": n_l, "avg_launch_us": 1e3 * ms / max(n_l, 1),
+                     "timed_launches": n_l, "avg_launch_us": 1e3 * ms / max(n_l, 1),
                      "algorithmic_bytes_per_launch": nbytes / max(n_l, 1)},
-        "kernels": {KERNEL_NAMES[k]: {"launches": v[0], "ms": v[1],
-                                      "GB/s": (v[2] / (v[1] * 1e-3)) / 1e9 if v[1] > 0 else 0}
-                    for k, v in prof.items()},
+        "kernels": {KERNEL_NAMES[k]: {"timed_launches": v[0], "ms": v[1],
+                                      "avg_launch_us": 1e3 * v[1] / v[0],
+                                      "GB/s": (v[2] / (v[1] * 1e-3)) / 1e9}
+                    for k, v in prof.items() if v[0] > 0},
+        "kernel_timing": "HIP events around every %dth launch of each kind in the timed steps"
+                         % PROFILE_EVERY,
     }
     if not args.no_cpu_baseline:
         cb, m_or, s_or = cpu_baseline(prm, 3, record=2)

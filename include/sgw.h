@@ -167,15 +167,16 @@ int sgw_apply_operator(sgw_ctx* ctx, const double* X, double* Y,
 int sgw_solve(sgw_ctx* ctx, const double* F, double* U, void* stream,
               sgw_step_stats* stats);
 
-/* Kernel timing (tracing).  enable != 0 records a HIP event pair around
- * every launch of the SG operator apply (kind 0), of the batched subdomain
- * triangular solves (kind 1) and of the Chebyshev preconditioner (kind 2)
- * on the launch stream, and clears the counters; enable == 0 stops
- * recording.  Adds two event records per timed launch. */
+/* Kernel timing (tracing).  enable = n > 0 records a HIP event pair on the
+ * launch stream around every n-th launch of each kind: the SG operator
+ * apply (kind 0), the batched subdomain triangular solves (kind 1) and the
+ * Chebyshev preconditioner (kind 2) in FP64, kinds 3, 4, 5 the same in
+ * FP32; it clears the counters.  enable == 0 stops recording.  Adds two
+ * event records per timed launch. */
 int sgw_profile(sgw_ctx* ctx, int enable);
 
-/* Launches, total kernel milliseconds and total algorithmic bytes of a kind
- * since the last sgw_profile call.  Bytes per SG-apply row:
+/* Timed launches, their total kernel milliseconds and total algorithmic
+ * bytes for one kind (0..5) since the last sgw_profile call.  Bytes per SG-apply row:
  * 7 (M+1) values + 7 column indices + P inputs + P outputs (+ P when the
  * output is accumulated), 8-byte values (4-byte in FP32 launches); per
  * triangular-solve launch: the right-hand sides in and out plus the

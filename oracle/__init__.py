@@ -23,7 +23,7 @@ stochastic Galerkin (SG) system, with no domain decomposition at all:
 
 Everything is float64.  Every function cites the passage it follows.
 Pins that tie this code to the paper and to mathematics live in
-``tests/test_oracle_*.py``.  Parity unpinned: none.
+``tests/test_oracle_*.py``.  Parity unpinned: none (every function has a pin).
 """
 
 from .pce import multi_indices, pce_size, he_triple, galerkin_tensor  # noqa: F401

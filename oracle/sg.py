@@ -16,8 +16,8 @@ SG matrix, factored once since K~ does not change in time) or by conjugate
 gradients preconditioned with I_P (x) K~_0^{-1} to a relative residual of
 1e-14.  The readings for a_0 (solved from M a_0 = f_0 - C v_0 - K u_0), the
 pulse width (alpha = width^2) and the output moments (mean = mode 0,
-variance = sum of squares of modes >= 1 in the normalised basis) are listed
-with all other readings in the design doc.
+variance = sum of squares of modes >= 1 in the normalised basis) are
+readings of points the paper leaves open.
 
 Vectors are numpy arrays of shape (N_free, P): row = free node, column = PCE
 mode.

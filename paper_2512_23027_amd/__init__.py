@@ -249,7 +249,7 @@ class Solver:
     def profile_read(self, kind):
         """(launches, ms, algorithmic bytes) of the timed launches of kind
         0 = SG apply, 1 = subdomain triangular solves, 2 = Chebyshev
-        preconditioner."""
+        preconditioner, all FP64; 3, 4, 5 = the same in FP32."""
         n, ms, b = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
         self._check(lib().sgw_profile_read(self.ctx, kind, ctypes.byref(n), ctypes.byref(ms),
                                            ctypes.byref(b)), "sgw_profile_read")

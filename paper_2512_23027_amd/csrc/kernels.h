@@ -72,9 +72,12 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
 // null).  With sc != null it first does the PCG stopping test of iteration
 // par (r'r from rrpart, see pcg_test) and skips converged blocks.  Returns
 // -1 (nothing launched) if Q, deg or the block size is out of range
-// (max_rows <= 4096, Q * max_rows * sizeof(T) <= 150 KiB).
+// (max_rows <= 4096, Q <= cheb_max_q, Q * max_rows * sizeof(T) <= 150 KiB).
 template <typename T>
 size_t cheb_lds_bytes(int max_rows, int Q);
+// largest mode tile cheb_apply accepts for blocks of up to max_rows rows
+template <typename T>
+int cheb_max_q(int max_rows);
 // Once per process before the first cheb_apply: allows the kernels the full
 // 160 KiB of LDS.  0 on success, -1 on a HIP error.
 int cheb_prepare();

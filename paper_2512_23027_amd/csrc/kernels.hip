@@ -993,13 +993,25 @@ int cheb_prepare() {
   return ok ? 0 : -1;
 }
 
+// Largest mode tile that keeps the per-thread arrays (3 x RPT x Q values
+// plus the matrix row) in registers under the 1024-thread launch bound:
+// larger tiles spill to scratch memory (measured: up to 400 MB of scratch
+// traffic per launch).
+template <typename T>
+int cheb_max_q(int max_rows) {
+  const int rpt = (max_rows + CHEB_TPB - 1) / CHEB_TPB;
+  if (sizeof(T) == 8) return rpt <= 1 ? 6 : (rpt <= 2 ? 2 : 1);
+  return rpt <= 1 ? 8 : (rpt <= 2 ? 4 : 2);
+}
+
 template <typename T>
 int cheb_apply(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                double* part2, double* sc, int par, double tol2, const double* rrpart,
                int* flags, hipStream_t st) {
-  if (Q < 1 || Q > 8 || deg < 1 || max_rows < 1 || max_rows > 4 * CHEB_TPB ||
-      cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024 || (sc && (!rrpart || !flags)))
+  if (Q < 1 || Q > cheb_max_q<T>(max_rows) || deg < 1 || max_rows < 1 ||
+      max_rows > 4 * CHEB_TPB || cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024 ||
+      (sc && (!rrpart || !flags)))
     return -1;
   const ChebTest t{sc, par, tol2, rrpart, flags};
   if (max_rows <= CHEB_TPB)
@@ -1111,6 +1123,8 @@ void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt, h
 // explicit instantiations
 template size_t tri_lds_bytes<double>(const DFactor&, int);
 template size_t cheb_lds_bytes<double>(int, int);
+template int cheb_max_q<double>(int);
+template int cheb_max_q<float>(int);
 template size_t cheb_lds_bytes<float>(int, int);
 template int cheb_apply<double>(const DEll<double>&, const int*, const double*, int, int, int,
                                 int, int, const double*, int, double*, int, double*, double*,

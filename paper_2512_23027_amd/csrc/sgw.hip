@@ -103,16 +103,17 @@ struct sgw_ctx {
   bool factored = false, has_state = false;
   long long stepno = 0;
   // kernel timing: event pairs around SG-apply (kind 0), triangular-solve
-  // (kind 1) and Chebyshev (kind 2) launches, every prof_every-th launch of
-  // a kind; launches, milliseconds and algorithmic bytes per kind
+  // (kind 1) and Chebyshev (kind 2) launches in FP64 (kinds 3-5: the same in
+  // FP32), every prof_every-th launch of a kind; launches, milliseconds and
+  // algorithmic bytes per kind
   bool prof = false;
   int prof_every = 1;
-  long long pseen[3] = {0, 0, 0};
+  long long pseen[6] = {0, 0, 0, 0, 0, 0};
   std::vector<hipEvent_t> ev;
   struct Pend { int a, kind; double bytes; };
   std::vector<Pend> pend;
-  long long pcnt[3] = {0, 0, 0};
-  double pms[3] = {0, 0, 0}, pbytes[3] = {0, 0, 0};
+  long long pcnt[6] = {0, 0, 0, 0, 0, 0};
+  double pms[6] = {0, 0, 0, 0, 0, 0}, pbytes[6] = {0, 0, 0, 0, 0, 0};
   // subdomain preconditioner: SGW_INNER_* and the Chebyshev degree
   int inner_prec = SGW_INNER_CHOLESKY, cheb_deg = 4;
   double factor_bytes_D = 0, factor_bytes_N = 0;
@@ -299,21 +300,23 @@ static void prof_harvest(sgw_ctx* c) {
 template <typename T>
 static void K1(sgw_ctx* c, const k::DEll<T>& A, int r0, int nrows, const T* x, int ldx, T* y,
                int ldy, double alpha, double beta, hipStream_t st) {
-  int a = prof_begin(c, 0, st);
+  const int kind = sizeof(T) == 4 ? 3 : 0;
+  int a = prof_begin(c, kind, st);
   k::sg_apply<T>(A, c->gt, r0, nrows, x, ldx, y, ldy, (T)alpha, (T)beta, 1, 0, 0, st);
   const double w = sizeof(T);
   double per_row = 7.0 * c->nk * w + 7.0 * 4.0 + 2.0 * c->P * w + (beta != 0.0 ? c->P * w : 0.0);
-  prof_end(c, a, 0, per_row * nrows, st);
+  prof_end(c, a, kind, per_row * nrows, st);
 }
 
 // K3 wrapper: algorithmic bytes = right-hand sides in and out + the factor.
 template <typename T>
 static void K3(sgw_ctx* c, SysT<T>& S, bool neumann, const T* rhs, int ldr, T* out, int ldo,
                hipStream_t st) {
-  int a = prof_begin(c, 1, st);
+  const int kind = sizeof(T) == 4 ? 4 : 1;
+  int a = prof_begin(c, kind, st);
   k::tri_solve<T>(S.F, S.Q, rhs, ldr, out, ldo, 1, 0, 0, st);
   double fb = (neumann ? c->factor_bytes_N : c->factor_bytes_D) * (sizeof(T) / 8.0);
-  prof_end(c, a, 1, 2.0 * sizeof(T) * c->P * S.nrows + fb, st);
+  prof_end(c, a, kind, 2.0 * sizeof(T) * c->P * S.nrows + fb, st);
 }
 
 // Subdomain preconditioner z = (I_P (x) (K~_0^s)^{-1}) r on the system's
@@ -328,12 +331,13 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
                         int test_par, double tol2, hipStream_t st) {
   const int P = c->P, n = S.nrows;
   if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
-    int a = prof_begin(c, 2, st);
+    const int kind = sizeof(T) == 4 ? 5 : 2;
+    int a = prof_begin(c, kind, st);
     (void)k::cheb_apply<T>(S.A, S.row_off, S.cheb_iv, S.nb, P, c->cheb_deg, S.cq,
                            S.max_block_rows, S.r, n, S.z, n, part, part2,
                            test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
                            c->part2, c->flags, st);
-    prof_end(c, a, 2, 2.0 * sizeof(T) * P * n + 7.0 * (sizeof(T) + 4.0) * n, st);
+    prof_end(c, a, kind, 2.0 * sizeof(T) * P * n + 7.0 * (sizeof(T) + 4.0) * n, st);
     return;
   }
   if (test_par >= 0) k::pcg_test(S.nb, P, test_par, c->part2, c->sc, tol2, c->flags, st);
@@ -809,7 +813,8 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
   pr.D.max_block_rows = maxblk(h.Ioff);
   pr.N.max_block_rows = maxblk(h.Toff);
   for (SysT<T>* S : {&pr.D, &pr.N}) {
-    int ntiles = (P + 7) / 8;
+    const int qmax = std::max(1, k::cheb_max_q<T>(S->max_block_rows));
+    int ntiles = (P + qmax - 1) / qmax;
     int q = (P + ntiles - 1) / ntiles;
     while (q > 1 && k::cheb_lds_bytes<T>(S->max_block_rows, q) > 150 * 1024) --q;
     S->cq = q;
@@ -965,7 +970,7 @@ int sgw_profile(sgw_ctx* c, int enable) {
   prof_harvest(c);
   c->prof = enable != 0;
   c->prof_every = std::max(1, enable);
-  for (int k2 = 0; k2 < 3; ++k2) {
+  for (int k2 = 0; k2 < 6; ++k2) {
     c->pcnt[k2] = 0;
     c->pms[k2] = 0.0;
     c->pbytes[k2] = 0.0;
@@ -975,7 +980,7 @@ int sgw_profile(sgw_ctx* c, int enable) {
 }
 
 int sgw_profile_read(sgw_ctx* c, int kind, long long* launches, double* ms, double* bytes) {
-  if (!c || kind < 0 || kind > 2) return SGW_EINVAL;
+  if (!c || kind < 0 || kind > 5) return SGW_EINVAL;
   prof_harvest(c);
   if (launches) *launches = c->pcnt[kind];
   if (ms) *ms = c->pms[kind];
@@ -1016,7 +1021,9 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
     if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
       int bestq = S.cq;
       for (int q = 1; q <= 8; ++q) {
-        if (q > c->P || k::cheb_lds_bytes<T>(S.max_block_rows, q) > 150 * 1024) continue;
+        if (q > c->P || q > k::cheb_max_q<T>(S.max_block_rows) ||
+            k::cheb_lds_bytes<T>(S.max_block_rows, q) > 150 * 1024)
+          continue;
         double us = time_it([&] {
           (void)k::cheb_apply<T>(S.A, S.row_off, S.cheb_iv, S.nb, c->P, c->cheb_deg, q,
                                  S.max_block_rows, S.r, S.nrows, S.z, S.nrows, c->part,

@@ -4,7 +4,7 @@ Tolerances (relative L2 over all mesh nodes, the error measure of Eq. Norm):
 * SG operator apply, FP64: 1e-13 (one sparse contraction, rounding only);
 * one SG solve at rtol 1e-12: 1e-10;
 * trajectories on the FP64 path with rtol 1e-12: 1e-10 on the mean and the
-  standard deviation at every 10th step (the north-star bound for FP64);
+  standard deviation at every 10th step (the bound for the FP64 path);
 * zero variance: modes >= 1 stay exactly zero.
 Sizes: the 32x32 problem (2x2 subdomains, ragged 64-row tails), an uneven
 37x37 problem with 2x3 subdomains of different sizes, a 64x64 problem with
