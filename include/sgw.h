@@ -81,7 +81,7 @@ typedef struct sgw_problem_desc {
   double inner_rtol;     /* subdomain solves: ||r_s|| <= inner_rtol ||b_s|| */
   int inner_max_iter;
   int precision;         /* SGW_FP64 or SGW_FP32_IR64 */
-  int guess;             /* initial interface guess, SGW_GUESS_* */
+  int guess;             /* initial interface guess, SGW_GUESS_* (LEARNED: see below) */
   double precond_rtol;   /* Neumann solves inside the preconditioner (<= 0: inner_rtol);
                             the interface PCG is the flexible (Polak-Ribiere) variant */
   int inner_prec;        /* preconditioner I_P (x) (K~_0^s)^-1 of the subdomain SG PCG:
@@ -197,12 +197,74 @@ int sgw_profile_read(sgw_ctx* ctx, int kind, long long* launches, double* ms,
  *   [18..25] FP64 Dirichlet Chebyshev   [26..33] FP64 Neumann Chebyshev
  *   [34..41] FP32 Dirichlet triangular  [42..49] FP32 Neumann triangular
  *   [50..57] FP32 Dirichlet Chebyshev   [58..65] FP32 Neumann Chebyshev
- * Enqueues on stream and waits for it. */
+ *   [66]     FP32 unrolled SG apply     [67] FP32 table-driven SG apply
+ * (the SG applies on the Dirichlet system).  Enqueues on stream and waits
+ * for it. */
 int sgw_autotune(sgw_ctx* ctx, void* stream, double* report, int nreport);
 
-/* Sizes: what = 0 P, 1 number of input PCE terms, 2 free nodes,
- * 3 interface nodes, 4 corner nodes, 5 subdomains, 6 (n+1)^2. */
+/* Sizes and counters: what = 0 P, 1 number of input PCE terms, 2 free
+ * nodes, 3 interface nodes (n_gamma), 4 corner nodes, 5 subdomains,
+ * 6 (n+1)^2, 7 training samples recorded since sgw_guess_record,
+ * 8 learned guesses replaced by the Newmark guess. */
 long long sgw_query(const sgw_ctx* ctx, int what);
+
+/* ---- Learned initial guess of the interface PCG ----------------------
+ * The paper starts each step's interface PCG from the previous solution
+ * (Alg. 1).  SGW_GUESS_LEARNED starts it from the Newmark extrapolation
+ * g = U_n + dt V_n + dt^2/2 A_n plus a correction predicted by a small
+ * network from the last four converged interface solutions; the PCG still
+ * runs to the same tolerance, so the guess only changes the iteration
+ * count.  One network serves every PCE mode j: its input is the 4 x n_gamma
+ * history of mode j (oldest first) divided by s_j = max_i |u_n^j(i)|, its
+ * output the correction (u_{n+1} - g) / s_j.  Layers n_in = 4 n_gamma ->
+ * hidden (ReLU) -> hidden (ReLU) -> n_gamma; FP32 master parameters, BF16
+ * weights in the matrix products (MFMA, FP32 accumulation), Adam.
+ * Fallbacks to g: fewer than four past steps, no model attached, a
+ * non-finite prediction, or an initial residual larger than that of the
+ * zero guess. */
+typedef struct sgw_mlp sgw_mlp;
+
+/* New network for interfaces of n_gamma nodes (He-uniform weights from the
+ * counter-based generator splitmix64 seeded with seed; the last layer is
+ * scaled by 0.1; zero biases).  Device memory from alloc (may be NULL).
+ * Errors: SGW_EINVAL, SGW_ENOMEM, SGW_EHIP. */
+int sgw_mlp_create(int n_gamma, int hidden, unsigned long long seed,
+                   const sgw_allocator* alloc, sgw_mlp** out);
+int sgw_mlp_destroy(sgw_mlp* m);
+const char* sgw_mlp_last_error(const sgw_mlp* m);
+/* Number of parameters: layout [W1 (hidden x 4 n_gamma, row-major), b1,
+ * W2 (hidden x hidden), b2, W3 (n_gamma x hidden), b3]. */
+long long sgw_mlp_num_params(const sgw_mlp* m);
+/* Copy the FP32 parameters out (set = 0) or in (set != 0; also refreshes
+ * the BF16 copies and clears the Adam moments); w in memory `where`. */
+int sgw_mlp_params(sgw_mlp* m, float* w, int set, int where, void* stream);
+/* y[nb][n_gamma] = network(x[nb][4 n_gamma]), device arrays; waits for the
+ * stream. */
+int sgw_mlp_forward(sgw_mlp* m, const float* x, float* y, int nb, void* stream);
+/* Mean squared error of the network on (x[nb][4 n_gamma], t[nb][n_gamma])
+ * (host *loss) and its gradient with respect to the parameters (device
+ * grad[num_params], may be NULL); waits for the stream. */
+int sgw_mlp_loss_grad(sgw_mlp* m, const float* x, const float* t, int nb,
+                      float* grad, float* loss, void* stream);
+/* Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error
+ * over nsamples device samples, `epochs` passes in minibatches of `batch`
+ * (shuffled with splitmix64 seeded with seed; a trailing partial batch is
+ * skipped).  *final_loss = mean minibatch loss of the last epoch. */
+int sgw_mlp_train(sgw_mlp* m, const float* x, const float* t, int nsamples,
+                  int epochs, int batch, double lr, unsigned long long seed,
+                  void* stream, float* final_loss);
+
+/* Record training samples from this context's trajectory: every later step
+ * with four past steps appends P samples (one per mode) -- input rows to
+ * X[capacity][4 n_gamma], targets to T[capacity][n_gamma], device FP32 --
+ * while room is left.  X = T = NULL stops recording.  The count is
+ * sgw_query(ctx, 7).  The caller keeps X and T alive while recording. */
+int sgw_guess_record(sgw_ctx* ctx, float* X, float* T, long long capacity);
+
+/* Attach the network used by SGW_GUESS_LEARNED (NULL detaches); its
+ * n_gamma must equal the context's interface size.  The context does not
+ * own it. */
+int sgw_set_guess_model(sgw_ctx* ctx, sgw_mlp* m);
 
 const char* sgw_last_error(const sgw_ctx* ctx);
 int sgw_destroy(sgw_ctx* ctx);

@@ -27,7 +27,10 @@ ERRORS = {-1: "SGW_EINVAL", -2: "SGW_ESTATE", -3: "SGW_ENOMEM",
 EXPORTS = ["sgw_create", "sgw_factor", "sgw_set_state", "sgw_get_state",
            "sgw_step", "sgw_read_moments", "sgw_apply_operator", "sgw_solve",
            "sgw_query", "sgw_last_error", "sgw_destroy", "sgw_profile",
-           "sgw_profile_read", "sgw_autotune"]
+           "sgw_profile_read", "sgw_autotune", "sgw_mlp_create", "sgw_mlp_destroy",
+           "sgw_mlp_last_error", "sgw_mlp_num_params", "sgw_mlp_params", "sgw_mlp_forward",
+           "sgw_mlp_loss_grad", "sgw_mlp_train", "sgw_guess_record", "sgw_set_guess_model"]
+NOT_INT = ("sgw_query", "sgw_last_error", "sgw_mlp_last_error", "sgw_mlp_num_params")
 
 
 class ProblemDesc(ctypes.Structure):
@@ -95,8 +98,21 @@ def lib():
         L.sgw_profile_read.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong),
                                        ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]
+        ull, fp = ctypes.c_ulonglong, ctypes.POINTER(ctypes.c_float)
+        L.sgw_mlp_create.argtypes = [ip, ip, ull, ctypes.POINTER(Allocator), ctypes.POINTER(vp)]
+        L.sgw_mlp_destroy.argtypes = [vp]
+        L.sgw_mlp_last_error.argtypes = [vp]
+        L.sgw_mlp_last_error.restype = ctypes.c_char_p
+        L.sgw_mlp_num_params.argtypes = [vp]
+        L.sgw_mlp_num_params.restype = ctypes.c_longlong
+        L.sgw_mlp_params.argtypes = [vp, vp, ip, ip, vp]
+        L.sgw_mlp_forward.argtypes = [vp, vp, vp, ip, vp]
+        L.sgw_mlp_loss_grad.argtypes = [vp, vp, vp, ip, vp, fp, vp]
+        L.sgw_mlp_train.argtypes = [vp, vp, vp, ip, ip, ip, dp, ull, vp, fp]
+        L.sgw_guess_record.argtypes = [vp, vp, vp, ctypes.c_longlong]
+        L.sgw_set_guess_model.argtypes = [vp, vp]
         for name in EXPORTS:
-            if name not in ("sgw_query", "sgw_last_error"):
+            if name not in NOT_INT:
                 getattr(L, name).restype = ip
         del dp
         _LIB = L
@@ -257,22 +273,139 @@ class Solver:
 
     def autotune(self):
         """Pick the fastest launch shapes; returns the timing report (us)."""
-        rep = (ctypes.c_double * 66)()
-        self._check(lib().sgw_autotune(self.ctx, self._stream(), rep, 66), "sgw_autotune")
+        rep = (ctypes.c_double * 68)()
+        self._check(lib().sgw_autotune(self.ctx, self._stream(), rep, 68), "sgw_autotune")
         r = list(rep)
         out = {"fp64": {"tri_dirichlet_us_by_Q": r[0:8], "tri_neumann_us_by_Q": r[8:16],
                         "cheb_dirichlet_us_by_Q": r[18:26], "cheb_neumann_us_by_Q": r[26:34]},
                "fp32": {"tri_dirichlet_us_by_Q": r[34:42], "tri_neumann_us_by_Q": r[42:50],
                         "cheb_dirichlet_us_by_Q": r[50:58], "cheb_neumann_us_by_Q": r[58:66]},
-               "sg_apply_unrolled_us": r[16], "sg_apply_table_us": r[17]}
+               "sg_apply_unrolled_us": r[16], "sg_apply_table_us": r[17],
+               "sg_apply_unrolled_fp32_us": r[66], "sg_apply_table_fp32_us": r[67]}
         for prec in ("fp64", "fp32"):  # keep only what was timed
             out[prec] = {k: v for k, v in out[prec].items() if max(v) > 0}
         return out
+
+    # -- learned guess ----------------------------------------------------------
+    def record_guess_samples(self, X=None, T=None):
+        """Record training samples of later steps into the float32 device
+        tensors X [cap, 4 n_gamma] and T [cap, n_gamma]; no arguments stop."""
+        if X is None:
+            self._rec = None
+            return self._check(lib().sgw_guess_record(self.ctx, None, None, 0), "sgw_guess_record")
+        assert X.dtype == self.torch.float32 and T.dtype == self.torch.float32
+        assert X.is_contiguous() and T.is_contiguous() and X.shape[0] == T.shape[0]
+        assert X.shape[1] == 4 * self.ninterface and T.shape[1] == self.ninterface
+        self._rec = (X, T)  # kept alive while recording
+        return self._check(lib().sgw_guess_record(self.ctx, _ptr(X), _ptr(T), X.shape[0]),
+                           "sgw_guess_record")
+
+    def recorded_samples(self):
+        return lib().sgw_query(self.ctx, 7)
+
+    def guess_fallbacks(self):
+        return lib().sgw_query(self.ctx, 8)
+
+    def set_guess_model(self, model):
+        """Network used when the solver runs with guess=SGW_GUESS_LEARNED."""
+        self._model = model
+        return self._check(lib().sgw_set_guess_model(self.ctx, model.m if model else None),
+                           "sgw_set_guess_model")
 
     def close(self):
         if self.ctx:
             lib().sgw_destroy(self.ctx)
             self.ctx = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GuessModel:
+    """The learned-guess network (see sgw.h): n_gamma interface nodes,
+    ``hidden`` units in each of the two hidden layers."""
+
+    def __init__(self, n_gamma, hidden=256, seed=0, use_torch_allocator=True):
+        import torch
+        self.torch = torch
+        self.n_gamma, self.hidden = n_gamma, hidden
+        self._live = {}
+        al = None
+        if use_torch_allocator:
+            dev = torch.cuda.current_device()
+
+            def _alloc(nbytes, user):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda:%d" % dev)
+                self._live[t.data_ptr()] = t
+                return t.data_ptr()
+
+            def _free(p, user):
+                self._live.pop(p, None)
+
+            self._afn, self._ffn = ALLOC_FN(_alloc), FREE_FN(_free)
+            al = Allocator(self._afn, self._ffn, None)
+        self.m = ctypes.c_void_p()
+        rc = lib().sgw_mlp_create(n_gamma, hidden, seed, ctypes.byref(al) if al else None,
+                                  ctypes.byref(self.m))
+        self._check(rc, "sgw_mlp_create")
+        self.num_params = lib().sgw_mlp_num_params(self.m)
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def _check(self, rc, what):
+        if rc < 0:
+            msg = lib().sgw_mlp_last_error(self.m).decode() if self.m else ""
+            raise SGWError("%s failed: %s (%s)" % (what, ERRORS.get(rc, rc), msg))
+        return rc
+
+    def _f32(self, t):
+        return t.to(device="cuda", dtype=self.torch.float32).contiguous()
+
+    def params(self):
+        w = self.torch.empty(self.num_params, dtype=self.torch.float32, device="cuda")
+        self._check(lib().sgw_mlp_params(self.m, _ptr(w), 0, SGW_DEVICE, self._stream()),
+                    "sgw_mlp_params")
+        return w
+
+    def set_params(self, w):
+        w = self._f32(w)
+        assert w.numel() == self.num_params
+        self._check(lib().sgw_mlp_params(self.m, _ptr(w), 1, SGW_DEVICE, self._stream()),
+                    "sgw_mlp_params")
+
+    def forward(self, x):
+        x = self._f32(x)
+        y = self.torch.empty(x.shape[0], self.n_gamma, dtype=self.torch.float32, device="cuda")
+        self._check(lib().sgw_mlp_forward(self.m, _ptr(x), _ptr(y), x.shape[0], self._stream()),
+                    "sgw_mlp_forward")
+        return y
+
+    def loss_grad(self, x, t):
+        x, t = self._f32(x), self._f32(t)
+        g = self.torch.empty(self.num_params, dtype=self.torch.float32, device="cuda")
+        loss = ctypes.c_float()
+        self._check(lib().sgw_mlp_loss_grad(self.m, _ptr(x), _ptr(t), x.shape[0], _ptr(g),
+                                            ctypes.byref(loss), self._stream()),
+                    "sgw_mlp_loss_grad")
+        return loss.value, g
+
+    def train(self, x, t, epochs=50, batch=256, lr=1e-3, seed=0):
+        x, t = self._f32(x), self._f32(t)
+        loss = ctypes.c_float()
+        self._check(lib().sgw_mlp_train(self.m, _ptr(x), _ptr(t), x.shape[0], epochs, batch, lr,
+                                        seed, self._stream(), ctypes.byref(loss)),
+                    "sgw_mlp_train")
+        return loss.value
+
+    def close(self):
+        if self.m:
+            lib().sgw_mlp_destroy(self.m)
+            self.m = ctypes.c_void_p()
             self._live.clear()
 
     def __del__(self):

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgw.so")
-SOURCES = ["setup.cpp", "kernels.hip", "sgw.hip"]
+SOURCES = ["setup.cpp", "kernels.hip", "sgw.hip", "mlp.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -37,12 +37,29 @@ struct DEll {
   const T* mval = nullptr;
 };
 
+// Column halo of the 64-row groups of a sliced-ELL matrix, for rows
+// [r0, r0 + nr): group g covers rows [r0 + 64g, r0 + 64g + 64) and its
+// distinct columns are idx[ptr[g] .. ptr[g+1]) (sorted); lcol[s*nr + r - r0]
+// is the position of col[s][r] in its group's list; hmax = the longest list.
+struct DHalo {
+  int r0 = 0, nr = 0, hmax = 0;
+  const int* ptr = nullptr;
+  const int* idx = nullptr;
+  const unsigned short* lcol = nullptr;
+};
+
 // y[i][r] = alpha * sum_k sum_j c_kij sum_s K_k[r, s] x[j][col]  (+ beta*y)
 // for rows r in [r0, r0 + nrows) of the matrix.  nbatch vectors with strides.
+// With a halo H of the same r0 covering the rows (and a generated kernel
+// for the basis) the kernel that stages x in LDS runs, else the
+// table-driven one.
 template <typename T>
-void sg_apply(const DEll<T>& A, const GTab& g, int r0, int nrows,
+void sg_apply(const DEll<T>& A, const GTab& g, const DHalo* H, int r0, int nrows,
               const T* x, int ldx, T* y, int ldy, T alpha, T beta,
               int nbatch, long long sx, long long sy, hipStream_t st);
+// Once per process before the first sg_apply: LDS attribute of the
+// generated kernels.  0 on success, -1 on a HIP error.
+int sg_apply_prepare();
 
 // y[j][r] = beta*y[j][r] + alpha * sum_s M[r, s] x[j][col]  for all P modes.
 template <typename T>

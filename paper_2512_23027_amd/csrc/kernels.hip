@@ -8,6 +8,7 @@
 // the lane that owns the row.
 #include "kernels.h"
 
+#include <algorithm>
 #include <cstdio>
 
 namespace sgw {
@@ -131,12 +132,14 @@ __global__ __launch_bounds__(SGW_WAVE) void k_sg_apply(
 #include "k1_spec.inc"
 
 template <typename T>
-void sg_apply(const DEll<T>& A, const GTab& g, int r0, int nrows, const T* x,
+void sg_apply(const DEll<T>& A, const GTab& g, const DHalo* H, int r0, int nrows, const T* x,
               int ldx, T* y, int ldy, T alpha, T beta, int nbatch,
               long long sx, long long sy, hipStream_t st) {
   if (nrows <= 0) return;
-  if (g.use_spec && sg_apply_specialised<T>(g.L, g.p_in, g.p_out, A, r0, nrows, x, ldx, y, ldy,
-                                            alpha, beta, nbatch, sx, sy, st))
+  if (g.use_spec && H && H->r0 == r0 && nrows <= H->nr &&
+      (size_t)g.P * H->hmax * sizeof(T) <= 150 * 1024 &&
+      sg_apply_specialised<T>(g.L, g.p_in, g.p_out, A, *H, r0, nrows, x, ldx, y, ldy, alpha,
+                              beta, nbatch, sx, sy, st))
     return;
   dim3 grid(ceil_div(nrows, SGW_WAVE), g.ng, nbatch);
   size_t sh = (size_t)g.GS * SGW_WAVE * sizeof(T);
@@ -155,6 +158,8 @@ void sg_apply(const DEll<T>& A, const GTab& g, int r0, int nrows, const T* x,
       break;
   }
 }
+
+int sg_apply_prepare() { return sg_apply_specialised_prepare() ? 0 : -1; }
 
 // Deterministic mass apply over all P modes: thread per (row, mode).
 template <typename T>
@@ -1134,8 +1139,8 @@ template int cheb_apply<float>(const DEll<float>&, const int*, const double*, in
                                double*, int, double, const double*, int*, hipStream_t);
 template size_t tri_lds_bytes<float>(const DFactor&, int);
 #define SGW_INST(T)                                                                          \
-  template void sg_apply<T>(const DEll<T>&, const GTab&, int, int, const T*, int, T*, int, T, \
-                            T, int, long long, long long, hipStream_t);                     \
+  template void sg_apply<T>(const DEll<T>&, const GTab&, const DHalo*, int, int, const T*,    \
+                            int, T*, int, T, T, int, long long, long long, hipStream_t);    \
   template void mass_apply<T>(const DEll<T>&, int, int, int, const T*, int, T*, int, T, T,   \
                               hipStream_t);                                                  \
   template void tri_solve<T>(const DFactor&, int, const T*, int, T*, int, int, long long,    \

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "mlp.h"
 #include "setup.h"
 #include "sgw.h"
 
@@ -40,6 +41,7 @@ template <typename T>
 struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   int nrows = 0, nb = 0, Q = 8;
   int cq = 8, max_block_rows = 0;     // Chebyshev mode tile, largest block
+  const k::DHalo* halo = nullptr;     // 64-row group halos of A (both precisions)
   const double* cheb_iv = nullptr;    // device, [nb][2] spectral intervals
   int last_its[2] = {0, 0};     // previous iteration counts (tight / loose tolerance)
   double loose_tol = 1e300;     // tolerances >= this use the second count
@@ -114,6 +116,20 @@ struct sgw_ctx {
   std::vector<Pend> pend;
   long long pcnt[6] = {0, 0, 0, 0, 0, 0};
   double pms[6] = {0, 0, 0, 0, 0, 0}, pbytes[6] = {0, 0, 0, 0, 0, 0};
+  // 64-row group halos of the SG-apply matrices: global system from row 0
+  // and from the first interface row, Dirichlet and Neumann systems
+  k::DHalo hal_G0, hal_GI, hal_D, hal_N;
+  // learned initial guess: ring of the last 4 converged interface solutions
+  // [4][P][nG], the Newmark guess of the current step [P][nG], per-mode
+  // scales [P], network input/output [P][4 nG] / [P][nG], the attached
+  // model and the sample recorder (caller's device arrays)
+  double *hist = nullptr, *gnew = nullptr, *smax = nullptr;
+  int hist_n = 0, hist_pos = 0;
+  float *mx = nullptr, *my = nullptr;
+  sgw_mlp* mlp = nullptr;
+  float *rec_x = nullptr, *rec_t = nullptr;
+  long long rec_cap = 0, rec_n = 0;
+  long long guess_fallbacks = 0;  // learned guesses replaced by the Newmark guess
   // subdomain preconditioner: SGW_INNER_* and the Chebyshev degree
   int inner_prec = SGW_INNER_CHOLESKY, cheb_deg = 4;
   double factor_bytes_D = 0, factor_bytes_N = 0;
@@ -298,11 +314,11 @@ static void prof_harvest(sgw_ctx* c) {
 // K1 wrapper: algorithmic bytes per row = 7 (M+1) values + 7 column indices
 // + P inputs + P outputs (+ P when the output is accumulated).
 template <typename T>
-static void K1(sgw_ctx* c, const k::DEll<T>& A, int r0, int nrows, const T* x, int ldx, T* y,
-               int ldy, double alpha, double beta, hipStream_t st) {
+static void K1(sgw_ctx* c, const k::DEll<T>& A, const k::DHalo* H, int r0, int nrows, const T* x,
+               int ldx, T* y, int ldy, double alpha, double beta, hipStream_t st) {
   const int kind = sizeof(T) == 4 ? 3 : 0;
   int a = prof_begin(c, kind, st);
-  k::sg_apply<T>(A, c->gt, r0, nrows, x, ldx, y, ldy, (T)alpha, (T)beta, 1, 0, 0, st);
+  k::sg_apply<T>(A, c->gt, H, r0, nrows, x, ldx, y, ldy, (T)alpha, (T)beta, 1, 0, 0, st);
   const double w = sizeof(T);
   double per_row = 7.0 * c->nk * w + 7.0 * 4.0 + 2.0 * c->P * w + (beta != 0.0 ? c->P * w : 0.0);
   prof_end(c, a, kind, per_row * nrows, st);
@@ -390,7 +406,7 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
       break;
     }
     const int par = it & 1;
-    K1<T>(c, S.A, 0, n, S.p, n, S.q, n, 1.0, 0.0, st);
+    K1<T>(c, S.A, S.halo, 0, n, S.p, n, S.q, n, 1.0, 0.0, st);
     k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
     k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part,
                  c->part2, c->flags, st);
@@ -428,10 +444,10 @@ template <typename T>
 static int schur_apply(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, T* w, T* q, hipStream_t st) {
   const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
   k::fill2d<T>(P, nI, w, NF, T(0), st);
-  K1<T>(c, pr.G, 0, nI, w, NF, pr.T1, NF, -1.0, 0.0, st);
+  K1<T>(c, pr.G, &c->hal_G0, 0, nI, w, NF, pr.T1, NF, -1.0, 0.0, st);
   int rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, w, NF, tl.inner, tl.inner_max_iter, st);
   if (rc < 0) return rc;
-  K1<T>(c, pr.G, nI, nG, w, NF, q, NF, 1.0, 0.0, st);
+  K1<T>(c, pr.G, &c->hal_GI, nI, nG, w, NF, q, NF, 1.0, 0.0, st);
   return rc;
 }
 
@@ -477,7 +493,7 @@ static int gdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st)
 // solution on exit.
 template <typename T>
 static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, hipStream_t st,
-                    int& outer_its, double& relres) {
+                    int& outer_its, double& relres, const double* fallback = nullptr) {
   const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
   int warn = 0, rc;
   // H2: condensation G = F_G - K~_GI K~_II^{-1} F_I
@@ -486,7 +502,7 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   warn |= rc;
   k::fill2d<T>(P, nG, pr.T1 + nI, NF, T(0), st);
   k::copy2d<T, T>(P, nG, F + nI, NF, pr.Gv + nI, NF, 1.0, st);
-  K1<T>(c, pr.G, nI, nG, pr.T1, NF, pr.Gv, NF, -1.0, 1.0, st);
+  K1<T>(c, pr.G, &c->hal_GI, nI, nG, pr.T1, NF, pr.Gv, NF, -1.0, 1.0, st);
   double gg;
   if ((rc = gdot<T>(c, pr.Gv + nI, pr.Gv + nI, gg, st))) return rc;
   // H3/H4: PCG on S U_G = G, initial guess in X's interface part
@@ -500,6 +516,18 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
   warn |= rc;
   k::axpby2d<T>(P, nG, 1.0, pr.Gv + nI, NF, -1.0, q, NF, r, NF, st);
+  if (fallback) {  // a learned guess worse than the zero guess is replaced
+    double rr0;
+    if ((rc = gdot<T>(c, r, r, rr0, st))) return rc;
+    if (!(rr0 <= gg)) {
+      k::copy2d<T, double>(P, nG, fallback, nG, x, NF, 1.0, st);
+      k::copy2d<T, T>(P, nG, x, NF, p, NF, 1.0, st);
+      if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
+      warn |= rc;
+      k::axpby2d<T>(P, nG, 1.0, pr.Gv + nI, NF, -1.0, q, NF, r, NF, st);
+      c->guess_fallbacks++;
+    }
+  }
   if ((rc = precond<T>(c, pr, tl, r, z, st)) < 0) return rc;
   warn |= rc;
   k::copy2d<T, T>(P, nG, z, NF, p, NF, 1.0, st);
@@ -548,7 +576,7 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   // H5: interior recovery U_I = K~_II^{-1} (F_I - K~_IG U_G)
   k::fill2d<T>(P, nI, X, NF, T(0), st);
   k::copy2d<T, T>(P, nI, F, NF, pr.T1, NF, 1.0, st);
-  K1<T>(c, pr.G, 0, nI, X, NF, pr.T1, NF, -1.0, 1.0, st);
+  K1<T>(c, pr.G, &c->hal_G0, 0, nI, X, NF, pr.T1, NF, -1.0, 1.0, st);
   rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, X, NF, tl.inner, tl.inner_max_iter, st);
   if (rc < 0) return rc;
   warn |= rc;
@@ -753,6 +781,39 @@ static bool spd_inverse(std::vector<double>& A, int n) {
 
 // Device state of one precision: operator values (FP32 copies for the
 // refinement path), system workspaces and interface vectors.
+// 64-row group halos of an ELL matrix for rows [r0, nrows) (see k::DHalo).
+static k::DHalo build_halo(sgw_ctx* c, const Ell& E, int r0) {
+  k::DHalo H;
+  const int nr = std::max(E.nrows - r0, 0);
+  H.r0 = r0;
+  H.nr = nr;
+  const int ng = (nr + 63) / 64;
+  std::vector<int> ptr{0}, idx, cols;
+  std::vector<unsigned short> lcol((size_t)E.W * std::max(nr, 1), 0);
+  for (int g = 0; g < ng; ++g) {
+    const int a = r0 + 64 * g, b = std::min(E.nrows, a + 64);
+    cols.clear();
+    for (int s = 0; s < E.W; ++s)
+      for (int r = a; r < b; ++r) cols.push_back(E.col[(size_t)s * E.nrows + r]);
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    for (int s = 0; s < E.W; ++s)
+      for (int r = a; r < b; ++r) {
+        const int cc = E.col[(size_t)s * E.nrows + r];
+        lcol[(size_t)s * nr + (r - r0)] =
+            (unsigned short)(std::lower_bound(cols.begin(), cols.end(), cc) - cols.begin());
+      }
+    idx.insert(idx.end(), cols.begin(), cols.end());
+    ptr.push_back((int)idx.size());
+    H.hmax = std::max(H.hmax, (int)cols.size());
+  }
+  if (idx.empty()) idx.push_back(0);
+  H.ptr = upload(c, ptr);
+  H.idx = upload(c, idx);
+  H.lcol = upload(c, lcol);
+  return H;
+}
+
 template <typename T>
 static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
   const Host& h = c->h;
@@ -812,6 +873,8 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
   };
   pr.D.max_block_rows = maxblk(h.Ioff);
   pr.N.max_block_rows = maxblk(h.Toff);
+  pr.D.halo = &c->hal_D;
+  pr.N.halo = &c->hal_N;
   for (SysT<T>* S : {&pr.D, &pr.N}) {
     const int qmax = std::max(1, k::cheb_max_q<T>(S->max_block_rows));
     int ntiles = (P + qmax - 1) / qmax;
@@ -867,7 +930,7 @@ static int fdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st)
 // correction K~ D = R is solved by the whole DD method in FP32 (coarse grid
 // FP64) to the relative tolerances below.  Stops when ||R|| <= rtol ||F||.
 static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int& outer_total,
-                    int& sweeps, double& relres) {
+                    int& sweeps, double& relres, const double* fallback = nullptr) {
   const sgw_problem_desc& d = c->h.d;
   const int P = c->P, NF = c->NF;
   PrecT<float>& pr = c->f32;
@@ -881,10 +944,17 @@ static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int&
   sweeps = 0;
   for (;;) {
     k::copy2d<double, double>(P, NF, F, NF, R, NF, 1.0, st);
-    K1<double>(c, c->d64.G, 0, NF, X, NF, R, NF, -1.0, 1.0, st);
+    K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, X, NF, R, NF, -1.0, 1.0, st);
     double rr;
     if ((rc = fdot<double>(c, R, R, rr, st))) return rc;
     relres = ff > 0.0 ? std::sqrt(rr / ff) : 0.0;
+    if (fallback && sweeps == 0 && !(rr <= ff)) {
+      // a learned interface guess worse than the zero guess: Newmark instead
+      k::copy2d<double, double>(P, c->nG, fallback, c->nG, X + c->nI, NF, 1.0, st);
+      c->guess_fallbacks++;
+      fallback = nullptr;
+      continue;
+    }
     if (!std::isfinite(rr)) {
       c->err = "non-finite refinement residual";
       return SGW_ENAN;
@@ -927,7 +997,8 @@ static bool prec_complete(const PrecT<T>& pr, bool refine) {
 }
 
 static bool check_pointers(sgw_ctx* c) {
-  const void* ps[] = {c->U, c->V, c->A, c->Um, c->Uc, c->Wm, c->F, c->meshbuf, c->meshbuf2,
+  const void* ps[] = {c->U, c->V, c->A, c->Um, c->Uc, c->Wm, c->F, c->hist, c->gnew, c->smax,
+                      c->mx, c->my, c->meshbuf, c->meshbuf2,
                       c->part, c->part2, c->sc, c->flags, c->goff, c->alloff, c->dd2mesh,
                       c->mdiag, c->torn_gidx, c->torn_w, c->gam_ptr, c->gam_torn, c->gam_w,
                       c->g2c, c->dc, c->uc, c->phi, c->gt.mask, c->gt.pair_beg, c->gt.ent_beg,
@@ -951,6 +1022,26 @@ extern "C" {
 
 const char* sgw_last_error(const sgw_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+int sgw_guess_record(sgw_ctx* c, float* X, float* T, long long capacity) {
+  if (!c || capacity < 0 || ((X == nullptr) != (T == nullptr)) || (X && capacity == 0))
+    return SGW_EINVAL;
+  c->rec_x = X;
+  c->rec_t = T;
+  c->rec_cap = X ? capacity : 0;
+  c->rec_n = 0;
+  return 0;
+}
+
+int sgw_set_guess_model(sgw_ctx* c, sgw_mlp* m) {
+  if (!c) return SGW_EINVAL;
+  if (m && m->ng != c->nG) {
+    c->err = "the model's n_gamma differs from the number of interface nodes";
+    return SGW_EINVAL;
+  }
+  c->mlp = m;
+  return 0;
+}
+
 long long sgw_query(const sgw_ctx* c, int what) {
   if (!c) return -1;
   switch (what) {
@@ -961,6 +1052,8 @@ long long sgw_query(const sgw_ctx* c, int what) {
     case 4: return c->nC;
     case 5: return c->nsub;
     case 6: return c->nn;
+    case 7: return c->rec_n;
+    case 8: return c->guess_fallbacks;
     default: return -1;
   }
 }
@@ -997,7 +1090,7 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  const int kReport = 66;
+  const int kReport = 68;
   std::vector<double> rep(kReport, -1.0);
   const int reps = 10;
   auto time_it = [&](auto&& fn) -> double {
@@ -1059,18 +1152,31 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
     tune_sys(c->f32.N, 42, 58);
   }
   {
-    SysT<double>& S = c->d64.D;
-    bool keep = c->gt.use_spec;
-    double us[2];
+    // generated (unrolled tensor, staged x) vs table-driven SG apply on the
+    // Dirichlet system, in FP64 and (refinement path) FP32; the precision the
+    // steps run in decides
+    const bool keep = c->gt.use_spec;
+    double us[4] = {-1.0, -1.0, -1.0, -1.0};
     for (int v = 0; v < 2; ++v) {
       c->gt.use_spec = v == 0;
+      SysT<double>& S = c->d64.D;
       us[v] = time_it([&] {
-        k::sg_apply<double>(S.A, c->gt, 0, S.nrows, S.r, S.nrows, S.q, S.nrows, 1.0, 0.0, 1, 0, 0, st);
+        k::sg_apply<double>(S.A, c->gt, S.halo, 0, S.nrows, S.r, S.nrows, S.q, S.nrows, 1.0, 0.0,
+                            1, 0, 0, st);
       });
+      if (c->f32.ready) {
+        SysT<float>& F = c->f32.D;
+        us[2 + v] = time_it([&] {
+          k::sg_apply<float>(F.A, c->gt, F.halo, 0, F.nrows, F.r, F.nrows, F.q, F.nrows, 1.0f,
+                             0.0f, 1, 0, 0, st);
+        });
+      }
     }
     rep[16] = us[0];
     rep[17] = us[1];
-    c->gt.use_spec = keep && us[0] <= us[1];
+    rep[66] = us[2];
+    rep[67] = us[3];
+    c->gt.use_spec = keep && (c->f32.ready ? us[2] <= us[3] : us[0] <= us[1]);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1156,6 +1262,15 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     *out = c;
     return SGW_EINVAL;
   }
+  c->hal_G0 = build_halo(c, h.glob, 0);
+  c->hal_GI = build_halo(c, h.glob, h.nI);
+  c->hal_D = build_halo(c, h.dir, 0);
+  c->hal_N = build_halo(c, h.neu, 0);
+  if (k::sg_apply_prepare() != 0) {
+    c->err = "hipFuncSetAttribute failed for the SG-apply kernels";
+    *out = c;
+    return SGW_EHIP;
+  }
   setup_prec<double>(c, c->d64, false);
   if (dd.precision == SGW_FP32_IR64) setup_prec<float>(c, c->f32, true);
   if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
@@ -1174,6 +1289,11 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     size_t nv = (size_t)P * h.NF;
     for (double** v : {&c->U, &c->V, &c->A, &c->Um, &c->Uc, &c->Wm, &c->F})
       *v = dalloc<double>(c, nv);
+    c->hist = dalloc<double>(c, (size_t)4 * P * h.nG);
+    c->gnew = dalloc<double>(c, (size_t)P * h.nG);
+    c->smax = dalloc<double>(c, (size_t)P);
+    c->mx = dalloc<float>(c, (size_t)P * 4 * h.nG);
+    c->my = dalloc<float>(c, (size_t)P * h.nG);
   }
   c->meshbuf = dalloc<double>(c, (size_t)std::max(P, 2) * h.nn);
   c->meshbuf2 = dalloc<double>(c, (size_t)P * h.nn);
@@ -1364,6 +1484,78 @@ int sgw_factor(sgw_ctx* c, void* stream) {
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// H3 (learned): the network sees, per PCE mode j, the last four converged
+// interface solutions u_{n-3..n} scaled by s_j = max|u_n^j|; it returns the
+// correction to the Newmark guess g_{n+1} in the same scale.
+// ---------------------------------------------------------------------------
+__global__ void k_hist_push(int P, int nG, const double* u, int ldu, double* slot) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)P * nG) return;
+  const int j = (int)(q / nG), i = (int)(q % nG);
+  slot[q] = u[(size_t)j * ldu + i];
+}
+// s_j = max_i |slot[j][i]| (+ the smallest normal number), one workgroup per mode
+__global__ __launch_bounds__(256) void k_mode_scale(int nG, const double* slot, double* smax) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nG; i += 256) m = fmax(m, fabs(slot[(size_t)j * nG + i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) smax[j] = sh[0] + 2.2250738585072014e-308;
+}
+// x[j][h nG + i] = hist[slot h][j][i] / s_j, h = 0..3 oldest first
+__global__ void k_guess_input(int P, int nG, const double* hist, int h0, const double* smax,
+                              float* x) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)P * 4 * nG) return;
+  const int j = (int)(q / (4 * nG)), r = (int)(q % (4 * nG));
+  const int h = r / nG, i = r % nG;
+  const int slot = (h0 + h) & 3;
+  x[q] = (float)(hist[((size_t)slot * P + j) * nG + i] / smax[j]);
+}
+// t[j][i] = (u_new[j][i] - g[j][i]) / s_j
+__global__ void k_guess_target(int P, int nG, const double* un, int ldu, const double* g,
+                               const double* smax, float* t) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)P * nG) return;
+  const int j = (int)(q / nG), i = (int)(q % nG);
+  t[q] = (float)((un[(size_t)j * ldu + i] - g[q]) / smax[j]);
+}
+// x = g + s_j y, or g where that is not finite
+__global__ void k_guess_apply(int P, int nG, const double* g, const double* smax, const float* y,
+                              double* x, int ldx) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)P * nG) return;
+  const int j = (int)(q / nG), i = (int)(q % nG);
+  const double v = g[q] + smax[j] * (double)y[q];
+  x[(size_t)j * ldx + i] = isfinite(v) ? v : g[q];
+}
+
+static int grid1(long long n) { return (int)((n + 255) / 256); }
+
+// Appends the interface part of the state u (ld NF) to the history ring.
+static void hist_push(sgw_ctx* c, const double* u, hipStream_t st) {
+  const int P = c->P, nG = c->nG;
+  k_hist_push<<<grid1((long long)P * nG), 256, 0, st>>>(P, nG, u + c->nI, c->NF,
+                                                       c->hist + (size_t)c->hist_pos * P * nG);
+  c->hist_pos = (c->hist_pos + 1) & 3;
+  c->hist_n = std::min(c->hist_n + 1, 4);
+}
+// network input of the current history (needs 4 entries) into c->mx
+static void guess_input(sgw_ctx* c, hipStream_t st) {
+  const int P = c->P, nG = c->nG;
+  const int newest = (c->hist_pos + 3) & 3;
+  k_mode_scale<<<P, 256, 0, st>>>(nG, c->hist + (size_t)newest * P * nG, c->smax);
+  k_guess_input<<<grid1((long long)P * 4 * nG), 256, 0, st>>>(P, nG, c->hist, c->hist_pos,
+                                                             c->smax, c->mx);
+}
+
 int sgw_set_state(sgw_ctx* c, const double* U, const double* V, const double* A, int where,
                   int step, void* stream) {
   if (!c) return SGW_EINVAL;
@@ -1393,12 +1585,17 @@ int sgw_set_state(sgw_ctx* c, const double* U, const double* V, const double* A,
     // (I(x)M) A = -(K U + C V); K = (K~ - a_m I(x)M)/s_k, C = a0 I(x)M + a1 K
     const double s = h.s_k, am = h.a_m, a0 = d.alpha0, a1 = d.alpha1;
     k::axpby2d<double>(P, NF, 1.0, c->U, NF, a1, c->V, NF, c->Wm, NF, st);
-    k::sg_apply<double>(c->d64.G, c->gt, 0, NF, c->Wm, NF, c->F, NF, -1.0 / s, 0.0, 1, 0, 0, st);
+    k::sg_apply<double>(c->d64.G, c->gt, &c->hal_G0, 0, NF, c->Wm, NF, c->F, NF, -1.0 / s, 0.0, 1, 0,
+                        0, st);
     k::mass_apply<double>(c->d64.G, 0, NF, P, c->Wm, NF, c->F, NF, am / s, 1.0, st);
     k::mass_apply<double>(c->d64.G, 0, NF, P, c->V, NF, c->F, NF, -a0, 1.0, st);
     int rc = mass_solve(c, c->F, c->A, st);
     if (rc) return rc;
   }
+  // the learned guess starts a new history with this state
+  c->hist_n = 0;
+  c->hist_pos = 0;
+  hist_push(c, c->U, st);
   HIPCHK(hipStreamSynchronize(st));
   c->stepno = step;
   c->has_state = true;
@@ -1440,34 +1637,59 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
                        c->Wm, st);
     k::mass_apply<double>(c->d64.G, 0, NF, P, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
     if (d.alpha1 != 0.0)
-      K1<double>(c, c->d64.G, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0, st);
-    // H3: initial interface guess
-    if (d.guess == SGW_GUESS_NEWMARK) {
-      // U + dt V + dt^2/2 A on the interface
-      k::axpby2d<double>(P, nG, 1.0, c->U + nI, NF, d.dt, c->V + nI, NF, c->d64.X + nI, NF, st);
-      k::axpby2d<double>(P, nG, 1.0, c->d64.X + nI, NF, 0.5 * d.dt * d.dt, c->A + nI, NF,
-                         c->d64.X + nI, NF, st);
-    } else {
+      K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0, st);
+    // H3: initial interface guess.  Newmark extrapolation g = U + dt V +
+    // dt^2/2 A on the interface (also the reference of the learned
+    // correction); the previous solution; or g plus the network's correction
+    // (with fewer than 4 past steps or no model attached: g)
+    const bool learned = d.guess == SGW_GUESS_LEARNED && c->mlp && c->hist_n >= 4;
+    const bool recording = c->rec_x && c->hist_n >= 4 && c->rec_n + P <= c->rec_cap;
+    k::axpby2d<double>(P, nG, 1.0, c->U + nI, NF, d.dt, c->V + nI, NF, c->gnew, nG, st);
+    k::axpby2d<double>(P, nG, 1.0, c->gnew, nG, 0.5 * d.dt * d.dt, c->A + nI, NF, c->gnew, nG,
+                       st);
+    if (learned || recording) guess_input(c, st);
+    if (learned) {
+      int mrc = sgw::mlp_forward(c->mlp, c->mx, c->my, P, st);
+      if (mrc < 0) {
+        c->err = "learned guess: " + c->mlp->err;
+        return mrc;
+      }
+      k_guess_apply<<<grid1((long long)P * nG), 256, 0, st>>>(P, nG, c->gnew, c->smax, c->my,
+                                                             c->d64.X + nI, NF);
+    } else if (d.guess == SGW_GUESS_PREV) {
       k::copy2d<double, double>(P, nG, c->U + nI, NF, c->d64.X + nI, NF, 1.0, st);
+    } else {
+      k::copy2d<double, double>(P, nG, c->gnew, nG, c->d64.X + nI, NF, 1.0, st);
     }
+    const double* fallback = learned ? c->gnew : nullptr;
     int its = 0, sweeps = 0;
     double rel = 0.0;
     int rc;
     if (d.precision == SGW_FP32_IR64) {
       // the refinement starts from the whole previous (or extrapolated) state
       k::copy2d<double, double>(P, nI, c->U, NF, c->d64.X, NF, 1.0, st);
-      if (d.guess == SGW_GUESS_NEWMARK) {
+      if (d.guess != SGW_GUESS_PREV) {
         k::axpby2d<double>(P, nI, 1.0, c->U, NF, d.dt, c->V, NF, c->d64.X, NF, st);
         k::axpby2d<double>(P, nI, 1.0, c->d64.X, NF, 0.5 * d.dt * d.dt, c->A, NF, c->d64.X, NF, st);
       }
-      rc = ir_solve(c, c->F, c->d64.X, st, its, sweeps, rel);
+      rc = ir_solve(c, c->F, c->d64.X, st, its, sweeps, rel, fallback);
       s.ir_sweeps += sweeps;
     } else {
       Tols tl{d.rtol, d.inner_rtol, d.precond_rtol, d.max_iter, d.inner_max_iter};
-      rc = dd_solve<double>(c, c->d64, tl, c->F, c->d64.X, st, its, rel);
+      rc = dd_solve<double>(c, c->d64, tl, c->F, c->d64.X, st, its, rel, fallback);
     }
     if (rc < 0) return rc;
     warn |= rc;
+    // H11: training sample (history, correction of the Newmark guess), then
+    // the new solution joins the history
+    if (recording) {
+      HIPCHK(hipMemcpyAsync(c->rec_x + (size_t)c->rec_n * 4 * nG, c->mx,
+                            (size_t)P * 4 * nG * sizeof(float), hipMemcpyDeviceToDevice, st));
+      k_guess_target<<<grid1((long long)P * nG), 256, 0, st>>>(
+          P, nG, c->d64.X + nI, NF, c->gnew, c->smax, c->rec_t + (size_t)c->rec_n * nG);
+      c->rec_n += P;
+    }
+    hist_push(c, c->d64.X, st);
     // H6: Newmark update
     k::newmark_update(P, NF, NF, c->d64.X, c->Um, c->V, c->A, d.dt, d.zeta, d.gamma, st);
     std::swap(c->U, c->d64.X);
@@ -1550,10 +1772,10 @@ int sgw_apply_operator(sgw_ctx* c, const double* X, double* Y, int precision, vo
       return SGW_ESTATE;
     }
     k::copy2d<float, double>(P, NF, c->Wm, NF, c->f32.Fb, NF, 1.0, st);
-    K1<float>(c, c->f32.G, 0, NF, c->f32.Fb, NF, c->f32.Xb, NF, 1.0, 0.0, st);
+    K1<float>(c, c->f32.G, &c->hal_G0, 0, NF, c->f32.Fb, NF, c->f32.Xb, NF, 1.0, 0.0, st);
     k::copy2d<double, float>(P, NF, c->f32.Xb, NF, c->F, NF, 1.0, st);
   } else {
-    K1<double>(c, c->d64.G, 0, NF, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
+    K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
   }
   return from_dd(c, c->F, Y, SGW_DEVICE, st);
 }

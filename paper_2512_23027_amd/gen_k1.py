@@ -7,16 +7,18 @@ in which the whole contraction y_i = sum_k sum_j c_kij (K_k x_j) is unrolled:
 the output modes of a lane's row live in registers and every tensor value is
 an immediate, so the inner loop has no table lookups and no LDS traffic.
 
-Layout and launch are those of the generic kernel (kernels.hip): one lane per
-matrix row, sliced-ELL values val[(k*7 + s)*nrows + r], mode-major vectors.
-All memory accesses are buffer loads/stores: a 32-bit per-lane offset (the
-row, or a neighbour column) plus a scalar offset (the coefficient matrix and
-slot, or the mode), so no 64-bit address is kept per load.
+Layout: one lane per matrix row, sliced-ELL values val[(k*7 + s)*nrows + r],
+mode-major vectors.  A workgroup owns 64 consecutive rows; it first copies x
+at the distinct columns its rows reference (the group's "halo", built on the
+host, all P modes) into LDS with independent loads, then contracts from LDS.
+Global accesses are buffer loads/stores: a 32-bit per-lane offset (the row,
+or a halo column) plus a scalar offset (the coefficient matrix and slot, or
+the mode), so no 64-bit address is kept per load.
 The coefficient matrices are split into up to four chunks, one per wave of a
 workgroup, so four waves share the 64 rows of a workgroup (registers per lane:
-14 KC for the chunk, 2 G for G outputs of a group, 28 for the neighbour
-values of the current and the next mode); the partial outputs are added in a
-fixed order through LDS.
+7 KC for the chunk, G for G outputs of a group, 14 for the neighbour values
+of the current and the next mode, 7 halo positions); the partial outputs are
+added in a fixed order through LDS.
 
 Run:  python -m paper_2512_23027_amd.gen_k1   (build.py runs it)
 """
@@ -92,15 +94,20 @@ def entries(L, p_in, p_out):
 
 
 def kernel_source(L, p_in, p_out):
-    """One kernel per output group; a workgroup = 64 rows x NCH waves, wave w
-    contracting coefficient matrices of chunk w.  The partial outputs of the
-    waves are added in a fixed order through LDS by wave 0."""
+    """One kernel per output group; a workgroup = 64 rows x NCH waves.
+
+    The workgroup first stages x at the distinct columns of its 64 rows (the
+    group's halo, all P modes) in LDS with independent loads; wave w then
+    contracts coefficient matrices of chunk w reading the neighbour values
+    from LDS.  The partial outputs of the waves are added in a fixed order
+    through LDS (the staging buffer, reused) by wave 0."""
     nk, P, ent = entries(L, p_in, p_out)
     ngroups = (P + MAX_GROUP - 1) // MAX_GROUP
     G = (P + ngroups - 1) // ngroups
     nch = min(MAX_WAVES, nk)
     KC = (nk + nch - 1) // nch
     nch = (nk + KC - 1) // KC
+    NT = 64 * nch
     name = "k1_L%d_%d_%d" % (L, p_in, p_out)
     lines = []
     tables = []
@@ -108,33 +115,45 @@ def kernel_source(L, p_in, p_out):
         i0, i1 = g * G, min(P, (g + 1) * G)
         gs = i1 - i0
         lines.append("template <typename T>")
-        lines.append("__global__ __launch_bounds__(%d, 2) void %s_g%d(DEll<T> A, int r0, int nrows, "
+        lines.append("__global__ __launch_bounds__(%d, 2) void %s_g%d(DEll<T> A, DHalo H, int r0, int nrows, "
                      "const T* __restrict__ x, int ldx, T* __restrict__ y, int ldy, T alpha, "
-                     "T beta, long long sx, long long sy) {" % (64 * nch, name, g))
-        if nch > 1:
-            lines.append("  __shared__ T part[%d][%d][64];" % (nch - 1, gs))
+                     "T beta, long long sx, long long sy) {" % (NT, name, g))
+        lines.append("  extern __shared__ unsigned char k1_smem[];")
+        lines.append("  T* xs = reinterpret_cast<T*>(k1_smem);  // [P][hs] staged x, then partial sums")
+        lines.append("  const int hs = H.hmax;")
         lines.append("  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;")
-        lines.append("  const int rl = blockIdx.x * 64 + lane;")
+        lines.append("  const int grp = blockIdx.x;")
+        lines.append("  const int rl = grp * 64 + lane;")
         lines.append("  x += (long long)blockIdx.z * sx;")
         lines.append("  y += (long long)blockIdx.z * sy;")
         lines.append("  const bool live = rl < nrows;")
         lines.append("  const int r = r0 + (live ? rl : nrows - 1);")
         lines.append("  const int NR = A.nrows;")
-        # buffer resources: per-lane 32-bit offsets, per-mode scalar offsets
-        lines.append("  const auto rc = buf_rsrc(A.col), rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y);")
+        lines.append("  const auto rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y);")
         lines.append("  const int rb = r * (int)sizeof(T);")
+        # staging: every thread owns halo entries h, loads all P modes at once
+        lines.append("  {")
+        lines.append("    const int h0 = H.ptr[grp], nh = H.ptr[grp + 1] - h0;")
+        lines.append("    for (int h = threadIdx.x; h < nh; h += %d) {" % NT)
+        lines.append("      const int co = H.idx[h0 + h] * (int)sizeof(T);")
+        for j in range(P):
+            lines.append("      const T v%d = buf_load<T>(rx, co, %d * ldx * (int)sizeof(T));" % (j, j))
+        for j in range(P):
+            lines.append("      xs[%d * hs + h] = v%d;" % (j, j))
+        lines.append("    }")
+        lines.append("  }")
+        lines.append("  const int rr = r - H.r0;")
         for q in range(7):
-            lines.append("  const int c%d = buf_load<int>(rc, r * 4, %d * NR * 4) * (int)sizeof(T);" % (q, q))
+            lines.append("  const int l%d = (int)H.lcol[%d * H.nr + rr];" % (q, q))
         for i in range(i0, i1):
             lines.append("  T y%d = T(0);" % i)
+        lines.append("  __syncthreads();")
         for ch in range(nch):
             k0, k1 = ch * KC, min(nk, (ch + 1) * KC)
             mine = [e for e in ent if k0 <= e[0] < k1 and i0 <= e[1] < i1]
             js = [j for j in range(P) if any(e[2] == j for e in mine)]
             if not js:
                 continue
-            jt = "%s_g%d_c%d_modes" % (name, g, ch)
-            tables.append("__device__ const int %s[%d] = {%s};" % (jt, len(js), ", ".join(map(str, js))))
             lines.append("  if (wv == %d) {  // coefficient matrices %d..%d" % (ch, k0, k1 - 1))
             for k in range(k0, k1):
                 for q in range(7):
@@ -142,23 +161,22 @@ def kernel_source(L, p_in, p_out):
                                  % (k, q, k * 7 + q))
             # A runtime loop over the modes of this chunk with one switch case
             # per mode keeps every mode's contraction in its own basic block,
-            # so the register live ranges stay those of one mode; the 7
-            # neighbour values of the next mode are loaded before the switch
-            # (software pipelining).
+            # so the register live ranges stay those of one mode.  Case t
+            # first reads the 7 neighbour values of the next mode from LDS
+            # (its offset is a compile-time constant), then contracts the
+            # current mode's values.
             for q in range(7):
-                lines.append("    T n%d = buf_load<T>(rx, c%d, %d * ldx * (int)sizeof(T));" % (q, q, js[0]))
+                lines.append("    T n%d = xs[%d * hs + l%d];" % (q, js[0], q))
             lines.append("#pragma clang loop unroll(disable)")
             lines.append("    for (int t = 0; t < %d; ++t) {" % len(js))
             for q in range(7):
                 lines.append("      const T u%d = n%d;" % (q, q))
-            lines.append("      if (t + 1 < %d) {" % len(js))
-            lines.append("        const int so = %s[t + 1] * ldx * (int)sizeof(T);" % jt)
-            for q in range(7):
-                lines.append("        n%d = buf_load<T>(rx, c%d, so);" % (q, q))
-            lines.append("      }")
             lines.append("      switch (t) {")
             for t, j in enumerate(js):
                 lines.append("        case %d: {  // mode %d" % (t, j))
+                if t + 1 < len(js):
+                    for q in range(7):
+                        lines.append("          n%d = xs[%d * hs + l%d];" % (q, js[t + 1], q))
                 for k in sorted({e[0] for e in mine if e[2] == j}):
                     expr = "k%d_0 * u0" % k
                     for q in range(1, 7):
@@ -173,14 +191,16 @@ def kernel_source(L, p_in, p_out):
             lines.append("    }")
             lines.append("  }")
         if nch > 1:
+            lines.append("  __syncthreads();  // every wave is done with the staged x")
             lines.append("  if (wv > 0) {")
             for i in range(i0, i1):
-                lines.append("    part[wv - 1][%d][lane] = y%d;" % (i - i0, i))
+                lines.append("    xs[((wv - 1) * %d + %d) * 64 + lane] = y%d;" % (gs, i - i0, i))
             lines.append("  }")
             lines.append("  __syncthreads();")
             lines.append("  if (wv != 0) return;")
             for i in range(i0, i1):
-                lines.append("  y%d = %s;" % (i, " + ".join(["y%d" % i] + ["part[%d][%d][lane]" % (w, i - i0)
+                lines.append("  y%d = %s;" % (i, " + ".join(["y%d" % i] + ["xs[(%d * %d + %d) * 64 + lane]"
+                                                                       % (w, gs, i - i0)
                                                                        for w in range(nch - 1)])))
         lines.append("  if (live) {")
         for i in range(i0, i1):
@@ -191,38 +211,67 @@ def kernel_source(L, p_in, p_out):
         lines.append("")
     # dispatcher
     lines.append("template <typename T>")
-    lines.append("static void %s_launch(const DEll<T>& A, int r0, int nrows, const T* x, int ldx, T* y, "
-                 "int ldy, T alpha, T beta, int nbatch, long long sx, long long sy, hipStream_t st) {"
-                 % name)
+    lines.append("static void %s_launch(const DEll<T>& A, const DHalo& H, int r0, int nrows, const T* x, "
+                 "int ldx, T* y, int ldy, T alpha, T beta, int nbatch, long long sx, long long sy, "
+                 "hipStream_t st) {" % name)
     lines.append("  dim3 grid((nrows + 63) / 64, 1, nbatch);")
     for g in range(ngroups):
-        lines.append("  %s_g%d<T><<<grid, %d, 0, st>>>(A, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy);"
-                     % (name, g, 64 * nch))
+        gs = min(P, (g + 1) * G) - g * G
+        lines.append("  {")
+        lines.append("    const size_t sh = sizeof(T) * (size_t)std::max(%d * H.hmax, %d);" % (P, (nch - 1) * gs * 64))
+        lines.append("    %s_g%d<T><<<grid, %d, sh, st>>>(A, H, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy);"
+                     % (name, g, NT))
+        lines.append("  }")
+    lines.append("}")
+    lines.append("")
+    # LDS attribute for every kernel of this basis
+    lines.append("static bool %s_prepare() {" % name)
+    lines.append("  bool ok = true;")
+    for g in range(ngroups):
+        for T in ("float", "double"):
+            lines.append("  ok = ok && hipFuncSetAttribute((const void*)%s_g%d<%s>, "
+                         "hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;"
+                         % (name, g, T))
+    lines.append("  return ok;")
     lines.append("}")
     lines.append("")
     return "\n".join(tables + [""] + lines), name, nk, P, len(ent)
+
+
+def max_lds_modes():
+    """Largest P among the generated bases (the staged x holds P x hmax)."""
+    return max(entries(*b)[1] for b in BASES)
 
 
 def generate():
     parts = ["// Generated by gen_k1.py -- specialised SG-apply kernels, do not edit.",
              "// Bases (L, p_in, p_out): " + ", ".join(str(b) for b in BASES), ""]
     disp = ["template <typename T>",
-            "static bool sg_apply_specialised(int L, int p_in, int p_out, const DEll<T>& A, int r0, "
-            "int nrows, const T* x, int ldx, T* y, int ldy, T alpha, T beta, int nbatch, "
-            "long long sx, long long sy, hipStream_t st) {"]
+            "static bool sg_apply_specialised(int L, int p_in, int p_out, const DEll<T>& A, "
+            "const DHalo& H, int r0, int nrows, const T* x, int ldx, T* y, int ldy, T alpha, "
+            "T beta, int nbatch, long long sx, long long sy, hipStream_t st) {"]
+    prep = ["// Allows every generated kernel the whole 160 KiB of LDS (they have no",
+            "// static LDS); once per process before the first launch.",
+            "static bool sg_apply_specialised_prepare() {",
+            "  bool ok = true;"]
     for (L, pi, po) in BASES:
         src, name, nk, P, nnz = kernel_source(L, pi, po)
         parts.append("// L=%d p_in=%d p_out=%d: %d coefficient matrices, P=%d, %d tensor entries"
                      % (L, pi, po, nk, P, nnz))
         parts.append(src)
         disp.append("  if (L == %d && p_in == %d && p_out == %d) {" % (L, pi, po))
-        disp.append("    %s_launch<T>(A, r0, nrows, x, ldx, y, ldy, alpha, beta, nbatch, sx, sy, st);"
+        disp.append("    %s_launch<T>(A, H, r0, nrows, x, ldx, y, ldy, alpha, beta, nbatch, sx, sy, st);"
                     % name)
         disp.append("    return true;")
         disp.append("  }")
+        prep.append("  ok = ok && %s_prepare();" % name)
     disp.append("  return false;")
     disp.append("}")
+    prep.append("  return ok;")
+    prep.append("}")
     parts.extend(disp)
+    parts.append("")
+    parts.extend(prep)
     text = "\n".join(parts) + "\n"
     old = open(OUT).read() if os.path.exists(OUT) else None
     if old != text:
