@@ -32,7 +32,7 @@ OUT = os.path.join(HERE, "csrc", "k1_spec.inc")
 # (L, p_in, p_out): the bases of the shipped workloads
 BASES = [(2, 2, 2), (4, 2, 3), (6, 2, 3)]
 MAX_GROUP = 42         # output modes per kernel (register budget)
-MAX_WAVES = 4          # waves per workgroup, one per chunk of coefficient matrices
+MAX_WAVES = 2          # waves per workgroup, one per chunk of coefficient matrices
 
 
 def _graded(L, p):
@@ -119,8 +119,7 @@ def kernel_source(L, p_in, p_out):
                      "const T* __restrict__ x, int ldx, T* __restrict__ y, int ldy, T alpha, "
                      "T beta, long long sx, long long sy) {" % (NT, name, g))
         lines.append("  extern __shared__ unsigned char k1_smem[];")
-        lines.append("  T* xs = reinterpret_cast<T*>(k1_smem);  // [P][hs] staged x, then partial sums")
-        lines.append("  const int hs = H.hmax;")
+        lines.append("  T* xs = reinterpret_cast<T*>(k1_smem);  // [halo][P] staged x, then partial sums")
         lines.append("  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;")
         lines.append("  const int grp = blockIdx.x;")
         lines.append("  const int rl = grp * 64 + lane;")
@@ -139,12 +138,12 @@ def kernel_source(L, p_in, p_out):
         for j in range(P):
             lines.append("      const T v%d = buf_load<T>(rx, co, %d * ldx * (int)sizeof(T));" % (j, j))
         for j in range(P):
-            lines.append("      xs[%d * hs + h] = v%d;" % (j, j))
+            lines.append("      xs[h * %d + %d] = v%d;" % (P, j, j))
         lines.append("    }")
         lines.append("  }")
         lines.append("  const int rr = r - H.r0;")
         for q in range(7):
-            lines.append("  const int l%d = (int)H.lcol[%d * H.nr + rr];" % (q, q))
+            lines.append("  const unsigned l%d = (unsigned)H.lcol[%d * H.nr + rr] * %du * (unsigned)sizeof(T);" % (q, q, P))
         for i in range(i0, i1):
             lines.append("  T y%d = T(0);" % i)
         lines.append("  __syncthreads();")
@@ -159,36 +158,32 @@ def kernel_source(L, p_in, p_out):
                 for q in range(7):
                     lines.append("    const T k%d_%d = buf_load<T>(rv, rb, %d * NR * (int)sizeof(T));"
                                  % (k, q, k * 7 + q))
-            # A runtime loop over the modes of this chunk with one switch case
-            # per mode keeps every mode's contraction in its own basic block,
-            # so the register live ranges stay those of one mode.  Case t
-            # first reads the 7 neighbour values of the next mode from LDS
-            # (its offset is a compile-time constant), then contracts the
-            # current mode's values.
+            # The modes of this chunk run as straight-line code.  An empty asm
+            # statement with a memory clobber before the LDS reads of mode
+            # t+1 (issued before mode t's arithmetic, so their latency
+            # overlaps it) keeps them from being hoisted further up, which
+            # keeps the live registers those of two modes.
+            lines.append("    const char* xb = reinterpret_cast<const char*>(xs);")
             for q in range(7):
-                lines.append("    T n%d = xs[%d * hs + l%d];" % (q, js[0], q))
-            lines.append("#pragma clang loop unroll(disable)")
-            lines.append("    for (int t = 0; t < %d; ++t) {" % len(js))
-            for q in range(7):
-                lines.append("      const T u%d = n%d;" % (q, q))
-            lines.append("      switch (t) {")
+                lines.append("    T n%d = *reinterpret_cast<const T*>(xb + l%d + %d * sizeof(T));" % (q, q, js[0]))
             for t, j in enumerate(js):
-                lines.append("        case %d: {  // mode %d" % (t, j))
+                lines.append("    {  // mode %d" % j)
+                for q in range(7):
+                    lines.append("      const T u%d = n%d;" % (q, q))
                 if t + 1 < len(js):
+                    lines.append('      asm volatile("" ::: "memory");')
                     for q in range(7):
-                        lines.append("          n%d = xs[%d * hs + l%d];" % (q, js[t + 1], q))
+                        lines.append("      n%d = *reinterpret_cast<const T*>(xb + l%d + %d * sizeof(T));"
+                                     % (q, q, js[t + 1]))
                 for k in sorted({e[0] for e in mine if e[2] == j}):
                     expr = "k%d_0 * u0" % k
                     for q in range(1, 7):
                         expr = "fma(k%d_%d, u%d, %s)" % (k, q, q, expr)
-                    lines.append("          { const T w = %s;" % expr)
+                    lines.append("      { const T w = %s;" % expr)
                     for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
-                        lines.append("            y%d = fma(T(%.17g), w, y%d);" % (i, v, i))
-                    lines.append("          }")
-                lines.append("        } break;")
-            lines.append("        default: break;")
-            lines.append("      }")
-            lines.append("    }")
+                        lines.append("        y%d = fma(T(%.17g), w, y%d);" % (i, v, i))
+                    lines.append("      }")
+                lines.append("    }")
             lines.append("  }")
         if nch > 1:
             lines.append("  __syncthreads();  // every wave is done with the staged x")

@@ -3,7 +3,8 @@ backward kernels against the numpy reference (oracle/mlp.py, same bfloat16
 operand rounding, float64 accumulation), Adam training, and the solver with
 SGW_GUESS_LEARNED on the 32x32, P = 6 problem: trained on trajectories of the
 training seeds, run on held-out seeds, its results match the oracle to the
-same bound as the other guesses and the iterations it saves are reported.
+same bound as the other guesses (1e-10 at rtol 1e-12, the FP64 bound) and
+the iterations it saves are reported.
 
 Tolerances: forward and gradient relative L2 error <= 2e-3 (a float32
 intermediate that falls next to a bfloat16 rounding boundary may round the
@@ -49,7 +50,7 @@ def test_forward_and_gradient_match_reference(sgw, ng, H, nb):
     g = g.cpu().numpy()
     W1, b1, W2, b2, W3, b3 = ref.unpack(np.arange(w.size), ng, H)
     for part in (W1, b1, W2, b2, W3, b3):  # every block of the gradient
-        idx = part.ravel()
+        idx = part.ravel().astype(np.int64)
         assert _rel(g[idx], gr[idx]) <= 2e-3
     m.close()
 
@@ -73,7 +74,7 @@ def test_params_roundtrip_and_training_reduces_loss(sgw):
 
 
 def _run(sgw, prm, nsteps, guess, model=None, record=None):
-    s = sgw.Solver(prm, rtol=1e-10, inner_rtol=1e-12, guess=guess)
+    s = sgw.Solver(prm, rtol=1e-12, inner_rtol=1e-14, guess=guess)
     s.factor()
     s.set_state()
     if model is not None:
@@ -120,7 +121,7 @@ def test_learned_guess_trained_on_own_trajectories(sgw):
                         ("learned", sgw.SGW_GUESS_LEARNED)):
             st, m, sd_, _, fb = _run(sgw, prm, 40, g, model=model)
             assert st["status"] == 0
-            assert rel_l2(m, mo) < 1e-9 and rel_l2(sd_, so) < 1e-9, (name, sd)
+            assert rel_l2(m, mo) < 1e-10 and rel_l2(sd_, so) < 1e-10, (name, sd)
             its[name] += st["outer_iters"]
     print("outer PCG iterations over %d held-out runs x 40 steps: %s (training loss %.3e)"
           % (len(test_seeds), its, loss))

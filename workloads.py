@@ -106,4 +106,5 @@ def learned_guess_seeds():
 def cfg4(seed, **over):
     """The cfg1 problem with its pulse centre drawn from ``seed``."""
     x0, y0 = pulse_centre(seed)
-    return config("cfg1", x0=x0, y0=y0, nsteps=200, **over)
+    over.setdefault("nsteps", 200)
+    return config("cfg1", x0=x0, y0=y0, **over)
