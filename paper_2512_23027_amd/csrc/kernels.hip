@@ -802,15 +802,16 @@ void gather_from_torn(int nG, int P, const int* gptr, const int* gtorn, const do
 
 template <typename T, int Q, int RPT>
 __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
-    DEll<T> A, const int* __restrict__ row_off, const double* __restrict__ iv, int P, int deg,
+    DEll<T> A, const int* __restrict__ row_off, const int* __restrict__ crow,
+    const unsigned short* __restrict__ cnb, const double* __restrict__ iv, int P, int deg,
     const T* __restrict__ r, int ldr, T* __restrict__ z, int ldz, double* __restrict__ part,
     double* __restrict__ part2, double* sc, int par, double tol2, const double* rrpart,
     int* flags) {
   // all LDS is dynamic (so the launch may use up to the whole 160 KiB):
-  // the reduction slots, then the current search direction [Q][n]
+  // the reduction slots, then two buffers of the search direction [Q][n]
   extern __shared__ unsigned char smem_raw[];
   double(*red)[CHEB_TPB / 64][Q] = reinterpret_cast<double(*)[CHEB_TPB / 64][Q]>(smem_raw);
-  T* Dk = reinterpret_cast<T*>(smem_raw + sizeof(double) * 2 * (CHEB_TPB / 64) * Q);
+  T* Dk0 = reinterpret_cast<T*>(smem_raw + sizeof(double) * 2 * (CHEB_TPB / 64) * Q);
   const int b = blockIdx.x, j0 = blockIdx.y * Q;
   if (sc) {  // stopping test of PCG iteration par, fused (see k_pcg_test)
     const double rr = sum_modes(rrpart, b, P);
@@ -829,24 +830,28 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
   const double delta = fmax(0.5 * (hi - lo), 1e-3 * theta);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
-  int lc[RPT][7];
+  // thread i owns the row at natural (lexicographic mesh) position i of the
+  // block, crow[r0 + i]; the LDS copy of the direction is in natural order,
+  // so the neighbour reads of a wave are nearly contiguous (few bank
+  // conflicts); cnb gives the neighbours' natural positions
+  int lc[RPT][7], row[RPT];
   T av[RPT][7], dinv[RPT];
   T res[RPT][Q], zz[RPT][Q], dd[RPT][Q];
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int i = threadIdx.x + t * CHEB_TPB;
     const bool live = i < n;
+    row[t] = live ? crow[r0 + i] : r0;
 #pragma unroll
     for (int sl = 0; sl < 7; ++sl) {
-      const size_t o = (size_t)sl * NR + r0 + (live ? i : 0);
-      lc[t][sl] = live ? A.col[o] - r0 : 0;
-      av[t][sl] = live ? A.val[o] : T(0);
+      lc[t][sl] = live ? (int)cnb[(size_t)sl * NR + r0 + i] : 0;
+      av[t][sl] = live ? A.val[(size_t)sl * NR + row[t]] : T(0);
     }
     dinv[t] = live ? T(1) / av[t][0] : T(0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int j = j0 + q;
-      const T v = (live && j < P) ? r[(size_t)j * ldr + r0 + i] : T(0);
+      const T v = (live && j < P) ? r[(size_t)j * ldr + row[t]] : T(0);
       res[t][q] = v;
       zz[t][q] = T(0);
       dd[t][q] = dinv[t] * v * (T)(1.0 / theta);
@@ -858,7 +863,10 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
 #pragma unroll
       for (int q = 0; q < Q; ++q) zz[t][q] += dd[t][q];
     if (k + 1 == deg) break;
-    __syncthreads();  // every read of the previous direction is done
+    // step k writes buffer k&1; the buffer written two steps earlier is free
+    // because every thread has passed the barrier of step k-1, after its
+    // reads of step k-2
+    T* Dk = Dk0 + (size_t)(k & 1) * Q * n;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int i = threadIdx.x + t * CHEB_TPB;
@@ -896,8 +904,8 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     for (int q = 0; q < Q; ++q) {
       const int j = j0 + q;
       if (j >= P) continue;
-      z[(size_t)j * ldz + r0 + i] = zz[t][q];
-      const double rv = (double)r[(size_t)j * ldr + r0 + i];
+      z[(size_t)j * ldz + row[t]] = zz[t][q];
+      const double rv = (double)r[(size_t)j * ldr + row[t]];
       srz[q] += rv * (double)zz[t][q];
       srr[q] += rv * rv;
     }
@@ -927,7 +935,7 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
 
 template <typename T>
 size_t cheb_lds_bytes(int max_rows, int Q) {
-  return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + (size_t)max_rows * Q * sizeof(T);
+  return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + 2 * (size_t)max_rows * Q * sizeof(T);
 }
 
 struct ChebTest {  // optional fused stopping test (sc == nullptr: none)
@@ -939,24 +947,26 @@ struct ChebTest {  // optional fused stopping test (sc == nullptr: none)
 };
 
 template <typename T, int Q, int RPT>
-static void launch_cheb(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P,
+static void launch_cheb(const DEll<T>& A, const int* row_off, const int* crow,
+                        const unsigned short* cnb, const double* iv, int nb, int P,
                         int deg, int max_rows, const T* r, int ldr, T* z, int ldz,
                         double* part, double* part2, const ChebTest& t, hipStream_t st) {
   dim3 grid(nb, ceil_div(P, Q));
   k_cheb<T, Q, RPT><<<grid, CHEB_TPB, cheb_lds_bytes<T>(max_rows, Q), st>>>(
-      A, row_off, iv, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par, t.tol2, t.rrpart,
-      t.flags);
+      A, row_off, crow, cnb, iv, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par, t.tol2,
+      t.rrpart, t.flags);
 }
 
 template <typename T, int RPT>
-static void cheb_q(int Q, const DEll<T>& A, const int* row_off, const double* iv, int nb, int P,
+static void cheb_q(int Q, const DEll<T>& A, const int* row_off, const int* crow,
+                   const unsigned short* cnb, const double* iv, int nb, int P,
                    int deg, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                    double* part2, const ChebTest& t, hipStream_t st) {
   switch (Q) {
 #define SGW_CHEB_CASE(q)                                                                      \
   case q:                                                                                    \
-    launch_cheb<T, q, RPT>(A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, \
-                           t, st);                                                           \
+    launch_cheb<T, q, RPT>(A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz,   \
+                           part, part2, t, st);                                              \
     break;
     SGW_CHEB_CASE(1)
     SGW_CHEB_CASE(2)
@@ -1010,21 +1020,25 @@ int cheb_max_q(int max_rows) {
 }
 
 template <typename T>
-int cheb_apply(const DEll<T>& A, const int* row_off, const double* iv, int nb, int P, int deg,
+int cheb_apply(const DEll<T>& A, const int* row_off, const int* crow, const unsigned short* cnb,
+               const double* iv, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                double* part2, double* sc, int par, double tol2, const double* rrpart,
                int* flags, hipStream_t st) {
   if (Q < 1 || Q > cheb_max_q<T>(max_rows) || deg < 1 || max_rows < 1 ||
       max_rows > 4 * CHEB_TPB || cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024 ||
-      (sc && (!rrpart || !flags)))
+      (sc && (!rrpart || !flags)) || !crow || !cnb)
     return -1;
   const ChebTest t{sc, par, tol2, rrpart, flags};
   if (max_rows <= CHEB_TPB)
-    cheb_q<T, 1>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, t, st);
+    cheb_q<T, 1>(Q, A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
+                 t, st);
   else if (max_rows <= 2 * CHEB_TPB)
-    cheb_q<T, 2>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, t, st);
+    cheb_q<T, 2>(Q, A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
+                 t, st);
   else
-    cheb_q<T, 4>(Q, A, row_off, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2, t, st);
+    cheb_q<T, 4>(Q, A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
+                 t, st);
   return 0;
 }
 
@@ -1131,10 +1145,12 @@ template size_t cheb_lds_bytes<double>(int, int);
 template int cheb_max_q<double>(int);
 template int cheb_max_q<float>(int);
 template size_t cheb_lds_bytes<float>(int, int);
-template int cheb_apply<double>(const DEll<double>&, const int*, const double*, int, int, int,
+template int cheb_apply<double>(const DEll<double>&, const int*, const int*,
+                                const unsigned short*, const double*, int, int, int,
                                 int, int, const double*, int, double*, int, double*, double*,
                                 double*, int, double, const double*, int*, hipStream_t);
-template int cheb_apply<float>(const DEll<float>&, const int*, const double*, int, int, int,
+template int cheb_apply<float>(const DEll<float>&, const int*, const int*, const unsigned short*,
+                               const double*, int, int, int,
                                int, int, const float*, int, float*, int, double*, double*,
                                double*, int, double, const double*, int*, hipStream_t);
 template size_t tri_lds_bytes<float>(const DFactor&, int);

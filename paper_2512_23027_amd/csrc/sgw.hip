@@ -43,6 +43,8 @@ struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   int cq = 8, max_block_rows = 0;     // Chebyshev mode tile, largest block
   const k::DHalo* halo = nullptr;     // 64-row group halos of A (both precisions)
   const double* cheb_iv = nullptr;    // device, [nb][2] spectral intervals
+  const int* crow = nullptr;          // device, system row of each natural block position
+  const unsigned short* cnb = nullptr;  // device, [7][nrows] neighbours' natural positions
   int last_its[2] = {0, 0};     // previous iteration counts (tight / loose tolerance)
   double loose_tol = 1e300;     // tolerances >= this use the second count
   k::DEll<T> A;
@@ -349,7 +351,7 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
   if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
     const int kind = sizeof(T) == 4 ? 5 : 2;
     int a = prof_begin(c, kind, st);
-    (void)k::cheb_apply<T>(S.A, S.row_off, S.cheb_iv, S.nb, P, c->cheb_deg, S.cq,
+    (void)k::cheb_apply<T>(S.A, S.row_off, S.crow, S.cnb, S.cheb_iv, S.nb, P, c->cheb_deg, S.cq,
                            S.max_block_rows, S.r, n, S.z, n, part, part2,
                            test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
                            c->part2, c->flags, st);
@@ -781,6 +783,37 @@ static bool spd_inverse(std::vector<double>& A, int n) {
 
 // Device state of one precision: operator values (FP32 copies for the
 // refinement path), system workspaces and interface vectors.
+// Natural (lexicographic mesh) order of the rows of every block of a
+// subdomain system: crow[r0 + i] = system row at position i of block
+// [r0, r1), cnb[s*nrows + r0 + i] = block-local position of that row's slot-s
+// neighbour.  mesh_of(row) gives a row's mesh node.
+template <class MeshOf>
+static void natural_order(sgw_ctx* c, const Ell& E, const std::vector<int>& off, MeshOf mesh_of,
+                          const int** crow_d, const unsigned short** cnb_d) {
+  const int NR = E.nrows, n1 = c->h.n + 1;
+  std::vector<int> crow(NR > 0 ? NR : 1), pos(NR > 0 ? NR : 1);
+  std::vector<unsigned short> cnb((size_t)E.W * std::max(NR, 1), 0);
+  for (size_t b = 0; b + 1 < off.size(); ++b) {
+    const int r0 = off[b], r1 = off[b + 1];
+    std::vector<int> rows;
+    for (int r = r0; r < r1; ++r) rows.push_back(r);
+    std::sort(rows.begin(), rows.end(), [&](int a, int q) {
+      const int va = mesh_of(a), vq = mesh_of(q);
+      return std::make_pair(va / n1, va % n1) < std::make_pair(vq / n1, vq % n1);
+    });
+    for (int i = 0; i < r1 - r0; ++i) {
+      crow[r0 + i] = rows[i];
+      pos[rows[i]] = i;
+    }
+  }
+  for (size_t b = 0; b + 1 < off.size(); ++b)
+    for (int i = off[b]; i < off[b + 1]; ++i)
+      for (int s = 0; s < E.W; ++s)
+        cnb[(size_t)s * NR + i] = (unsigned short)pos[E.col[(size_t)s * NR + crow[i]]];
+  *crow_d = upload(c, crow);
+  *cnb_d = upload(c, cnb);
+}
+
 // 64-row group halos of an ELL matrix for rows [r0, nrows) (see k::DHalo).
 static k::DHalo build_halo(sgw_ctx* c, const Ell& E, int r0) {
   k::DHalo H;
@@ -875,6 +908,16 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
   pr.N.max_block_rows = maxblk(h.Toff);
   pr.D.halo = &c->hal_D;
   pr.N.halo = &c->hal_N;
+  if constexpr (sizeof(T) == 8) {
+    natural_order(c, h.dir, h.Ioff, [&](int r) { return h.dd2mesh[r]; }, &pr.D.crow, &pr.D.cnb);
+    natural_order(c, h.neu, h.Toff, [&](int r) { return h.dd2mesh[h.torn2dd[r]]; }, &pr.N.crow,
+                  &pr.N.cnb);
+  } else {
+    pr.D.crow = c->d64.D.crow;
+    pr.D.cnb = c->d64.D.cnb;
+    pr.N.crow = c->d64.N.crow;
+    pr.N.cnb = c->d64.N.cnb;
+  }
   for (SysT<T>* S : {&pr.D, &pr.N}) {
     const int qmax = std::max(1, k::cheb_max_q<T>(S->max_block_rows));
     int ntiles = (P + qmax - 1) / qmax;
@@ -990,7 +1033,8 @@ static bool prec_complete(const PrecT<T>& pr, bool refine) {
   const void* ps[] = {pr.G.col, pr.G.val, pr.G.mval, pr.D.A.col, pr.D.A.val, pr.N.A.col,
                       pr.N.A.val, pr.D.x, pr.D.r, pr.D.z, pr.D.p, pr.D.q, pr.N.x, pr.N.r,
                       pr.N.z, pr.N.p, pr.N.q, pr.X, pr.R, pr.Z, pr.Zp, pr.Pw, pr.Qw, pr.T1,
-                      pr.Gv, pr.Tt, pr.Yt, pr.D.row_off, pr.N.row_off};
+                      pr.Gv, pr.Tt, pr.Yt, pr.D.row_off, pr.N.row_off, pr.D.crow, pr.D.cnb,
+                      pr.N.crow, pr.N.cnb, pr.D.cheb_iv, pr.N.cheb_iv};
   for (const void* p : ps)
     if (!p) return false;
   return !refine || (pr.Fb && pr.Xb);
@@ -1118,7 +1162,7 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
             k::cheb_lds_bytes<T>(S.max_block_rows, q) > 150 * 1024)
           continue;
         double us = time_it([&] {
-          (void)k::cheb_apply<T>(S.A, S.row_off, S.cheb_iv, S.nb, c->P, c->cheb_deg, q,
+          (void)k::cheb_apply<T>(S.A, S.row_off, S.crow, S.cnb, S.cheb_iv, S.nb, c->P, c->cheb_deg, q,
                                  S.max_block_rows, S.r, S.nrows, S.z, S.nrows, c->part,
                                  c->part2, nullptr, 0, 0.0, nullptr, nullptr, st);
         });
