@@ -149,6 +149,16 @@ int sgw_get_state(sgw_ctx* ctx, double* U, double* V, double* A, int where,
  * error code. */
 int sgw_step(sgw_ctx* ctx, int nsteps, void* stream, sgw_step_stats* stats);
 
+/* Several independent problems (contexts, all distinct, on this device) in
+ * one call: every context advances nsteps steps on its own stream --
+ * streams[i], or when streams is NULL a non-blocking stream the context
+ * creates and owns -- from its own host thread, so the problems' kernels
+ * overlap on the GPU.  stats and status (may be NULL) receive each
+ * context's statistics and return code.  Returns the first error, else
+ * SGW_NOT_CONVERGED if any context reported it, else 0. */
+int sgw_step_batch(sgw_ctx** ctx, int n, int nsteps, void** streams,
+                   sgw_step_stats* stats, int* status);
+
 /* Mean (mode 0) and variance (sum of squares of modes >= 1, normalised
  * basis) of U over all (n+1)^2 mesh nodes; either pointer may be NULL. */
 int sgw_read_moments(sgw_ctx* ctx, double* mean, double* var, int where,

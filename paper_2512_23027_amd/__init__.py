@@ -29,7 +29,8 @@ EXPORTS = ["sgw_create", "sgw_factor", "sgw_set_state", "sgw_get_state",
            "sgw_query", "sgw_last_error", "sgw_destroy", "sgw_profile",
            "sgw_profile_read", "sgw_autotune", "sgw_mlp_create", "sgw_mlp_destroy",
            "sgw_mlp_last_error", "sgw_mlp_num_params", "sgw_mlp_params", "sgw_mlp_forward",
-           "sgw_mlp_loss_grad", "sgw_mlp_train", "sgw_guess_record", "sgw_set_guess_model"]
+           "sgw_mlp_loss_grad", "sgw_mlp_train", "sgw_guess_record", "sgw_set_guess_model",
+           "sgw_step_batch"]
 NOT_INT = ("sgw_query", "sgw_last_error", "sgw_mlp_last_error", "sgw_mlp_num_params")
 
 
@@ -111,6 +112,8 @@ def lib():
         L.sgw_mlp_train.argtypes = [vp, vp, vp, ip, ip, ip, dp, ull, vp, fp]
         L.sgw_guess_record.argtypes = [vp, vp, vp, ctypes.c_longlong]
         L.sgw_set_guess_model.argtypes = [vp, vp]
+        L.sgw_step_batch.argtypes = [ctypes.POINTER(vp), ip, ip, ctypes.POINTER(vp),
+                                     ctypes.POINTER(StepStats), ctypes.POINTER(ip)]
         for name in EXPORTS:
             if name not in NOT_INT:
                 getattr(L, name).restype = ip
@@ -323,6 +326,27 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def step_batch(solvers, nsteps=1):
+    """Advance several independent problems together (sgw_step_batch): each
+    on its own stream and host thread, their kernels overlapping on the GPU.
+    Returns one statistics dict (with "status") per solver."""
+    n = len(solvers)
+    ctxs = (ctypes.c_void_p * n)(*[s.ctx.value for s in solvers])
+    stats = (StepStats * n)()
+    status = (ctypes.c_int * n)()
+    rc = lib().sgw_step_batch(ctxs, n, nsteps, None, stats, status)
+    for s, r in zip(solvers, status):
+        s._check(r, "sgw_step_batch")
+    if rc < 0:
+        raise SGWError("sgw_step_batch failed: %s" % ERRORS.get(rc, rc))
+    out = []
+    for st, r in zip(stats, status):
+        d = st.as_dict()
+        d["status"] = r
+        out.append(d)
+    return out
 
 
 class GuessModel:

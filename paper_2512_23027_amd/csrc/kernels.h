@@ -76,6 +76,7 @@ struct DFactor {
   const double *lr_val, *lc_val, *dinv, *dinvT;  // dinv row-major, dinvT column-major
   const float *lr_valf, *lc_valf, *dinvf, *dinvTf;
   int max_rows = 0, max_level_rows = 0, max_sn = 0, max_levels = 0, max_lvl_d = 0;
+  const int* order = nullptr;  // launch order of the blocks (largest first), may be null
 };
 template <typename T>
 size_t tri_lds_bytes(const DFactor& f, int Q);
@@ -85,7 +86,8 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
 
 // Chebyshev polynomial preconditioner (degree deg, Q modes per workgroup) on
 // the blocks of A's mean matrix; iv[2b], iv[2b+1] = spectral interval of
-// block b; crow[r0 + i] = system row at natural (lexicographic) position i
+// block b; order (may be null) = launch order of the blocks (largest
+// first); crow[r0 + i] = system row at natural (lexicographic) position i
 // of the block starting at r0, cnb[s*nrows + r0 + i] = natural position of
 // that row's slot-s neighbour within the block.  Writes z and part[b*P + j] = r_j'z_j (part2 = r_j'r_j if not
 // null).  With sc != null it first does the PCG stopping test of iteration
@@ -101,8 +103,8 @@ int cheb_max_q(int max_rows);
 // 160 KiB of LDS.  0 on success, -1 on a HIP error.
 int cheb_prepare();
 template <typename T>
-int cheb_apply(const DEll<T>& A, const int* row_off, const int* crow, const unsigned short* cnb,
-               const double* iv, int nb, int P, int deg,
+int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int* crow,
+               const unsigned short* cnb, const double* iv, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                double* part2, double* sc, int par, double tol2, const double* rrpart,
                int* flags, hipStream_t st);

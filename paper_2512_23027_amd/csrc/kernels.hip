@@ -227,7 +227,7 @@ __global__ __launch_bounds__(TRI_TPB) void k_tri_solve(
   int* s_lsn = s_lrow + f.max_levels + 1;     // level -> first supernode
   int* s_gf = s_lsn + f.max_levels + 1;
   int* s_gb = s_gf + f.max_levels + 1;
-  const int b = blockIdx.x;
+  const int b = f.order ? f.order[blockIdx.x] : blockIdx.x;  // largest blocks first
   const int q0 = blockIdx.y * Q;
   rhs += (long long)blockIdx.z * sr;
   out += (long long)blockIdx.z * so;
@@ -802,8 +802,9 @@ void gather_from_torn(int nG, int P, const int* gptr, const int* gtorn, const do
 
 template <typename T, int Q, int RPT>
 __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
-    DEll<T> A, const int* __restrict__ row_off, const int* __restrict__ crow,
-    const unsigned short* __restrict__ cnb, const double* __restrict__ iv, int P, int deg,
+    DEll<T> A, const int* __restrict__ row_off, const int* __restrict__ order,
+    const int* __restrict__ crow, const unsigned short* __restrict__ cnb,
+    const double* __restrict__ iv, int P, int deg,
     const T* __restrict__ r, int ldr, T* __restrict__ z, int ldz, double* __restrict__ part,
     double* __restrict__ part2, double* sc, int par, double tol2, const double* rrpart,
     int* flags) {
@@ -812,7 +813,7 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
   extern __shared__ unsigned char smem_raw[];
   double(*red)[CHEB_TPB / 64][Q] = reinterpret_cast<double(*)[CHEB_TPB / 64][Q]>(smem_raw);
   T* Dk0 = reinterpret_cast<T*>(smem_raw + sizeof(double) * 2 * (CHEB_TPB / 64) * Q);
-  const int b = blockIdx.x, j0 = blockIdx.y * Q;
+  const int b = order ? order[blockIdx.x] : blockIdx.x, j0 = blockIdx.y * Q;
   if (sc) {  // stopping test of PCG iteration par, fused (see k_pcg_test)
     const double rr = sum_modes(rrpart, b, P);
     const bool act = sc[(size_t)b * 8 + 2 + par] != 0.0 && rr > tol2 * sc[(size_t)b * 8 + 4];
@@ -938,7 +939,8 @@ size_t cheb_lds_bytes(int max_rows, int Q) {
   return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + 2 * (size_t)max_rows * Q * sizeof(T);
 }
 
-struct ChebTest {  // optional fused stopping test (sc == nullptr: none)
+struct ChebTest {  // optional fused stopping test (sc == nullptr: none), block order
+  const int* order;
   double* sc;
   int par;
   double tol2;
@@ -953,8 +955,8 @@ static void launch_cheb(const DEll<T>& A, const int* row_off, const int* crow,
                         double* part, double* part2, const ChebTest& t, hipStream_t st) {
   dim3 grid(nb, ceil_div(P, Q));
   k_cheb<T, Q, RPT><<<grid, CHEB_TPB, cheb_lds_bytes<T>(max_rows, Q), st>>>(
-      A, row_off, crow, cnb, iv, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par, t.tol2,
-      t.rrpart, t.flags);
+      A, row_off, t.order, crow, cnb, iv, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par,
+      t.tol2, t.rrpart, t.flags);
 }
 
 template <typename T, int RPT>
@@ -1020,8 +1022,8 @@ int cheb_max_q(int max_rows) {
 }
 
 template <typename T>
-int cheb_apply(const DEll<T>& A, const int* row_off, const int* crow, const unsigned short* cnb,
-               const double* iv, int nb, int P, int deg,
+int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int* crow,
+               const unsigned short* cnb, const double* iv, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                double* part2, double* sc, int par, double tol2, const double* rrpart,
                int* flags, hipStream_t st) {
@@ -1029,7 +1031,7 @@ int cheb_apply(const DEll<T>& A, const int* row_off, const int* crow, const unsi
       max_rows > 4 * CHEB_TPB || cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024 ||
       (sc && (!rrpart || !flags)) || !crow || !cnb)
     return -1;
-  const ChebTest t{sc, par, tol2, rrpart, flags};
+  const ChebTest t{order, sc, par, tol2, rrpart, flags};
   if (max_rows <= CHEB_TPB)
     cheb_q<T, 1>(Q, A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
                  t, st);
@@ -1145,12 +1147,12 @@ template size_t cheb_lds_bytes<double>(int, int);
 template int cheb_max_q<double>(int);
 template int cheb_max_q<float>(int);
 template size_t cheb_lds_bytes<float>(int, int);
-template int cheb_apply<double>(const DEll<double>&, const int*, const int*,
+template int cheb_apply<double>(const DEll<double>&, const int*, const int*, const int*,
                                 const unsigned short*, const double*, int, int, int,
                                 int, int, const double*, int, double*, int, double*, double*,
                                 double*, int, double, const double*, int*, hipStream_t);
-template int cheb_apply<float>(const DEll<float>&, const int*, const int*, const unsigned short*,
-                               const double*, int, int, int,
+template int cheb_apply<float>(const DEll<float>&, const int*, const int*, const int*,
+                               const unsigned short*, const double*, int, int, int,
                                int, int, const float*, int, float*, int, double*, double*,
                                double*, int, double, const double*, int*, hipStream_t);
 template size_t tri_lds_bytes<float>(const DFactor&, int);

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -43,6 +44,7 @@ struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   int cq = 8, max_block_rows = 0;     // Chebyshev mode tile, largest block
   const k::DHalo* halo = nullptr;     // 64-row group halos of A (both precisions)
   const double* cheb_iv = nullptr;    // device, [nb][2] spectral intervals
+  const int* lpt = nullptr;           // device, blocks by decreasing size (launch order)
   const int* crow = nullptr;          // device, system row of each natural block position
   const unsigned short* cnb = nullptr;  // device, [7][nrows] neighbours' natural positions
   int last_its[2] = {0, 0};     // previous iteration counts (tight / loose tolerance)
@@ -129,6 +131,7 @@ struct sgw_ctx {
   int hist_n = 0, hist_pos = 0;
   float *mx = nullptr, *my = nullptr;
   sgw_mlp* mlp = nullptr;
+  hipStream_t own_stream = nullptr;  // created by sgw_step_batch when no stream is given
   float *rec_x = nullptr, *rec_t = nullptr;
   long long rec_cap = 0, rec_n = 0;
   long long guess_fallbacks = 0;  // learned guesses replaced by the Newmark guess
@@ -351,7 +354,8 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
   if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
     const int kind = sizeof(T) == 4 ? 5 : 2;
     int a = prof_begin(c, kind, st);
-    (void)k::cheb_apply<T>(S.A, S.row_off, S.crow, S.cnb, S.cheb_iv, S.nb, P, c->cheb_deg, S.cq,
+    (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_iv, S.nb, P, c->cheb_deg,
+                           S.cq,
                            S.max_block_rows, S.r, n, S.z, n, part, part2,
                            test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
                            c->part2, c->flags, st);
@@ -908,6 +912,25 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
   pr.N.max_block_rows = maxblk(h.Toff);
   pr.D.halo = &c->hal_D;
   pr.N.halo = &c->hal_N;
+  // largest blocks first (longest-processing-time order for the per-block
+  // kernels; matters for uneven partitions)
+  auto lpt = [&](const std::vector<int>& off) {
+    std::vector<int> o(off.size() - 1);
+    for (size_t b = 0; b < o.size(); ++b) o[b] = (int)b;
+    std::stable_sort(o.begin(), o.end(), [&](int a, int q) {
+      return off[a + 1] - off[a] > off[q + 1] - off[q];
+    });
+    return o;
+  };
+  if constexpr (sizeof(T) == 8) {
+    pr.D.lpt = upload(c, lpt(h.Ioff));
+    pr.N.lpt = upload(c, lpt(h.Toff));
+    pr.D.F.order = pr.D.lpt;
+    pr.N.F.order = pr.N.lpt;
+  } else {
+    pr.D.lpt = c->d64.D.lpt;
+    pr.N.lpt = c->d64.N.lpt;
+  }
   if constexpr (sizeof(T) == 8) {
     natural_order(c, h.dir, h.Ioff, [&](int r) { return h.dd2mesh[r]; }, &pr.D.crow, &pr.D.cnb);
     natural_order(c, h.neu, h.Toff, [&](int r) { return h.dd2mesh[h.torn2dd[r]]; }, &pr.N.crow,
@@ -1162,7 +1185,8 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
             k::cheb_lds_bytes<T>(S.max_block_rows, q) > 150 * 1024)
           continue;
         double us = time_it([&] {
-          (void)k::cheb_apply<T>(S.A, S.row_off, S.crow, S.cnb, S.cheb_iv, S.nb, c->P, c->cheb_deg, q,
+          (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_iv, S.nb, c->P,
+                                 c->cheb_deg, q,
                                  S.max_block_rows, S.r, S.nrows, S.z, S.nrows, c->part,
                                  c->part2, nullptr, 0, 0.0, nullptr, nullptr, st);
         });
@@ -1243,6 +1267,7 @@ int sgw_destroy(sgw_ctx* c) {
     else (void)hipFree(p);
   }
   if (c->hflags) (void)hipHostFree(c->hflags);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
   return 0;
 }
@@ -1749,6 +1774,45 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
   s.inner_solves = c->inner_solves;
   if (stats) *stats = s;
   return warn ? SGW_NOT_CONVERGED : 0;
+}
+
+// H9: several independent problems in one call.  Each context advances on
+// its own stream from its own host thread, so the kernels of the problems
+// overlap on the GPU while every problem keeps its own convergence checks.
+int sgw_step_batch(sgw_ctx** ctx, int n, int nsteps, void** streams, sgw_step_stats* stats,
+                   int* status) {
+  if (!ctx || n <= 0 || nsteps < 0) return SGW_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctx[i]) return SGW_EINVAL;
+    for (int q = 0; q < i; ++q)
+      if (ctx[q] == ctx[i]) return SGW_EINVAL;  // a context is not thread-safe
+  }
+  for (int i = 0; i < n; ++i)
+    if (!streams && !ctx[i]->own_stream &&
+        hipStreamCreateWithFlags(&ctx[i]->own_stream, hipStreamNonBlocking) != hipSuccess) {
+      ctx[i]->err = "stream creation failed";
+      return SGW_EHIP;
+    }
+  std::vector<int> rc(n, 0);
+  std::vector<std::thread> th;
+  th.reserve(n);
+  for (int i = 0; i < n; ++i)
+    th.emplace_back([&, i] {
+      if (hipSetDevice(ctx[i]->dev) != hipSuccess) {
+        rc[i] = SGW_EHIP;
+        return;
+      }
+      void* st = streams ? streams[i] : (void*)ctx[i]->own_stream;
+      rc[i] = sgw_step(ctx[i], nsteps, st, stats ? &stats[i] : nullptr);
+    });
+  for (auto& t : th) t.join();
+  int worst = 0;
+  for (int i = 0; i < n; ++i) {
+    if (status) status[i] = rc[i];
+    if (rc[i] < 0 && worst >= 0) worst = rc[i];
+    if (rc[i] > 0 && worst == 0) worst = SGW_NOT_CONVERGED;
+  }
+  return worst;
 }
 
 int sgw_solve(sgw_ctx* c, const double* F, double* U, void* stream, sgw_step_stats* stats) {
