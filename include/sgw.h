@@ -90,6 +90,9 @@ typedef struct sgw_problem_desc {
                             approximates it by a Chebyshev polynomial in the
                             Jacobi-scaled mean matrix (blocks of <= 4096 rows) */
   int cheb_degree;       /* degree of that polynomial (<= 0: 4; at most 64) */
+  int graphs;            /* != 0: subdomain PCG iterations that need no host check run
+                            as replays of captured HIP graphs (pairs of iterations);
+                            results are identical, timing kernels (sgw_profile) off */
 } sgw_problem_desc;
 
 /* Optional device allocator.  alloc returns device memory of >= bytes
@@ -215,7 +218,7 @@ int sgw_autotune(sgw_ctx* ctx, void* stream, double* report, int nreport);
 /* Sizes and counters: what = 0 P, 1 number of input PCE terms, 2 free
  * nodes, 3 interface nodes (n_gamma), 4 corner nodes, 5 subdomains,
  * 6 (n+1)^2, 7 training samples recorded since sgw_guess_record,
- * 8 learned guesses replaced by the Newmark guess. */
+ * 8 learned guesses replaced by the Newmark guess, 9 graph replays. */
 long long sgw_query(const sgw_ctx* ctx, int what);
 
 /* ---- Learned initial guess of the interface PCG ----------------------

@@ -48,7 +48,7 @@ class ProblemDesc(ctypes.Structure):
                 ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int),
                 ("precond_rtol", ctypes.c_double), ("inner_prec", ctypes.c_int),
-                ("cheb_degree", ctypes.c_int)]
+                ("cheb_degree", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -143,7 +143,7 @@ class Solver:
     def __init__(self, prm, rtol=None, inner_rtol=None, max_iter=1000,
                  inner_max_iter=1000, precision=SGW_FP64, guess=SGW_GUESS_PREV,
                  precond_rtol=None, inner_prec=SGW_INNER_CHOLESKY, cheb_degree=0,
-                 use_torch_allocator=True):
+                 graphs=False, use_torch_allocator=True):
         import torch
         self.torch = torch
         L = lib()
@@ -167,6 +167,7 @@ class Solver:
         d.precision, d.guess = precision, guess
         d.precond_rtol = precond_rtol if precond_rtol is not None else 0.0
         d.inner_prec, d.cheb_degree = inner_prec, cheb_degree
+        d.graphs = 1 if graphs else 0
         self.desc = d
         self._live = {}
         al = None
@@ -308,6 +309,9 @@ class Solver:
 
     def guess_fallbacks(self):
         return lib().sgw_query(self.ctx, 8)
+
+    def graph_launches(self):
+        return lib().sgw_query(self.ctx, 9)
 
     def set_guess_model(self, model):
         """Network used when the solver runs with guess=SGW_GUESS_LEARNED."""

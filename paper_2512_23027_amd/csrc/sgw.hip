@@ -132,6 +132,19 @@ struct sgw_ctx {
   float *mx = nullptr, *my = nullptr;
   sgw_mlp* mlp = nullptr;
   hipStream_t own_stream = nullptr;  // created by sgw_step_batch when no stream is given
+  // captured pairs of inner PCG iterations (desc.graphs): key = system,
+  // tolerance; captured on cap_stream, replayed on the solve's stream
+  bool use_graphs = false;
+  hipStream_t cap_stream = nullptr;
+  struct GraphKey {
+    const void* sys;
+    double tol2;
+    bool operator<(const GraphKey& o) const {
+      return sys != o.sys ? sys < o.sys : tol2 < o.tol2;
+    }
+  };
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  long long graph_launches = 0;
   float *rec_x = nullptr, *rec_t = nullptr;
   long long rec_cap = 0, rec_n = 0;
   long long guess_fallbacks = 0;  // learned guesses replaced by the Newmark guess
@@ -384,6 +397,40 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
 template <typename T> struct NegligibleBlock { static constexpr double value = 0.0; };
 template <> struct NegligibleBlock<float> { static constexpr double value = 1e-20; };
 
+// Captures (once per system and tolerance) what enqueue() launches into an
+// executable graph.  Capture runs on a private stream and executes nothing.
+template <class Enqueue>
+static int pair_graph(sgw_ctx* c, const void* sys, double tol2, Enqueue enqueue,
+                      hipGraphExec_t* out) {
+  const sgw_ctx::GraphKey key{sys, tol2};
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    *out = it->second;
+    return 0;
+  }
+  if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->err = "stream creation failed";
+    return SGW_EHIP;
+  }
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    c->err = "graph capture could not start";
+    return SGW_EHIP;
+  }
+  enqueue(c->cap_stream);
+  if (hipStreamEndCapture(c->cap_stream, &g) != hipSuccess ||
+      hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    c->err = "graph capture failed";
+    return SGW_EHIP;
+  }
+  (void)hipGraphDestroy(g);
+  c->graphs[key] = ge;
+  *out = ge;
+  return 0;
+}
+
 template <typename T>
 static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb, T* out,
                        int ldo, double tol, int maxit, hipStream_t st) {
@@ -406,17 +453,43 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
       return SGW_ENAN;
     }
   }
+  // one iteration up to the stopping test, and its p update
+  auto first_half = [&](int par, hipStream_t s) {
+    K1<T>(c, S.A, S.halo, 0, n, S.p, n, S.q, n, 1.0, 0.0, s);
+    k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, s);
+    k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part,
+                 c->part2, c->flags, s);
+    precond_dot<T>(c, S, neumann, c->part, nullptr, par, tol2, s);
+  };
+  auto second_half = [&](int par, hipStream_t s) {
+    k::pcg_p<T>(nb, S.row_off, P, par, c->sc, c->part, S.z, n, S.p, n, s);
+  };
+  // H9: while no stopping test is due, pairs of iterations (even, odd)
+  // replay a captured graph; frozen blocks make extra iterations harmless
+  if (c->use_graphs && !c->prof && nact > 0) {
+    hipGraphExec_t ge = nullptr;
+    while (it + 3 < predicted && it + 2 <= maxit) {
+      if (!ge) {
+        int grc = pair_graph(c, &S, tol2, [&](hipStream_t s) {
+          first_half(0, s);
+          second_half(0, s);
+          first_half(1, s);
+          second_half(1, s);
+        }, &ge);
+        if (grc) return grc;
+      }
+      HIPCHK(hipGraphLaunch(ge, st));
+      c->graph_launches++;
+      it += 2;
+    }
+  }
   while (nact > 0) {
     if (it >= maxit) {
       rc = SGW_NOT_CONVERGED;
       break;
     }
     const int par = it & 1;
-    K1<T>(c, S.A, S.halo, 0, n, S.p, n, S.q, n, 1.0, 0.0, st);
-    k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, st);
-    k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part,
-                 c->part2, c->flags, st);
-    precond_dot<T>(c, S, neumann, c->part, nullptr, par, tol2, st);
+    first_half(par, st);
     ++it;
     if (it + 1 >= predicted || it >= maxit) {
       HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -433,7 +506,7 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
       }
       if (nact == 0) break;
     }
-    k::pcg_p<T>(nb, S.row_off, P, par, c->sc, c->part, S.z, n, S.p, n, st);
+    second_half(par, st);
   }
   k::copy2d<T, T>(P, n, S.x, n, out, ldo, 1.0, st);
   predicted = it;
@@ -1121,6 +1194,7 @@ long long sgw_query(const sgw_ctx* c, int what) {
     case 6: return c->nn;
     case 7: return c->rec_n;
     case 8: return c->guess_fallbacks;
+    case 9: return c->graph_launches;
     default: return -1;
   }
 }
@@ -1268,6 +1342,8 @@ int sgw_destroy(sgw_ctx* c) {
   }
   if (c->hflags) (void)hipHostFree(c->hflags);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return 0;
 }
@@ -1297,6 +1373,7 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   }
   c->inner_prec = dd.inner_prec;
   c->cheb_deg = dd.cheb_degree;
+  c->use_graphs = dd.graphs != 0;
   int rc = build_host(dd, c->h, c->err);  // host-side validation and set-up
   if (rc) {
     *out = c;

@@ -228,3 +228,23 @@ def test_mixed_precision_trajectory(sgw, name, over, nsteps, every, inner):
                                   precision=sgw.SGW_FP32_IR64, inner_prec=inner)
     assert em < 1e-6 and es < 1e-6, (em, es)
     assert all(st["ir_sweeps"] >= st["steps"] for st in stats)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_give_identical_states(sgw, precision):
+    """Inner PCG iterations replayed from captured HIP graphs: the states are
+    bitwise those of eager launches (same kernels, same order)."""
+    prm = workloads.config("cfg2", n=64, xsplits=workloads.uniform_splits(64, 4),
+                           ysplits=workloads.uniform_splits(64, 4), dt=0.004)
+    out = []
+    for graphs in (False, True):
+        s = sgw.Solver(prm, rtol=1e-10, inner_rtol=1e-12, precision=precision, inner_prec=1,
+                       cheb_degree=8, graphs=graphs)
+        s.factor()
+        s.set_state()
+        for _ in range(3):
+            assert s.step(4)["status"] == 0
+        out.append((s.get_state()[0].clone(), s.graph_launches()))
+        s.close()
+    assert out[0][1] == 0 and out[1][1] > 0
+    assert torch.equal(out[0][0], out[1][0])
