@@ -37,16 +37,29 @@ struct DEll {
   const T* mval = nullptr;
 };
 
-// Column halo of the 64-row groups of a sliced-ELL matrix, for rows
-// [r0, r0 + nr): group g covers rows [r0 + 64g, r0 + 64g + 64) and its
-// distinct columns are idx[ptr[g] .. ptr[g+1]) (sorted); lcol[s*nr + r - r0]
-// is the position of col[s][r] in its group's list; hmax = the longest list.
+// Column halo of the row groups (at most 64 rows each) of a sliced-ELL
+// matrix, for rows [r0, r0 + nr): group g covers rows [grow[g], grow[g+1])
+// and its distinct columns are idx[ptr[g] .. ptr[g+1]) (sorted);
+// lcol[s*nr + r - r0] is the position of col[s][r] in its group's list;
+// hmax = the longest list.  Either plain 64-row chunks (aligned64), or
+// groups that never straddle the blocks of a block-diagonal system: then
+// gblk[g] = block of group g and bgrp[b] = first group of block b.
 struct DHalo {
-  int r0 = 0, nr = 0, hmax = 0;
+  int r0 = 0, nr = 0, hmax = 0, ng = 0;
+  bool aligned64 = true;
   const int* ptr = nullptr;
   const int* idx = nullptr;
   const unsigned short* lcol = nullptr;
+  const int* grow = nullptr;
+  const int* gblk = nullptr;
+  const int* bgrp = nullptr;
 };
+// workgroups (row groups) covering rows [r0, r0 + nrows) of a halo starting at r0
+inline int halo_groups(const DHalo& H, int r0, int nrows) {
+  if (r0 != H.r0 || nrows > H.nr) return -1;
+  if (nrows == H.nr) return H.ng;
+  return H.aligned64 ? (nrows + 63) / 64 : -1;
+}
 
 // y[i][r] = alpha * sum_k sum_j c_kij sum_s K_k[r, s] x[j][col]  (+ beta*y)
 // for rows r in [r0, r0 + nrows) of the matrix.  nbatch vectors with strides.
@@ -60,6 +73,20 @@ void sg_apply(const DEll<T>& A, const GTab& g, const DHalo* H, int r0, int nrows
 // Once per process before the first sg_apply: LDS attribute of the
 // generated kernels.  0 on success, -1 on a HIP error.
 int sg_apply_prepare();
+// number of generated (unrolled-tensor) kernels for the basis, one per group
+// of output modes; 0 if none is generated
+int sg_apply_generated(int L, int p_in, int p_out);
+// The SG apply of one subdomain PCG iteration on a block-aligned halo (all
+// nrows rows): p = z + beta_b pold (beta_b = new r'z of block b from rzpart
+// over its old r'z in sc[b*8 + 1 - par], 0 if that is infinite; the new r'z
+// goes to sc[b*8 + par]), pnew = p on every row, q = K~ p, and
+// pqg[g*K + k] = p'q over the rows of group g and the output modes of
+// generated kernel k (K = sg_apply_generated(...)).  Returns false (nothing launched) if
+// no generated kernel fits.
+template <typename T>
+bool sg_apply_pcg(const DEll<T>& A, const GTab& g, const DHalo& H, int nrows, const T* pold,
+                  const T* z, T* pnew, int ld, T* q, const double* rzpart, double* sc, int par,
+                  double* pqg, hipStream_t st);
 
 // y[j][r] = beta*y[j][r] + alpha * sum_s M[r, s] x[j][col]  for all P modes.
 template <typename T>
@@ -123,10 +150,13 @@ void pcg_start(int nb, int P, const double* part, const double* part2, double* s
                double tol2, double negl, int* flags, hipStream_t st);
 // x += alpha_b p ; r -= alpha_b q with alpha_b = r'z / p'q (p'q from part);
 // part2[b*P + j] = ||r_bj||^2
+// (with bgrp: p'q summed from the partials part[g*pqn + k], k < pqn, of the
+// block's groups g = bgrp[b] .. bgrp[b+1]-1)
 template <typename T>
 void pcg_xr(int nb, const int* row_off, int P, int par, const double* sc, T* x, int ldx,
             const T* p, int ldp, T* r, int ldr, const T* q, int ldq, const double* part,
-            double* part2, int* flags, hipStream_t st);
+            double* part2, int* flags, hipStream_t st, const int* bgrp = nullptr,
+            int pqn = 0);
 // stopping test of iteration par from part2 (exact-preconditioner path)
 void pcg_test(int nb, int P, int par, const double* part2, double* sc, double tol2,
               int* flags, hipStream_t st);

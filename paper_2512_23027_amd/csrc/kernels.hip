@@ -136,8 +136,8 @@ void sg_apply(const DEll<T>& A, const GTab& g, const DHalo* H, int r0, int nrows
               int ldx, T* y, int ldy, T alpha, T beta, int nbatch,
               long long sx, long long sy, hipStream_t st) {
   if (nrows <= 0) return;
-  if (g.use_spec && H && H->r0 == r0 && nrows <= H->nr &&
-      (size_t)g.P * H->hmax * sizeof(T) <= 150 * 1024 &&
+  if (g.use_spec && H && halo_groups(*H, r0, nrows) > 0 &&
+      (size_t)g.P * H->hmax * sizeof(T) <= 120 * 1024 &&
       sg_apply_specialised<T>(g.L, g.p_in, g.p_out, A, *H, r0, nrows, x, ldx, y, ldy, alpha,
                               beta, nbatch, sx, sy, st))
     return;
@@ -160,6 +160,20 @@ void sg_apply(const DEll<T>& A, const GTab& g, const DHalo* H, int r0, int nrows
 }
 
 int sg_apply_prepare() { return sg_apply_specialised_prepare() ? 0 : -1; }
+int sg_apply_generated(int L, int p_in, int p_out) {
+  return sg_apply_specialised_groups(L, p_in, p_out);
+}
+
+template <typename T>
+bool sg_apply_pcg(const DEll<T>& A, const GTab& g, const DHalo& H, int nrows, const T* pold,
+                  const T* z, T* pnew, int ld, T* q, const double* rzpart, double* sc, int par,
+                  double* pqg, hipStream_t st) {
+  if (!g.use_spec || H.aligned64 || !H.bgrp || nrows != H.nr ||
+      (size_t)g.P * H.hmax * sizeof(T) > 120 * 1024)
+    return false;
+  return sg_apply_pcg_specialised<T>(g.L, g.p_in, g.p_out, A, H, nrows, pold, z, pnew, ld, q,
+                                     rzpart, sc, par, pqg, st);
+}
 
 // Deterministic mass apply over all P modes: thread per (row, mode).
 template <typename T>
@@ -532,6 +546,7 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_start(int nb, int P, const do
     double* s = sc + (size_t)b * 8;
     const bool act = s[4] > floor_bb && s[4] > tol2 * s[4] && s[4] > 0.0;
     s[2] = act ? 1.0 : 0.0;
+    s[1] = INFINITY;  // "previous r'z" of iteration 0: beta = 0 in the fused SG apply
     if (act) atomicAdd(&nact, 1);
   }
   __syncthreads();
@@ -553,7 +568,8 @@ void pcg_start(int nb, int P, const double* part, const double* part2, double* s
 template <typename T>
 __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
     const int* row_off, int P, int par, const double* sc, T* x, int ldx, const T* p, int ldp,
-    T* r, int ldr, const T* q, int ldq, const double* part, double* part2, int* flags) {
+    T* r, int ldr, const T* q, int ldq, const double* part, double* part2, int* flags,
+    const int* bgrp, int pqn) {
   __shared__ double sh[SGW_BLOCK / 64];
   const int blk = blockIdx.x, j = blockIdx.y;
   const int r0 = row_off[blk], r1 = row_off[blk + 1];
@@ -561,7 +577,12 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
   const bool act = s[2 + par] != 0.0;
   double al = 0.0;
   if (act) {
-    const double pq = sum_modes(part, blk, P);
+    double pq = 0.0;
+    if (bgrp) {  // per-group partials of the fused SG apply (pqn per group)
+      for (int q = bgrp[blk] * pqn; q < bgrp[blk + 1] * pqn; ++q) pq += part[q];
+    } else {
+      pq = sum_modes(part, blk, P);
+    }
     if (pq > 0.0) {
       al = s[par] / pq;
     } else if (j == 0 && threadIdx.x == 0) {
@@ -592,9 +613,9 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
 template <typename T>
 void pcg_xr(int nb, const int* row_off, int P, int par, const double* sc, T* x, int ldx,
             const T* p, int ldp, T* r, int ldr, const T* q, int ldq, const double* part,
-            double* part2, int* flags, hipStream_t st) {
+            double* part2, int* flags, hipStream_t st, const int* bgrp, int pqn) {
   k_pcg_xr<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, par, sc, x, ldx, p, ldp, r, ldr,
-                                                 q, ldq, part, part2, flags);
+                                                 q, ldq, part, part2, flags, bgrp, pqn);
 }
 
 // Stopping test of iteration par (used with the exact preconditioner; the
@@ -1167,7 +1188,10 @@ template size_t tri_lds_bytes<float>(const DFactor&, int);
                            const T*, int, const T*, int, double*, hipStream_t);             \
   template void pcg_xr<T>(int, const int*, int, int, const double*, T*, int, const T*, int, \
                           T*, int, const T*, int, const double*, double*, int*,            \
-                          hipStream_t);                                                      \
+                          hipStream_t, const int*, int);                                     \
+  template bool sg_apply_pcg<T>(const DEll<T>&, const GTab&, const DHalo&, int, const T*,    \
+                                const T*, T*, int, T*, const double*, double*, int, double*, \
+                                hipStream_t);                                                \
   template void pcg_p<T>(int, const int*, int, int, double*, const double*, const T*, int,  \
                          T*, int, hipStream_t);                                              \
   template void fill2d<T>(int, int, T*, int, T, hipStream_t);                               \

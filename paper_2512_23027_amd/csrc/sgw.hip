@@ -53,6 +53,7 @@ struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   k::DFactor F;
   const int* row_off = nullptr;  // device
   T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  T* p2 = nullptr;  // second direction buffer of the fused iteration (alternates with p)
 };
 
 // Everything one precision of the DD solve needs: the global operator, the
@@ -123,6 +124,8 @@ struct sgw_ctx {
   // 64-row group halos of the SG-apply matrices: global system from row 0
   // and from the first interface row, Dirichlet and Neumann systems
   k::DHalo hal_G0, hal_GI, hal_D, hal_N;
+  int k1_generated = 0;        // generated SG-apply kernels of the basis (output groups)
+  double* pqg = nullptr;       // [groups][P] p'q partials of the fused SG apply
   // learned initial guess: ring of the last 4 converged interface solutions
   // [4][P][nG], the Newmark guess of the current step [P][nG], per-mode
   // scales [P], network input/output [P][4 nG] / [P][nG], the attached
@@ -437,10 +440,14 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
   const int P = c->P, n = S.nrows, nb = S.nb;
   const double tol2 = tol * tol;
   int& predicted = S.last_its[tol >= S.loose_tol ? 1 : 0];
+  // fused iteration: the SG apply also forms p (alternating buffers) and the
+  // p'q partial sums (generated kernel on a block-aligned halo)
+  const bool fused = c->gt.use_spec && c->k1_generated > 0 && S.halo && !S.halo->aligned64 &&
+                     (size_t)P * S.halo->hmax * sizeof(T) <= 120 * 1024;
   k::copy2d<T, T>(P, n, b, ldb, S.r, n, 1.0, st);
   k::fill2d<T>(P, n, S.x, n, T(0), st);
   precond_dot<T>(c, S, neumann, c->part, c->part2, -1, 0.0, st);
-  k::copy2d<T, T>(P, n, S.z, n, S.p, n, 1.0, st);
+  if (!fused) k::copy2d<T, T>(P, n, S.z, n, S.p, n, 1.0, st);
   k::pcg_start(nb, P, c->part, c->part2, c->sc, tol2, NegligibleBlock<T>::value, c->flags, st);
   int it = 0, rc = 0;
   int nact = 1;
@@ -455,14 +462,27 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
   }
   // one iteration up to the stopping test, and its p update
   auto first_half = [&](int par, hipStream_t s) {
-    K1<T>(c, S.A, S.halo, 0, n, S.p, n, S.q, n, 1.0, 0.0, s);
-    k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr, s);
-    k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part,
-                 c->part2, c->flags, s);
+    if (fused) {
+      T* pold = par ? S.p : S.p2;
+      T* pnew = par ? S.p2 : S.p;
+      const int a = prof_begin(c, sizeof(T) == 4 ? 3 : 0, s);
+      (void)k::sg_apply_pcg<T>(S.A, c->gt, *S.halo, n, pold, S.z, pnew, n, S.q, c->part, c->sc,
+                               par, c->pqg, s);
+      prof_end(c, a, sizeof(T) == 4 ? 3 : 0,
+               (7.0 * c->nk * sizeof(T) + 7.0 * 4.0 + 4.0 * P * sizeof(T)) * n, s);
+      k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, pnew, n, S.r, n, S.q, n, c->pqg,
+                   c->part2, c->flags, s, S.halo->bgrp, c->k1_generated);
+    } else {
+      K1<T>(c, S.A, S.halo, 0, n, S.p, n, S.q, n, 1.0, 0.0, s);
+      k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr,
+                    s);
+      k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part,
+                   c->part2, c->flags, s);
+    }
     precond_dot<T>(c, S, neumann, c->part, nullptr, par, tol2, s);
   };
   auto second_half = [&](int par, hipStream_t s) {
-    k::pcg_p<T>(nb, S.row_off, P, par, c->sc, c->part, S.z, n, S.p, n, s);
+    if (!fused) k::pcg_p<T>(nb, S.row_off, P, par, c->sc, c->part, S.z, n, S.p, n, s);
   };
   // H9: while no stopping test is due, pairs of iterations (even, odd)
   // replay a captured graph; frozen blocks make extra iterations harmless
@@ -891,17 +911,35 @@ static void natural_order(sgw_ctx* c, const Ell& E, const std::vector<int>& off,
   *cnb_d = upload(c, cnb);
 }
 
-// 64-row group halos of an ELL matrix for rows [r0, nrows) (see k::DHalo).
-static k::DHalo build_halo(sgw_ctx* c, const Ell& E, int r0) {
+// Row-group halos of an ELL matrix for rows [r0, nrows) (see k::DHalo):
+// plain 64-row chunks, or (boff = block offsets of a block-diagonal system,
+// r0 = 0) chunks of at most 64 rows that never straddle a block.
+static k::DHalo build_halo(sgw_ctx* c, const Ell& E, int r0,
+                           const std::vector<int>* boff = nullptr) {
   k::DHalo H;
   const int nr = std::max(E.nrows - r0, 0);
   H.r0 = r0;
   H.nr = nr;
-  const int ng = (nr + 63) / 64;
+  std::vector<int> grow, gblk, bgrp;
+  if (boff) {
+    H.aligned64 = false;
+    for (size_t b = 0; b + 1 < boff->size(); ++b) {
+      bgrp.push_back((int)grow.size());
+      for (int a = (*boff)[b]; a < (*boff)[b + 1]; a += 64) {
+        grow.push_back(a);
+        gblk.push_back((int)b);
+      }
+    }
+    bgrp.push_back((int)grow.size());
+  } else {
+    for (int a = r0; a < E.nrows; a += 64) grow.push_back(a);
+  }
+  H.ng = (int)grow.size();
+  grow.push_back(E.nrows);
   std::vector<int> ptr{0}, idx, cols;
   std::vector<unsigned short> lcol((size_t)E.W * std::max(nr, 1), 0);
-  for (int g = 0; g < ng; ++g) {
-    const int a = r0 + 64 * g, b = std::min(E.nrows, a + 64);
+  for (int g = 0; g < H.ng; ++g) {
+    const int a = grow[g], b = grow[g + 1];
     cols.clear();
     for (int s = 0; s < E.W; ++s)
       for (int r = a; r < b; ++r) cols.push_back(E.col[(size_t)s * E.nrows + r]);
@@ -921,6 +959,11 @@ static k::DHalo build_halo(sgw_ctx* c, const Ell& E, int r0) {
   H.ptr = upload(c, ptr);
   H.idx = upload(c, idx);
   H.lcol = upload(c, lcol);
+  H.grow = upload(c, grow);
+  if (boff) {
+    H.gblk = upload(c, gblk.empty() ? std::vector<int>{0} : gblk);
+    H.bgrp = upload(c, bgrp);
+  }
   return H;
 }
 
@@ -1032,6 +1075,7 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
     S->z = dalloc<T>(c, n);
     S->p = dalloc<T>(c, n);
     S->q = dalloc<T>(c, n);
+    S->p2 = dalloc<T>(c, n);
   }
   size_t nv = (size_t)P * h.NF;
   for (T** v : {&pr.X, &pr.R, &pr.Z, &pr.Zp, &pr.Pw, &pr.Qw, &pr.T1, &pr.Gv}) *v = dalloc<T>(c, nv);
@@ -1130,7 +1174,7 @@ static bool prec_complete(const PrecT<T>& pr, bool refine) {
                       pr.N.A.val, pr.D.x, pr.D.r, pr.D.z, pr.D.p, pr.D.q, pr.N.x, pr.N.r,
                       pr.N.z, pr.N.p, pr.N.q, pr.X, pr.R, pr.Z, pr.Zp, pr.Pw, pr.Qw, pr.T1,
                       pr.Gv, pr.Tt, pr.Yt, pr.D.row_off, pr.N.row_off, pr.D.crow, pr.D.cnb,
-                      pr.N.crow, pr.N.cnb, pr.D.cheb_iv, pr.N.cheb_iv};
+                      pr.N.crow, pr.N.cnb, pr.D.cheb_iv, pr.N.cheb_iv, pr.D.p2, pr.N.p2};
   for (const void* p : ps)
     if (!p) return false;
   return !refine || (pr.Fb && pr.Xb);
@@ -1138,7 +1182,7 @@ static bool prec_complete(const PrecT<T>& pr, bool refine) {
 
 static bool check_pointers(sgw_ctx* c) {
   const void* ps[] = {c->U, c->V, c->A, c->Um, c->Uc, c->Wm, c->F, c->hist, c->gnew, c->smax,
-                      c->mx, c->my, c->meshbuf, c->meshbuf2,
+                      c->mx, c->my, c->pqg, c->meshbuf, c->meshbuf2,
                       c->part, c->part2, c->sc, c->flags, c->goff, c->alloff, c->dd2mesh,
                       c->mdiag, c->torn_gidx, c->torn_w, c->gam_ptr, c->gam_torn, c->gam_w,
                       c->g2c, c->dc, c->uc, c->phi, c->gt.mask, c->gt.pair_beg, c->gt.ent_beg,
@@ -1410,8 +1454,10 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   }
   c->hal_G0 = build_halo(c, h.glob, 0);
   c->hal_GI = build_halo(c, h.glob, h.nI);
-  c->hal_D = build_halo(c, h.dir, 0);
-  c->hal_N = build_halo(c, h.neu, 0);
+  c->hal_D = build_halo(c, h.dir, 0, &h.Ioff);
+  c->hal_N = build_halo(c, h.neu, 0, &h.Toff);
+  c->k1_generated = k::sg_apply_generated(h.d.L, h.d.p_in, h.d.p_out);
+  c->pqg = dalloc<double>(c, (size_t)P * std::max(c->hal_D.ng, c->hal_N.ng));
   if (k::sg_apply_prepare() != 0) {
     c->err = "hipFuncSetAttribute failed for the SG-apply kernels";
     *out = c;

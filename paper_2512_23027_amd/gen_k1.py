@@ -93,8 +93,14 @@ def entries(L, p_in, p_out):
     return len(kin), len(out), ent
 
 
-def kernel_source(L, p_in, p_out):
+def kernel_source(L, p_in, p_out, pcg=False):
     """One kernel per output group; a workgroup = 64 rows x NCH waves.
+
+    pcg=True: the variant for the subdomain PCG iteration.  It stages
+    p = z + beta p_old (beta = the block's new r'z / old r'z, 0 on the first
+    iteration), writes p to pnew for its own rows, applies the operator to it
+    and writes p'q over the group's rows and the kernel's output modes to
+    pqg[group * (output-group kernels) + kernel].
 
     The workgroup first stages x at the distinct columns of its 64 rows (the
     group's halo, all P modes) in LDS with independent loads; wave w then
@@ -108,35 +114,55 @@ def kernel_source(L, p_in, p_out):
     KC = (nk + nch - 1) // nch
     nch = (nk + KC - 1) // KC
     NT = 64 * nch
-    name = "k1_L%d_%d_%d" % (L, p_in, p_out)
+    name = "k1_L%d_%d_%d" % (L, p_in, p_out) + ("_pcg" if pcg else "")
     lines = []
     tables = []
     for g in range(ngroups):
         i0, i1 = g * G, min(P, (g + 1) * G)
         gs = i1 - i0
         lines.append("template <typename T>")
+        extra = (", const T* __restrict__ zs, T* __restrict__ pnew, const double* __restrict__ rzpart, "
+                 "double* __restrict__ sc, int par, double* __restrict__ pqg") if pcg else ""
         lines.append("__global__ __launch_bounds__(%d, 2) void %s_g%d(DEll<T> A, DHalo H, int r0, int nrows, "
                      "const T* __restrict__ x, int ldx, T* __restrict__ y, int ldy, T alpha, "
-                     "T beta, long long sx, long long sy) {" % (NT, name, g))
+                     "T beta, long long sx, long long sy%s) {" % (NT, name, g, extra))
         lines.append("  extern __shared__ unsigned char k1_smem[];")
-        lines.append("  T* xs = reinterpret_cast<T*>(k1_smem);  // [halo][P] staged x, then partial sums")
+        lines.append("  T* xs = reinterpret_cast<T*>(k1_smem);  // [halo][P] staged x")
+        lines.append("  T* part = xs + (size_t)%d * H.hmax;  // partial outputs of waves 1..%d" % (P, nch - 1))
         lines.append("  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;")
         lines.append("  const int grp = blockIdx.x;")
-        lines.append("  const int rl = grp * 64 + lane;")
+        lines.append("  const int g0 = H.grow[grp], gn = H.grow[grp + 1] - g0;  // rows of this group")
         lines.append("  x += (long long)blockIdx.z * sx;")
         lines.append("  y += (long long)blockIdx.z * sy;")
-        lines.append("  const bool live = rl < nrows;")
-        lines.append("  const int r = r0 + (live ? rl : nrows - 1);")
+        lines.append("  const bool live = lane < gn && g0 + lane - r0 < nrows;")
+        lines.append("  const int r = g0 + (live ? lane : 0);")
         lines.append("  const int NR = A.nrows;")
         lines.append("  const auto rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y);")
         lines.append("  const int rb = r * (int)sizeof(T);")
         # staging: every thread owns halo entries h, loads all P modes at once
+        if pcg:
+            lines.append("  // beta of this group's block; the block's first group stores the new r'z")
+            lines.append("  const int blk = H.gblk[grp];")
+            lines.append("  double rzn = 0.0;")
+            lines.append("  for (int j = 0; j < %d; ++j) rzn += rzpart[(size_t)blk * %d + j];" % (P, P))
+            lines.append("  const double rzo = sc[(size_t)blk * 8 + 1 - par];")
+            lines.append("  const T bt = (T)(isinf(rzo) ? 0.0 : rzn / rzo);")
+            lines.append("  if (threadIdx.x == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
+            lines.append("  const auto rz = buf_rsrc(zs);")
         lines.append("  {")
         lines.append("    const int h0 = H.ptr[grp], nh = H.ptr[grp + 1] - h0;")
         lines.append("    for (int h = threadIdx.x; h < nh; h += %d) {" % NT)
         lines.append("      const int co = H.idx[h0 + h] * (int)sizeof(T);")
-        for j in range(P):
-            lines.append("      const T v%d = buf_load<T>(rx, co, %d * ldx * (int)sizeof(T));" % (j, j))
+        if pcg:
+            for j in range(P):
+                lines.append("      T v%d = buf_load<T>(rz, co, %d * ldx * (int)sizeof(T));" % (j, j))
+            lines.append("      if (bt != T(0)) {")
+            for j in range(P):
+                lines.append("        v%d = fma(bt, buf_load<T>(rx, co, %d * ldx * (int)sizeof(T)), v%d);" % (j, j, j))
+            lines.append("      }")
+        else:
+            for j in range(P):
+                lines.append("      const T v%d = buf_load<T>(rx, co, %d * ldx * (int)sizeof(T));" % (j, j))
         for j in range(P):
             lines.append("      xs[h * %d + %d] = v%d;" % (P, j, j))
         lines.append("    }")
@@ -147,6 +173,13 @@ def kernel_source(L, p_in, p_out):
         for i in range(i0, i1):
             lines.append("  T y%d = T(0);" % i)
         lines.append("  __syncthreads();")
+        if pcg and g == 0:
+            lines.append("  if (wv == %d && live) {  // the new direction of the own row" % (nch - 1))
+            lines.append("    const auto rp = buf_rsrc(pnew);")
+            lines.append("    const char* xb0 = reinterpret_cast<const char*>(xs);")
+            for j in range(P):
+                lines.append("    buf_store<T>(*reinterpret_cast<const T*>(xb0 + l0 + %d * sizeof(T)), rp, rb, %d * ldx * (int)sizeof(T));" % (j, j))
+            lines.append("  }")
         for ch in range(nch):
             k0, k1 = ch * KC, min(nk, (ch + 1) * KC)
             mine = [e for e in ent if k0 <= e[0] < k1 and i0 <= e[1] < i1]
@@ -186,15 +219,14 @@ def kernel_source(L, p_in, p_out):
                 lines.append("    }")
             lines.append("  }")
         if nch > 1:
-            lines.append("  __syncthreads();  // every wave is done with the staged x")
             lines.append("  if (wv > 0) {")
             for i in range(i0, i1):
-                lines.append("    xs[((wv - 1) * %d + %d) * 64 + lane] = y%d;" % (gs, i - i0, i))
+                lines.append("    part[((wv - 1) * %d + %d) * 64 + lane] = y%d;" % (gs, i - i0, i))
             lines.append("  }")
             lines.append("  __syncthreads();")
             lines.append("  if (wv != 0) return;")
             for i in range(i0, i1):
-                lines.append("  y%d = %s;" % (i, " + ".join(["y%d" % i] + ["xs[(%d * %d + %d) * 64 + lane]"
+                lines.append("  y%d = %s;" % (i, " + ".join(["y%d" % i] + ["part[(%d * %d + %d) * 64 + lane]"
                                                                        % (w, gs, i - i0)
                                                                        for w in range(nch - 1)])))
         lines.append("  if (live) {")
@@ -202,20 +234,36 @@ def kernel_source(L, p_in, p_out):
             lines.append("    { T v = alpha * y%d; if (beta != T(0)) v = fma(beta, buf_load<T>(ry, rb, %d * ldy * (int)sizeof(T)), v);"
                          " buf_store<T>(v, ry, rb, %d * ldy * (int)sizeof(T)); }" % (i, i, i))
         lines.append("  }")
+        if pcg:
+            lines.append("  {  // p'q over this group's rows and this kernel's output modes")
+            lines.append("    const char* xb0 = reinterpret_cast<const char*>(xs);")
+            lines.append("    double v = 0.0;")
+            lines.append("    if (live) {")
+            for i in range(i0, i1):
+                lines.append("      v += (double)(alpha * y%d) * (double)*reinterpret_cast<const T*>(xb0 + l0 + %d * sizeof(T));" % (i, i))
+            lines.append("    }")
+            lines.append("    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);")
+            lines.append("    if (lane == 0) pqg[(size_t)grp * %d + %d] = v;" % (ngroups, g))
+            lines.append("  }")
         lines.append("}")
         lines.append("")
-    # dispatcher
+    # dispatcher: one workgroup per row group of the halo that starts at r0
+    xsig = (", const T* zs, T* pnew, const double* rzpart, double* sc, int par, double* pqg"
+            if pcg else "")
+    xarg = ", zs, pnew, rzpart, sc, par, pqg" if pcg else ""
     lines.append("template <typename T>")
     lines.append("static void %s_launch(const DEll<T>& A, const DHalo& H, int r0, int nrows, const T* x, "
-                 "int ldx, T* y, int ldy, T alpha, T beta, int nbatch, long long sx, long long sy, "
-                 "hipStream_t st) {" % name)
-    lines.append("  dim3 grid((nrows + 63) / 64, 1, nbatch);")
+                 "int ldx, T* y, int ldy, T alpha, T beta, int nbatch, long long sx, long long sy%s, "
+                 "hipStream_t st) {" % (name, xsig))
+    lines.append("  const int ngrp = halo_groups(H, r0, nrows);")
+    lines.append("  if (ngrp <= 0) return;")
+    lines.append("  dim3 grid(ngrp, 1, nbatch);")
     for g in range(ngroups):
         gs = min(P, (g + 1) * G) - g * G
         lines.append("  {")
-        lines.append("    const size_t sh = sizeof(T) * (size_t)std::max(%d * H.hmax, %d);" % (P, (nch - 1) * gs * 64))
-        lines.append("    %s_g%d<T><<<grid, %d, sh, st>>>(A, H, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy);"
-                     % (name, g, NT))
+        lines.append("    const size_t sh = sizeof(T) * ((size_t)%d * H.hmax + %d);" % (P, (nch - 1) * gs * 64))
+        lines.append("    %s_g%d<T><<<grid, %d, sh, st>>>(A, H, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy%s);"
+                     % (name, g, NT, xarg))
         lines.append("  }")
     lines.append("}")
     lines.append("")
@@ -249,18 +297,43 @@ def generate():
             "// static LDS); once per process before the first launch.",
             "static bool sg_apply_specialised_prepare() {",
             "  bool ok = true;"]
+    dpcg = ["template <typename T>",
+            "static bool sg_apply_pcg_specialised(int L, int p_in, int p_out, const DEll<T>& A, "
+            "const DHalo& H, int nrows, const T* pold, const T* zs, T* pnew, int ld, T* q, "
+            "const double* rzpart, double* sc, int par, double* pqg, hipStream_t st) {"]
     for (L, pi, po) in BASES:
         src, name, nk, P, nnz = kernel_source(L, pi, po)
+        srcp, namep, _, _, _ = kernel_source(L, pi, po, pcg=True)
         parts.append("// L=%d p_in=%d p_out=%d: %d coefficient matrices, P=%d, %d tensor entries"
                      % (L, pi, po, nk, P, nnz))
         parts.append(src)
+        parts.append(srcp)
         disp.append("  if (L == %d && p_in == %d && p_out == %d) {" % (L, pi, po))
         disp.append("    %s_launch<T>(A, H, r0, nrows, x, ldx, y, ldy, alpha, beta, nbatch, sx, sy, st);"
                     % name)
         disp.append("    return true;")
         disp.append("  }")
+        dpcg.append("  if (L == %d && p_in == %d && p_out == %d) {" % (L, pi, po))
+        dpcg.append("    %s_launch<T>(A, H, H.r0, nrows, pold, ld, q, ld, T(1), T(0), 1, 0, 0, zs, pnew, "
+                    "rzpart, sc, par, pqg, st);" % namep)
+        dpcg.append("    return true;")
+        dpcg.append("  }")
         prep.append("  ok = ok && %s_prepare();" % name)
+        prep.append("  ok = ok && %s_prepare();" % namep)
     disp.append("  return false;")
+    disp.append("}")
+    dpcg.append("  return false;")
+    dpcg.append("}")
+    disp.append("")
+    disp.extend(dpcg)
+    disp.append("")
+    disp.append("// number of output-group kernels of the basis (0: none generated)")
+    disp.append("static int sg_apply_specialised_groups(int L, int p_in, int p_out) {")
+    for (L, pi, po) in BASES:
+        P = entries(L, pi, po)[1]
+        ng = (P + MAX_GROUP - 1) // MAX_GROUP
+        disp.append("  if (L == %d && p_in == %d && p_out == %d) return %d;" % (L, pi, po, ng))
+    disp.append("  return 0;")
     disp.append("}")
     prep.append("  return ok;")
     prep.append("}")
