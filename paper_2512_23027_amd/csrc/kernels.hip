@@ -129,6 +129,16 @@ __global__ __launch_bounds__(SGW_WAVE) void k_sg_apply(
 }
 
 // Kernels with the Galerkin tensor of a fixed basis unrolled (gen_k1.py).
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i to XCD
+// i % 8), each with its own L2.  This bijection gives XCD x a contiguous
+// range of logical indices, so neighbouring row groups, whose column halos
+// overlap, share an L2.
+__device__ __forceinline__ int xcd_group(int i, int n) {
+  const int nx = 8, x = i % nx, k = i / nx;
+  const int per = n / nx, rem = n % nx;
+  return x * per + min(x, rem) + k;
+}
+
 #include "k1_spec.inc"
 
 template <typename T>

@@ -130,7 +130,7 @@ def kernel_source(L, p_in, p_out, pcg=False):
         lines.append("  T* xs = reinterpret_cast<T*>(k1_smem);  // [halo][P] staged x")
         lines.append("  T* part = xs + (size_t)%d * H.hmax;  // partial outputs of waves 1..%d" % (P, nch - 1))
         lines.append("  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;")
-        lines.append("  const int grp = blockIdx.x;")
+        lines.append("  const int grp = xcd_group(blockIdx.x, gridDim.x);")
         lines.append("  const int g0 = H.grow[grp], gn = H.grow[grp + 1] - g0;  // rows of this group")
         lines.append("  x += (long long)blockIdx.z * sx;")
         lines.append("  y += (long long)blockIdx.z * sy;")
