@@ -90,6 +90,10 @@ typedef struct sgw_problem_desc {
                             approximates it by a Chebyshev polynomial in the
                             Jacobi-scaled mean matrix (blocks of <= 4096 rows) */
   int cheb_degree;       /* degree of that polynomial (<= 0: 4; at most 64) */
+  double ir_outer_rtol;  /* refinement path (SGW_FP32_IR64): FP32 interface PCG per sweep */
+  double ir_inner_rtol;  /*   FP32 Dirichlet solves */
+  double ir_precond_rtol;/*   FP32 Neumann solves in the preconditioner
+                            (each <= 0: 1e-5, 1e-6, 1e-3) */
   int graphs;            /* != 0: subdomain PCG iterations that need no host check run
                             as replays of captured HIP graphs (pairs of iterations);
                             results are identical, timing kernels (sgw_profile) off */

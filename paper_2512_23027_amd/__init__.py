@@ -48,7 +48,9 @@ class ProblemDesc(ctypes.Structure):
                 ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int),
                 ("precond_rtol", ctypes.c_double), ("inner_prec", ctypes.c_int),
-                ("cheb_degree", ctypes.c_int), ("graphs", ctypes.c_int)]
+                ("cheb_degree", ctypes.c_int), ("ir_outer_rtol", ctypes.c_double),
+                ("ir_inner_rtol", ctypes.c_double), ("ir_precond_rtol", ctypes.c_double),
+                ("graphs", ctypes.c_int)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -143,7 +145,7 @@ class Solver:
     def __init__(self, prm, rtol=None, inner_rtol=None, max_iter=1000,
                  inner_max_iter=1000, precision=SGW_FP64, guess=SGW_GUESS_PREV,
                  precond_rtol=None, inner_prec=SGW_INNER_CHOLESKY, cheb_degree=0,
-                 graphs=False, use_torch_allocator=True):
+                 graphs=False, ir_rtols=(0.0, 0.0, 0.0), use_torch_allocator=True):
         import torch
         self.torch = torch
         L = lib()
@@ -168,6 +170,7 @@ class Solver:
         d.precond_rtol = precond_rtol if precond_rtol is not None else 0.0
         d.inner_prec, d.cheb_degree = inner_prec, cheb_degree
         d.graphs = 1 if graphs else 0
+        d.ir_outer_rtol, d.ir_inner_rtol, d.ir_precond_rtol = ir_rtols
         self.desc = d
         self._live = {}
         al = None

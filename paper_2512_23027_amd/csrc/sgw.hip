@@ -1065,8 +1065,8 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
     S->cq = q;
   }
   const sgw_problem_desc& d = h.d;
-  double loose = refine ? kIrPrecondRtol : d.precond_rtol;
-  double tight = refine ? kIrInnerRtol : d.inner_rtol;
+  double loose = refine ? d.ir_precond_rtol : d.precond_rtol;
+  double tight = refine ? d.ir_inner_rtol : d.inner_rtol;
   if (loose > tight) pr.N.loose_tol = loose;
   for (SysT<T>* S : {&pr.D, &pr.N}) {
     size_t n = (size_t)P * S->nrows;
@@ -1118,7 +1118,7 @@ static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int&
   const int P = c->P, NF = c->NF;
   PrecT<float>& pr = c->f32;
   double* R = c->d64.R;
-  Tols tl{kIrOuterRtol, kIrInnerRtol, kIrPrecondRtol, d.max_iter, d.inner_max_iter};
+  Tols tl{d.ir_outer_rtol, d.ir_inner_rtol, d.ir_precond_rtol, d.max_iter, d.inner_max_iter};
   double ff;
   int rc = fdot<double>(c, F, F, ff, st);
   if (rc) return rc;
@@ -1409,6 +1409,9 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   if (!(dd.inner_rtol > 0)) dd.inner_rtol = 1e-3 * dd.rtol;
   if (!(dd.precond_rtol > 0)) dd.precond_rtol = dd.inner_rtol;
   if (dd.cheb_degree <= 0) dd.cheb_degree = 4;
+  if (!(dd.ir_outer_rtol > 0)) dd.ir_outer_rtol = kIrOuterRtol;
+  if (!(dd.ir_inner_rtol > 0)) dd.ir_inner_rtol = kIrInnerRtol;
+  if (!(dd.ir_precond_rtol > 0)) dd.ir_precond_rtol = kIrPrecondRtol;
   if ((dd.inner_prec != SGW_INNER_CHOLESKY && dd.inner_prec != SGW_INNER_CHEBYSHEV) ||
       dd.cheb_degree > 64 || (dd.precision != SGW_FP64 && dd.precision != SGW_FP32_IR64)) {
     c->err = "inner_prec, cheb_degree or precision out of range";
