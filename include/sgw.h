@@ -198,7 +198,9 @@ int sgw_profile(sgw_ctx* ctx, int enable);
  * output is accumulated), 8-byte values (4-byte in FP32 launches); per
  * triangular-solve launch: the right-hand sides in and out plus the
  * factor's values and indices; per Chebyshev launch: the right-hand sides
- * in and out plus the mean matrix's values and column indices. */
+ * in and out plus the mean matrix's values and column indices of the
+ * blocks the launch actually processes (converged blocks are skipped; the
+ * kernel counts them on the device). */
 int sgw_profile_read(sgw_ctx* ctx, int kind, long long* launches, double* ms,
                      double* bytes);
 

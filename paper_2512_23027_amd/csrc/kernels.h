@@ -118,7 +118,9 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
 // of the block starting at r0, cnb[s*nrows + r0 + i] = natural position of
 // that row's slot-s neighbour within the block.  Writes z and part[b*P + j] = r_j'z_j (part2 = r_j'r_j if not
 // null).  With sc != null it first does the PCG stopping test of iteration
-// par (r'r from rrpart, see pcg_test) and skips converged blocks.  Returns
+// par (r'r from rrpart, see pcg_test) and skips converged blocks.  With acct
+// != null, every active workgroup adds its algorithmic bytes (right-hand
+// sides in and out, the block's mean matrix once) to *acct.  Returns
 // -1 (nothing launched) if Q, deg or the block size is out of range
 // (max_rows <= 4096, Q <= cheb_max_q, Q * max_rows * sizeof(T) <= 150 KiB).
 template <typename T>
@@ -134,7 +136,7 @@ int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int
                const unsigned short* cnb, const double* iv, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                double* part2, double* sc, int par, double tol2, const double* rrpart,
-               int* flags, hipStream_t st);
+               int* flags, unsigned long long* acct, hipStream_t st);
 
 // Segmented dot products: partial[b * P + j] = sum_{r in block b} a[j][r] b[j][r]
 // (row_off relative to the vectors; a second vector pair is optional).

@@ -838,7 +838,7 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     const double* __restrict__ iv, int P, int deg,
     const T* __restrict__ r, int ldr, T* __restrict__ z, int ldz, double* __restrict__ part,
     double* __restrict__ part2, double* sc, int par, double tol2, const double* rrpart,
-    int* flags) {
+    int* flags, unsigned long long* acct) {
   // all LDS is dynamic (so the launch may use up to the whole 160 KiB):
   // the reduction slots, then two buffers of the search direction [Q][n]
   extern __shared__ unsigned char smem_raw[];
@@ -857,6 +857,11 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
   }
   const int r0 = row_off[b], n = row_off[b + 1] - r0;
   const int NR = A.nrows;
+  if (acct && threadIdx.x == 0) {  // algorithmic bytes of this (active) workgroup
+    const int nq = min(Q, P - j0);
+    atomicAdd(acct, (unsigned long long)(2 * sizeof(T) * nq * n +
+                                         (blockIdx.y == 0 ? 7 * (sizeof(T) + 4) * n : 0)));
+  }
   const double lo = iv[2 * b], hi = iv[2 * b + 1];
   const double theta = 0.5 * (hi + lo);
   const double delta = fmax(0.5 * (hi - lo), 1e-3 * theta);
@@ -970,8 +975,9 @@ size_t cheb_lds_bytes(int max_rows, int Q) {
   return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + 2 * (size_t)max_rows * Q * sizeof(T);
 }
 
-struct ChebTest {  // optional fused stopping test (sc == nullptr: none), block order
-  const int* order;
+struct ChebTest {  // optional fused stopping test (sc == nullptr: none), block order,
+  const int* order;  // byte counter of timed launches (may be null)
+  unsigned long long* acct;
   double* sc;
   int par;
   double tol2;
@@ -987,7 +993,7 @@ static void launch_cheb(const DEll<T>& A, const int* row_off, const int* crow,
   dim3 grid(nb, ceil_div(P, Q));
   k_cheb<T, Q, RPT><<<grid, CHEB_TPB, cheb_lds_bytes<T>(max_rows, Q), st>>>(
       A, row_off, t.order, crow, cnb, iv, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par,
-      t.tol2, t.rrpart, t.flags);
+      t.tol2, t.rrpart, t.flags, t.acct);
 }
 
 template <typename T, int RPT>
@@ -1057,12 +1063,12 @@ int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int
                const unsigned short* cnb, const double* iv, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                double* part2, double* sc, int par, double tol2, const double* rrpart,
-               int* flags, hipStream_t st) {
+               int* flags, unsigned long long* acct, hipStream_t st) {
   if (Q < 1 || Q > cheb_max_q<T>(max_rows) || deg < 1 || max_rows < 1 ||
       max_rows > 4 * CHEB_TPB || cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024 ||
       (sc && (!rrpart || !flags)) || !crow || !cnb)
     return -1;
-  const ChebTest t{order, sc, par, tol2, rrpart, flags};
+  const ChebTest t{order, acct, sc, par, tol2, rrpart, flags};
   if (max_rows <= CHEB_TPB)
     cheb_q<T, 1>(Q, A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
                  t, st);
@@ -1181,11 +1187,13 @@ template size_t cheb_lds_bytes<float>(int, int);
 template int cheb_apply<double>(const DEll<double>&, const int*, const int*, const int*,
                                 const unsigned short*, const double*, int, int, int,
                                 int, int, const double*, int, double*, int, double*, double*,
-                                double*, int, double, const double*, int*, hipStream_t);
+                                double*, int, double, const double*, int*, unsigned long long*,
+                                hipStream_t);
 template int cheb_apply<float>(const DEll<float>&, const int*, const int*, const int*,
                                const unsigned short*, const double*, int, int, int,
                                int, int, const float*, int, float*, int, double*, double*,
-                               double*, int, double, const double*, int*, hipStream_t);
+                               double*, int, double, const double*, int*, unsigned long long*,
+                               hipStream_t);
 template size_t tri_lds_bytes<float>(const DFactor&, int);
 #define SGW_INST(T)                                                                          \
   template void sg_apply<T>(const DEll<T>&, const GTab&, const DHalo*, int, int, const T*,    \

@@ -115,6 +115,9 @@ struct sgw_ctx {
   // algorithmic bytes per kind
   bool prof = false;
   int prof_every = 1;
+  unsigned long long* acct = nullptr;   // device [2]: K3c bytes of timed FP64 / FP32 launches
+  unsigned long long* acct_h = nullptr; // pinned copy
+  unsigned long long acct_seen[2] = {0, 0};
   long long pseen[6] = {0, 0, 0, 0, 0, 0};
   std::vector<hipEvent_t> ev;
   struct Pend { int a, kind; double bytes; };
@@ -320,6 +323,13 @@ static void prof_end(sgw_ctx* c, int a, int kind, double bytes, hipStream_t st) 
 }
 static void prof_harvest(sgw_ctx* c) {
   if (c->pend.empty()) return;
+  if (c->acct && hipMemcpy(c->acct_h, c->acct, 2 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost) == hipSuccess) {
+    for (int q = 0; q < 2; ++q) {
+      c->pbytes[q ? 5 : 2] += (double)(c->acct_h[q] - c->acct_seen[q]);
+      c->acct_seen[q] = c->acct_h[q];
+    }
+  }
   for (auto& p : c->pend) {
     float ms = 0.f;
     if (hipEventSynchronize(c->ev[p.a + 1]) == hipSuccess &&
@@ -370,12 +380,14 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
   if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
     const int kind = sizeof(T) == 4 ? 5 : 2;
     int a = prof_begin(c, kind, st);
+    // timed launches count their bytes on the device (converged blocks are
+    // skipped inside the kernel); harvested into the kind's total
     (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_iv, S.nb, P, c->cheb_deg,
                            S.cq,
                            S.max_block_rows, S.r, n, S.z, n, part, part2,
                            test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
-                           c->part2, c->flags, st);
-    prof_end(c, a, kind, 2.0 * sizeof(T) * P * n + 7.0 * (sizeof(T) + 4.0) * n, st);
+                           c->part2, c->flags, a >= 0 ? c->acct + (sizeof(T) == 4) : nullptr, st);
+    prof_end(c, a, kind, 0.0, st);
     return;
   }
   if (test_par >= 0) k::pcg_test(S.nb, P, test_par, c->part2, c->sc, tol2, c->flags, st);
@@ -1248,6 +1260,11 @@ int sgw_profile(sgw_ctx* c, int enable) {
   prof_harvest(c);
   c->prof = enable != 0;
   c->prof_every = std::max(1, enable);
+  if (c->acct && hipMemcpy(c->acct_h, c->acct, 2 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost) == hipSuccess) {
+    c->acct_seen[0] = c->acct_h[0];
+    c->acct_seen[1] = c->acct_h[1];
+  }
   for (int k2 = 0; k2 < 6; ++k2) {
     c->pcnt[k2] = 0;
     c->pms[k2] = 0.0;
@@ -1306,7 +1323,7 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
           (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_iv, S.nb, c->P,
                                  c->cheb_deg, q,
                                  S.max_block_rows, S.r, S.nrows, S.z, S.nrows, c->part,
-                                 c->part2, nullptr, 0, 0.0, nullptr, nullptr, st);
+                                 c->part2, nullptr, 0, 0.0, nullptr, nullptr, nullptr, st);
         });
         rep[cheb + q - 1] = us;
         if (us < best) {
@@ -1385,6 +1402,7 @@ int sgw_destroy(sgw_ctx* c) {
     else (void)hipFree(p);
   }
   if (c->hflags) (void)hipHostFree(c->hflags);
+  if (c->acct_h) (void)hipHostFree(c->acct_h);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1579,6 +1597,10 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     co.max_rem = std::max(co.max_rem, c->rem_off_h[s + 1] - c->rem_off_h[s]);
   c->dc = dalloc<double>(c, (size_t)std::max(1, h.nC * P));
   c->uc = dalloc<double>(c, (size_t)std::max(1, h.nC * P));
+  c->acct = dalloc<unsigned long long>(c, 2);
+  if (hipHostMalloc((void**)&c->acct_h, 2 * sizeof(unsigned long long)) != hipSuccess)
+    c->acct_h = nullptr;
+  if (!c->acct_h) c->acct = nullptr;
   if (hipHostMalloc((void**)&c->hflags, 16 * sizeof(int)) != hipSuccess) {
     c->err = "pinned allocation failed";
     *out = c;
