@@ -112,19 +112,27 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
                int ldo, int nbatch, long long sr, long long so, hipStream_t st);
 
 // Chebyshev polynomial preconditioner (degree deg, Q modes per workgroup) on
-// the blocks of A's mean matrix; iv[2b], iv[2b+1] = spectral interval of
-// block b; order (may be null) = launch order of the blocks (largest
-// first); crow[r0 + i] = system row at natural (lexicographic) position i
-// of the block starting at r0, cnb[s*nrows + r0 + i] = natural position of
-// that row's slot-s neighbour within the block.  Writes z and part[b*P + j] = r_j'z_j (part2 = r_j'r_j if not
-// null).  With sc != null it first does the PCG stopping test of iteration
-// par (r'r from rrpart, see pcg_test) and skips converged blocks.  With acct
-// != null, every active workgroup adds its algorithmic bytes (right-hand
-// sides in and out, the block's mean matrix once) to *acct.  Returns
-// -1 (nothing launched) if Q, deg or the block size is out of range
-// (max_rows <= 4096, Q <= cheb_max_q, Q * max_rows * sizeof(T) <= 150 KiB).
+// the blocks of A's mean matrix; coef[b * 2 deg ...] = the iteration
+// coefficients of block b (cheb_coefficients); order (may be null) = launch
+// order of the blocks (largest first); crow[r0 + i] = system row at natural
+// (lexicographic) position i of the block starting at r0, cnb[s*nrows + r0 +
+// i] = natural position of that row's slot-s neighbour within the block
+// (slot 0: the row itself).  Writes z and part[b*P + j] = r_j'z_j (part2 =
+// r_j'r_j if not null).  With sc != null it first does the PCG stopping test
+// of iteration par (r'r from rrpart, see pcg_test) and skips converged
+// blocks.  With acct != null, every active workgroup adds its algorithmic
+// bytes (right-hand sides in and out, the block's mean matrix once) to
+// *acct.  Returns -1 (nothing launched) if Q, deg or the block size is out
+// of range (max_rows <= 4096, Q <= cheb_max_q, cheb_lds_bytes <= 150 KiB).
 template <typename T>
 size_t cheb_lds_bytes(int max_rows, int Q);
+// Coefficients of deg Chebyshev steps on the spectral interval [lo, hi] of
+// one block (Saad, Alg. 12.1), in the layout cheb_apply reads: out[0] =
+// 1/theta, out[1] = 0, out[2k] = rho_k rho_{k-1}, out[2k+1] = 2 rho_k / delta
+// for k = 1..deg-1 (theta, delta: centre and half width of the interval,
+// the half width at least 1e-3 theta; rho_0 = delta / theta,
+// rho_k = 1 / (2 theta / delta - rho_{k-1})).  Computed in double.
+void cheb_coefficients(double lo, double hi, int deg, double* out);
 // largest mode tile cheb_apply accepts for blocks of up to max_rows rows
 template <typename T>
 int cheb_max_q(int max_rows);
@@ -133,7 +141,7 @@ int cheb_max_q(int max_rows);
 int cheb_prepare();
 template <typename T>
 int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int* crow,
-               const unsigned short* cnb, const double* iv, int nb, int P, int deg,
+               const unsigned short* cnb, const T* coef, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                double* part2, double* sc, int par, double tol2, const double* rrpart,
                int* flags, unsigned long long* acct, hipStream_t st);
@@ -151,11 +159,12 @@ void seg_dot(int nb, const int* row_off, int P, const T* a, int lda,
 void pcg_start(int nb, int P, const double* part, const double* part2, double* sc,
                double tol2, double negl, int* flags, hipStream_t st);
 // x += alpha_b p ; r -= alpha_b q with alpha_b = r'z / p'q (p'q from part);
-// part2[b*P + j] = ||r_bj||^2
+// part2[b*P + j] = ||r_bj||^2 on the active blocks; flags[3] = the largest
+// number of iterations a block has taken (flags has 4 entries)
 // (with bgrp: p'q summed from the partials part[g*pqn + k], k < pqn, of the
 // block's groups g = bgrp[b] .. bgrp[b+1]-1)
 template <typename T>
-void pcg_xr(int nb, const int* row_off, int P, int par, const double* sc, T* x, int ldx,
+void pcg_xr(int nb, const int* row_off, int P, int par, double* sc, T* x, int ldx,
             const T* p, int ldp, T* r, int ldr, const T* q, int ldq, const double* part,
             double* part2, int* flags, hipStream_t st, const int* bgrp = nullptr,
             int pqn = 0);
@@ -177,6 +186,17 @@ void fill2d(int P, int n, T* dst, int ldd, T v, hipStream_t st);
 template <typename T>
 void axpby2d(int P, int n, double a, const T* x, int ldx, double b, const T* y,
              int ldy, T* dst, int ldd, hipStream_t st);
+// the same with device coefficients: a = sa * ds[ia], b = sb * ds[ib] (an
+// index < 0 takes sa or sb alone)
+template <typename T>
+void axpby2d_dev(int P, int n, double sa, int ia, const T* x, int ldx, double sb, int ib,
+                 const T* y, int ldy, T* dst, int ldd, const double* ds, hipStream_t st);
+// Interface PCG scalars in ds (device; sums over the P partials of a, b):
+// mode 0: ds[par] = sum a (r'z); mode 1: ds[2] = alpha = ds[par] / sum a
+// (sum a = p'q; if not > 0: alpha = 0 and ds[4] = 1, or 2 if non-finite);
+// mode 2: ds[3] = beta = (sum a - sum b) / ds[par], ds[1 - par] = sum a.
+void outer_scalars(int mode, int P, const double* a, const double* b, double* ds, int par,
+                   hipStream_t st);
 
 // Newmark predictor (Eq. UmCm, UmCm2) and the mass-term vector of the force.
 void newmark_predict(int P, int n, int ld, const double* U, const double* V,

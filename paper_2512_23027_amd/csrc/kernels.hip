@@ -9,6 +9,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 
 namespace sgw {
@@ -557,6 +558,7 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_start(int nb, int P, const do
     const bool act = s[4] > floor_bb && s[4] > tol2 * s[4] && s[4] > 0.0;
     s[2] = act ? 1.0 : 0.0;
     s[1] = INFINITY;  // "previous r'z" of iteration 0: beta = 0 in the fused SG apply
+    s[5] = 0.0;       // iterations taken by the block
     if (act) atomicAdd(&nact, 1);
   }
   __syncthreads();
@@ -564,6 +566,7 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_start(int nb, int P, const do
     flags[0] = nact;
     flags[1] = 0;
     flags[2] = bad;
+    flags[3] = 0;
   }
 }
 
@@ -573,20 +576,29 @@ void pcg_start(int nb, int P, const double* part, const double* part2, double* s
 }
 
 // x += alpha p, r -= alpha q on the active blocks, alpha = r'z / p'q of the
-// block (p'q summed from part); writes part2 = r'r per (block, mode) for every
-// block.  Workgroup (0, 0) clears the active counter for the test that follows.
+// block (p'q summed from part); writes part2 = r'r per (block, mode) of the
+// active blocks (a converged block is frozen: its r'r is not read again).
+// Counts the block's iterations in sc[8b + 5] and keeps their maximum over
+// the blocks in flags[3].  Workgroup (0, 0) clears the active counter for the
+// test that follows.
 template <typename T>
 __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
-    const int* row_off, int P, int par, const double* sc, T* x, int ldx, const T* p, int ldp,
+    const int* row_off, int P, int par, double* sc, T* x, int ldx, const T* p, int ldp,
     T* r, int ldr, const T* q, int ldq, const double* part, double* part2, int* flags,
     const int* bgrp, int pqn) {
   __shared__ double sh[SGW_BLOCK / 64];
   const int blk = blockIdx.x, j = blockIdx.y;
   const int r0 = row_off[blk], r1 = row_off[blk + 1];
-  const double* s = sc + (size_t)blk * 8;
+  double* s = sc + (size_t)blk * 8;
   const bool act = s[2 + par] != 0.0;
+  if (blk == 0 && j == 0 && threadIdx.x == 0) flags[0] = 0;
+  if (!act) return;
+  if (j == 0 && threadIdx.x == 0) {
+    s[5] += 1.0;
+    atomicMax(&flags[3], (int)s[5]);
+  }
   double al = 0.0;
-  if (act) {
+  {
     double pq = 0.0;
     if (bgrp) {  // per-group partials of the fused SG apply (pqn per group)
       for (int q = bgrp[blk] * pqn; q < bgrp[blk + 1] * pqn; ++q) pq += part[q];
@@ -600,7 +612,6 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
       else atomicOr(&flags[2], 1);
     }
   }
-  if (blk == 0 && j == 0 && threadIdx.x == 0) flags[0] = 0;
   const T alt = (T)al;
   double acc = 0.0;
   T* xp = x + (size_t)j * ldx;
@@ -621,7 +632,7 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
 }
 
 template <typename T>
-void pcg_xr(int nb, const int* row_off, int P, int par, const double* sc, T* x, int ldx,
+void pcg_xr(int nb, const int* row_off, int P, int par, double* sc, T* x, int ldx,
             const T* p, int ldp, T* r, int ldr, const T* q, int ldq, const double* part,
             double* part2, int* flags, hipStream_t st, const int* bgrp, int pqn) {
   k_pcg_xr<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, par, sc, x, ldx, p, ldp, r, ldr,
@@ -731,6 +742,53 @@ void axpby2d(int P, int n, double a, const T* x, int ldx, double b, const T* y,
   if (N > 0) k_axpby2d<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(P, n, a, x, ldx, b, y, ldy, dst, ldd);
 }
 
+// dst = sa * (ia >= 0 ? ds[ia] : 1) * x + sb * (ib >= 0 ? ds[ib] : 1) * y with
+// the coefficients read from device scalars
+template <typename T>
+__global__ void k_axpby2d_dev(int P, int n, double sa, int ia, const T* x, int ldx, double sb,
+                              int ib, const T* y, int ldy, T* dst, int ldd, const double* ds) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)P * n) return;
+  const double a = ia >= 0 ? sa * ds[ia] : sa, b = ib >= 0 ? sb * ds[ib] : sb;
+  int j = (int)(t / n), r = (int)(t % n);
+  double v = a * (double)x[(size_t)j * ldx + r] + b * (double)y[(size_t)j * ldy + r];
+  dst[(size_t)j * ldd + r] = (T)v;
+}
+template <typename T>
+void axpby2d_dev(int P, int n, double sa, int ia, const T* x, int ldx, double sb, int ib,
+                 const T* y, int ldy, T* dst, int ldd, const double* ds, hipStream_t st) {
+  long long N = (long long)P * n;
+  if (N > 0)
+    k_axpby2d_dev<T><<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(P, n, sa, ia, x, ldx, sb, ib,
+                                                                   y, ldy, dst, ldd, ds);
+}
+
+// Scalars of the interface PCG (one thread; sums of the P mode partials in
+// mode order, as the host would form them)
+__global__ void k_outer_scalars(int mode, int P, const double* a, const double* b, double* ds,
+                                int par) {
+  double sa = 0.0, sb = 0.0;
+  for (int j = 0; j < P; ++j) sa += a[j];
+  if (mode == 0) {  // start: r'z
+    ds[par] = sa;
+  } else if (mode == 1) {  // alpha = r'z / p'q, breakdown flag
+    if (sa > 0.0) {
+      ds[2] = ds[par] / sa;
+    } else {
+      ds[2] = 0.0;
+      ds[4] = isfinite(sa) ? 1.0 : 2.0;
+    }
+  } else {  // flexible beta = (r'z - r'z_prev) / r'z_old; r'z of the next iteration
+    for (int j = 0; j < P; ++j) sb += b[j];
+    ds[3] = (sa - sb) / ds[par];
+    ds[1 - par] = sa;
+  }
+}
+void outer_scalars(int mode, int P, const double* a, const double* b, double* ds, int par,
+                   hipStream_t st) {
+  k_outer_scalars<<<1, 1, 0, st>>>(mode, P, a, b, ds, par);
+}
+
 // ---------------------------------------------------------------------------
 // K7: Newmark predictor (Eq. UmCm, UmCm2) and update (Sec. 2).
 // Wm = Um + wc Uc is the vector the mass matrix multiplies in the effective
@@ -830,20 +888,83 @@ void gather_from_torn(int nG, int P, const int* gptr, const int* gtorn, const do
 // fixed order.
 // ---------------------------------------------------------------------------
 #define CHEB_TPB 1024
+#define CHEB_MAX_DEG 64
+#define CHEB_COEF_BYTES (2 * CHEB_MAX_DEG * 8)
+
+// Q consecutive values of one row in an LDS direction buffer, read in the
+// widest naturally aligned pieces (the row's byte offset is a multiple of
+// Q * sizeof(T)).
+template <typename T, int Q>
+__device__ __forceinline__ void lds_read_row(const unsigned char* p, T (&v)[Q]) {
+  constexpr int bytes = Q * (int)sizeof(T);
+  constexpr int piece = bytes % 16 == 0 ? 16 : (bytes % 8 == 0 ? 8 : 4);
+  constexpr int per = piece / (int)sizeof(T) > 0 ? piece / (int)sizeof(T) : 1;
+  if constexpr (piece == 16 && sizeof(T) == 4) {
+#pragma unroll
+    for (int c = 0; c < Q / 4; ++c) {
+      const float4 w = *reinterpret_cast<const float4*>(p + 16 * c);
+      v[4 * c] = w.x; v[4 * c + 1] = w.y; v[4 * c + 2] = w.z; v[4 * c + 3] = w.w;
+    }
+  } else if constexpr (piece >= 8 && sizeof(T) == 4) {
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c) {
+      const float2 w = *reinterpret_cast<const float2*>(p + 8 * c);
+      v[2 * c] = w.x; v[2 * c + 1] = w.y;
+    }
+  } else if constexpr (piece == 16 && sizeof(T) == 8) {
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c) {
+      const double2 w = *reinterpret_cast<const double2*>(p + 16 * c);
+      v[2 * c] = w.x; v[2 * c + 1] = w.y;
+    }
+  } else {
+    (void)per;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = *reinterpret_cast<const T*>(p + q * sizeof(T));
+  }
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ void lds_write_row(unsigned char* p, const T (&v)[Q]) {
+  constexpr int bytes = Q * (int)sizeof(T);
+  if constexpr (bytes % 16 == 0 && sizeof(T) == 4) {
+#pragma unroll
+    for (int c = 0; c < Q / 4; ++c)
+      *reinterpret_cast<float4*>(p + 16 * c) =
+          make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+  } else if constexpr (bytes % 8 == 0 && sizeof(T) == 4) {
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c)
+      *reinterpret_cast<float2*>(p + 8 * c) = make_float2(v[2 * c], v[2 * c + 1]);
+  } else if constexpr (bytes % 16 == 0 && sizeof(T) == 8) {
+#pragma unroll
+    for (int c = 0; c < Q / 2; ++c)
+      *reinterpret_cast<double2*>(p + 16 * c) = make_double2(v[2 * c], v[2 * c + 1]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) *reinterpret_cast<T*>(p + q * sizeof(T)) = v[q];
+  }
+}
 
 template <typename T, int Q, int RPT>
 __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     DEll<T> A, const int* __restrict__ row_off, const int* __restrict__ order,
     const int* __restrict__ crow, const unsigned short* __restrict__ cnb,
-    const double* __restrict__ iv, int P, int deg,
+    const T* __restrict__ coef, int P, int deg,
     const T* __restrict__ r, int ldr, T* __restrict__ z, int ldz, double* __restrict__ part,
     double* __restrict__ part2, double* sc, int par, double tol2, const double* rrpart,
     int* flags, unsigned long long* acct) {
   // all LDS is dynamic (so the launch may use up to the whole 160 KiB):
-  // the reduction slots, then two buffers of the search direction [Q][n]
-  extern __shared__ unsigned char smem_raw[];
-  double(*red)[CHEB_TPB / 64][Q] = reinterpret_cast<double(*)[CHEB_TPB / 64][Q]>(smem_raw);
-  T* Dk0 = reinterpret_cast<T*>(smem_raw + sizeof(double) * 2 * (CHEB_TPB / 64) * Q);
+  // two buffers of the search direction, each [RPT * CHEB_TPB][Q] (the Q
+  // modes of a row side by side, at a fixed stride, so every LDS offset but
+  // the neighbour's row is a constant), the step coefficients, the
+  // reduction slots
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr size_t kBuf = sizeof(T) * (size_t)RPT * CHEB_TPB * Q;
+  unsigned char* dir = smem_raw;
+  T* cs = reinterpret_cast<T*>(smem_raw + 2 * kBuf);
+  double(*red)[CHEB_TPB / 64][Q] =
+      reinterpret_cast<double(*)[CHEB_TPB / 64][Q]>(smem_raw + 2 * kBuf + CHEB_COEF_BYTES);
   const int b = order ? order[blockIdx.x] : blockIdx.x, j0 = blockIdx.y * Q;
   if (sc) {  // stopping test of PCG iteration par, fused (see k_pcg_test)
     const double rr = sum_modes(rrpart, b, P);
@@ -862,18 +983,25 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     atomicAdd(acct, (unsigned long long)(2 * sizeof(T) * nq * n +
                                          (blockIdx.y == 0 ? 7 * (sizeof(T) + 4) * n : 0)));
   }
-  const double lo = iv[2 * b], hi = iv[2 * b + 1];
-  const double theta = 0.5 * (hi + lo);
-  const double delta = fmax(0.5 * (hi - lo), 1e-3 * theta);
-  const double sigma = theta / delta;
-  double rho = 1.0 / sigma;
+  // the block's step coefficients, staged in LDS (read after the first
+  // barrier)
+  for (int e = threadIdx.x; e < 2 * deg; e += CHEB_TPB) cs[e] = coef[(size_t)b * 2 * deg + e];
   // thread i owns the row at natural (lexicographic mesh) position i of the
   // block, crow[r0 + i]; the LDS copy of the direction is in natural order,
-  // so the neighbour reads of a wave are nearly contiguous (few bank
-  // conflicts); cnb gives the neighbours' natural positions
-  int lc[RPT][7], row[RPT];
+  // so the neighbour reads and the writes of a wave are nearly contiguous
+  // (few bank conflicts; measured: rows in system order with scattered LDS
+  // positions take twice as long per step); cnb gives the neighbours'
+  // natural positions (slot 0 is the row itself, whose value the thread
+  // holds)
+  unsigned lo[RPT][7];
+  int row[RPT];
   T av[RPT][7], dinv[RPT];
+  // the right-hand side stays in registers for the final r'z when small
+  // (else it is read again)
+  constexpr bool kKeepR = RPT * Q * sizeof(T) <= 24;
+  T rin[kKeepR ? RPT : 1][kKeepR ? Q : 1];
   T res[RPT][Q], zz[RPT][Q], dd[RPT][Q];
+  const T inv_theta = coef[(size_t)b * 2 * deg];
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int i = threadIdx.x + t * CHEB_TPB;
@@ -881,7 +1009,7 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     row[t] = live ? crow[r0 + i] : r0;
 #pragma unroll
     for (int sl = 0; sl < 7; ++sl) {
-      lc[t][sl] = live ? (int)cnb[(size_t)sl * NR + r0 + i] : 0;
+      lo[t][sl] = (live ? (unsigned)cnb[(size_t)sl * NR + r0 + i] : 0u) * (unsigned)(Q * sizeof(T));
       av[t][sl] = live ? A.val[(size_t)sl * NR + row[t]] : T(0);
     }
     dinv[t] = live ? T(1) / av[t][0] : T(0);
@@ -889,45 +1017,55 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     for (int q = 0; q < Q; ++q) {
       const int j = j0 + q;
       const T v = (live && j < P) ? r[(size_t)j * ldr + row[t]] : T(0);
+      if constexpr (kKeepR) rin[t][q] = v;
       res[t][q] = v;
       zz[t][q] = T(0);
-      dd[t][q] = dinv[t] * v * (T)(1.0 / theta);
+      dd[t][q] = dinv[t] * v * inv_theta;
     }
   }
-  for (int k = 0; k < deg; ++k) {
+  // one Chebyshev step; step k writes direction buffer k & 1 (compile-time
+  // offset): the buffer written two steps earlier is free because every
+  // thread has passed the barrier of step k-1, after its reads of step k-2
+  auto step = [&](auto bufc, int k) -> bool {
+    constexpr size_t boff = decltype(bufc)::value * kBuf;
 #pragma unroll
     for (int t = 0; t < RPT; ++t)
 #pragma unroll
       for (int q = 0; q < Q; ++q) zz[t][q] += dd[t][q];
-    if (k + 1 == deg) break;
-    // step k writes buffer k&1; the buffer written two steps earlier is free
-    // because every thread has passed the barrier of step k-1, after its
-    // reads of step k-2
-    T* Dk = Dk0 + (size_t)(k & 1) * Q * n;
+    if (k + 1 == deg) return true;
+    unsigned char* Dk = dir + boff;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int i = threadIdx.x + t * CHEB_TPB;
-      if (i < n)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) Dk[q * n + i] = dd[t][q];
+      if (i < n) lds_write_row<T, Q>(Dk + (size_t)i * Q * sizeof(T), dd[t]);
     }
     __syncthreads();
-    const double rn = 1.0 / (2.0 * sigma - rho);
-    const T c1 = (T)(rn * rho), c2 = (T)(2.0 * rn / delta);
-    rho = rn;
+    const T c1 = cs[2 * (k + 1)], c2 = cs[2 * (k + 1) + 1];
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int i = threadIdx.x + t * CHEB_TPB;
       if (i >= n) continue;
+      T ad[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) ad[q] = av[t][0] * dd[t][q];
+#pragma unroll
+      for (int sl = 1; sl < 7; ++sl) {
+        T nv[Q];
+        lds_read_row<T, Q>(Dk + lo[t][sl], nv);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) ad[q] = fmadd(av[t][sl], nv[q], ad[q]);
+      }
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        T ad = av[t][0] * Dk[q * n + lc[t][0]];
-#pragma unroll
-        for (int sl = 1; sl < 7; ++sl) ad = fmadd(av[t][sl], Dk[q * n + lc[t][sl]], ad);
-        res[t][q] -= ad;
+        res[t][q] -= ad[q];
         dd[t][q] = fmadd(c1, dd[t][q], c2 * dinv[t] * res[t][q]);
       }
     }
+    return false;
+  };
+  for (int k = 0;; k += 2) {
+    if (step(std::integral_constant<int, 0>{}, k)) break;
+    if (step(std::integral_constant<int, 1>{}, k + 1)) break;
   }
   // store z; partial sums of r'z and r'r
   double srz[Q], srr[Q];
@@ -942,7 +1080,9 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
       const int j = j0 + q;
       if (j >= P) continue;
       z[(size_t)j * ldz + row[t]] = zz[t][q];
-      const double rv = (double)r[(size_t)j * ldr + row[t]];
+      double rv;
+      if constexpr (kKeepR) rv = (double)rin[t][q];
+      else rv = (double)r[(size_t)j * ldr + row[t]];
       srz[q] += rv * (double)zz[t][q];
       srr[q] += rv * rv;
     }
@@ -970,9 +1110,29 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
   }
 }
 
+void cheb_coefficients(double lo, double hi, int deg, double* out) {
+  const double theta = 0.5 * (hi + lo);
+  const double delta = std::max(0.5 * (hi - lo), 1e-3 * theta);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  out[0] = 1.0 / theta;
+  out[1] = 0.0;
+  for (int k = 1; k < deg; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    out[2 * k] = rn * rho;
+    out[2 * k + 1] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+
+static int cheb_rpt(int max_rows) {
+  return max_rows <= CHEB_TPB ? 1 : (max_rows <= 2 * CHEB_TPB ? 2 : 4);
+}
+
 template <typename T>
 size_t cheb_lds_bytes(int max_rows, int Q) {
-  return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + 2 * (size_t)max_rows * Q * sizeof(T);
+  return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + CHEB_COEF_BYTES +
+         2 * (size_t)cheb_rpt(max_rows) * CHEB_TPB * Q * sizeof(T);
 }
 
 struct ChebTest {  // optional fused stopping test (sc == nullptr: none), block order,
@@ -987,24 +1147,24 @@ struct ChebTest {  // optional fused stopping test (sc == nullptr: none), block 
 
 template <typename T, int Q, int RPT>
 static void launch_cheb(const DEll<T>& A, const int* row_off, const int* crow,
-                        const unsigned short* cnb, const double* iv, int nb, int P,
+                        const unsigned short* cnb, const T* coef, int nb, int P,
                         int deg, int max_rows, const T* r, int ldr, T* z, int ldz,
                         double* part, double* part2, const ChebTest& t, hipStream_t st) {
   dim3 grid(nb, ceil_div(P, Q));
   k_cheb<T, Q, RPT><<<grid, CHEB_TPB, cheb_lds_bytes<T>(max_rows, Q), st>>>(
-      A, row_off, t.order, crow, cnb, iv, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par,
+      A, row_off, t.order, crow, cnb, coef, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par,
       t.tol2, t.rrpart, t.flags, t.acct);
 }
 
 template <typename T, int RPT>
 static void cheb_q(int Q, const DEll<T>& A, const int* row_off, const int* crow,
-                   const unsigned short* cnb, const double* iv, int nb, int P,
+                   const unsigned short* cnb, const T* coef, int nb, int P,
                    int deg, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                    double* part2, const ChebTest& t, hipStream_t st) {
   switch (Q) {
 #define SGW_CHEB_CASE(q)                                                                      \
   case q:                                                                                    \
-    launch_cheb<T, q, RPT>(A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz,   \
+    launch_cheb<T, q, RPT>(A, row_off, crow, cnb, coef, nb, P, deg, max_rows, r, ldr, z, ldz, \
                            part, part2, t, st);                                              \
     break;
     SGW_CHEB_CASE(1)
@@ -1060,23 +1220,23 @@ int cheb_max_q(int max_rows) {
 
 template <typename T>
 int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int* crow,
-               const unsigned short* cnb, const double* iv, int nb, int P, int deg,
+               const unsigned short* cnb, const T* coef, int nb, int P, int deg,
                int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
                double* part2, double* sc, int par, double tol2, const double* rrpart,
                int* flags, unsigned long long* acct, hipStream_t st) {
-  if (Q < 1 || Q > cheb_max_q<T>(max_rows) || deg < 1 || max_rows < 1 ||
+  if (Q < 1 || Q > cheb_max_q<T>(max_rows) || deg < 1 || deg > CHEB_MAX_DEG || max_rows < 1 ||
       max_rows > 4 * CHEB_TPB || cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024 ||
-      (sc && (!rrpart || !flags)) || !crow || !cnb)
+      (sc && (!rrpart || !flags)) || !crow || !cnb || !coef)
     return -1;
   const ChebTest t{order, acct, sc, par, tol2, rrpart, flags};
   if (max_rows <= CHEB_TPB)
-    cheb_q<T, 1>(Q, A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
+    cheb_q<T, 1>(Q, A, row_off, crow, cnb, coef, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
                  t, st);
   else if (max_rows <= 2 * CHEB_TPB)
-    cheb_q<T, 2>(Q, A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
+    cheb_q<T, 2>(Q, A, row_off, crow, cnb, coef, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
                  t, st);
   else
-    cheb_q<T, 4>(Q, A, row_off, crow, cnb, iv, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
+    cheb_q<T, 4>(Q, A, row_off, crow, cnb, coef, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
                  t, st);
   return 0;
 }
@@ -1190,7 +1350,7 @@ template int cheb_apply<double>(const DEll<double>&, const int*, const int*, con
                                 double*, int, double, const double*, int*, unsigned long long*,
                                 hipStream_t);
 template int cheb_apply<float>(const DEll<float>&, const int*, const int*, const int*,
-                               const unsigned short*, const double*, int, int, int,
+                               const unsigned short*, const float*, int, int, int,
                                int, int, const float*, int, float*, int, double*, double*,
                                double*, int, double, const double*, int*, unsigned long long*,
                                hipStream_t);
@@ -1204,7 +1364,7 @@ template size_t tri_lds_bytes<float>(const DFactor&, int);
                              long long, hipStream_t);                                        \
   template void seg_dot<T>(int, const int*, int, const T*, int, const T*, int, double*,     \
                            const T*, int, const T*, int, double*, hipStream_t);             \
-  template void pcg_xr<T>(int, const int*, int, int, const double*, T*, int, const T*, int, \
+  template void pcg_xr<T>(int, const int*, int, int, double*, T*, int, const T*, int, \
                           T*, int, const T*, int, const double*, double*, int*,            \
                           hipStream_t, const int*, int);                                     \
   template bool sg_apply_pcg<T>(const DEll<T>&, const GTab&, const DHalo&, int, const T*,    \
@@ -1215,6 +1375,8 @@ template size_t tri_lds_bytes<float>(const DFactor&, int);
   template void fill2d<T>(int, int, T*, int, T, hipStream_t);                               \
   template void axpby2d<T>(int, int, double, const T*, int, double, const T*, int, T*, int, \
                            hipStream_t);                                                     \
+  template void axpby2d_dev<T>(int, int, double, int, const T*, int, double, int, const T*,  \
+                               int, T*, int, const double*, hipStream_t);                    \
   template void scatter_to_torn<T>(int, int, const int*, const double*, const T*, int, T*,  \
                                    int, hipStream_t);                                        \
   template void gather_from_torn<T>(int, int, const int*, const int*, const double*,        \

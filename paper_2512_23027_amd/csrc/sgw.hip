@@ -43,11 +43,13 @@ struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   int nrows = 0, nb = 0, Q = 8;
   int cq = 8, max_block_rows = 0;     // Chebyshev mode tile, largest block
   const k::DHalo* halo = nullptr;     // 64-row group halos of A (both precisions)
-  const double* cheb_iv = nullptr;    // device, [nb][2] spectral intervals
+  const T* cheb_cc = nullptr;         // device, [nb][2 deg] Chebyshev step coefficients
   const int* lpt = nullptr;           // device, blocks by decreasing size (launch order)
   const int* crow = nullptr;          // device, system row of each natural block position
   const unsigned short* cnb = nullptr;  // device, [7][nrows] neighbours' natural positions
-  int last_its[2] = {0, 0};     // previous iteration counts (tight / loose tolerance)
+  // iteration count of the previous solve, by call site (see inner_solve)
+  // and tolerance class (tight / loose)
+  int last_its[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double loose_tol = 1e300;     // tolerances >= this use the second count
   k::DEll<T> A;
   k::DFactor F;
@@ -92,6 +94,8 @@ struct sgw_ctx {
   double *U = nullptr, *V = nullptr, *A = nullptr, *Um = nullptr, *Uc = nullptr,
          *Wm = nullptr, *F = nullptr, *meshbuf = nullptr, *meshbuf2 = nullptr;
   double *part = nullptr, *part2 = nullptr, *sc = nullptr, *dc = nullptr, *uc = nullptr;
+  double* osc = nullptr;   // interface PCG: G'G and r'r partials, device scalars
+  double* hosc = nullptr;  // pinned copy of osc
   int* flags = nullptr;
   int* hflags = nullptr;
   const int* goff = nullptr;   // {0, nG}: rows relative to an interface-part pointer
@@ -117,6 +121,7 @@ struct sgw_ctx {
   int prof_every = 1;
   unsigned long long* acct = nullptr;   // device [2]: K3c bytes of timed FP64 / FP32 launches
   unsigned long long* acct_h = nullptr; // pinned copy
+  bool acct_staged = false;             // acct_h holds the counters (prof_stage)
   unsigned long long acct_seen[2] = {0, 0};
   long long pseen[6] = {0, 0, 0, 0, 0, 0};
   std::vector<hipEvent_t> ev;
@@ -321,10 +326,19 @@ static void prof_end(sgw_ctx* c, int a, int kind, double bytes, hipStream_t st) 
   (void)hipEventRecord(c->ev[a + 1], st);
   c->pend.push_back({a, kind, bytes});
 }
+// Before a stream synchronisation: the device byte counters are copied on
+// the stream, so the harvest after it needs no copy of its own.
+static void prof_stage(sgw_ctx* c, hipStream_t st) {
+  if (c->pend.empty() || !c->acct) return;
+  c->acct_staged = hipMemcpyAsync(c->acct_h, c->acct, 2 * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, st) == hipSuccess;
+}
 static void prof_harvest(sgw_ctx* c) {
   if (c->pend.empty()) return;
-  if (c->acct && hipMemcpy(c->acct_h, c->acct, 2 * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost) == hipSuccess) {
+  const bool staged = c->acct_staged;
+  c->acct_staged = false;
+  if (c->acct && (staged || hipMemcpy(c->acct_h, c->acct, 2 * sizeof(unsigned long long),
+                                      hipMemcpyDeviceToHost) == hipSuccess)) {
     for (int q = 0; q < 2; ++q) {
       c->pbytes[q ? 5 : 2] += (double)(c->acct_h[q] - c->acct_seen[q]);
       c->acct_seen[q] = c->acct_h[q];
@@ -382,7 +396,7 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
     int a = prof_begin(c, kind, st);
     // timed launches count their bytes on the device (converged blocks are
     // skipped inside the kernel); harvested into the kind's total
-    (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_iv, S.nb, P, c->cheb_deg,
+    (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, P, c->cheb_deg,
                            S.cq,
                            S.max_block_rows, S.r, n, S.z, n, part, part2,
                            test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
@@ -446,12 +460,20 @@ static int pair_graph(sgw_ctx* c, const void* sys, double tol2, Enqueue enqueue,
   return 0;
 }
 
+// Call sites of inner_solve, each with its own iteration prediction.
+enum { kSiteSchur = 0, kSiteNeumann = 1, kSiteCondense = 2, kSiteRecover = 3 };
+
+// Batched block PCG.  The host reads the device's convergence flags only
+// once the predicted number of iterations (that of the previous solve from
+// the same call site) has been issued, then after every further iteration;
+// a block that has converged is frozen (every kernel of an iteration skips
+// it), so iterations issued past its convergence cost a few microseconds.
 template <typename T>
 static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb, T* out,
-                       int ldo, double tol, int maxit, hipStream_t st) {
+                       int ldo, double tol, int maxit, int site, hipStream_t st) {
   const int P = c->P, n = S.nrows, nb = S.nb;
   const double tol2 = tol * tol;
-  int& predicted = S.last_its[tol >= S.loose_tol ? 1 : 0];
+  int& predicted = S.last_its[2 * site + (tol >= S.loose_tol ? 1 : 0)];
   // fused iteration: the SG apply also forms p (alternating buffers) and the
   // p'q partial sums (generated kernel on a block-aligned halo)
   const bool fused = c->gt.use_spec && c->k1_generated > 0 && S.halo && !S.halo->aligned64 &&
@@ -463,8 +485,9 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
   k::pcg_start(nb, P, c->part, c->part2, c->sc, tol2, NegligibleBlock<T>::value, c->flags, st);
   int it = 0, rc = 0;
   int nact = 1;
+  int done = 0;  // iterations of the slowest block (device count)
   if (predicted <= 1) {
-    HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     nact = c->hflags[0];
     if (c->hflags[2]) {
@@ -500,7 +523,7 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
   // replay a captured graph; frozen blocks make extra iterations harmless
   if (c->use_graphs && !c->prof && nact > 0) {
     hipGraphExec_t ge = nullptr;
-    while (it + 3 < predicted && it + 2 <= maxit) {
+    while (it + 2 <= predicted && it + 2 <= maxit) {
       if (!ge) {
         int grc = pair_graph(c, &S, tol2, [&](hipStream_t s) {
           first_half(0, s);
@@ -523,11 +546,13 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
     const int par = it & 1;
     first_half(par, st);
     ++it;
-    if (it + 1 >= predicted || it >= maxit) {
-      HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    if (it >= predicted || it >= maxit) {
+      HIPCHK(hipMemcpyAsync(c->hflags, c->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+      prof_stage(c, st);
       HIPCHK(hipStreamSynchronize(st));
       prof_harvest(c);
       nact = c->hflags[0];
+      done = c->hflags[3];
       if (c->hflags[1]) {
         c->err = "breakdown (p'q <= 0) in a subdomain solve";
         return SGW_EBREAKDOWN;
@@ -541,8 +566,8 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
     second_half(par, st);
   }
   k::copy2d<T, T>(P, n, S.x, n, out, ldo, 1.0, st);
-  predicted = it;
-  c->inner_its += it;
+  predicted = done;
+  c->inner_its += done;
   c->inner_solves += 1;
   return rc;
 }
@@ -556,7 +581,8 @@ static int schur_apply(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, T* w, T* q, hip
   const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
   k::fill2d<T>(P, nI, w, NF, T(0), st);
   K1<T>(c, pr.G, &c->hal_G0, 0, nI, w, NF, pr.T1, NF, -1.0, 0.0, st);
-  int rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, w, NF, tl.inner, tl.inner_max_iter, st);
+  int rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, w, NF, tl.inner, tl.inner_max_iter,
+                          kSiteSchur, st);
   if (rc < 0) return rc;
   K1<T>(c, pr.G, &c->hal_GI, nI, nG, w, NF, q, NF, 1.0, 0.0, st);
   return rc;
@@ -572,7 +598,8 @@ template <typename T>
 static int precond(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* r, T* z, hipStream_t st) {
   const int P = c->P, NF = c->NF, NT = c->NT, nG = c->nG;
   k::scatter_to_torn<T>(NT, P, c->torn_gidx, c->torn_w, r, NF, pr.Tt, NT, st);
-  int rc = inner_solve<T>(c, pr.N, true, pr.Tt, NT, pr.Yt, NT, tl.precond, tl.inner_max_iter, st);
+  int rc = inner_solve<T>(c, pr.N, true, pr.Tt, NT, pr.Yt, NT, tl.precond, tl.inner_max_iter,
+                          kSiteNeumann, st);
   if (rc < 0) return rc;
   if (c->nC > 0) {
     k::coarse_rhs<T>(c->co, r, NF, pr.Yt, NT, c->dc, st);
@@ -584,21 +611,6 @@ static int precond(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* r, T* z, h
   return rc;
 }
 
-// Dot product over the interface rows (one block), FP64 sums, fixed order.
-template <typename T>
-static int gdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st) {
-  k::seg_dot<T>(1, c->goff, c->P, a, c->NF, b, c->NF, c->part, nullptr, 0, nullptr, 0, nullptr,
-                st);
-  std::vector<double> h(c->P);
-  HIPCHK(hipMemcpyAsync(h.data(), c->part, c->P * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  prof_harvest(c);
-  double s = 0.0;
-  for (double v : h) s += v;
-  out = s;
-  return 0;
-}
-
 // One SG system K~ U = F on the DD numbering (F, X full [P][NF] arrays of
 // this precision); X holds the interface initial guess on entry and the full
 // solution on exit.
@@ -608,14 +620,38 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
   int warn = 0, rc;
   // H2: condensation G = F_G - K~_GI K~_II^{-1} F_I
-  rc = inner_solve<T>(c, pr.D, false, F, NF, pr.T1, NF, tl.inner, tl.inner_max_iter, st);
+  rc = inner_solve<T>(c, pr.D, false, F, NF, pr.T1, NF, tl.inner, tl.inner_max_iter,
+                      kSiteCondense, st);
   if (rc < 0) return rc;
   warn |= rc;
   k::fill2d<T>(P, nG, pr.T1 + nI, NF, T(0), st);
   k::copy2d<T, T>(P, nG, F + nI, NF, pr.Gv + nI, NF, 1.0, st);
   K1<T>(c, pr.G, &c->hal_GI, nI, nG, pr.T1, NF, pr.Gv, NF, -1.0, 1.0, st);
-  double gg;
-  if ((rc = gdot<T>(c, pr.Gv + nI, pr.Gv + nI, gg, st))) return rc;
+  // The PCG scalars (alpha, beta, r'z) stay on the device; the host reads
+  // r'r (and G'G at the start) for the stopping test, once per iteration.
+  // osc = [G'G partials (P)][r'r partials (P)][ds: r'z by parity, alpha,
+  // beta, breakdown flag, ...]
+  double* const ggp = c->osc;
+  double* const rrp = c->osc + P;
+  double* const ds = c->osc + 2 * P;
+  auto read_rr = [&](double& rr, bool with_gg, double* gg) -> int {
+    const int off = with_gg ? 0 : P;
+    HIPCHK(hipMemcpyAsync(c->hosc + off, c->osc + off, (2 * P + 8 - off) * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    prof_stage(c, st);
+    HIPCHK(hipStreamSynchronize(st));
+    prof_harvest(c);
+    rr = 0.0;
+    for (int j = 0; j < P; ++j) rr += c->hosc[P + j];
+    if (with_gg) {
+      *gg = 0.0;
+      for (int j = 0; j < P; ++j) *gg += c->hosc[j];
+    }
+    return 0;
+  };
+  k::fill2d<double>(1, 8, ds, 8, 0.0, st);
+  k::seg_dot<T>(1, c->goff, P, pr.Gv + nI, NF, pr.Gv + nI, NF, ggp, nullptr, 0, nullptr, 0,
+                nullptr, st);
   // H3/H4: PCG on S U_G = G, initial guess in X's interface part
   T* x = X + nI;
   T* r = pr.R + nI;
@@ -627,9 +663,11 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
   warn |= rc;
   k::axpby2d<T>(P, nG, 1.0, pr.Gv + nI, NF, -1.0, q, NF, r, NF, st);
+  double gg = 0.0, rr = 0.0;
   if (fallback) {  // a learned guess worse than the zero guess is replaced
     double rr0;
-    if ((rc = gdot<T>(c, r, r, rr0, st))) return rc;
+    k::seg_dot<T>(1, c->goff, P, r, NF, r, NF, rrp, nullptr, 0, nullptr, 0, nullptr, st);
+    if ((rc = read_rr(rr0, true, &gg))) return rc;
     if (!(rr0 <= gg)) {
       k::copy2d<T, double>(P, nG, fallback, nG, x, NF, 1.0, st);
       k::copy2d<T, T>(P, nG, x, NF, p, NF, 1.0, st);
@@ -642,9 +680,10 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   if ((rc = precond<T>(c, pr, tl, r, z, st)) < 0) return rc;
   warn |= rc;
   k::copy2d<T, T>(P, nG, z, NF, p, NF, 1.0, st);
-  double rz, rr;
-  if ((rc = gdot<T>(c, r, z, rz, st))) return rc;
-  if ((rc = gdot<T>(c, r, r, rr, st))) return rc;
+  int par = 0;
+  k::seg_dot<T>(1, c->goff, P, r, NF, z, NF, c->part, r, NF, r, NF, rrp, st);
+  k::outer_scalars(0, P, c->part, nullptr, ds, par, st);
+  if ((rc = read_rr(rr, true, &gg))) return rc;
   const double stop2 = tl.rtol * tl.rtol * gg;
   // flexible CG (Polak-Ribiere beta): the preconditioner's Neumann solves run
   // to their own tolerance, so M^{-1} may vary slightly between iterations;
@@ -657,30 +696,29 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
     }
     if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
     warn |= rc;
-    double pq;
-    if ((rc = gdot<T>(c, p, q, pq, st))) return rc;
-    if (!(pq > 0.0)) {
-      c->err = "breakdown (p'Sp <= 0) in the interface PCG";
-      return std::isfinite(pq) ? SGW_EBREAKDOWN : SGW_ENAN;
-    }
-    double al = rz / pq;
-    k::axpby2d<T>(P, nG, 1.0, x, NF, al, p, NF, x, NF, st);
-    k::axpby2d<T>(P, nG, 1.0, r, NF, -al, q, NF, r, NF, st);
+    k::seg_dot<T>(1, c->goff, P, p, NF, q, NF, c->part, nullptr, 0, nullptr, 0, nullptr, st);
+    k::outer_scalars(1, P, c->part, nullptr, ds, par, st);
+    k::axpby2d_dev<T>(P, nG, 1.0, -1, x, NF, 1.0, 2, p, NF, x, NF, ds, st);
+    k::axpby2d_dev<T>(P, nG, 1.0, -1, r, NF, -1.0, 2, q, NF, r, NF, ds, st);
     ++it;
-    if ((rc = gdot<T>(c, r, r, rr, st))) return rc;
+    k::seg_dot<T>(1, c->goff, P, r, NF, r, NF, rrp, nullptr, 0, nullptr, 0, nullptr, st);
+    if ((rc = read_rr(rr, false, nullptr))) return rc;
+    if (c->hosc[2 * P + 4] != 0.0) {
+      c->err = "breakdown (p'Sp <= 0) in the interface PCG";
+      return c->hosc[2 * P + 4] == 1.0 ? SGW_EBREAKDOWN : SGW_ENAN;
+    }
     if (!std::isfinite(rr)) {
       c->err = "non-finite interface residual";
       return SGW_ENAN;
     }
     if (rr <= stop2) break;
-    k::copy2d<T, T>(P, nG, z, NF, zp, NF, 1.0, st);
+    std::swap(z, zp);  // zp = the previous preconditioned residual
     if ((rc = precond<T>(c, pr, tl, r, z, st)) < 0) return rc;
     warn |= rc;
-    double rzn, rzo;
-    if ((rc = gdot<T>(c, r, z, rzn, st))) return rc;
-    if ((rc = gdot<T>(c, r, zp, rzo, st))) return rc;
-    k::axpby2d<T>(P, nG, 1.0, z, NF, (rzn - rzo) / rz, p, NF, p, NF, st);
-    rz = rzn;
+    k::seg_dot<T>(1, c->goff, P, r, NF, z, NF, c->part, r, NF, zp, NF, c->part2, st);
+    k::outer_scalars(2, P, c->part, c->part2, ds, par, st);
+    k::axpby2d_dev<T>(P, nG, 1.0, -1, z, NF, 1.0, 3, p, NF, p, NF, ds, st);
+    par ^= 1;
   }
   outer_its = it;
   relres = gg > 0.0 ? std::sqrt(rr / gg) : 0.0;
@@ -688,7 +726,8 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   k::fill2d<T>(P, nI, X, NF, T(0), st);
   k::copy2d<T, T>(P, nI, F, NF, pr.T1, NF, 1.0, st);
   K1<T>(c, pr.G, &c->hal_G0, 0, nI, X, NF, pr.T1, NF, -1.0, 1.0, st);
-  rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, X, NF, tl.inner, tl.inner_max_iter, st);
+  rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, X, NF, tl.inner, tl.inner_max_iter,
+                      kSiteRecover, st);
   if (rc < 0) return rc;
   warn |= rc;
   return warn ? SGW_NOT_CONVERGED : 0;
@@ -1022,15 +1061,20 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
   };
   pr.D.Q = pickq(pr.D.F);
   pr.N.Q = pickq(pr.N.F);
-  // Chebyshev preconditioner: spectral intervals (shared by both
-  // precisions), largest block, default mode tile
-  if constexpr (sizeof(T) == 8) {
-    pr.D.cheb_iv = upload(c, h.chebD);
-    pr.N.cheb_iv = upload(c, h.chebN);
-  } else {
-    pr.D.cheb_iv = c->d64.D.cheb_iv;
-    pr.N.cheb_iv = c->d64.N.cheb_iv;
-  }
+  // Chebyshev preconditioner: step coefficients of every block (from its
+  // spectral interval, in double, then rounded to T), largest block
+  auto coefs = [&](const std::vector<double>& iv) {
+    const int deg = c->cheb_deg, nb = (int)(iv.size() / 2);
+    std::vector<double> cd(2 * (size_t)deg);
+    std::vector<T> cc(std::max<size_t>(2 * (size_t)deg * nb, 1), T(0));
+    for (int b = 0; b < nb; ++b) {
+      k::cheb_coefficients(iv[2 * b], iv[2 * b + 1], deg, cd.data());
+      for (int e = 0; e < 2 * deg; ++e) cc[(size_t)b * 2 * deg + e] = (T)cd[e];
+    }
+    return upload(c, cc);
+  };
+  pr.D.cheb_cc = coefs(h.chebD);
+  pr.N.cheb_cc = coefs(h.chebN);
   auto maxblk = [&](const std::vector<int>& off) {
     int m = 0;
     for (size_t b = 0; b + 1 < off.size(); ++b) m = std::max(m, off[b + 1] - off[b]);
@@ -1106,17 +1150,25 @@ __global__ void k_add_f32(long long N, double* x, const float* d, double scale) 
   if (t < N) x[t] += scale * (double)d[t];
 }
 
-// Dot product over all rows of full [P][NF] arrays (FP64 sums)
+// Dot products over all rows of full [P][NF] arrays (FP64 sums): out = a'b
+// and, with c and d, out2 = c'd, read with one synchronisation
 template <typename T>
-static int fdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st) {
-  k::seg_dot<T>(1, c->alloff, c->P, a, c->NF, b, c->NF, c->part, nullptr, 0, nullptr, 0,
-                nullptr, st);
-  std::vector<double> h(c->P);
-  HIPCHK(hipMemcpyAsync(h.data(), c->part, c->P * sizeof(double), hipMemcpyDeviceToHost, st));
+static int fdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st,
+                const T* cc = nullptr, const T* dd = nullptr, double* out2 = nullptr) {
+  const int P = c->P;
+  k::seg_dot<T>(1, c->alloff, P, a, c->NF, b, c->NF, c->osc, cc, c->NF, dd, c->NF,
+                cc ? c->osc + P : nullptr, st);
+  HIPCHK(hipMemcpyAsync(c->hosc, c->osc, (cc ? 2 : 1) * P * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  prof_stage(c, st);
   HIPCHK(hipStreamSynchronize(st));
-  double s = 0.0;
-  for (double v : h) s += v;
-  out = s;
+  prof_harvest(c);
+  out = 0.0;
+  for (int j = 0; j < P; ++j) out += c->hosc[j];
+  if (cc) {
+    *out2 = 0.0;
+    for (int j = 0; j < P; ++j) *out2 += c->hosc[P + j];
+  }
   return 0;
 }
 
@@ -1131,17 +1183,18 @@ static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int&
   PrecT<float>& pr = c->f32;
   double* R = c->d64.R;
   Tols tl{d.ir_outer_rtol, d.ir_inner_rtol, d.ir_precond_rtol, d.max_iter, d.inner_max_iter};
-  double ff;
-  int rc = fdot<double>(c, F, F, ff, st);
-  if (rc) return rc;
+  double ff = 0.0;
+  int rc = 0;
   int warn = 0;
   outer_total = 0;
   sweeps = 0;
-  for (;;) {
+  for (bool first = true;; first = false) {
     k::copy2d<double, double>(P, NF, F, NF, R, NF, 1.0, st);
     K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, X, NF, R, NF, -1.0, 1.0, st);
     double rr;
-    if ((rc = fdot<double>(c, R, R, rr, st))) return rc;
+    if (first) rc = fdot<double>(c, R, R, rr, st, F, F, &ff);  // with F'F
+    else rc = fdot<double>(c, R, R, rr, st);
+    if (rc) return rc;
     relres = ff > 0.0 ? std::sqrt(rr / ff) : 0.0;
     if (fallback && sweeps == 0 && !(rr <= ff)) {
       // a learned interface guess worse than the zero guess: Newmark instead
@@ -1186,7 +1239,7 @@ static bool prec_complete(const PrecT<T>& pr, bool refine) {
                       pr.N.A.val, pr.D.x, pr.D.r, pr.D.z, pr.D.p, pr.D.q, pr.N.x, pr.N.r,
                       pr.N.z, pr.N.p, pr.N.q, pr.X, pr.R, pr.Z, pr.Zp, pr.Pw, pr.Qw, pr.T1,
                       pr.Gv, pr.Tt, pr.Yt, pr.D.row_off, pr.N.row_off, pr.D.crow, pr.D.cnb,
-                      pr.N.crow, pr.N.cnb, pr.D.cheb_iv, pr.N.cheb_iv, pr.D.p2, pr.N.p2};
+                      pr.N.crow, pr.N.cnb, pr.D.cheb_cc, pr.N.cheb_cc, pr.D.p2, pr.N.p2};
   for (const void* p : ps)
     if (!p) return false;
   return !refine || (pr.Fb && pr.Xb);
@@ -1195,7 +1248,8 @@ static bool prec_complete(const PrecT<T>& pr, bool refine) {
 static bool check_pointers(sgw_ctx* c) {
   const void* ps[] = {c->U, c->V, c->A, c->Um, c->Uc, c->Wm, c->F, c->hist, c->gnew, c->smax,
                       c->mx, c->my, c->pqg, c->meshbuf, c->meshbuf2,
-                      c->part, c->part2, c->sc, c->flags, c->goff, c->alloff, c->dd2mesh,
+                      c->part, c->part2, c->osc, c->sc, c->flags, c->goff, c->alloff,
+                      c->dd2mesh,
                       c->mdiag, c->torn_gidx, c->torn_w, c->gam_ptr, c->gam_torn, c->gam_w,
                       c->g2c, c->dc, c->uc, c->phi, c->gt.mask, c->gt.pair_beg, c->gt.ent_beg,
                       c->gt.pair_cnt, c->gt.ent_i, c->gt.ent_c, c->gt.ent_cf};
@@ -1320,7 +1374,7 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
             k::cheb_lds_bytes<T>(S.max_block_rows, q) > 150 * 1024)
           continue;
         double us = time_it([&] {
-          (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_iv, S.nb, c->P,
+          (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, c->P,
                                  c->cheb_deg, q,
                                  S.max_block_rows, S.r, S.nrows, S.z, S.nrows, c->part,
                                  c->part2, nullptr, 0, 0.0, nullptr, nullptr, nullptr, st);
@@ -1402,6 +1456,7 @@ int sgw_destroy(sgw_ctx* c) {
     else (void)hipFree(p);
   }
   if (c->hflags) (void)hipHostFree(c->hflags);
+  if (c->hosc) (void)hipHostFree(c->hosc);
   if (c->acct_h) (void)hipHostFree(c->acct_h);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -1513,6 +1568,7 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   int nbmax = std::max(1, h.nsub);
   c->part = dalloc<double>(c, (size_t)nbmax * P);
   c->part2 = dalloc<double>(c, (size_t)nbmax * P);
+  c->osc = dalloc<double>(c, (size_t)2 * P + 8);
   c->sc = dalloc<double>(c, (size_t)nbmax * 8);
   c->flags = dalloc<int>(c, 4);
   c->goff = upload(c, std::vector<int>{0, h.nG});  // rows of the interface part
@@ -1601,7 +1657,8 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   if (hipHostMalloc((void**)&c->acct_h, 2 * sizeof(unsigned long long)) != hipSuccess)
     c->acct_h = nullptr;
   if (!c->acct_h) c->acct = nullptr;
-  if (hipHostMalloc((void**)&c->hflags, 16 * sizeof(int)) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->hflags, 16 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hosc, (2 * (size_t)P + 8) * sizeof(double)) != hipSuccess) {
     c->err = "pinned allocation failed";
     *out = c;
     return SGW_ENOMEM;
@@ -1644,7 +1701,7 @@ int sgw_factor(sgw_ctx* c, void* stream) {
         k::fill2d<double>(P, NT, c->d64.Tt, NT, 0.0, st);
         k_basis_rhs<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->d64.Tt, NT);
         int rc = inner_solve<double>(c, c->d64.N, true, c->d64.Tt, NT, c->d64.Yt, NT, tol,
-                                     c->h.d.inner_max_iter, st);
+                                     c->h.d.inner_max_iter, kSiteNeumann, st);
         if (rc < 0) return rc;
         k_basis_store<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->d64.Yt, NT, c->fs);
       }

@@ -96,7 +96,8 @@ def entries(L, p_in, p_out):
 def kernel_source(L, p_in, p_out, pcg=False):
     """One kernel per output group; a workgroup = 64 rows x NCH waves.
 
-    pcg=True: the variant for the subdomain PCG iteration.  It stages
+    pcg=True: the variant for the subdomain PCG iteration (a block whose
+    active flag of iteration par is clear is skipped).  It stages
     p = z + beta p_old (beta = the block's new r'z / old r'z, 0 on the first
     iteration), writes p to pnew for its own rows, applies the operator to it
     and writes p'q over the group's rows and the kernel's output modes to
@@ -143,6 +144,7 @@ def kernel_source(L, p_in, p_out, pcg=False):
         if pcg:
             lines.append("  // beta of this group's block; the block's first group stores the new r'z")
             lines.append("  const int blk = H.gblk[grp];")
+            lines.append("  if (sc[(size_t)blk * 8 + 2 + par] == 0.0) return;  // converged block: frozen")
             lines.append("  double rzn = 0.0;")
             lines.append("  for (int j = 0; j < %d; ++j) rzn += rzpart[(size_t)blk * %d + j];" % (P, P))
             lines.append("  const double rzo = sc[(size_t)blk * 8 + 1 - par];")
