@@ -523,10 +523,33 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return m;
 }
 
-__device__ __forceinline__ double sum_modes(const double* part, int b, int P) {
+// Sum of p[0..n) in index order.  The loads of a chunk are issued together,
+// so a sum costs one memory round trip per chunk instead of one per value.
+__device__ __forceinline__ double sum_seq(const double* p, int n) {
   double v = 0.0;
-  for (int j = 0; j < P; ++j) v += part[(size_t)b * P + j];
+  int j = 0;
+  for (; j + 16 <= n; j += 16) {
+    double t[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t[k] = p[j + k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v += t[k];
+  }
+  if (j + 4 <= n) {
+    double t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = p[j + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v += t[k];
+    j += 4;
+  }
+  for (; j < n; ++j) v += p[j];
   return v;
+}
+
+// the P partials of block b, in mode order
+__device__ __forceinline__ double sum_modes(const double* part, int b, int P) {
+  return sum_seq(part + (size_t)b * P, P);
 }
 
 // Start of a solve (x0 = 0, r = b, z = M r): r'z into the even slot, b'b = r'r,
@@ -601,7 +624,7 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
   {
     double pq = 0.0;
     if (bgrp) {  // per-group partials of the fused SG apply (pqn per group)
-      for (int q = bgrp[blk] * pqn; q < bgrp[blk + 1] * pqn; ++q) pq += part[q];
+      pq = sum_seq(part + (size_t)bgrp[blk] * pqn, (bgrp[blk + 1] - bgrp[blk]) * pqn);
     } else {
       pq = sum_modes(part, blk, P);
     }
