@@ -5,7 +5,8 @@
 //   H2  static condensation: Dirichlet solves per subdomain, G = F_G - K_GI x_I
 //   H3  interface initial guess
 //   H4  PCG on S U_G = G with the two-level Neumann-Neumann preconditioner
-//   H5  interior recovery (Dirichlet solves)
+//   H5  interior recovery, accumulated from the Schur applies of H4 (no
+//       Dirichlet solve of its own)
 //   H6  Newmark update
 // The subdomain solves with the SG-coupled matrices (H8) run as batched
 // block-PCG with the mean-matrix preconditioner I_P (x) (K~_0^s)^{-1}.
@@ -461,7 +462,7 @@ static int pair_graph(sgw_ctx* c, const void* sys, double tol2, Enqueue enqueue,
 }
 
 // Call sites of inner_solve, each with its own iteration prediction.
-enum { kSiteSchur = 0, kSiteNeumann = 1, kSiteCondense = 2, kSiteRecover = 3 };
+enum { kSiteSchur = 0, kSiteNeumann = 1, kSiteCondense = 2 };
 
 // Batched block PCG.  The host reads the device's convergence flags only
 // once the predicted number of iterations (that of the previous solve from
@@ -627,6 +628,12 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   k::fill2d<T>(P, nG, pr.T1 + nI, NF, T(0), st);
   k::copy2d<T, T>(P, nG, F + nI, NF, pr.Gv + nI, NF, 1.0, st);
   K1<T>(c, pr.G, &c->hal_GI, nI, nG, pr.T1, NF, pr.Gv, NF, -1.0, 1.0, st);
+  // H5 without a final solve: every Schur apply S p leaves w = -K~_II^{-1}
+  // K~_IG p in the interior part of its input vector (Pw), so the interior
+  // solution U_I = K~_II^{-1} (F_I - K~_IG U_G) accumulates alongside the
+  // interface iterate: U_I = K~_II^{-1} F_I + w(x0) + sum_k alpha_k w(p_k),
+  // which is one update over all rows, X += alpha Pw.
+  k::copy2d<T, T>(P, nI, pr.T1, NF, X, NF, 1.0, st);
   // The PCG scalars (alpha, beta, r'z) stay on the device; the host reads
   // r'r (and G'G at the start) for the stopping test, once per iteration.
   // osc = [G'G partials (P)][r'r partials (P)][ds: r'z by parity, alpha,
@@ -663,17 +670,20 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
   warn |= rc;
   k::axpby2d<T>(P, nG, 1.0, pr.Gv + nI, NF, -1.0, q, NF, r, NF, st);
+  k::axpby2d<T>(P, nI, 1.0, X, NF, 1.0, pr.Pw, NF, X, NF, st);  // U_I += w(x0)
   double gg = 0.0, rr = 0.0;
   if (fallback) {  // a learned guess worse than the zero guess is replaced
     double rr0;
     k::seg_dot<T>(1, c->goff, P, r, NF, r, NF, rrp, nullptr, 0, nullptr, 0, nullptr, st);
     if ((rc = read_rr(rr0, true, &gg))) return rc;
     if (!(rr0 <= gg)) {
+      k::axpby2d<T>(P, nI, 1.0, X, NF, -1.0, pr.Pw, NF, X, NF, st);  // U_I -= w(x0)
       k::copy2d<T, double>(P, nG, fallback, nG, x, NF, 1.0, st);
       k::copy2d<T, T>(P, nG, x, NF, p, NF, 1.0, st);
       if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
       warn |= rc;
       k::axpby2d<T>(P, nG, 1.0, pr.Gv + nI, NF, -1.0, q, NF, r, NF, st);
+      k::axpby2d<T>(P, nI, 1.0, X, NF, 1.0, pr.Pw, NF, X, NF, st);
       c->guess_fallbacks++;
     }
   }
@@ -698,7 +708,7 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
     warn |= rc;
     k::seg_dot<T>(1, c->goff, P, p, NF, q, NF, c->part, nullptr, 0, nullptr, 0, nullptr, st);
     k::outer_scalars(1, P, c->part, nullptr, ds, par, st);
-    k::axpby2d_dev<T>(P, nG, 1.0, -1, x, NF, 1.0, 2, p, NF, x, NF, ds, st);
+    k::axpby2d_dev<T>(P, NF, 1.0, -1, X, NF, 1.0, 2, pr.Pw, NF, X, NF, ds, st);  // U += alpha Pw
     k::axpby2d_dev<T>(P, nG, 1.0, -1, r, NF, -1.0, 2, q, NF, r, NF, ds, st);
     ++it;
     k::seg_dot<T>(1, c->goff, P, r, NF, r, NF, rrp, nullptr, 0, nullptr, 0, nullptr, st);
@@ -722,14 +732,6 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   }
   outer_its = it;
   relres = gg > 0.0 ? std::sqrt(rr / gg) : 0.0;
-  // H5: interior recovery U_I = K~_II^{-1} (F_I - K~_IG U_G)
-  k::fill2d<T>(P, nI, X, NF, T(0), st);
-  k::copy2d<T, T>(P, nI, F, NF, pr.T1, NF, 1.0, st);
-  K1<T>(c, pr.G, &c->hal_G0, 0, nI, X, NF, pr.T1, NF, -1.0, 1.0, st);
-  rc = inner_solve<T>(c, pr.D, false, pr.T1, NF, X, NF, tl.inner, tl.inner_max_iter,
-                      kSiteRecover, st);
-  if (rc < 0) return rc;
-  warn |= rc;
   return warn ? SGW_NOT_CONVERGED : 0;
 }
 
