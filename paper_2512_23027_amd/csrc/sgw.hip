@@ -613,11 +613,13 @@ static int precond(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* r, T* z, h
 }
 
 // One SG system K~ U = F on the DD numbering (F, X full [P][NF] arrays of
-// this precision); X holds the interface initial guess on entry and the full
-// solution on exit.
+// this precision); X holds the interface initial guess on entry (with
+// zero_guess the guess is zero and X need not be set) and the full solution
+// on exit.
 template <typename T>
 static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, hipStream_t st,
-                    int& outer_its, double& relres, const double* fallback = nullptr) {
+                    int& outer_its, double& relres, const double* fallback = nullptr,
+                    bool zero_guess = false) {
   const int P = c->P, NF = c->NF, nI = c->nI, nG = c->nG;
   int warn = 0, rc;
   // H2: condensation G = F_G - K~_GI K~_II^{-1} F_I
@@ -666,11 +668,16 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   T* zp = pr.Zp + nI;
   T* p = pr.Pw + nI;
   T* q = pr.Qw + nI;
-  k::copy2d<T, T>(P, nG, x, NF, p, NF, 1.0, st);
-  if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
-  warn |= rc;
-  k::axpby2d<T>(P, nG, 1.0, pr.Gv + nI, NF, -1.0, q, NF, r, NF, st);
-  k::axpby2d<T>(P, nI, 1.0, X, NF, 1.0, pr.Pw, NF, X, NF, st);  // U_I += w(x0)
+  if (zero_guess) {  // x0 = 0: r = G, no Schur apply
+    k::fill2d<T>(P, nG, x, NF, T(0), st);
+    k::copy2d<T, T>(P, nG, pr.Gv + nI, NF, r, NF, 1.0, st);
+  } else {
+    k::copy2d<T, T>(P, nG, x, NF, p, NF, 1.0, st);
+    if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
+    warn |= rc;
+    k::axpby2d<T>(P, nG, 1.0, pr.Gv + nI, NF, -1.0, q, NF, r, NF, st);
+    k::axpby2d<T>(P, nI, 1.0, X, NF, 1.0, pr.Pw, NF, X, NF, st);  // U_I += w(x0)
+  }
   double gg = 0.0, rr = 0.0;
   if (fallback) {  // a learned guess worse than the zero guess is replaced
     double rr0;
@@ -1218,10 +1225,9 @@ static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int&
     // which keeps the FP32 values away from the ends of their range
     const double scale = std::sqrt(rr / ((double)P * NF));
     k::copy2d<float, double>(P, NF, R, NF, pr.Fb, NF, 1.0 / scale, st);
-    k::fill2d<float>(P, NF, pr.Xb, NF, 0.0f, st);
     int its = 0;
     double rel32 = 0.0;
-    rc = dd_solve<float>(c, pr, tl, pr.Fb, pr.Xb, st, its, rel32);
+    rc = dd_solve<float>(c, pr, tl, pr.Fb, pr.Xb, st, its, rel32, nullptr, true);
     if (rc < 0) return rc;
     warn |= rc;
     outer_total += its;
