@@ -217,8 +217,11 @@ int sgw_profile_read(sgw_ctx* ctx, int kind, long long* launches, double* ms,
  *   [34..41] FP32 Dirichlet triangular  [42..49] FP32 Neumann triangular
  *   [50..57] FP32 Dirichlet Chebyshev   [58..65] FP32 Neumann Chebyshev
  *   [66]     FP32 unrolled SG apply     [67] FP32 table-driven SG apply
- * (the SG applies on the Dirichlet system).  Enqueues on stream and waits
- * for it. */
+ *   [68..71] Chebyshev launch shape kept for FP64 Dirichlet, FP64 Neumann,
+ *            FP32 Dirichlet, FP32 Neumann (0, 1, 2: 1024, 512, 256 threads
+ *            per workgroup; -1 when not tuned)
+ * (the SG applies on the Dirichlet system; a Chebyshev entry is the fastest
+ * launch shape for that Q).  Enqueues on stream and waits for it. */
 int sgw_autotune(sgw_ctx* ctx, void* stream, double* report, int nreport);
 
 /* Sizes and counters: what = 0 P, 1 number of input PCE terms, 2 free

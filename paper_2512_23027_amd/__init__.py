@@ -280,8 +280,8 @@ class Solver:
 
     def autotune(self):
         """Pick the fastest launch shapes; returns the timing report (us)."""
-        rep = (ctypes.c_double * 68)()
-        self._check(lib().sgw_autotune(self.ctx, self._stream(), rep, 68), "sgw_autotune")
+        rep = (ctypes.c_double * 72)()
+        self._check(lib().sgw_autotune(self.ctx, self._stream(), rep, 72), "sgw_autotune")
         r = list(rep)
         out = {"fp64": {"tri_dirichlet_us_by_Q": r[0:8], "tri_neumann_us_by_Q": r[8:16],
                         "cheb_dirichlet_us_by_Q": r[18:26], "cheb_neumann_us_by_Q": r[26:34]},
@@ -291,6 +291,11 @@ class Solver:
                "sg_apply_unrolled_fp32_us": r[66], "sg_apply_table_fp32_us": r[67]}
         for prec in ("fp64", "fp32"):  # keep only what was timed
             out[prec] = {k: v for k, v in out[prec].items() if max(v) > 0}
+        # workgroup size of the kept Chebyshev launch shape (None: not tuned)
+        tpb = {0: 1024, 1: 512, 2: 256}
+        out["cheb_threads_per_group"] = {
+            name: tpb.get(int(v)) for name, v in zip(
+                ("fp64_dirichlet", "fp64_neumann", "fp32_dirichlet", "fp32_neumann"), r[68:72])}
         return out
 
     # -- learned guess ----------------------------------------------------------

@@ -111,8 +111,9 @@ template <typename T>
 void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
                int ldo, int nbatch, long long sr, long long so, hipStream_t st);
 
-// Chebyshev polynomial preconditioner (degree deg, Q modes per workgroup) on
-// the blocks of A's mean matrix; coef[b * 2 deg ...] = the iteration
+// Chebyshev polynomial preconditioner (degree deg, Q modes per workgroup,
+// launch shape 0, 1, 2 = 1024, 512, 256 threads per workgroup with 1, 2 or 4
+// rows per thread) on the blocks of A's mean matrix; coef[b * 2 deg ...] = the iteration
 // coefficients of block b (cheb_coefficients); order (may be null) = launch
 // order of the blocks (largest first); crow[r0 + i] = system row at natural
 // (lexicographic) position i of the block starting at r0, cnb[s*nrows + r0 +
@@ -122,10 +123,11 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
 // of iteration par (r'r from rrpart, see pcg_test) and skips converged
 // blocks.  With acct != null, every active workgroup adds its algorithmic
 // bytes (right-hand sides in and out, the block's mean matrix once) to
-// *acct.  Returns -1 (nothing launched) if Q, deg or the block size is out
-// of range (max_rows <= 4096, Q <= cheb_max_q, cheb_lds_bytes <= 150 KiB).
+// *acct.  Returns -1 (nothing launched) if Q, the shape, deg or the block
+// size is out of range (max_rows <= 4 x the workgroup size, Q <= cheb_max_q,
+// deg <= 64, cheb_lds_bytes <= 150 KiB).
 template <typename T>
-size_t cheb_lds_bytes(int max_rows, int Q);
+size_t cheb_lds_bytes(int max_rows, int Q, int shape);
 // Coefficients of deg Chebyshev steps on the spectral interval [lo, hi] of
 // one block (Saad, Alg. 12.1), in the layout cheb_apply reads: out[0] =
 // 1/theta, out[1] = 0, out[2k] = rho_k rho_{k-1}, out[2k+1] = 2 rho_k / delta
@@ -134,17 +136,18 @@ size_t cheb_lds_bytes(int max_rows, int Q);
 // rho_k = 1 / (2 theta / delta - rho_{k-1})).  Computed in double.
 void cheb_coefficients(double lo, double hi, int deg, double* out);
 // largest mode tile cheb_apply accepts for blocks of up to max_rows rows
+// with the given shape (0: the shape does not cover such blocks)
 template <typename T>
-int cheb_max_q(int max_rows);
+int cheb_max_q(int max_rows, int shape);
 // Once per process before the first cheb_apply: allows the kernels the full
 // 160 KiB of LDS.  0 on success, -1 on a HIP error.
 int cheb_prepare();
 template <typename T>
 int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int* crow,
                const unsigned short* cnb, const T* coef, int nb, int P, int deg,
-               int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
-               double* part2, double* sc, int par, double tol2, const double* rrpart,
-               int* flags, unsigned long long* acct, hipStream_t st);
+               int Q, int shape, int max_rows, const T* r, int ldr, T* z, int ldz,
+               double* part, double* part2, double* sc, int par, double tol2,
+               const double* rrpart, int* flags, unsigned long long* acct, hipStream_t st);
 
 // Segmented dot products: partial[b * P + j] = sum_{r in block b} a[j][r] b[j][r]
 // (row_off relative to the vectors; a second vector pair is optional).

@@ -969,8 +969,8 @@ __device__ __forceinline__ void lds_write_row(unsigned char* p, const T (&v)[Q])
   }
 }
 
-template <typename T, int Q, int RPT>
-__global__ __launch_bounds__(CHEB_TPB) void k_cheb(
+template <typename T, int Q, int RPT, int TPB>
+__global__ __launch_bounds__(TPB) void k_cheb(
     DEll<T> A, const int* __restrict__ row_off, const int* __restrict__ order,
     const int* __restrict__ crow, const unsigned short* __restrict__ cnb,
     const T* __restrict__ coef, int P, int deg,
@@ -978,16 +978,16 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     double* __restrict__ part2, double* sc, int par, double tol2, const double* rrpart,
     int* flags, unsigned long long* acct) {
   // all LDS is dynamic (so the launch may use up to the whole 160 KiB):
-  // two buffers of the search direction, each [RPT * CHEB_TPB][Q] (the Q
+  // two buffers of the search direction, each [RPT * TPB][Q] (the Q
   // modes of a row side by side, at a fixed stride, so every LDS offset but
   // the neighbour's row is a constant), the step coefficients, the
   // reduction slots
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr size_t kBuf = sizeof(T) * (size_t)RPT * CHEB_TPB * Q;
+  constexpr size_t kBuf = sizeof(T) * (size_t)RPT * TPB * Q;
   unsigned char* dir = smem_raw;
   T* cs = reinterpret_cast<T*>(smem_raw + 2 * kBuf);
-  double(*red)[CHEB_TPB / 64][Q] =
-      reinterpret_cast<double(*)[CHEB_TPB / 64][Q]>(smem_raw + 2 * kBuf + CHEB_COEF_BYTES);
+  double(*red)[TPB / 64][Q] =
+      reinterpret_cast<double(*)[TPB / 64][Q]>(smem_raw + 2 * kBuf + CHEB_COEF_BYTES);
   const int b = order ? order[blockIdx.x] : blockIdx.x, j0 = blockIdx.y * Q;
   if (sc) {  // stopping test of PCG iteration par, fused (see k_pcg_test)
     const double rr = sum_modes(rrpart, b, P);
@@ -1008,7 +1008,7 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
   }
   // the block's step coefficients, staged in LDS (read after the first
   // barrier)
-  for (int e = threadIdx.x; e < 2 * deg; e += CHEB_TPB) cs[e] = coef[(size_t)b * 2 * deg + e];
+  for (int e = threadIdx.x; e < 2 * deg; e += TPB) cs[e] = coef[(size_t)b * 2 * deg + e];
   // thread i owns the row at natural (lexicographic mesh) position i of the
   // block, crow[r0 + i]; the LDS copy of the direction is in natural order,
   // so the neighbour reads and the writes of a wave are nearly contiguous
@@ -1027,7 +1027,7 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
   const T inv_theta = coef[(size_t)b * 2 * deg];
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
-    const int i = threadIdx.x + t * CHEB_TPB;
+    const int i = threadIdx.x + t * TPB;
     const bool live = i < n;
     row[t] = live ? crow[r0 + i] : r0;
 #pragma unroll
@@ -1059,14 +1059,14 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
     unsigned char* Dk = dir + boff;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int i = threadIdx.x + t * CHEB_TPB;
+      const int i = threadIdx.x + t * TPB;
       if (i < n) lds_write_row<T, Q>(Dk + (size_t)i * Q * sizeof(T), dd[t]);
     }
     __syncthreads();
     const T c1 = cs[2 * (k + 1)], c2 = cs[2 * (k + 1) + 1];
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int i = threadIdx.x + t * CHEB_TPB;
+      const int i = threadIdx.x + t * TPB;
       if (i >= n) continue;
       T ad[Q];
 #pragma unroll
@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
   for (int q = 0; q < Q; ++q) srz[q] = srr[q] = 0.0;
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
-    const int i = threadIdx.x + t * CHEB_TPB;
+    const int i = threadIdx.x + t * TPB;
     if (i >= n) continue;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -1124,7 +1124,7 @@ __global__ __launch_bounds__(CHEB_TPB) void k_cheb(
   if (threadIdx.x < Q && j0 + (int)threadIdx.x < P) {
     const int q = threadIdx.x;
     double a = 0.0, bq = 0.0;
-    for (int v = 0; v < CHEB_TPB / 64; ++v) {
+    for (int v = 0; v < TPB / 64; ++v) {
       a += red[0][v][q];
       bq += red[1][v][q];
     }
@@ -1148,14 +1148,20 @@ void cheb_coefficients(double lo, double hi, int deg, double* out) {
   }
 }
 
-static int cheb_rpt(int max_rows) {
-  return max_rows <= CHEB_TPB ? 1 : (max_rows <= 2 * CHEB_TPB ? 2 : 4);
+// Launch shapes: shape 0, 1, 2 = workgroups of 1024, 512, 256 threads; each
+// thread owns RPT = 1, 2 or 4 rows of the block (the smallest that covers
+// the largest block); 0 if the shape cannot cover max_rows.
+static int cheb_tpb(int shape) { return CHEB_TPB >> shape; }
+static int cheb_rpt(int max_rows, int shape) {
+  const int tpb = cheb_tpb(shape);
+  return max_rows <= tpb ? 1 : (max_rows <= 2 * tpb ? 2 : (max_rows <= 4 * tpb ? 4 : 0));
 }
 
 template <typename T>
-size_t cheb_lds_bytes(int max_rows, int Q) {
-  return sizeof(double) * 2 * (CHEB_TPB / 64) * Q + CHEB_COEF_BYTES +
-         2 * (size_t)cheb_rpt(max_rows) * CHEB_TPB * Q * sizeof(T);
+size_t cheb_lds_bytes(int max_rows, int Q, int shape) {
+  const int tpb = cheb_tpb(shape);
+  return sizeof(double) * 2 * (tpb / 64) * Q + CHEB_COEF_BYTES +
+         2 * (size_t)cheb_rpt(max_rows, shape) * tpb * Q * sizeof(T);
 }
 
 struct ChebTest {  // optional fused stopping test (sc == nullptr: none), block order,
@@ -1168,27 +1174,35 @@ struct ChebTest {  // optional fused stopping test (sc == nullptr: none), block 
   int* flags;
 };
 
-template <typename T, int Q, int RPT>
-static void launch_cheb(const DEll<T>& A, const int* row_off, const int* crow,
-                        const unsigned short* cnb, const T* coef, int nb, int P,
-                        int deg, int max_rows, const T* r, int ldr, T* z, int ldz,
-                        double* part, double* part2, const ChebTest& t, hipStream_t st) {
-  dim3 grid(nb, ceil_div(P, Q));
-  k_cheb<T, Q, RPT><<<grid, CHEB_TPB, cheb_lds_bytes<T>(max_rows, Q), st>>>(
-      A, row_off, t.order, crow, cnb, coef, P, deg, r, ldr, z, ldz, part, part2, t.sc, t.par,
-      t.tol2, t.rrpart, t.flags, t.acct);
+struct ChebArgs {
+  const int* row_off;
+  const int* crow;
+  const unsigned short* cnb;
+  const void* coef;
+  int nb, P, deg, max_rows, shape;
+  const void* r;
+  int ldr;
+  void* z;
+  int ldz;
+  double *part, *part2;
+};
+
+template <typename T, int Q, int RPT, int TPB>
+static void launch_cheb(const DEll<T>& A, const ChebArgs& a, const ChebTest& t, hipStream_t st) {
+  dim3 grid(a.nb, ceil_div(a.P, Q));
+  k_cheb<T, Q, RPT, TPB><<<grid, TPB, cheb_lds_bytes<T>(a.max_rows, Q, a.shape), st>>>(
+      A, a.row_off, t.order, a.crow, a.cnb, static_cast<const T*>(a.coef), a.P, a.deg,
+      static_cast<const T*>(a.r), a.ldr, static_cast<T*>(a.z), a.ldz, a.part, a.part2, t.sc,
+      t.par, t.tol2, t.rrpart, t.flags, t.acct);
 }
 
-template <typename T, int RPT>
-static void cheb_q(int Q, const DEll<T>& A, const int* row_off, const int* crow,
-                   const unsigned short* cnb, const T* coef, int nb, int P,
-                   int deg, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
-                   double* part2, const ChebTest& t, hipStream_t st) {
+template <typename T, int RPT, int TPB>
+static void cheb_q(int Q, const DEll<T>& A, const ChebArgs& a, const ChebTest& t,
+                   hipStream_t st) {
   switch (Q) {
-#define SGW_CHEB_CASE(q)                                                                      \
-  case q:                                                                                    \
-    launch_cheb<T, q, RPT>(A, row_off, crow, cnb, coef, nb, P, deg, max_rows, r, ldr, z, ldz, \
-                           part, part2, t, st);                                              \
+#define SGW_CHEB_CASE(q)                            \
+  case q:                                          \
+    launch_cheb<T, q, RPT, TPB>(A, a, t, st);      \
     break;
     SGW_CHEB_CASE(1)
     SGW_CHEB_CASE(2)
@@ -1205,11 +1219,11 @@ static void cheb_q(int Q, const DEll<T>& A, const int* row_off, const int* crow,
 
 // The kernels have no static LDS, so the whole 160 KiB may be dynamic; the
 // attribute is set once for every instantiation before the first launch.
-template <typename T, int RPT>
+template <typename T, int RPT, int TPB>
 static bool cheb_attr_rpt() {
   bool ok = true;
 #define SGW_CHEB_ATTR(q)                                                                \
-  ok = ok && hipFuncSetAttribute((const void*)k_cheb<T, q, RPT>,                         \
+  ok = ok && hipFuncSetAttribute((const void*)k_cheb<T, q, RPT, TPB>,                    \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == \
                  hipSuccess;
   SGW_CHEB_ATTR(1)
@@ -1223,20 +1237,26 @@ static bool cheb_attr_rpt() {
 #undef SGW_CHEB_ATTR
   return ok;
 }
+template <typename T, int TPB>
+static bool cheb_attr_tpb() {
+  return cheb_attr_rpt<T, 1, TPB>() && cheb_attr_rpt<T, 2, TPB>() && cheb_attr_rpt<T, 4, TPB>();
+}
 int cheb_prepare() {
-  bool ok = cheb_attr_rpt<double, 1>() && cheb_attr_rpt<double, 2>() &&
-            cheb_attr_rpt<double, 4>() && cheb_attr_rpt<float, 1>() &&
-            cheb_attr_rpt<float, 2>() && cheb_attr_rpt<float, 4>();
+  bool ok = cheb_attr_tpb<double, CHEB_TPB>() && cheb_attr_tpb<double, CHEB_TPB / 2>() &&
+            cheb_attr_tpb<double, CHEB_TPB / 4>() && cheb_attr_tpb<float, CHEB_TPB>() &&
+            cheb_attr_tpb<float, CHEB_TPB / 2>() && cheb_attr_tpb<float, CHEB_TPB / 4>();
   return ok ? 0 : -1;
 }
 
 // Largest mode tile that keeps the per-thread arrays (3 x RPT x Q values
-// plus the matrix row) in registers under the 1024-thread launch bound:
-// larger tiles spill to scratch memory (measured: up to 400 MB of scratch
-// traffic per launch).
+// plus the matrix rows) in registers: larger tiles spill to scratch memory
+// (measured: up to 400 MB of scratch traffic per launch); 0 if the shape
+// cannot cover max_rows.
 template <typename T>
-int cheb_max_q(int max_rows) {
-  const int rpt = (max_rows + CHEB_TPB - 1) / CHEB_TPB;
+int cheb_max_q(int max_rows, int shape) {
+  if (shape < 0 || shape > 2) return 0;
+  const int rpt = cheb_rpt(max_rows, shape);
+  if (rpt == 0) return 0;
   if (sizeof(T) == 8) return rpt <= 1 ? 6 : (rpt <= 2 ? 2 : 1);
   return rpt <= 1 ? 8 : (rpt <= 2 ? 4 : 2);
 }
@@ -1244,23 +1264,29 @@ int cheb_max_q(int max_rows) {
 template <typename T>
 int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int* crow,
                const unsigned short* cnb, const T* coef, int nb, int P, int deg,
-               int Q, int max_rows, const T* r, int ldr, T* z, int ldz, double* part,
-               double* part2, double* sc, int par, double tol2, const double* rrpart,
-               int* flags, unsigned long long* acct, hipStream_t st) {
-  if (Q < 1 || Q > cheb_max_q<T>(max_rows) || deg < 1 || deg > CHEB_MAX_DEG || max_rows < 1 ||
-      max_rows > 4 * CHEB_TPB || cheb_lds_bytes<T>(max_rows, Q) > 150 * 1024 ||
+               int Q, int shape, int max_rows, const T* r, int ldr, T* z, int ldz,
+               double* part, double* part2, double* sc, int par, double tol2,
+               const double* rrpart, int* flags, unsigned long long* acct, hipStream_t st) {
+  if (Q < 1 || Q > cheb_max_q<T>(max_rows, shape) || deg < 1 || deg > CHEB_MAX_DEG ||
+      max_rows < 1 || cheb_lds_bytes<T>(max_rows, Q, shape) > 150 * 1024 ||
       (sc && (!rrpart || !flags)) || !crow || !cnb || !coef)
     return -1;
   const ChebTest t{order, acct, sc, par, tol2, rrpart, flags};
-  if (max_rows <= CHEB_TPB)
-    cheb_q<T, 1>(Q, A, row_off, crow, cnb, coef, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
-                 t, st);
-  else if (max_rows <= 2 * CHEB_TPB)
-    cheb_q<T, 2>(Q, A, row_off, crow, cnb, coef, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
-                 t, st);
-  else
-    cheb_q<T, 4>(Q, A, row_off, crow, cnb, coef, nb, P, deg, max_rows, r, ldr, z, ldz, part, part2,
-                 t, st);
+  const ChebArgs a{row_off, crow, cnb, coef, nb, P, deg, max_rows, shape, r, ldr, z, ldz,
+                   part, part2};
+  const int rpt = cheb_rpt(max_rows, shape);
+#define SGW_CHEB_SHAPE(tpb)                                \
+  if (rpt == 1) cheb_q<T, 1, tpb>(Q, A, a, t, st);         \
+  else if (rpt == 2) cheb_q<T, 2, tpb>(Q, A, a, t, st);    \
+  else cheb_q<T, 4, tpb>(Q, A, a, t, st);
+  if (shape == 0) {
+    SGW_CHEB_SHAPE(CHEB_TPB)
+  } else if (shape == 1) {
+    SGW_CHEB_SHAPE(CHEB_TPB / 2)
+  } else {
+    SGW_CHEB_SHAPE(CHEB_TPB / 4)
+  }
+#undef SGW_CHEB_SHAPE
   return 0;
 }
 
@@ -1363,18 +1389,18 @@ void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt, h
 
 // explicit instantiations
 template size_t tri_lds_bytes<double>(const DFactor&, int);
-template size_t cheb_lds_bytes<double>(int, int);
-template int cheb_max_q<double>(int);
-template int cheb_max_q<float>(int);
-template size_t cheb_lds_bytes<float>(int, int);
+template size_t cheb_lds_bytes<double>(int, int, int);
+template int cheb_max_q<double>(int, int);
+template int cheb_max_q<float>(int, int);
+template size_t cheb_lds_bytes<float>(int, int, int);
 template int cheb_apply<double>(const DEll<double>&, const int*, const int*, const int*,
                                 const unsigned short*, const double*, int, int, int,
-                                int, int, const double*, int, double*, int, double*, double*,
+                                int, int, int, const double*, int, double*, int, double*, double*,
                                 double*, int, double, const double*, int*, unsigned long long*,
                                 hipStream_t);
 template int cheb_apply<float>(const DEll<float>&, const int*, const int*, const int*,
                                const unsigned short*, const float*, int, int, int,
-                               int, int, const float*, int, float*, int, double*, double*,
+                               int, int, int, const float*, int, float*, int, double*, double*,
                                double*, int, double, const double*, int*, unsigned long long*,
                                hipStream_t);
 template size_t tri_lds_bytes<float>(const DFactor&, int);

@@ -43,6 +43,7 @@ template <typename T>
 struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   int nrows = 0, nb = 0, Q = 8;
   int cq = 8, max_block_rows = 0;     // Chebyshev mode tile, largest block
+  int cshape = 0;                     // Chebyshev launch shape (k::cheb_apply)
   const k::DHalo* halo = nullptr;     // 64-row group halos of A (both precisions)
   const T* cheb_cc = nullptr;         // device, [nb][2 deg] Chebyshev step coefficients
   const int* lpt = nullptr;           // device, blocks by decreasing size (launch order)
@@ -398,8 +399,7 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
     // timed launches count their bytes on the device (converged blocks are
     // skipped inside the kernel); harvested into the kind's total
     (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, P, c->cheb_deg,
-                           S.cq,
-                           S.max_block_rows, S.r, n, S.z, n, part, part2,
+                           S.cq, S.cshape, S.max_block_rows, S.r, n, S.z, n, part, part2,
                            test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
                            c->part2, c->flags, a >= 0 ? c->acct + (sizeof(T) == 4) : nullptr, st);
     prof_end(c, a, kind, 0.0, st);
@@ -1123,11 +1123,12 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
     pr.N.cnb = c->d64.N.cnb;
   }
   for (SysT<T>* S : {&pr.D, &pr.N}) {
-    const int qmax = std::max(1, k::cheb_max_q<T>(S->max_block_rows));
+    const int qmax = std::max(1, k::cheb_max_q<T>(S->max_block_rows, 0));
     int ntiles = (P + qmax - 1) / qmax;
     int q = (P + ntiles - 1) / ntiles;
-    while (q > 1 && k::cheb_lds_bytes<T>(S->max_block_rows, q) > 150 * 1024) --q;
+    while (q > 1 && k::cheb_lds_bytes<T>(S->max_block_rows, q, 0) > 150 * 1024) --q;
     S->cq = q;
+    S->cshape = 0;
   }
   const sgw_problem_desc& d = h.d;
   double loose = refine ? d.ir_precond_rtol : d.precond_rtol;
@@ -1354,7 +1355,7 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  const int kReport = 68;
+  const int kReport = 72;
   std::vector<double> rep(kReport, -1.0);
   const int reps = 10;
   auto time_it = [&](auto&& fn) -> double {
@@ -1371,29 +1372,33 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
   // mode tiles of one system: triangular solve (report at tri) and Chebyshev
   // (report at cheb); the preconditioner the context uses decides which one
   // is timed
-  auto tune_sys = [&](auto& S, int tri, int cheb) {
+  auto tune_sys = [&](auto& S, int tri, int cheb, int shape_slot) {
     using T = std::remove_reference_t<decltype(*S.r)>;
     k::fill2d<T>(c->P, S.nrows, S.r, S.nrows, T(1), st);
     double best = 1e300;
     if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
-      int bestq = S.cq;
-      for (int q = 1; q <= 8; ++q) {
-        if (q > c->P || q > k::cheb_max_q<T>(S.max_block_rows) ||
-            k::cheb_lds_bytes<T>(S.max_block_rows, q) > 150 * 1024)
-          continue;
-        double us = time_it([&] {
-          (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, c->P,
-                                 c->cheb_deg, q,
-                                 S.max_block_rows, S.r, S.nrows, S.z, S.nrows, c->part,
-                                 c->part2, nullptr, 0, 0.0, nullptr, nullptr, nullptr, st);
-        });
-        rep[cheb + q - 1] = us;
-        if (us < best) {
-          best = us;
-          bestq = q;
+      int bestq = S.cq, bests = S.cshape;
+      for (int shape = 0; shape < 3; ++shape)
+        for (int q = 1; q <= 8; ++q) {
+          if (q > c->P || q > k::cheb_max_q<T>(S.max_block_rows, shape) ||
+              k::cheb_lds_bytes<T>(S.max_block_rows, q, shape) > 150 * 1024)
+            continue;
+          double us = time_it([&] {
+            (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, c->P,
+                                   c->cheb_deg, q, shape, S.max_block_rows, S.r, S.nrows, S.z,
+                                   S.nrows, c->part, c->part2, nullptr, 0, 0.0, nullptr,
+                                   nullptr, nullptr, st);
+          });
+          if (rep[cheb + q - 1] < 0.0 || us < rep[cheb + q - 1]) rep[cheb + q - 1] = us;
+          if (us < best) {
+            best = us;
+            bestq = q;
+            bests = shape;
+          }
         }
-      }
       S.cq = bestq;
+      S.cshape = bests;
+      rep[shape_slot] = bests;
     } else {
       int bestq = S.Q;
       for (int q = 1; q <= 8; ++q) {
@@ -1410,11 +1415,11 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
       S.Q = bestq;
     }
   };
-  tune_sys(c->d64.D, 0, 18);
-  tune_sys(c->d64.N, 8, 26);
+  tune_sys(c->d64.D, 0, 18, 68);
+  tune_sys(c->d64.N, 8, 26, 69);
   if (c->f32.ready) {
-    tune_sys(c->f32.D, 34, 50);
-    tune_sys(c->f32.N, 42, 58);
+    tune_sys(c->f32.D, 34, 50, 70);
+    tune_sys(c->f32.N, 42, 58, 71);
   }
   {
     // generated (unrolled tensor, staged x) vs table-driven SG apply on the
