@@ -122,11 +122,12 @@ def solver_settings(precision="mixed"):
         return dict(precision=sgw.SGW_FP64, guess=sgw.SGW_GUESS_PREV, rtol=1e-9,
                     inner_rtol=1e-12, precond_rtol=1e-4, inner_prec=sgw.SGW_INNER_CHEBYSHEV,
                     cheb_degree=8)
-    # refinement sweeps: FP32 interface PCG and Dirichlet solves to 1e-5,
-    # Neumann solves to 1e-3 (500 steps stay within 1e-7 of the oracle)
+    # refinement sweeps: FP32 interface PCG and Dirichlet solves to 3e-5,
+    # Neumann solves to 3e-3 (500 steps stay within 3e-7 of the oracle; the
+    # tighter 1e-5 / 1e-5 / 1e-3 gives 9e-8 at 7% fewer steps per second)
     return dict(precision=sgw.SGW_FP32_IR64, guess=sgw.SGW_GUESS_NEWMARK, rtol=1e-8,
                 inner_rtol=1e-11, precond_rtol=1e-4, inner_prec=sgw.SGW_INNER_CHEBYSHEV,
-                cheb_degree=8, ir_rtols=(1e-5, 1e-5, 1e-3))
+                cheb_degree=8, ir_rtols=(3e-5, 3e-5, 3e-3))
 
 
 def copy_calibration(nbytes=1 << 30, reps=10):

@@ -603,20 +603,22 @@ void pcg_start(int nb, int P, const double* part, const double* part2, double* s
 // active blocks (a converged block is frozen: its r'r is not read again).
 // Counts the block's iterations in sc[8b + 5] and keeps their maximum over
 // the blocks in flags[3].  Workgroup (0, 0) clears the active counter for the
-// test that follows.
+// test that follows.  A workgroup takes XR_MODES modes of one block (the
+// loads of a row's modes are independent and in flight together).
+#define XR_MODES 4
 template <typename T>
 __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
-    const int* row_off, int P, int par, double* sc, T* x, int ldx, const T* p, int ldp,
-    T* r, int ldr, const T* q, int ldq, const double* part, double* part2, int* flags,
-    const int* bgrp, int pqn) {
-  __shared__ double sh[SGW_BLOCK / 64];
-  const int blk = blockIdx.x, j = blockIdx.y;
+    const int* row_off, int P, int par, double* sc, T* __restrict__ x, int ldx,
+    const T* __restrict__ p, int ldp, T* __restrict__ r, int ldr, const T* __restrict__ q,
+    int ldq, const double* part, double* part2, int* flags, const int* bgrp, int pqn) {
+  __shared__ double sh[SGW_BLOCK / 64][XR_MODES];
+  const int blk = blockIdx.x, j0 = blockIdx.y * XR_MODES;
   const int r0 = row_off[blk], r1 = row_off[blk + 1];
   double* s = sc + (size_t)blk * 8;
   const bool act = s[2 + par] != 0.0;
-  if (blk == 0 && j == 0 && threadIdx.x == 0) flags[0] = 0;
+  if (blk == 0 && blockIdx.y == 0 && threadIdx.x == 0) flags[0] = 0;
   if (!act) return;
-  if (j == 0 && threadIdx.x == 0) {
+  if (blockIdx.y == 0 && threadIdx.x == 0) {
     s[5] += 1.0;
     atomicMax(&flags[3], (int)s[5]);
   }
@@ -630,36 +632,60 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_pcg_xr(
     }
     if (pq > 0.0) {
       al = s[par] / pq;
-    } else if (j == 0 && threadIdx.x == 0) {
+    } else if (blockIdx.y == 0 && threadIdx.x == 0) {
       if (isfinite(pq)) atomicOr(&flags[1], 1);
       else atomicOr(&flags[2], 1);
     }
   }
   const T alt = (T)al;
-  double acc = 0.0;
-  T* xp = x + (size_t)j * ldx;
-  T* rp = r + (size_t)j * ldr;
-  const T* pp = p + (size_t)j * ldp;
-  const T* qp = q + (size_t)j * ldq;
+  const int nq = min(XR_MODES, P - j0);
+  double acc[XR_MODES];
+#pragma unroll
+  for (int m = 0; m < XR_MODES; ++m) acc[m] = 0.0;
+  // modes past P repeat the last one (loaded, not stored or counted)
+  size_t jo[XR_MODES];
+#pragma unroll
+  for (int m = 0; m < XR_MODES; ++m) jo[m] = (size_t)(j0 + min(m, nq - 1));
   for (int i = r0 + threadIdx.x; i < r1; i += SGW_BLOCK) {
-    T rv = rp[i];
-    if (al != 0.0) {
-      xp[i] = fmadd(alt, pp[i], xp[i]);
-      rv = fmadd(-alt, qp[i], rv);
-      rp[i] = rv;
+    T rv[XR_MODES], xv[XR_MODES], pv[XR_MODES], qv[XR_MODES];
+#pragma unroll
+    for (int m = 0; m < XR_MODES; ++m) {
+      rv[m] = r[jo[m] * ldr + i];
+      xv[m] = x[jo[m] * ldx + i];
+      pv[m] = p[jo[m] * ldp + i];
+      qv[m] = q[jo[m] * ldq + i];
     }
-    acc += (double)rv * (double)rv;
+#pragma unroll
+    for (int m = 0; m < XR_MODES; ++m) {
+      if (m >= nq) break;
+      if (al != 0.0) {
+        x[jo[m] * ldx + i] = fmadd(alt, pv[m], xv[m]);
+        rv[m] = fmadd(-alt, qv[m], rv[m]);
+        r[jo[m] * ldr + i] = rv[m];
+      }
+      acc[m] += (double)rv[m] * (double)rv[m];
+    }
   }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) part2[(size_t)blk * P + j] = acc;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int m = 0; m < XR_MODES; ++m) {
+    const double v = wave_sum(acc[m]);
+    if (lane == 0) sh[w][m] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nq) {
+    double t = 0.0;
+    for (int v = 0; v < SGW_BLOCK / 64; ++v) t += sh[v][threadIdx.x];
+    part2[(size_t)blk * P + j0 + threadIdx.x] = t;
+  }
 }
 
 template <typename T>
 void pcg_xr(int nb, const int* row_off, int P, int par, double* sc, T* x, int ldx,
             const T* p, int ldp, T* r, int ldr, const T* q, int ldq, const double* part,
             double* part2, int* flags, hipStream_t st, const int* bgrp, int pqn) {
-  k_pcg_xr<T><<<dim3(nb, P), SGW_BLOCK, 0, st>>>(row_off, P, par, sc, x, ldx, p, ldp, r, ldr,
-                                                 q, ldq, part, part2, flags, bgrp, pqn);
+  k_pcg_xr<T><<<dim3(nb, ceil_div(P, XR_MODES)), SGW_BLOCK, 0, st>>>(
+      row_off, P, par, sc, x, ldx, p, ldp, r, ldr, q, ldq, part, part2, flags, bgrp, pqn);
 }
 
 // Stopping test of iteration par (used with the exact preconditioner; the
