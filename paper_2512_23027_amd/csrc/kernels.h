@@ -113,15 +113,17 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
 
 // Chebyshev polynomial preconditioner (degree deg, Q modes per workgroup,
 // launch shape 0, 1, 2 = 1024, 512, 256 threads per workgroup with 1, 2 or 4
-// rows per thread) on the blocks of A's mean matrix; coef[b * 2 deg ...] = the iteration
-// coefficients of block b (cheb_coefficients); order (may be null) = launch
-// order of the blocks (largest first); crow[r0 + i] = system row at natural
-// (lexicographic) position i of the block starting at r0, cnb[s*nrows + r0 +
-// i] = natural position of that row's slot-s neighbour within the block
-// (slot 0: the row itself).  Writes z and part[b*P + j] = r_j'z_j (part2 =
-// r_j'r_j if not null).  With sc != null it first does the PCG stopping test
-// of iteration par (r'r from rrpart, see pcg_test) and skips converged
-// blocks.  With acct != null, every active workgroup adds its algorithmic
+// rows per thread) on the blocks of the mean matrix; coef[b * 2 deg ...] =
+// the iteration coefficients of block b (cheb_coefficients); order (may be
+// null) = launch order of the blocks (largest first); crow[r0 + i] = system
+// row at natural (lexicographic) position i of the block starting at r0;
+// [8]-records by natural position r0 + i: cnb[8 (r0 + i) + s] = natural
+// position of that row's slot-s neighbour within the block (slot 0: the row
+// itself), cval[8 (r0 + i) + s] = its mean-matrix value (slots 7 and
+// unused ones: value 0, position of the row itself).  Writes z and
+// part[b*P + j] = r_j'z_j (part2 = r_j'r_j if not null).  With sc != null it
+// first does the PCG stopping test of iteration par (r'r from rrpart, see
+// pcg_test) and skips converged blocks.  With acct != null, every active workgroup adds its algorithmic
 // bytes (right-hand sides in and out, the block's mean matrix once) to
 // *acct.  Returns -1 (nothing launched) if Q, the shape, deg or the block
 // size is out of range (max_rows <= 4 x the workgroup size, Q <= cheb_max_q,
@@ -143,7 +145,7 @@ int cheb_max_q(int max_rows, int shape);
 // 160 KiB of LDS.  0 on success, -1 on a HIP error.
 int cheb_prepare();
 template <typename T>
-int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int* crow,
+int cheb_apply(const T* cval, const int* row_off, const int* order, const int* crow,
                const unsigned short* cnb, const T* coef, int nb, int P, int deg,
                int Q, int shape, int max_rows, const T* r, int ldr, T* z, int ldz,
                double* part, double* part2, double* sc, int par, double tol2,

@@ -973,6 +973,23 @@ __device__ __forceinline__ void lds_read_row(const unsigned char* p, T (&v)[Q]) 
   }
 }
 
+// 8 consecutive values from global memory (32-byte aligned for float,
+// 64-byte for double) in 16-byte loads
+template <typename T>
+__device__ __forceinline__ void load_row8(const T* p, T (&v)[8]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double2 a = reinterpret_cast<const double2*>(p)[c];
+      v[2 * c] = a.x;
+      v[2 * c + 1] = a.y;
+    }
+  }
+}
+
 template <typename T, int Q>
 __device__ __forceinline__ void lds_write_row(unsigned char* p, const T (&v)[Q]) {
   constexpr int bytes = Q * (int)sizeof(T);
@@ -997,7 +1014,7 @@ __device__ __forceinline__ void lds_write_row(unsigned char* p, const T (&v)[Q])
 
 template <typename T, int Q, int RPT, int TPB>
 __global__ __launch_bounds__(TPB) void k_cheb(
-    DEll<T> A, const int* __restrict__ row_off, const int* __restrict__ order,
+    const T* __restrict__ cval, const int* __restrict__ row_off, const int* __restrict__ order,
     const int* __restrict__ crow, const unsigned short* __restrict__ cnb,
     const T* __restrict__ coef, int P, int deg,
     const T* __restrict__ r, int ldr, T* __restrict__ z, int ldz, double* __restrict__ part,
@@ -1026,7 +1043,6 @@ __global__ __launch_bounds__(TPB) void k_cheb(
     if (!act) return;  // converged block: its z and r'z are not used again
   }
   const int r0 = row_off[b], n = row_off[b + 1] - r0;
-  const int NR = A.nrows;
   if (acct && threadIdx.x == 0) {  // algorithmic bytes of this (active) workgroup
     const int nq = min(Q, P - j0);
     atomicAdd(acct, (unsigned long long)(2 * sizeof(T) * nq * n +
@@ -1051,15 +1067,27 @@ __global__ __launch_bounds__(TPB) void k_cheb(
   T rin[kKeepR ? RPT : 1][kKeepR ? Q : 1];
   T res[RPT][Q], zz[RPT][Q], dd[RPT][Q];
   const T inv_theta = coef[(size_t)b * 2 * deg];
+  // the neighbour positions and the mean-matrix row of natural position i
+  // are [8]-records (16-byte loads, independent of crow)
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int i = threadIdx.x + t * TPB;
     const bool live = i < n;
     row[t] = live ? crow[r0 + i] : r0;
+    uint4 nb4 = make_uint4(0u, 0u, 0u, 0u);
+    T a8[8];
+    if (live) {
+      nb4 = *reinterpret_cast<const uint4*>(cnb + (size_t)(r0 + i) * 8);
+      load_row8(cval + (size_t)(r0 + i) * 8, a8);
+    } else {
+#pragma unroll
+      for (int sl = 0; sl < 8; ++sl) a8[sl] = T(0);
+    }
+    const unsigned nbw[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
 #pragma unroll
     for (int sl = 0; sl < 7; ++sl) {
-      lo[t][sl] = (live ? (unsigned)cnb[(size_t)sl * NR + r0 + i] : 0u) * (unsigned)(Q * sizeof(T));
-      av[t][sl] = live ? A.val[(size_t)sl * NR + row[t]] : T(0);
+      lo[t][sl] = ((nbw[sl >> 1] >> (16 * (sl & 1))) & 0xffffu) * (unsigned)(Q * sizeof(T));
+      av[t][sl] = a8[sl];
     }
     dinv[t] = live ? T(1) / av[t][0] : T(0);
 #pragma unroll
@@ -1214,21 +1242,21 @@ struct ChebArgs {
 };
 
 template <typename T, int Q, int RPT, int TPB>
-static void launch_cheb(const DEll<T>& A, const ChebArgs& a, const ChebTest& t, hipStream_t st) {
+static void launch_cheb(const T* cval, const ChebArgs& a, const ChebTest& t, hipStream_t st) {
   dim3 grid(a.nb, ceil_div(a.P, Q));
   k_cheb<T, Q, RPT, TPB><<<grid, TPB, cheb_lds_bytes<T>(a.max_rows, Q, a.shape), st>>>(
-      A, a.row_off, t.order, a.crow, a.cnb, static_cast<const T*>(a.coef), a.P, a.deg,
+      cval, a.row_off, t.order, a.crow, a.cnb, static_cast<const T*>(a.coef), a.P, a.deg,
       static_cast<const T*>(a.r), a.ldr, static_cast<T*>(a.z), a.ldz, a.part, a.part2, t.sc,
       t.par, t.tol2, t.rrpart, t.flags, t.acct);
 }
 
 template <typename T, int RPT, int TPB>
-static void cheb_q(int Q, const DEll<T>& A, const ChebArgs& a, const ChebTest& t,
+static void cheb_q(int Q, const T* cval, const ChebArgs& a, const ChebTest& t,
                    hipStream_t st) {
   switch (Q) {
 #define SGW_CHEB_CASE(q)                            \
   case q:                                          \
-    launch_cheb<T, q, RPT, TPB>(A, a, t, st);      \
+    launch_cheb<T, q, RPT, TPB>(cval, a, t, st);   \
     break;
     SGW_CHEB_CASE(1)
     SGW_CHEB_CASE(2)
@@ -1288,23 +1316,23 @@ int cheb_max_q(int max_rows, int shape) {
 }
 
 template <typename T>
-int cheb_apply(const DEll<T>& A, const int* row_off, const int* order, const int* crow,
+int cheb_apply(const T* cval, const int* row_off, const int* order, const int* crow,
                const unsigned short* cnb, const T* coef, int nb, int P, int deg,
                int Q, int shape, int max_rows, const T* r, int ldr, T* z, int ldz,
                double* part, double* part2, double* sc, int par, double tol2,
                const double* rrpart, int* flags, unsigned long long* acct, hipStream_t st) {
   if (Q < 1 || Q > cheb_max_q<T>(max_rows, shape) || deg < 1 || deg > CHEB_MAX_DEG ||
       max_rows < 1 || cheb_lds_bytes<T>(max_rows, Q, shape) > 150 * 1024 ||
-      (sc && (!rrpart || !flags)) || !crow || !cnb || !coef)
+      (sc && (!rrpart || !flags)) || !crow || !cnb || !coef || !cval)
     return -1;
   const ChebTest t{order, acct, sc, par, tol2, rrpart, flags};
   const ChebArgs a{row_off, crow, cnb, coef, nb, P, deg, max_rows, shape, r, ldr, z, ldz,
                    part, part2};
   const int rpt = cheb_rpt(max_rows, shape);
 #define SGW_CHEB_SHAPE(tpb)                                \
-  if (rpt == 1) cheb_q<T, 1, tpb>(Q, A, a, t, st);         \
-  else if (rpt == 2) cheb_q<T, 2, tpb>(Q, A, a, t, st);    \
-  else cheb_q<T, 4, tpb>(Q, A, a, t, st);
+  if (rpt == 1) cheb_q<T, 1, tpb>(Q, cval, a, t, st);         \
+  else if (rpt == 2) cheb_q<T, 2, tpb>(Q, cval, a, t, st);    \
+  else cheb_q<T, 4, tpb>(Q, cval, a, t, st);
   if (shape == 0) {
     SGW_CHEB_SHAPE(CHEB_TPB)
   } else if (shape == 1) {
@@ -1419,12 +1447,12 @@ template size_t cheb_lds_bytes<double>(int, int, int);
 template int cheb_max_q<double>(int, int);
 template int cheb_max_q<float>(int, int);
 template size_t cheb_lds_bytes<float>(int, int, int);
-template int cheb_apply<double>(const DEll<double>&, const int*, const int*, const int*,
+template int cheb_apply<double>(const double*, const int*, const int*, const int*,
                                 const unsigned short*, const double*, int, int, int,
                                 int, int, int, const double*, int, double*, int, double*, double*,
                                 double*, int, double, const double*, int*, unsigned long long*,
                                 hipStream_t);
-template int cheb_apply<float>(const DEll<float>&, const int*, const int*, const int*,
+template int cheb_apply<float>(const float*, const int*, const int*, const int*,
                                const unsigned short*, const float*, int, int, int,
                                int, int, int, const float*, int, float*, int, double*, double*,
                                double*, int, double, const double*, int*, unsigned long long*,

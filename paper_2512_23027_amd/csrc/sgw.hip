@@ -48,7 +48,8 @@ struct SysT {  // batched block-diagonal SG system (Dirichlet or Neumann)
   const T* cheb_cc = nullptr;         // device, [nb][2 deg] Chebyshev step coefficients
   const int* lpt = nullptr;           // device, blocks by decreasing size (launch order)
   const int* crow = nullptr;          // device, system row of each natural block position
-  const unsigned short* cnb = nullptr;  // device, [7][nrows] neighbours' natural positions
+  const unsigned short* cnb = nullptr;  // device, [nrows][8] neighbours' natural positions
+  const T* cval = nullptr;            // device, [nrows][8] mean-matrix rows, natural order
   // iteration count of the previous solve, by call site (see inner_solve)
   // and tolerance class (tight / loose)
   int last_its[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -100,6 +101,7 @@ struct sgw_ctx {
   double* hosc = nullptr;  // pinned copy of osc
   int* flags = nullptr;
   int* hflags = nullptr;
+  std::vector<int> crow_h[2];  // natural order of the Dirichlet / Neumann blocks (host)
   const int* goff = nullptr;   // {0, nG}: rows relative to an interface-part pointer
   const int* alloff = nullptr; // {0, NF}
   const int* dd2mesh = nullptr;
@@ -398,7 +400,8 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
     int a = prof_begin(c, kind, st);
     // timed launches count their bytes on the device (converged blocks are
     // skipped inside the kernel); harvested into the kind's total
-    (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, P, c->cheb_deg,
+    (void)k::cheb_apply<T>(S.cval, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, P,
+                           c->cheb_deg,
                            S.cq, S.cshape, S.max_block_rows, S.r, n, S.z, n, part, part2,
                            test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
                            c->part2, c->flags, a >= 0 ? c->acct + (sizeof(T) == 4) : nullptr, st);
@@ -942,14 +945,16 @@ static bool spd_inverse(std::vector<double>& A, int n) {
 // refinement path), system workspaces and interface vectors.
 // Natural (lexicographic mesh) order of the rows of every block of a
 // subdomain system: crow[r0 + i] = system row at position i of block
-// [r0, r1), cnb[s*nrows + r0 + i] = block-local position of that row's slot-s
-// neighbour.  mesh_of(row) gives a row's mesh node.
+// [r0, r1), cnb[8 (r0 + i) + s] = block-local position of that row's slot-s
+// neighbour (slots past the matrix width: the row itself).  mesh_of(row)
+// gives a row's mesh node.  crow_h keeps the host copy of crow.
 template <class MeshOf>
 static void natural_order(sgw_ctx* c, const Ell& E, const std::vector<int>& off, MeshOf mesh_of,
-                          const int** crow_d, const unsigned short** cnb_d) {
+                          const int** crow_d, const unsigned short** cnb_d,
+                          std::vector<int>& crow_h) {
   const int NR = E.nrows, n1 = c->h.n + 1;
   std::vector<int> crow(NR > 0 ? NR : 1), pos(NR > 0 ? NR : 1);
-  std::vector<unsigned short> cnb((size_t)E.W * std::max(NR, 1), 0);
+  std::vector<unsigned short> cnb((size_t)8 * std::max(NR, 1), 0);
   for (size_t b = 0; b + 1 < off.size(); ++b) {
     const int r0 = off[b], r1 = off[b + 1];
     std::vector<int> rows;
@@ -965,10 +970,13 @@ static void natural_order(sgw_ctx* c, const Ell& E, const std::vector<int>& off,
   }
   for (size_t b = 0; b + 1 < off.size(); ++b)
     for (int i = off[b]; i < off[b + 1]; ++i)
-      for (int s = 0; s < E.W; ++s)
-        cnb[(size_t)s * NR + i] = (unsigned short)pos[E.col[(size_t)s * NR + crow[i]]];
+      for (int s = 0; s < 8; ++s)
+        cnb[(size_t)8 * i + s] =
+            (unsigned short)(s < std::min(E.W, 7) ? pos[E.col[(size_t)s * NR + crow[i]]]
+                                                  : i - off[b]);
   *crow_d = upload(c, crow);
   *cnb_d = upload(c, cnb);
+  crow_h = crow;
 }
 
 // Row-group halos of an ELL matrix for rows [r0, nrows) (see k::DHalo):
@@ -1113,15 +1121,27 @@ static void setup_prec(sgw_ctx* c, PrecT<T>& pr, bool refine) {
     pr.N.lpt = c->d64.N.lpt;
   }
   if constexpr (sizeof(T) == 8) {
-    natural_order(c, h.dir, h.Ioff, [&](int r) { return h.dd2mesh[r]; }, &pr.D.crow, &pr.D.cnb);
+    natural_order(c, h.dir, h.Ioff, [&](int r) { return h.dd2mesh[r]; }, &pr.D.crow, &pr.D.cnb,
+                  c->crow_h[0]);
     natural_order(c, h.neu, h.Toff, [&](int r) { return h.dd2mesh[h.torn2dd[r]]; }, &pr.N.crow,
-                  &pr.N.cnb);
+                  &pr.N.cnb, c->crow_h[1]);
   } else {
     pr.D.crow = c->d64.D.crow;
     pr.D.cnb = c->d64.D.cnb;
     pr.N.crow = c->d64.N.crow;
     pr.N.cnb = c->d64.N.cnb;
   }
+  // the mean-matrix rows (coefficient slot k = 0) in natural order, as
+  // [8]-records of this precision
+  auto pack_mean = [&](const Ell& E, const std::vector<int>& crow) {
+    const int NR = E.nrows, W = std::min(E.W, 7);
+    std::vector<T> cv((size_t)8 * std::max(NR, 1), T(0));
+    for (int i = 0; i < NR; ++i)
+      for (int s = 0; s < W; ++s) cv[(size_t)8 * i + s] = (T)E.val[(size_t)s * NR + crow[i]];
+    return upload(c, cv);
+  };
+  pr.D.cval = pack_mean(h.dir, c->crow_h[0]);
+  pr.N.cval = pack_mean(h.neu, c->crow_h[1]);
   for (SysT<T>* S : {&pr.D, &pr.N}) {
     const int qmax = std::max(1, k::cheb_max_q<T>(S->max_block_rows, 0));
     int ntiles = (P + qmax - 1) / qmax;
@@ -1248,7 +1268,8 @@ static bool prec_complete(const PrecT<T>& pr, bool refine) {
                       pr.N.A.val, pr.D.x, pr.D.r, pr.D.z, pr.D.p, pr.D.q, pr.N.x, pr.N.r,
                       pr.N.z, pr.N.p, pr.N.q, pr.X, pr.R, pr.Z, pr.Zp, pr.Pw, pr.Qw, pr.T1,
                       pr.Gv, pr.Tt, pr.Yt, pr.D.row_off, pr.N.row_off, pr.D.crow, pr.D.cnb,
-                      pr.N.crow, pr.N.cnb, pr.D.cheb_cc, pr.N.cheb_cc, pr.D.p2, pr.N.p2};
+                      pr.N.crow, pr.N.cnb, pr.D.cheb_cc, pr.N.cheb_cc, pr.D.cval, pr.N.cval,
+                      pr.D.p2, pr.N.p2};
   for (const void* p : ps)
     if (!p) return false;
   return !refine || (pr.Fb && pr.Xb);
@@ -1384,7 +1405,7 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
               k::cheb_lds_bytes<T>(S.max_block_rows, q, shape) > 150 * 1024)
             continue;
           double us = time_it([&] {
-            (void)k::cheb_apply<T>(S.A, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, c->P,
+            (void)k::cheb_apply<T>(S.cval, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, c->P,
                                    c->cheb_deg, q, shape, S.max_block_rows, S.r, S.nrows, S.z,
                                    S.nrows, c->part, c->part2, nullptr, 0, 0.0, nullptr,
                                    nullptr, nullptr, st);
