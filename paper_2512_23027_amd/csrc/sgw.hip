@@ -104,6 +104,9 @@ struct sgw_ctx {
   std::vector<int> crow_h[2];  // natural order of the Dirichlet / Neumann blocks (host)
   const int* goff = nullptr;   // {0, nG}: rows relative to an interface-part pointer
   const int* alloff = nullptr; // {0, NF}
+  const int* fchunk = nullptr;  // row chunks of [0, NF) for the whole-array dot products
+  int nfchunk = 0;
+  double* hpart = nullptr;      // pinned, 2 x nfchunk x P partial sums
   const int* dd2mesh = nullptr;
   const double* mdiag = nullptr;
   // interface <-> torn maps
@@ -1180,24 +1183,28 @@ __global__ void k_add_f32(long long N, double* x, const float* d, double scale) 
   if (t < N) x[t] += scale * (double)d[t];
 }
 
-// Dot products over all rows of full [P][NF] arrays (FP64 sums): out = a'b
-// and, with c and d, out2 = c'd, read with one synchronisation
+// Dot products over all rows of full [P][NF] arrays (FP64 sums over row
+// chunks and modes, fixed order): out = a'b and, with c and d, out2 = c'd,
+// read with one synchronisation
 template <typename T>
 static int fdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st,
                 const T* cc = nullptr, const T* dd = nullptr, double* out2 = nullptr) {
-  const int P = c->P;
-  k::seg_dot<T>(1, c->alloff, P, a, c->NF, b, c->NF, c->osc, cc, c->NF, dd, c->NF,
-                cc ? c->osc + P : nullptr, st);
-  HIPCHK(hipMemcpyAsync(c->hosc, c->osc, (cc ? 2 : 1) * P * sizeof(double),
-                        hipMemcpyDeviceToHost, st));
+  const int P = c->P, nc = c->nfchunk;
+  const size_t np = (size_t)nc * P;
+  k::seg_dot<T>(nc, c->fchunk, P, a, c->NF, b, c->NF, c->part, cc, c->NF, dd, c->NF,
+                cc ? c->part2 : nullptr, st);
+  HIPCHK(hipMemcpyAsync(c->hpart, c->part, np * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (cc)
+    HIPCHK(hipMemcpyAsync(c->hpart + np, c->part2, np * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
   prof_stage(c, st);
   HIPCHK(hipStreamSynchronize(st));
   prof_harvest(c);
   out = 0.0;
-  for (int j = 0; j < P; ++j) out += c->hosc[j];
+  for (size_t e = 0; e < np; ++e) out += c->hpart[e];
   if (cc) {
     *out2 = 0.0;
-    for (int j = 0; j < P; ++j) *out2 += c->hosc[P + j];
+    for (size_t e = 0; e < np; ++e) *out2 += c->hpart[np + e];
   }
   return 0;
 }
@@ -1279,6 +1286,7 @@ static bool check_pointers(sgw_ctx* c) {
   const void* ps[] = {c->U, c->V, c->A, c->Um, c->Uc, c->Wm, c->F, c->hist, c->gnew, c->smax,
                       c->mx, c->my, c->pqg, c->meshbuf, c->meshbuf2,
                       c->part, c->part2, c->osc, c->sc, c->flags, c->goff, c->alloff,
+                      c->fchunk,
                       c->dd2mesh,
                       c->mdiag, c->torn_gidx, c->torn_w, c->gam_ptr, c->gam_torn, c->gam_w,
                       c->g2c, c->dc, c->uc, c->phi, c->gt.mask, c->gt.pair_beg, c->gt.ent_beg,
@@ -1491,6 +1499,7 @@ int sgw_destroy(sgw_ctx* c) {
   }
   if (c->hflags) (void)hipHostFree(c->hflags);
   if (c->hosc) (void)hipHostFree(c->hosc);
+  if (c->hpart) (void)hipHostFree(c->hpart);
   if (c->acct_h) (void)hipHostFree(c->acct_h);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -1599,7 +1608,7 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   }
   c->meshbuf = dalloc<double>(c, (size_t)std::max(P, 2) * h.nn);
   c->meshbuf2 = dalloc<double>(c, (size_t)P * h.nn);
-  int nbmax = std::max(1, h.nsub);
+  int nbmax = std::max(64, h.nsub);  // also the row chunks of the whole-array dots (<= 64)
   c->part = dalloc<double>(c, (size_t)nbmax * P);
   c->part2 = dalloc<double>(c, (size_t)nbmax * P);
   c->osc = dalloc<double>(c, (size_t)2 * P + 8);
@@ -1607,6 +1616,13 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   c->flags = dalloc<int>(c, 4);
   c->goff = upload(c, std::vector<int>{0, h.nG});  // rows of the interface part
   c->alloff = upload(c, std::vector<int>{0, h.NF});
+  {  // about 64 row chunks (one workgroup per chunk and mode in a dot product)
+    const int nch = std::max(1, std::min(64, (h.NF + 1023) / 1024));
+    std::vector<int> fc(nch + 1);
+    for (int i = 0; i <= nch; ++i) fc[i] = (int)((long long)h.NF * i / nch);
+    c->fchunk = upload(c, fc);
+    c->nfchunk = nch;
+  }
   c->dd2mesh = upload(c, h.dd2mesh);
   std::vector<double> md(h.NF);
   for (int r = 0; r < h.NF; ++r) md[r] = h.glob.mval[r];  // slot 0 = diagonal
@@ -1692,7 +1708,9 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     c->acct_h = nullptr;
   if (!c->acct_h) c->acct = nullptr;
   if (hipHostMalloc((void**)&c->hflags, 16 * sizeof(int)) != hipSuccess ||
-      hipHostMalloc((void**)&c->hosc, (2 * (size_t)P + 8) * sizeof(double)) != hipSuccess) {
+      hipHostMalloc((void**)&c->hosc, (2 * (size_t)P + 8) * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hpart, 2 * (size_t)c->nfchunk * P * sizeof(double)) !=
+          hipSuccess) {
     c->err = "pinned allocation failed";
     *out = c;
     return SGW_ENOMEM;
