@@ -196,7 +196,8 @@ void axpby2d(int P, int n, double a, const T* x, int ldx, double b, const T* y,
 template <typename T>
 void axpby2d_dev(int P, int n, double sa, int ia, const T* x, int ldx, double sb, int ib,
                  const T* y, int ldy, T* dst, int ldd, const double* ds, hipStream_t st);
-// Interface PCG scalars in ds (device; sums over the P partials of a, b):
+// Interface PCG scalars in ds (device; sums over the P partials of a, b in
+// a fixed order; P may count (row chunk, mode) partials):
 // mode 0: ds[par] = sum a (r'z); mode 1: ds[2] = alpha = ds[par] / sum a
 // (sum a = p'q; if not > 0: alpha = 0 and ds[4] = 1, or 2 if non-finite);
 // mode 2: ds[3] = beta = (sum a - sum b) / ds[par], ds[1 - par] = sum a.

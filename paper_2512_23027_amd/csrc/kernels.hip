@@ -812,12 +812,20 @@ void axpby2d_dev(int P, int n, double sa, int ia, const T* x, int ldx, double sb
                                                                    y, ldy, dst, ldd, ds);
 }
 
-// Scalars of the interface PCG (one thread; sums of the P mode partials in
-// mode order, as the host would form them)
-__global__ void k_outer_scalars(int mode, int P, const double* a, const double* b, double* ds,
-                                int par) {
-  double sa = 0.0, sb = 0.0;
-  for (int j = 0; j < P; ++j) sa += a[j];
+// Scalars of the interface PCG (one workgroup; the partial sums are added
+// in a fixed order: per thread over a stride, then the threads' sums)
+__global__ __launch_bounds__(SGW_BLOCK) void k_outer_scalars(int mode, int P, const double* a,
+                                                            const double* b, double* ds,
+                                                            int par) {
+  __shared__ double sh[SGW_BLOCK / 64];
+  double va = 0.0, vb = 0.0;
+  for (int j = threadIdx.x; j < P; j += SGW_BLOCK) {
+    va += a[j];
+    if (mode == 2) vb += b[j];
+  }
+  const double sa = block_sum(va, sh);
+  const double sb = mode == 2 ? block_sum(vb, sh) : 0.0;
+  if (threadIdx.x != 0) return;
   if (mode == 0) {  // start: r'z
     ds[par] = sa;
   } else if (mode == 1) {  // alpha = r'z / p'q, breakdown flag
@@ -828,14 +836,13 @@ __global__ void k_outer_scalars(int mode, int P, const double* a, const double* 
       ds[4] = isfinite(sa) ? 1.0 : 2.0;
     }
   } else {  // flexible beta = (r'z - r'z_prev) / r'z_old; r'z of the next iteration
-    for (int j = 0; j < P; ++j) sb += b[j];
     ds[3] = (sa - sb) / ds[par];
     ds[1 - par] = sa;
   }
 }
 void outer_scalars(int mode, int P, const double* a, const double* b, double* ds, int par,
                    hipStream_t st) {
-  k_outer_scalars<<<1, 1, 0, st>>>(mode, P, a, b, ds, par);
+  k_outer_scalars<<<1, SGW_BLOCK, 0, st>>>(mode, P, a, b, ds, par);
 }
 
 // ---------------------------------------------------------------------------

@@ -102,7 +102,8 @@ struct sgw_ctx {
   int* flags = nullptr;
   int* hflags = nullptr;
   std::vector<int> crow_h[2];  // natural order of the Dirichlet / Neumann blocks (host)
-  const int* goff = nullptr;   // {0, nG}: rows relative to an interface-part pointer
+  const int* goff = nullptr;   // row chunks of [0, nG), relative to an interface-part pointer
+  int ngchunk = 1;
   const int* alloff = nullptr; // {0, NF}
   const int* fchunk = nullptr;  // row chunks of [0, NF) for the whole-array dot products
   int nfchunk = 0;
@@ -644,28 +645,31 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   k::copy2d<T, T>(P, nI, pr.T1, NF, X, NF, 1.0, st);
   // The PCG scalars (alpha, beta, r'z) stay on the device; the host reads
   // r'r (and G'G at the start) for the stopping test, once per iteration.
-  // osc = [G'G partials (P)][r'r partials (P)][ds: r'z by parity, alpha,
-  // beta, breakdown flag, ...]
+  // Dot products over the interface rows give partial sums per (row chunk,
+  // mode), NP = chunks x P of them, summed in a fixed order.  osc = [G'G
+  // partials (NP)][r'r partials (NP)][ds: r'z by parity, alpha, beta,
+  // breakdown flag, ...]
+  const int gc = c->ngchunk, NP = gc * P;
   double* const ggp = c->osc;
-  double* const rrp = c->osc + P;
-  double* const ds = c->osc + 2 * P;
+  double* const rrp = c->osc + NP;
+  double* const ds = c->osc + 2 * NP;
   auto read_rr = [&](double& rr, bool with_gg, double* gg) -> int {
-    const int off = with_gg ? 0 : P;
-    HIPCHK(hipMemcpyAsync(c->hosc + off, c->osc + off, (2 * P + 8 - off) * sizeof(double),
+    const int off = with_gg ? 0 : NP;
+    HIPCHK(hipMemcpyAsync(c->hosc + off, c->osc + off, (2 * NP + 8 - off) * sizeof(double),
                           hipMemcpyDeviceToHost, st));
     prof_stage(c, st);
     HIPCHK(hipStreamSynchronize(st));
     prof_harvest(c);
     rr = 0.0;
-    for (int j = 0; j < P; ++j) rr += c->hosc[P + j];
+    for (int j = 0; j < NP; ++j) rr += c->hosc[NP + j];
     if (with_gg) {
       *gg = 0.0;
-      for (int j = 0; j < P; ++j) *gg += c->hosc[j];
+      for (int j = 0; j < NP; ++j) *gg += c->hosc[j];
     }
     return 0;
   };
   k::fill2d<double>(1, 8, ds, 8, 0.0, st);
-  k::seg_dot<T>(1, c->goff, P, pr.Gv + nI, NF, pr.Gv + nI, NF, ggp, nullptr, 0, nullptr, 0,
+  k::seg_dot<T>(gc, c->goff, P, pr.Gv + nI, NF, pr.Gv + nI, NF, ggp, nullptr, 0, nullptr, 0,
                 nullptr, st);
   // H3/H4: PCG on S U_G = G, initial guess in X's interface part
   T* x = X + nI;
@@ -687,7 +691,7 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   double gg = 0.0, rr = 0.0;
   if (fallback) {  // a learned guess worse than the zero guess is replaced
     double rr0;
-    k::seg_dot<T>(1, c->goff, P, r, NF, r, NF, rrp, nullptr, 0, nullptr, 0, nullptr, st);
+    k::seg_dot<T>(gc, c->goff, P, r, NF, r, NF, rrp, nullptr, 0, nullptr, 0, nullptr, st);
     if ((rc = read_rr(rr0, true, &gg))) return rc;
     if (!(rr0 <= gg)) {
       k::axpby2d<T>(P, nI, 1.0, X, NF, -1.0, pr.Pw, NF, X, NF, st);  // U_I -= w(x0)
@@ -704,8 +708,8 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
   warn |= rc;
   k::copy2d<T, T>(P, nG, z, NF, p, NF, 1.0, st);
   int par = 0;
-  k::seg_dot<T>(1, c->goff, P, r, NF, z, NF, c->part, r, NF, r, NF, rrp, st);
-  k::outer_scalars(0, P, c->part, nullptr, ds, par, st);
+  k::seg_dot<T>(gc, c->goff, P, r, NF, z, NF, c->part, r, NF, r, NF, rrp, st);
+  k::outer_scalars(0, NP, c->part, nullptr, ds, par, st);
   if ((rc = read_rr(rr, true, &gg))) return rc;
   const double stop2 = tl.rtol * tl.rtol * gg;
   // flexible CG (Polak-Ribiere beta): the preconditioner's Neumann solves run
@@ -719,16 +723,16 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
     }
     if ((rc = schur_apply<T>(c, pr, tl, pr.Pw, pr.Qw, st)) < 0) return rc;
     warn |= rc;
-    k::seg_dot<T>(1, c->goff, P, p, NF, q, NF, c->part, nullptr, 0, nullptr, 0, nullptr, st);
-    k::outer_scalars(1, P, c->part, nullptr, ds, par, st);
+    k::seg_dot<T>(gc, c->goff, P, p, NF, q, NF, c->part, nullptr, 0, nullptr, 0, nullptr, st);
+    k::outer_scalars(1, NP, c->part, nullptr, ds, par, st);
     k::axpby2d_dev<T>(P, NF, 1.0, -1, X, NF, 1.0, 2, pr.Pw, NF, X, NF, ds, st);  // U += alpha Pw
     k::axpby2d_dev<T>(P, nG, 1.0, -1, r, NF, -1.0, 2, q, NF, r, NF, ds, st);
     ++it;
-    k::seg_dot<T>(1, c->goff, P, r, NF, r, NF, rrp, nullptr, 0, nullptr, 0, nullptr, st);
+    k::seg_dot<T>(gc, c->goff, P, r, NF, r, NF, rrp, nullptr, 0, nullptr, 0, nullptr, st);
     if ((rc = read_rr(rr, false, nullptr))) return rc;
-    if (c->hosc[2 * P + 4] != 0.0) {
+    if (c->hosc[2 * NP + 4] != 0.0) {
       c->err = "breakdown (p'Sp <= 0) in the interface PCG";
-      return c->hosc[2 * P + 4] == 1.0 ? SGW_EBREAKDOWN : SGW_ENAN;
+      return c->hosc[2 * NP + 4] == 1.0 ? SGW_EBREAKDOWN : SGW_ENAN;
     }
     if (!std::isfinite(rr)) {
       c->err = "non-finite interface residual";
@@ -738,8 +742,8 @@ static int dd_solve(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* F, T* X, 
     std::swap(z, zp);  // zp = the previous preconditioned residual
     if ((rc = precond<T>(c, pr, tl, r, z, st)) < 0) return rc;
     warn |= rc;
-    k::seg_dot<T>(1, c->goff, P, r, NF, z, NF, c->part, r, NF, zp, NF, c->part2, st);
-    k::outer_scalars(2, P, c->part, c->part2, ds, par, st);
+    k::seg_dot<T>(gc, c->goff, P, r, NF, z, NF, c->part, r, NF, zp, NF, c->part2, st);
+    k::outer_scalars(2, NP, c->part, c->part2, ds, par, st);
     k::axpby2d_dev<T>(P, nG, 1.0, -1, z, NF, 1.0, 3, p, NF, p, NF, ds, st);
     par ^= 1;
   }
@@ -1611,10 +1615,15 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   int nbmax = std::max(64, h.nsub);  // also the row chunks of the whole-array dots (<= 64)
   c->part = dalloc<double>(c, (size_t)nbmax * P);
   c->part2 = dalloc<double>(c, (size_t)nbmax * P);
-  c->osc = dalloc<double>(c, (size_t)2 * P + 8);
+  c->ngchunk = std::max(1, std::min(16, (h.nG + 255) / 256));
+  c->osc = dalloc<double>(c, (size_t)2 * c->ngchunk * P + 8);
   c->sc = dalloc<double>(c, (size_t)nbmax * 8);
   c->flags = dalloc<int>(c, 4);
-  c->goff = upload(c, std::vector<int>{0, h.nG});  // rows of the interface part
+  {  // row chunks of the interface part (one workgroup per chunk and mode)
+    std::vector<int> gc(c->ngchunk + 1);
+    for (int i = 0; i <= c->ngchunk; ++i) gc[i] = (int)((long long)h.nG * i / c->ngchunk);
+    c->goff = upload(c, gc);
+  }
   c->alloff = upload(c, std::vector<int>{0, h.NF});
   {  // about 64 row chunks (one workgroup per chunk and mode in a dot product)
     const int nch = std::max(1, std::min(64, (h.NF + 1023) / 1024));
@@ -1708,7 +1717,8 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     c->acct_h = nullptr;
   if (!c->acct_h) c->acct = nullptr;
   if (hipHostMalloc((void**)&c->hflags, 16 * sizeof(int)) != hipSuccess ||
-      hipHostMalloc((void**)&c->hosc, (2 * (size_t)P + 8) * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hosc, (2 * (size_t)c->ngchunk * P + 8) * sizeof(double)) !=
+          hipSuccess ||
       hipHostMalloc((void**)&c->hpart, 2 * (size_t)c->nfchunk * P * sizeof(double)) !=
           hipSuccess) {
     c->err = "pinned allocation failed";
