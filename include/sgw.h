@@ -224,6 +224,18 @@ int sgw_profile_read(sgw_ctx* ctx, int kind, long long* launches, double* ms,
  * launch shape for that Q).  Enqueues on stream and waits for it. */
 int sgw_autotune(sgw_ctx* ctx, void* stream, double* report, int nreport);
 
+/* Chebyshev preconditioner tile of one subdomain system, set by hand (as
+ * sgw_autotune would keep it): precision = SGW_FP64 (the FP64 systems) or
+ * SGW_FP32_IR64 (the FP32 systems of the refinement path), system = 0
+ * Dirichlet, 1 Neumann; q = modes per workgroup (1..8); shape = 0, 1, 2 for
+ * workgroups of 1024, 512, 256 threads (1, 2 or 4 rows per thread, the
+ * fewest that cover the system's largest block).  Used by the parity tests
+ * of every launch shape.  Returns SGW_EINVAL (context unchanged) when the
+ * combination is not feasible for the system (too many modes for the
+ * registers, LDS above 150 KiB, blocks larger than 4 x the workgroup) or
+ * the FP32 systems do not exist. */
+int sgw_set_cheb_tile(sgw_ctx* ctx, int precision, int system, int q, int shape);
+
 /* Sizes and counters: what = 0 P, 1 number of input PCE terms, 2 free
  * nodes, 3 interface nodes (n_gamma), 4 corner nodes, 5 subdomains,
  * 6 (n+1)^2, 7 training samples recorded since sgw_guess_record,

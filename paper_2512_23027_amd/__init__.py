@@ -30,7 +30,7 @@ EXPORTS = ["sgw_create", "sgw_factor", "sgw_set_state", "sgw_get_state",
            "sgw_profile_read", "sgw_autotune", "sgw_mlp_create", "sgw_mlp_destroy",
            "sgw_mlp_last_error", "sgw_mlp_num_params", "sgw_mlp_params", "sgw_mlp_forward",
            "sgw_mlp_loss_grad", "sgw_mlp_train", "sgw_guess_record", "sgw_set_guess_model",
-           "sgw_step_batch"]
+           "sgw_step_batch", "sgw_set_cheb_tile"]
 NOT_INT = ("sgw_query", "sgw_last_error", "sgw_mlp_last_error", "sgw_mlp_num_params")
 
 
@@ -98,6 +98,7 @@ def lib():
         L.sgw_destroy.argtypes = [vp]
         L.sgw_profile.argtypes = [vp, ip]
         L.sgw_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ip]
+        L.sgw_set_cheb_tile.argtypes = [vp, ip, ip, ip, ip]
         L.sgw_profile_read.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong),
                                        ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]
@@ -277,6 +278,12 @@ class Solver:
         self._check(lib().sgw_profile_read(self.ctx, kind, ctypes.byref(n), ctypes.byref(ms),
                                            ctypes.byref(b)), "sgw_profile_read")
         return n.value, ms.value, b.value
+
+    def set_cheb_tile(self, precision, system, q, shape):
+        """Chebyshev tile of one subdomain system (0 Dirichlet, 1 Neumann):
+        q modes per workgroup, launch shape 0/1/2 = 1024/512/256 threads."""
+        return self._check(lib().sgw_set_cheb_tile(self.ctx, precision, system, q, shape),
+                           "sgw_set_cheb_tile")
 
     def autotune(self):
         """Pick the fastest launch shapes; returns the timing report (us)."""

@@ -1492,6 +1492,30 @@ int sgw_autotune(sgw_ctx* c, void* stream, double* report, int nreport) {
   return 0;
 }
 
+int sgw_set_cheb_tile(sgw_ctx* c, int precision, int system, int q, int shape) {
+  if (!c) return SGW_EINVAL;
+  auto set = [&](auto& S) -> int {
+    using T = std::remove_reference_t<decltype(*S.r)>;
+    if (q < 1 || q > c->P || q > k::cheb_max_q<T>(S.max_block_rows, shape) ||
+        k::cheb_lds_bytes<T>(S.max_block_rows, q, shape) > 150 * 1024) {
+      c->err = "Chebyshev tile not feasible for this system";
+      return SGW_EINVAL;
+    }
+    S.cq = q;
+    S.cshape = shape;
+    return 0;
+  };
+  if (system != 0 && system != 1) {
+    c->err = "system must be 0 (Dirichlet) or 1 (Neumann)";
+    return SGW_EINVAL;
+  }
+  if (precision == SGW_FP64) return system == 0 ? set(c->d64.D) : set(c->d64.N);
+  if (precision == SGW_FP32_IR64 && c->f32.ready)
+    return system == 0 ? set(c->f32.D) : set(c->f32.N);
+  c->err = "no such precision in this context";
+  return SGW_EINVAL;
+}
+
 int sgw_destroy(sgw_ctx* c) {
   if (!c) return 0;
   (void)hipDeviceSynchronize();

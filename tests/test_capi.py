@@ -82,6 +82,7 @@ def test_null_arguments(L):
     assert L.sgw_create(None, None, None) == -1
     assert L.sgw_step(None, 1, None, None) == -1
     assert L.sgw_query(None, 0) == -1
+    assert L.sgw_set_cheb_tile(None, 0, 0, 1, 0) == -1
 
 
 @pytest.mark.parametrize("field,value", [("inner_prec", 7), ("cheb_degree", 65),

@@ -30,9 +30,11 @@ def sgw():
     return m
 
 
-def _trajectory(sgw, prm, nsteps, rtol, every=10, **kw):
+def _trajectory(sgw, prm, nsteps, rtol, every=10, prep=None, **kw):
     s = sgw.Solver(prm, rtol=rtol, inner_rtol=rtol * 1e-2, **kw)
     s.factor()
+    if prep:
+        prep(s)
     s.set_state()
     ref = SGProblem(prm)
     U, V, A = ref.initial_state()
@@ -147,6 +149,43 @@ def test_chebyshev_degrees(sgw, deg):
     prm = workloads.config("cfg1")
     (em, es), _ = _trajectory(sgw, prm, 20, 1e-12, inner_prec=1, cheb_degree=deg)
     assert em < 1e-10 and es < 1e-10, (em, es)
+
+
+def _cheb_tiles(sgw, precision, shape, qs):
+    """Set the first feasible q of qs with the given launch shape on both
+    subdomain systems (a system the shape cannot cover keeps its tile)."""
+    kept = []
+    def prep(s):
+        for system in (0, 1):
+            for q in qs:
+                try:
+                    s.set_cheb_tile(precision, system, q, shape)
+                    kept.append((system, q))
+                    break
+                except sgw.SGWError:
+                    continue
+    return prep, kept
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("ragged", [False, True])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_chebyshev_launch_shapes(sgw, precision, shape, ragged):
+    """Every launch shape of the Chebyshev kernel (1024, 512, 256 threads;
+    blocks of 961 and 1089 rows give 1, 2 or 4 rows per thread) with the
+    largest feasible mode tile, or a tile that does not divide P = 6."""
+    prm = workloads.config("cfg1", n=64, xsplits=workloads.uniform_splits(64, 2),
+                           ysplits=workloads.uniform_splits(64, 2))
+    qs = [4, 5, 1] if ragged else [8, 7, 6, 5, 4, 3, 2, 1]
+    prep, kept = _cheb_tiles(sgw, precision, shape, qs)
+    if precision == 0:
+        (em, es), _ = _trajectory(sgw, prm, 10, 1e-12, every=5, prep=prep, inner_prec=1)
+        assert em < 1e-10 and es < 1e-10, (em, es)
+    else:
+        (em, es), _ = _trajectory(sgw, prm, 10, 1e-10, every=5, prep=prep, inner_prec=1,
+                                  precision=sgw.SGW_FP32_IR64)
+        assert em < 1e-6 and es < 1e-6, (em, es)
+    assert kept and kept[0][0] == 0, kept  # the Dirichlet system took the shape
 
 
 def test_sigma_zero_modes_stay_zero(sgw):
