@@ -12,7 +12,7 @@ is excluded and reported separately.
 
 Default solver: FP32 DD-PCG inside FP64 iterative refinement of the whole SG
 system (relative SG residual <= 1e-8 per step; FP32 interface PCG and
-Dirichlet solves to 1e-5, Neumann solves to 1e-3), Chebyshev subdomain
+Dirichlet solves to 3e-5, Neumann solves to 1e-2), Chebyshev subdomain
 preconditioner of degree 8, Newmark-extrapolated initial guess.
 --precision fp64 runs the plain FP64 DD-PCG instead.
 
@@ -123,11 +123,11 @@ def solver_settings(precision="mixed"):
                     inner_rtol=1e-12, precond_rtol=1e-4, inner_prec=sgw.SGW_INNER_CHEBYSHEV,
                     cheb_degree=8)
     # refinement sweeps: FP32 interface PCG and Dirichlet solves to 3e-5,
-    # Neumann solves to 3e-3 (500 steps stay within 3e-7 of the oracle; the
-    # tighter 1e-5 / 1e-5 / 1e-3 gives 9e-8 at 7% fewer steps per second)
+    # Neumann solves to 1e-2 (500 steps stay within 3.3e-7 of the oracle; the
+    # tighter 1e-5 / 1e-5 / 1e-3 gives 9e-8 at 10% fewer steps per second)
     return dict(precision=sgw.SGW_FP32_IR64, guess=sgw.SGW_GUESS_NEWMARK, rtol=1e-8,
                 inner_rtol=1e-11, precond_rtol=1e-4, inner_prec=sgw.SGW_INNER_CHEBYSHEV,
-                cheb_degree=8, ir_rtols=(3e-5, 3e-5, 3e-3))
+                cheb_degree=8, ir_rtols=(3e-5, 3e-5, 1e-2))
 
 
 def copy_calibration(nbytes=1 << 30, reps=10):
