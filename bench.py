@@ -261,7 +261,8 @@ def main():
                                       "avg_launch_us": 1e3 * v[1] / v[0],
                                       "GB/s": (v[2] / (v[1] * 1e-3)) / 1e9}
                     for k, v in prof.items() if v[0] > 0},
-        "kernel_timing": "HIP events around every %dth launch of each kind in the timed steps"
+        "kernel_timing": "HIP events around every %dth launch of each kind in the timed steps "
+                         "(the Chebyshev launches record theirs at the kernel's start and end)"
                          % PROFILE_EVERY,
     }
     if not args.no_cpu_baseline:

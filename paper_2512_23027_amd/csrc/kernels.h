@@ -125,7 +125,9 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
 // first does the PCG stopping test of iteration par (r'r from rrpart, see
 // pcg_test) and skips converged blocks.  With acct != null, every active workgroup adds its algorithmic
 // bytes (right-hand sides in and out, the block's mean matrix once) to
-// *acct.  Returns -1 (nothing launched) if Q, the shape, deg or the block
+// *acct.  With ev0 and ev1 the launch itself records them at the kernel's
+// start and end (timing without the dispatch).  Returns -1 (nothing
+// launched) if Q, the shape, deg or the block
 // size is out of range (max_rows <= 4 x the workgroup size, Q <= cheb_max_q,
 // deg <= 64, cheb_lds_bytes <= 150 KiB).
 template <typename T>
@@ -149,7 +151,8 @@ int cheb_apply(const T* cval, const int* row_off, const int* order, const int* c
                const unsigned short* cnb, const T* coef, int nb, int P, int deg,
                int Q, int shape, int max_rows, const T* r, int ldr, T* z, int ldz,
                double* part, double* part2, double* sc, int par, double tol2,
-               const double* rrpart, int* flags, unsigned long long* acct, hipStream_t st);
+               const double* rrpart, int* flags, unsigned long long* acct, hipStream_t st,
+               hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Segmented dot products: partial[b * P + j] = sum_{r in block b} a[j][r] b[j][r]
 // (row_off relative to the vectors; a second vector pair is optional).

@@ -8,6 +8,8 @@
 // the lane that owns the row.
 #include "kernels.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <type_traits>
 #include <cstdio>
@@ -1233,6 +1235,7 @@ struct ChebTest {  // optional fused stopping test (sc == nullptr: none), block 
   double tol2;
   const double* rrpart;
   int* flags;
+  hipEvent_t ev0, ev1;  // timing events recorded by the launch itself (may be null)
 };
 
 struct ChebArgs {
@@ -1251,7 +1254,16 @@ struct ChebArgs {
 template <typename T, int Q, int RPT, int TPB>
 static void launch_cheb(const T* cval, const ChebArgs& a, const ChebTest& t, hipStream_t st) {
   dim3 grid(a.nb, ceil_div(a.P, Q));
-  k_cheb<T, Q, RPT, TPB><<<grid, TPB, cheb_lds_bytes<T>(a.max_rows, Q, a.shape), st>>>(
+  const unsigned lds = (unsigned)cheb_lds_bytes<T>(a.max_rows, Q, a.shape);
+  if (t.ev0) {  // the dispatch records the events: kernel start and end
+    hipExtLaunchKernelGGL(k_cheb<T, Q, RPT, TPB>, grid, dim3(TPB), lds, st, t.ev0, t.ev1, 0u,
+                          cval, a.row_off, t.order, a.crow, a.cnb,
+                          static_cast<const T*>(a.coef), a.P, a.deg,
+                          static_cast<const T*>(a.r), a.ldr, static_cast<T*>(a.z), a.ldz,
+                          a.part, a.part2, t.sc, t.par, t.tol2, t.rrpart, t.flags, t.acct);
+    return;
+  }
+  k_cheb<T, Q, RPT, TPB><<<grid, TPB, lds, st>>>(
       cval, a.row_off, t.order, a.crow, a.cnb, static_cast<const T*>(a.coef), a.P, a.deg,
       static_cast<const T*>(a.r), a.ldr, static_cast<T*>(a.z), a.ldz, a.part, a.part2, t.sc,
       t.par, t.tol2, t.rrpart, t.flags, t.acct);
@@ -1327,12 +1339,13 @@ int cheb_apply(const T* cval, const int* row_off, const int* order, const int* c
                const unsigned short* cnb, const T* coef, int nb, int P, int deg,
                int Q, int shape, int max_rows, const T* r, int ldr, T* z, int ldz,
                double* part, double* part2, double* sc, int par, double tol2,
-               const double* rrpart, int* flags, unsigned long long* acct, hipStream_t st) {
+               const double* rrpart, int* flags, unsigned long long* acct, hipStream_t st,
+               hipEvent_t ev0, hipEvent_t ev1) {
   if (Q < 1 || Q > cheb_max_q<T>(max_rows, shape) || deg < 1 || deg > CHEB_MAX_DEG ||
       max_rows < 1 || cheb_lds_bytes<T>(max_rows, Q, shape) > 150 * 1024 ||
       (sc && (!rrpart || !flags)) || !crow || !cnb || !coef || !cval)
     return -1;
-  const ChebTest t{order, acct, sc, par, tol2, rrpart, flags};
+  const ChebTest t{order, acct, sc, par, tol2, rrpart, flags, ev1 ? ev0 : nullptr, ev1};
   const ChebArgs a{row_off, crow, cnb, coef, nb, P, deg, max_rows, shape, r, ldr, z, ldz,
                    part, part2};
   const int rpt = cheb_rpt(max_rows, shape);
@@ -1458,12 +1471,12 @@ template int cheb_apply<double>(const double*, const int*, const int*, const int
                                 const unsigned short*, const double*, int, int, int,
                                 int, int, int, const double*, int, double*, int, double*, double*,
                                 double*, int, double, const double*, int*, unsigned long long*,
-                                hipStream_t);
+                                hipStream_t, hipEvent_t, hipEvent_t);
 template int cheb_apply<float>(const float*, const int*, const int*, const int*,
                                const unsigned short*, const float*, int, int, int,
                                int, int, int, const float*, int, float*, int, double*, double*,
                                double*, int, double, const double*, int*, unsigned long long*,
-                               hipStream_t);
+                               hipStream_t, hipEvent_t, hipEvent_t);
 template size_t tri_lds_bytes<float>(const DFactor&, int);
 #define SGW_INST(T)                                                                          \
   template void sg_apply<T>(const DEll<T>&, const GTab&, const DHalo*, int, int, const T*,    \

@@ -317,7 +317,9 @@ static k::DFactor upload_factor(sgw_ctx* c, const Factor& f) {
 // kernel timing (sgw_profile): a HIP event pair around each timed launch,
 // harvested at the host synchronisation points the solver has anyway.
 // ---------------------------------------------------------------------------
-static int prof_begin(sgw_ctx* c, int kind, hipStream_t st) {
+// record = false: the caller's launch records the pair itself (at the
+// kernel's start and end, hipExtLaunchKernelGGL).
+static int prof_begin(sgw_ctx* c, int kind, hipStream_t st, bool record = true) {
   if (!c->prof) return -1;
   if (c->pseen[kind]++ % c->prof_every != 0) return -1;
   int a = (int)c->pend.size() * 2;
@@ -326,12 +328,13 @@ static int prof_begin(sgw_ctx* c, int kind, hipStream_t st) {
     if (hipEventCreate(&e) != hipSuccess) return -1;
     c->ev.push_back(e);
   }
-  (void)hipEventRecord(c->ev[a], st);
+  if (record) (void)hipEventRecord(c->ev[a], st);
   return a;
 }
-static void prof_end(sgw_ctx* c, int a, int kind, double bytes, hipStream_t st) {
+static void prof_end(sgw_ctx* c, int a, int kind, double bytes, hipStream_t st,
+                     bool record = true) {
   if (a < 0) return;
-  (void)hipEventRecord(c->ev[a + 1], st);
+  if (record) (void)hipEventRecord(c->ev[a + 1], st);
   c->pend.push_back({a, kind, bytes});
 }
 // Before a stream synchronisation: the device byte counters are copied on
@@ -401,15 +404,17 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
   const int P = c->P, n = S.nrows;
   if (c->inner_prec == SGW_INNER_CHEBYSHEV) {
     const int kind = sizeof(T) == 4 ? 5 : 2;
-    int a = prof_begin(c, kind, st);
+    int a = prof_begin(c, kind, st, false);
     // timed launches count their bytes on the device (converged blocks are
-    // skipped inside the kernel); harvested into the kind's total
+    // skipped inside the kernel; harvested into the kind's total) and record
+    // their event pair at the kernel's start and end
     (void)k::cheb_apply<T>(S.cval, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, P,
                            c->cheb_deg,
                            S.cq, S.cshape, S.max_block_rows, S.r, n, S.z, n, part, part2,
                            test_par >= 0 ? c->sc : nullptr, std::max(test_par, 0), tol2,
-                           c->part2, c->flags, a >= 0 ? c->acct + (sizeof(T) == 4) : nullptr, st);
-    prof_end(c, a, kind, 0.0, st);
+                           c->part2, c->flags, a >= 0 ? c->acct + (sizeof(T) == 4) : nullptr, st,
+                           a >= 0 ? c->ev[a] : nullptr, a >= 0 ? c->ev[a + 1] : nullptr);
+    prof_end(c, a, kind, 0.0, st, false);
     return;
   }
   if (test_par >= 0) k::pcg_test(S.nb, P, test_par, c->part2, c->sc, tol2, c->flags, st);
