@@ -262,7 +262,7 @@ def main():
                                       "GB/s": (v[2] / (v[1] * 1e-3)) / 1e9}
                     for k, v in prof.items() if v[0] > 0},
         "kernel_timing": "HIP events around every %dth launch of each kind in the timed steps "
-                         "(the Chebyshev launches record theirs at the kernel's start and end)"
+                         "(the Chebyshev launches have theirs recorded with their dispatch)"
                          % PROFILE_EVERY,
     }
     if not args.no_cpu_baseline:

@@ -189,8 +189,8 @@ int sgw_solve(sgw_ctx* ctx, const double* F, double* U, void* stream,
  * apply (kind 0), the batched subdomain triangular solves (kind 1) and the
  * Chebyshev preconditioner (kind 2) in FP64, kinds 3, 4, 5 the same in
  * FP32; it clears the counters.  enable == 0 stops recording.  Adds two
- * event records per timed launch (the Chebyshev launches record theirs
- * themselves, at the kernel's start and end). */
+ * event records per timed launch (the Chebyshev launches have theirs
+ * recorded with the kernel's dispatch, hipExtLaunchKernelGGL). */
 int sgw_profile(sgw_ctx* ctx, int enable);
 
 /* Timed launches, their total kernel milliseconds and total algorithmic

@@ -125,8 +125,8 @@ void tri_solve(const DFactor& f, int Q, const T* rhs, int ldr, T* out,
 // first does the PCG stopping test of iteration par (r'r from rrpart, see
 // pcg_test) and skips converged blocks.  With acct != null, every active workgroup adds its algorithmic
 // bytes (right-hand sides in and out, the block's mean matrix once) to
-// *acct.  With ev0 and ev1 the launch itself records them at the kernel's
-// start and end (timing without the dispatch).  Returns -1 (nothing
+// *acct.  With ev0 and ev1 the launch records them with the kernel's
+// dispatch (hipExtLaunchKernelGGL).  Returns -1 (nothing
 // launched) if Q, the shape, deg or the block
 // size is out of range (max_rows <= 4 x the workgroup size, Q <= cheb_max_q,
 // deg <= 64, cheb_lds_bytes <= 150 KiB).

@@ -317,8 +317,8 @@ static k::DFactor upload_factor(sgw_ctx* c, const Factor& f) {
 // kernel timing (sgw_profile): a HIP event pair around each timed launch,
 // harvested at the host synchronisation points the solver has anyway.
 // ---------------------------------------------------------------------------
-// record = false: the caller's launch records the pair itself (at the
-// kernel's start and end, hipExtLaunchKernelGGL).
+// record = false: the caller's launch records the pair itself
+// (hipExtLaunchKernelGGL, with the kernel's dispatch).
 static int prof_begin(sgw_ctx* c, int kind, hipStream_t st, bool record = true) {
   if (!c->prof) return -1;
   if (c->pseen[kind]++ % c->prof_every != 0) return -1;
@@ -406,8 +406,8 @@ static void precond_dot(sgw_ctx* c, SysT<T>& S, bool neumann, double* part, doub
     const int kind = sizeof(T) == 4 ? 5 : 2;
     int a = prof_begin(c, kind, st, false);
     // timed launches count their bytes on the device (converged blocks are
-    // skipped inside the kernel; harvested into the kind's total) and record
-    // their event pair at the kernel's start and end
+    // skipped inside the kernel; harvested into the kind's total) and have
+    // their event pair recorded by the launch itself
     (void)k::cheb_apply<T>(S.cval, S.row_off, S.lpt, S.crow, S.cnb, S.cheb_cc, S.nb, P,
                            c->cheb_deg,
                            S.cq, S.cshape, S.max_block_rows, S.r, n, S.z, n, part, part2,
