@@ -1,32 +1,37 @@
 #!/usr/bin/env python
 """Benchmark of the SG-DD-PCG hot path on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): 256x256 P1
-mesh (66,049 nodes), 8x8 subdomains, KLE 4 terms, sigma 0.3, correlation
-length 0.3, PCE order 3 (P = 35, 2.28 M unknowns), dt = 1e-3, rtol 1e-8,
-pulse centre drawn from seed 2.  A step is one Newmark time step of the whole
-hot path (effective force, condensation, interface PCG with the two-level
-NN preconditioner and its subdomain solves, recovery, update) with the state
-resident in HBM.  Set-up (mesh, KLE/PCE, factors, coarse grid, autotuning)
-is excluded and reported separately.
+Workload (default, the largest configuration; one GPU holds it): 512x512 P1
+mesh (263,169 nodes), 16x16 subdomains, KLE 8 terms, sigma 0.3, correlation
+length 0.25, PCE order 3 (P = 165, 43.1 M SG unknowns), dt = 1e-3, rtol
+1e-8, pulse centre drawn from seed 5.  A step is one Newmark time step of
+the whole hot path (effective force, condensation, interface PCG with the
+two-level NN preconditioner and its batched subdomain solves, recovery,
+update) with the state resident in HBM.  Set-up (mesh, KLE/PCE, factors,
+coarse grid, autotuning) is excluded and reported separately.
 
-Default solver: FP32 DD-PCG inside FP64 iterative refinement of the whole SG
-system (relative SG residual <= 1e-8 per step; FP32 interface PCG and
-Dirichlet solves to 3e-5, Neumann solves to 1e-2), Chebyshev subdomain
-preconditioner of degree 8, Newmark-extrapolated initial guess.
---precision fp64 runs the plain FP64 DD-PCG instead.
+Two solver stacks run on the same GPU, one after the other:
+* full stack (the headline value): FP32 DD-PCG inside FP64 iterative
+  refinement of the whole SG system (relative SG residual <= 1e-8 per
+  step; FP32 interface PCG and Dirichlet solves to 3e-5, Neumann solves to
+  1e-2), batched subdomain solves with the degree-8 Chebyshev mean-matrix
+  preconditioner and autotuned tiles, Newmark-extrapolated initial guess;
+* plain FP64 DD-PCG (the paper's method: previous-solution guess, FP64
+  throughout, interface rtol 1e-9).
+--workload cfg2 runs the 256x256, P = 35 configuration instead.
 
 Prints one JSON line.  Extra legs:
-* accuracy: the state after 2 steps is compared with the oracle's, computed
-  here; the states after the warm-up and after the timed steps are compared
-  with the stored oracle values (tests/golden/cfg2_oracle.txt) when those
-  steps were recorded there (defaults: steps 10 and 200).  Relative L2 of
-  the mean and standard-deviation fields;
-* roofline: per-launch HIP event timing of the SG apply and the subdomain
-  triangular solves inside the timed region; the dominant one is reported
-  against the 8 TB/s HBM peak;
-* cpu_baseline: the oracle (numpy/scipy, mean-preconditioned CG) timed on
-  the host for the first three steps.
+* accuracy: after the timed steps each stack restarts from the initial state
+  and runs to the last stored oracle step; the mean and standard-deviation
+  fields over all mesh nodes are compared with the stored oracle values
+  (tests/golden/<workload>_oracle.npz, written from the oracle alone) at every
+  stored step (relative L2);
+* roofline: per-launch HIP event timing of the kernel kinds inside the timed
+  region; the dominant one is reported against its roofline (HBM bytes or
+  FP32 vector arithmetic, whichever bounds it);
+* cpu_baseline: the oracle (numpy/scipy FP64, mean-preconditioned CG, no
+  domain decomposition) on the host: a bounded sample of its first time step
+  (see cpu_baseline()).
 
 --copy-calibration runs only a plain device copy of known size (the
 reference kernel for scaling HBM traffic counters).
@@ -35,6 +40,7 @@ reference kernel for scaling HBM traffic counters).
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -43,6 +49,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SG-DD-PCG time-steps/s at ≤1e-6 rel err vs FP64 oracle; PCG iters/step; GB/s"
 HBM_PEAK_GBS = 8000.0
+# MI355X vector peaks (256 CUs, 2.4 GHz): FP64 78.6 TFLOP/s; FP32 157.3 TFLOP/s
+# with packed (two-per-lane) FMAs, which this build does not emit, so its
+# FP32 code can reach at most the 78.6 of one FMA per lane per clock
+FP32_VECTOR_PEAK_TFS = 157.3
+FP64_VECTOR_PEAK_TFS = 78.6
 KERNEL_NAMES = {0: "k1 SG operator apply, FP64 (K1)",
                 1: "k_tri_solve batched supernodal triangular solves, FP64 (K3)",
                 2: "k_cheb Chebyshev subdomain preconditioner, FP64 (K3c)",
@@ -51,43 +62,48 @@ KERNEL_NAMES = {0: "k1 SG operator apply, FP64 (K1)",
                 5: "k_cheb Chebyshev subdomain preconditioner, FP32 (K3c)"}
 PROFILE_EVERY = 5    # time every 5th launch of each kind (event records cost time)
 
-
-KERNEL_SOURCES = {0: ("k1_spec.inc",), 3: ("k1_spec.inc",)}  # others: kernels.hip
-
-
-def kernel_sources_digest(kernel_kind):
-    """sha256 over the source file(s) of a kernel kind (the generated SG-apply
-    kernels, or kernels.hip): HBM counters recorded for other sources are
-    stale."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES.get(kernel_kind, ("kernels.hip",)):
-        h.update(open(os.path.join(ROOT, "paper_2512_23027_amd", "csrc", name), "rb").read())
-    return h.hexdigest()
+WORKLOADS = {
+    "cfg5": "cfg5: 512x512 P1 mesh (263,169 nodes), 16x16 subdomains, KLE 8 terms, sigma 0.3, "
+            "corr. length 0.25, PCE order 3 (P=165, 43.1M SG unknowns), dt 1e-3, pulse seed 5",
+    "cfg2": "cfg2: 256x256 P1 mesh (66,049 nodes), 8x8 subdomains, KLE 4 terms, sigma 0.3, "
+            "corr. length 0.3, PCE order 3 (P=35, 2.28M SG unknowns), dt 1e-3, pulse seed 2",
+}
 
 
-def traffic_from_profiles(kernel_kind):
-    """HBM bytes per launch measured by rocprofv3 counters, if recorded for
-    the current kernel sources (profiles/traffic_*.txt), else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_k%d_cfg2.txt" % kernel_kind)
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel_sources_sha256") != kernel_sources_digest(kernel_kind):
-        return None
+def sg_apply_counts(prm):
+    """(algorithmic bytes per row of one FP32 SG apply in a subdomain PCG
+    iteration, flops per row): 7 (M+1) matrix values + 7 column indices +
+    p_old and z in, p and q out (P modes each), 4-byte values; flops =
+    2 (7 |KJ| + nnz(c)) with |KJ| the distinct (k, j) pairs of the Galerkin
+    tensor (each W_kj = K_k x_j costs 7 FMAs, each tensor entry one FMA)."""
+    from paper_2512_23027_amd import gen_k1
+    nk, P, ent = gen_k1.entries(prm["L"], prm["p_in"], prm["p_out"])
+    kj = {(e[0], e[2]) for e in ent}
+    bpr = 7 * nk * 4 + 7 * 4 + 4 * P * 4
+    fpr = 2 * (7 * len(kj) + len(ent))
+    return bpr, fpr
+
+
+def cpu_model():
     try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
-def cpu_baseline(prm, nsteps, record):
-    """The oracle timed on the host for the first nsteps steps; returns the
-    moments after step record too."""
+def cpu_baseline(prm, golden_steps):
+    """The oracle on the host, on a bounded sample of the same workload.
+
+    Full oracle steps take minutes at the largest size, so the sample is its
+    first time step's conjugate-gradient work, timed for as many CG
+    iterations as fit in about 20 s: each CG iteration is one SG operator
+    apply plus one mean-matrix preconditioner solve (the oracle's own
+    apply_Kt and factor), and a step costs the per-step iteration count the
+    oracle reports for this workload (its golden run).  Returns the rate in
+    time-steps/s."""
     import numpy as np
     from oracle.sg import SGProblem
     threads = 1
@@ -98,23 +114,31 @@ def cpu_baseline(prm, nsteps, record):
         pass
     pr = SGProblem(prm, solver="cg")
     U, V, A = pr.initial_state()
-    t0 = time.perf_counter()
-    spent = 0.0
-    for n in range(1, nsteps + 1):
-        U, V, A = pr.step(U, V, A)
-        if n == record:
-            spent -= time.perf_counter()
-            mean, std = pr.moments(U)
-            spent += time.perf_counter()
-    dt = time.perf_counter() - t0 - spent
-    return {"value": nsteps / dt, "unit": "time-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d time steps of the same workload (numpy/scipy FP64, CG with "
-                      "the mean-matrix preconditioner to 1e-14, no domain decomposition)"
-                      % nsteps}, mean, std
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(pr.Kt[0].tocsc())
+    its, t0 = 0, time.perf_counter()
+    while True:  # the two operations of a CG iteration on the step's vectors
+        Q = pr.apply_Kt(U)
+        lu.solve(Q)
+        its += 1
+        if time.perf_counter() - t0 > 20.0:
+            break
+    per_it = (time.perf_counter() - t0) / its
+    cg_per_step = golden_steps.get("cg_iterations_per_step")
+    if not cg_per_step:
+        return None
+    return {"value": 1.0 / (per_it * cg_per_step), "unit": "time-steps/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "threads_note": "%d BLAS threads in the dense Galerkin contractions; scipy's sparse "
+                            "products and triangular solves run on one thread" % threads,
+            "sample": "%d CG iterations (SG operator apply + mean-matrix preconditioner solve, "
+                      "%.2f s each) of the oracle's first time step, scaled by the %.1f CG "
+                      "iterations per step the oracle takes on this workload"
+                      % (its, per_it, cg_per_step)}
 
 
 def solver_settings(precision="mixed"):
-    """Solver options of the timed configuration."""
+    """Solver options of the two timed stacks."""
     import paper_2512_23027_amd as sgw
     if precision == "fp64":
         # the nominal 1e-8 leaves the standard deviation of the first steps
@@ -123,8 +147,8 @@ def solver_settings(precision="mixed"):
                     inner_rtol=1e-12, precond_rtol=1e-4, inner_prec=sgw.SGW_INNER_CHEBYSHEV,
                     cheb_degree=8)
     # refinement sweeps: FP32 interface PCG and Dirichlet solves to 3e-5,
-    # Neumann solves to 1e-2 (500 steps stay within 3.3e-7 of the oracle; the
-    # tighter 1e-5 / 1e-5 / 1e-3 gives 9e-8 at 10% fewer steps per second)
+    # Neumann solves to 1e-2 (500 steps of the 256x256 workload stay within
+    # 3.3e-7 of the oracle)
     return dict(precision=sgw.SGW_FP32_IR64, guess=sgw.SGW_GUESS_NEWMARK, rtol=1e-8,
                 inner_rtol=1e-11, precond_rtol=1e-4, inner_prec=sgw.SGW_INNER_CHEBYSHEV,
                 cheb_degree=8, ir_rtols=(3e-5, 3e-5, 1e-2))
@@ -141,137 +165,181 @@ def copy_calibration(nbytes=1 << 30, reps=10):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}))
 
 
-def golden_errors(step, mean, std):
-    """Errors against the stored oracle values of step, or None."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
+def load_golden(name):
+    """{step: (mean, std)} of the stored oracle run, and its metadata."""
     import numpy as np
-    import golden_cfg2
-    g = golden_cfg2.load()
-    if step not in g:
-        return None
-    sub = golden_cfg2.subgrid(256)
-    _, _, gm, gs = g[step]
-    return {"step": step, "source": "stored oracle (sub-grid of every 16th node)",
-            "mean": float(np.linalg.norm(mean[sub] - gm) / np.linalg.norm(gm)),
-            "std": float(np.linalg.norm(std[sub] - gs) / np.linalg.norm(gs))}
+    path = os.path.join(ROOT, "tests", "golden", "%s_oracle.npz" % name)
+    if not os.path.exists(path):
+        return {}, {}
+    z = np.load(path, allow_pickle=False)
+    out = {int(s): (z["mean_%d" % s], z["std_%d" % s]) for s in z["steps"]}
+    meta = {}
+    if "cg_iterations" in z.files:
+        meta["cg_iterations_per_step"] = float(np.mean(z["cg_iterations"]))
+    return out, meta
+
+
+def run_stack(sgw, prm, opts, warm, steps, golden, log):
+    """Set up one solver stack, time `steps` steps after `warm` warm-up steps,
+    then rerun from the initial state to the stored oracle steps."""
+    import numpy as np
+    import torch
+    from oracle.sg import rel_l2
+    t0 = time.perf_counter()
+    s = sgw.Solver(prm, **opts)
+    log("context created (%.1f s)" % (time.perf_counter() - t0))
+    s.factor()
+    log("coarse grid factored (%.1f s)" % (time.perf_counter() - t0))
+    tune = s.autotune()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log("autotuned; set-up %.1f s" % setup_s)
+    s.set_state()
+    if warm:
+        s.step(warm)
+    torch.cuda.synchronize()
+    s.profile(True, every=PROFILE_EVERY)
+    t1 = time.perf_counter()
+    st = s.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    prof = {k: s.profile_read(k) for k in range(6)}
+    s.profile(False)
+    log("timed %d steps: %.3f s" % (steps, elapsed))
+    errors = []
+    if golden:
+        s.set_state()
+        done = 0
+        for step in sorted(golden):
+            s.step(step - done)
+            done = step
+            m, v = s.moments()
+            gm, gs = golden[step]
+            errors.append({"step": step, "mean": rel_l2(m.cpu().numpy(), gm),
+                           "std": rel_l2(np.sqrt(v.cpu().numpy()), gs)})
+        log("accuracy: %s" % errors)
+    s.close()
+    return {"steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+            "pcg_iters_per_step": st["outer_iters"] / st["steps"],
+            "inner_iters_per_step": st["inner_iters"] / st["steps"],
+            "ir_sweeps_per_step": st["ir_sweeps"] / st["steps"], "setup_s": setup_s,
+            "autotune_us": tune, "prof": prof, "errors": errors}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=190)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cfg5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 stack")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--print-kernel-digest", type=int, default=None, metavar="KIND")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
-        return
-    if args.print_kernel_digest is not None:
-        print(kernel_sources_digest(args.print_kernel_digest))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the domain decomposition would shard by blocks of subdomains)",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2512_23027_amd as sgw
     import workloads
-    from oracle.sg import rel_l2
+
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    prm = workloads.config("cfg2")
-    warm = max(args.warmup, 2)
-    opts = solver_settings(args.precision)
-    t0 = time.perf_counter()
-    s = sgw.Solver(prm, **opts)
-    s.factor()
-    tune = s.autotune()
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
+    prm = workloads.config(args.workload)
+    golden, gmeta = load_golden(args.workload)
+    log("workload %s, stored oracle steps %s" % (args.workload, sorted(golden)))
+    full = run_stack(sgw, prm, solver_settings("mixed"), args.warmup, args.steps, golden, log)
+    plain = None
+    if not args.no_fp64:
+        plain = run_stack(sgw, prm, solver_settings("fp64"), args.warmup, args.steps, golden,
+                          log)
 
-    def moments():
-        m, v = s.moments()
-        return m.cpu().numpy(), np.sqrt(v.cpu().numpy())
-
-    s.set_state()
-    s.step(2)
-    mean2, std2 = moments()
-    errors = []
-    if warm > 2:
-        s.step(warm - 2)
-        e = golden_errors(warm, *moments())
-        if e:
-            errors.append(e)
-    torch.cuda.synchronize()
-    s.profile(True, every=PROFILE_EVERY)
-    t1 = time.perf_counter()
-    st = s.step(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t1
-    prof = {k: s.profile_read(k) for k in range(6)}
-    s.profile(False)
-    e = golden_errors(warm + args.steps, *moments())
-    if e:
-        errors.append(e)
-    s.close()
-    mixed = args.precision == "mixed"
-
+    prof = full["prof"]
     kdom = max(prof, key=lambda k: prof[k][1])
     n_l, ms, nbytes = prof[kdom]
-    achieved = (nbytes / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
-    traffic = traffic_from_profiles(kdom)
+    avg_s = ms * 1e-3 / max(n_l, 1)
+    bytes_per_launch = nbytes / max(n_l, 1)
+    gbs = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": KERNEL_NAMES[kdom], "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "timed_launches": n_l, "avg_launch_us": 1e6 * avg_s,
+            "algorithmic_bytes_per_launch": bytes_per_launch}
+    if kdom in (0, 3):
+        # the SG apply: bytes and flops per row; ALU-bound when the flops
+        # take longer at the vector peak than the bytes at the HBM peak
+        bpr, fpr = sg_apply_counts(prm)
+        w = 4 if kdom == 3 else 8
+        bpr = bpr if w == 4 else bpr * 2 - 7 * 4
+        flops = bytes_per_launch / bpr * fpr
+        tfs = flops / avg_s / 1e12 if avg_s > 0 else 0.0
+        peak = FP32_VECTOR_PEAK_TFS if w == 4 else FP64_VECTOR_PEAK_TFS
+        roof["flops_per_launch"] = flops
+        roof["hbm_frac"] = roof["frac"]
+        roof["alu_tflops"] = tfs
+        if flops / (peak * 1e12) > bytes_per_launch / (HBM_PEAK_GBS * 1e9):
+            roof.update({"bound": "alu", "achieved": tfs, "peak": peak, "unit": "TFLOP/s",
+                         "frac": tfs / peak,
+                         "note": "FP32 peak counts packed (two per lane) FMAs, which this "
+                                 "build does not emit (one FMA per lane per clock: 78.6)"
+                         if w == 4 else "FP64 vector peak"})
+    errs = full["errors"]
     out = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": full["steps_per_s"],
         "unit": "time-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": warm,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": full["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64-refinement" if mixed else "f64",
+        "dtype": "f32+f64-refinement",
         "data": "synthetic",
-        "config": {"workload": "cfg2: 256x256 P1 mesh (66,049 nodes), 8x8 subdomains, KLE 4 "
-                               "terms, sigma 0.3, corr. length 0.3, PCE order 3 (P=35, 2.28M "
-                               "unknowns), dt 1e-3, " + (
-                                   "FP32 DD-PCG in FP64 iterative refinement to SG residual "
-                                   "1e-8, Newmark-extrapolated guess" if mixed else
-                                   "FP64 DD-PCG, interface rtol 1e-9 (preconditioner solves 1e-4)"),
-                   "global_batch": 1, "precision": args.precision},
-        "pcg_iters_per_step": st["outer_iters"] / st["steps"],
-        "inner_iters_per_step": st["inner_iters"] / st["steps"],
-        "ir_sweeps_per_step": st["ir_sweeps"] / st["steps"],
-        "setup_s": setup_s,
-        "autotune_us": tune,
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[kdom],
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "timed_launches": n_l, "avg_launch_us": 1e3 * ms / max(n_l, 1),
-                     "algorithmic_bytes_per_launch": nbytes / max(n_l, 1)},
+        "config": {"workload": WORKLOADS[args.workload] + "; full stack: FP32 DD-PCG in FP64 "
+                   "iterative refinement to SG residual 1e-8, batched Chebyshev-preconditioned "
+                   "subdomain solves, autotuned tiles, Newmark-extrapolated guess",
+                   "global_batch": 1},
+        "pcg_iters_per_step": full["pcg_iters_per_step"],
+        "inner_iters_per_step": full["inner_iters_per_step"],
+        "ir_sweeps_per_step": full["ir_sweeps_per_step"],
+        "setup_s": full["setup_s"],
+        "roofline": roof,
         "kernels": {KERNEL_NAMES[k]: {"timed_launches": v[0], "ms": v[1],
                                       "avg_launch_us": 1e3 * v[1] / v[0],
                                       "GB/s": (v[2] / (v[1] * 1e-3)) / 1e9}
                     for k, v in prof.items() if v[0] > 0},
         "kernel_timing": "HIP events around every %dth launch of each kind in the timed steps "
-                         "(the Chebyshev launches have theirs recorded with their dispatch)"
-                         % PROFILE_EVERY,
+                         "(the Chebyshev launches have theirs recorded with their dispatch); "
+                         "bytes of the fused SG-apply and Chebyshev launches counted on the "
+                         "device over the rows they process" % PROFILE_EVERY,
+        "rel_err_vs_oracle": errs,
     }
+    if plain is not None:
+        out["plain_fp64_same_gpu"] = {
+            "value": plain["steps_per_s"], "ms_per_step": plain["ms_per_step"],
+            "pcg_iters_per_step": plain["pcg_iters_per_step"],
+            "inner_iters_per_step": plain["inner_iters_per_step"], "setup_s": plain["setup_s"],
+            "config": "FP64 DD-PCG (interface rtol 1e-9, Neumann solves 1e-4), previous-solution "
+                      "guess, batched Chebyshev-preconditioned subdomain solves",
+            "rel_err_vs_oracle": plain["errors"]}
+        out["speedup_vs_plain_fp64"] = full["steps_per_s"] / plain["steps_per_s"]
     if not args.no_cpu_baseline:
-        cb, m_or, s_or = cpu_baseline(prm, 3, record=2)
-        out["cpu_baseline"] = cb
-        errors.insert(0, {"step": 2, "source": "oracle run here (all nodes)",
-                          "mean": rel_l2(mean2, m_or), "std": rel_l2(std2, s_or)})
-    out["rel_err_vs_oracle"] = errors
-    out["accuracy_ok"] = bool(errors) and all(max(e["mean"], e["std"]) <= 1e-6 for e in errors)
+        cb = cpu_baseline(prm, gmeta)
+        if cb:
+            out["cpu_baseline"] = cb
+    ok = bool(errs) and all(max(e["mean"], e["std"]) <= 1e-6 for e in errs)
+    if plain is not None and plain["errors"]:
+        ok = ok and all(max(e["mean"], e["std"]) <= 1e-6 for e in plain["errors"])
+    out["accuracy_ok"] = ok
     print(json.dumps(out), flush=True)
 
 

@@ -58,6 +58,17 @@ enum { SGW_HOST = 0, SGW_DEVICE = 1 };
 enum { SGW_FP64 = 0, SGW_FP32_IR64 = 1 };
 enum { SGW_GUESS_PREV = 0, SGW_GUESS_NEWMARK = 1, SGW_GUESS_LEARNED = 2 };
 enum { SGW_INNER_CHOLESKY = 0, SGW_INNER_CHEBYSHEV = 1 };
+/* Interface preconditioner (Sec. 5; the one-level variants are those the
+ * paper compares in Sec. 6.1, defined in the thesis it cites):
+ * SGW_PRECOND_NN2: the two-level Neumann-Neumann preconditioner with the
+ *   corner coarse grid (Eq. NNCP2);
+ * SGW_PRECOND_NN1: one-level Neumann-Neumann, sum_s R_s^T D_s S_s^{-1} D_s R_s
+ *   with each subdomain's whole local (Neumann) problem, corners included,
+ *   and no coarse grid (the mass term keeps every local problem
+ *   nonsingular, so no floating-subdomain treatment is needed);
+ * SGW_PRECOND_LUMPED: one-level lumped, S_s^{-1} replaced by the inverse of
+ *   the subdomain's interface block (K~^s_GG)^{-1}. */
+enum { SGW_PRECOND_NN2 = 0, SGW_PRECOND_NN1 = 1, SGW_PRECOND_LUMPED = 2 };
 
 /* Problem description.  Fields follow the paper's problem statement:
  * Eq. CovarKer2D_chapt2 (sigma, bx, by), Eq. KLEchapt2 (L), Eq. c0pce
@@ -97,6 +108,7 @@ typedef struct sgw_problem_desc {
   int graphs;            /* != 0: subdomain PCG iterations that need no host check run
                             as replays of captured HIP graphs (pairs of iterations);
                             results are identical, timing kernels (sgw_profile) off */
+  int precond;           /* interface preconditioner, SGW_PRECOND_* (0: two-level NN) */
 } sgw_problem_desc;
 
 /* Optional device allocator.  alloc returns device memory of >= bytes
@@ -240,43 +252,47 @@ int sgw_set_cheb_tile(sgw_ctx* ctx, int precision, int system, int q, int shape)
 /* Sizes and counters: what = 0 P, 1 number of input PCE terms, 2 free
  * nodes, 3 interface nodes (n_gamma), 4 corner nodes, 5 subdomains,
  * 6 (n+1)^2, 7 training samples recorded since sgw_guess_record,
- * 8 learned guesses replaced by the Newmark guess, 9 graph replays. */
+ * 8 learned guesses replaced by the Newmark guess, 9 graph replays,
+ * 10 samples in the store of sgw_guess_train. */
 long long sgw_query(const sgw_ctx* ctx, int what);
 
 /* ---- Learned initial guess of the interface PCG ----------------------
  * The paper starts each step's interface PCG from the previous solution
  * (Alg. 1).  SGW_GUESS_LEARNED starts it from the Newmark extrapolation
- * g = U_n + dt V_n + dt^2/2 A_n plus a correction predicted by a small
- * network from the last four converged interface solutions; the PCG still
- * runs to the same tolerance, so the guess only changes the iteration
- * count.  One network serves every PCE mode j: its input is the 4 x n_gamma
- * history of mode j (oldest first) divided by s_j = max_i |u_n^j(i)|, its
- * output the correction (u_{n+1} - g) / s_j.  Layers n_in = 4 n_gamma ->
- * hidden (ReLU) -> hidden (ReLU) -> n_gamma; FP32 master parameters, BF16
- * weights in the matrix products (MFMA, FP32 accumulation), Adam.
- * Fallbacks to g: fewer than four past steps, no model attached, a
- * non-finite prediction, or an initial residual larger than that of the
- * zero guess. */
+ * g_{n+1} = U_n + dt V_n + dt^2/2 A_n plus a correction predicted by a small
+ * network; the PCG still runs to the same tolerance, so the guess only
+ * changes the iteration count.  The network is shared by every interface
+ * node i and PCE mode j: its input row is the history of the node's last
+ * four converged interface values, taken as their deviations from the
+ * Newmark extrapolations made at those steps, c_m = u_m - g_m for
+ * m = n-3..n (oldest first), divided by s_j = max_i |c_n^j(i)|; its output
+ * is the next deviation c_{n+1} / s_j.  One forward pass takes the
+ * n_gamma x P rows of a step.  Layers 4 -> hidden (ReLU) -> hidden (ReLU) ->
+ * 1; FP32 master parameters, BF16 weights in the matrix products (MFMA, FP32
+ * accumulation), Adam.  Fallbacks to g: fewer than four past steps, no
+ * model attached, a non-finite prediction, or an initial residual larger
+ * than that of the zero guess. */
 typedef struct sgw_mlp sgw_mlp;
 
-/* New network for interfaces of n_gamma nodes (He-uniform weights from the
- * counter-based generator splitmix64 seeded with seed; the last layer is
- * scaled by 0.1; zero biases).  Device memory from alloc (may be NULL).
- * Errors: SGW_EINVAL, SGW_ENOMEM, SGW_EHIP. */
-int sgw_mlp_create(int n_gamma, int hidden, unsigned long long seed,
+/* New perceptron n_in -> hidden (ReLU) -> hidden (ReLU) -> n_out
+ * (He-uniform weights from the counter-based generator splitmix64 seeded
+ * with seed; the last layer is scaled by 0.1; zero biases).  The solver's
+ * guess needs n_in = 4, n_out = 1.  Device memory from alloc (may be
+ * NULL).  Errors: SGW_EINVAL, SGW_ENOMEM, SGW_EHIP. */
+int sgw_mlp_create(int n_in, int n_out, int hidden, unsigned long long seed,
                    const sgw_allocator* alloc, sgw_mlp** out);
 int sgw_mlp_destroy(sgw_mlp* m);
 const char* sgw_mlp_last_error(const sgw_mlp* m);
-/* Number of parameters: layout [W1 (hidden x 4 n_gamma, row-major), b1,
- * W2 (hidden x hidden), b2, W3 (n_gamma x hidden), b3]. */
+/* Number of parameters: layout [W1 (hidden x n_in, row-major), b1,
+ * W2 (hidden x hidden), b2, W3 (n_out x hidden), b3]. */
 long long sgw_mlp_num_params(const sgw_mlp* m);
 /* Copy the FP32 parameters out (set = 0) or in (set != 0; also refreshes
  * the BF16 copies and clears the Adam moments); w in memory `where`. */
 int sgw_mlp_params(sgw_mlp* m, float* w, int set, int where, void* stream);
-/* y[nb][n_gamma] = network(x[nb][4 n_gamma]), device arrays; waits for the
+/* y[nb][n_out] = network(x[nb][n_in]), device arrays; waits for the
  * stream. */
 int sgw_mlp_forward(sgw_mlp* m, const float* x, float* y, int nb, void* stream);
-/* Mean squared error of the network on (x[nb][4 n_gamma], t[nb][n_gamma])
+/* Mean squared error of the network on (x[nb][n_in], t[nb][n_out])
  * (host *loss) and its gradient with respect to the parameters (device
  * grad[num_params], may be NULL); waits for the stream. */
 int sgw_mlp_loss_grad(sgw_mlp* m, const float* x, const float* t, int nb,
@@ -290,16 +306,45 @@ int sgw_mlp_train(sgw_mlp* m, const float* x, const float* t, int nsamples,
                   void* stream, float* final_loss);
 
 /* Record training samples from this context's trajectory: every later step
- * with four past steps appends P samples (one per mode) -- input rows to
- * X[capacity][4 n_gamma], targets to T[capacity][n_gamma], device FP32 --
- * while room is left.  X = T = NULL stops recording.  The count is
- * sgw_query(ctx, 7).  The caller keeps X and T alive while recording. */
+ * with four past steps appends n_gamma x P samples (mode-major, one per
+ * (mode, interface node)) -- input rows to X[capacity][4], targets to
+ * T[capacity], device FP32 -- while room is left.  X = T = NULL stops
+ * recording.  The count is sgw_query(ctx, 7).  The caller keeps X and T
+ * alive while recording. */
 int sgw_guess_record(sgw_ctx* ctx, float* X, float* T, long long capacity);
 
-/* Attach the network used by SGW_GUESS_LEARNED (NULL detaches); its
- * n_gamma must equal the context's interface size.  The context does not
- * own it. */
+/* Attach the network used by SGW_GUESS_LEARNED (NULL detaches); it must
+ * have n_in = 4 and n_out = 1.  The context does not own it. */
 int sgw_set_guess_model(sgw_ctx* ctx, sgw_mlp* m);
+
+/* Initial interface guess of later steps, SGW_GUESS_* (replaces the one
+ * given at create).  Errors: SGW_EINVAL. */
+int sgw_set_guess(sgw_ctx* ctx, int mode);
+
+/* Training of the attached network on the solver's own trajectories, in
+ * one call: the context advances nsteps steps from its current state
+ * (sgw_set_state chooses the trajectory; the steps use the context's guess
+ * mode), recording every step's samples into a store the context owns
+ * (device memory from its allocator; samples of earlier calls are kept
+ * unless clear != 0), then, if epochs > 0, trains the attached network with
+ * Adam on every stored sample (sgw_mlp_train with these parameters).
+ * *final_loss (may be NULL) receives the mean loss of the last epoch.
+ * Errors: SGW_ESTATE (no model attached, no state, not factored),
+ * SGW_EINVAL, SGW_ENOMEM, and those of sgw_step. */
+typedef struct sgw_train_desc {
+  int nsteps;               /* steps to record (>= 0) */
+  int clear;                /* != 0: drop the samples of earlier calls first */
+  int epochs, batch;        /* training passes and minibatch size (epochs 0: record only) */
+  double lr;                /* Adam step */
+  unsigned long long seed;  /* minibatch shuffling */
+} sgw_train_desc;
+int sgw_guess_train(sgw_ctx* ctx, const sgw_train_desc* td, void* stream,
+                    float* final_loss);
+
+/* The chaos coefficients of the current displacement U (Eq. uPCE),
+ * mode-major [P][(n+1)^2] in memory `where` (same as the U of
+ * sgw_get_state). */
+int sgw_read_pce(sgw_ctx* ctx, double* U, int where, void* stream);
 
 const char* sgw_last_error(const sgw_ctx* ctx);
 int sgw_destroy(sgw_ctx* ctx);

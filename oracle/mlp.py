@@ -11,10 +11,10 @@ GPU's matrix cores see them; with ``bf16=False`` it is the exact float64
 network, whose backward pass is pinned by central finite differences of its
 forward pass (tests/test_oracle_mlp.py).
 
-Network: x (n, 4 n_gamma) -> h1 = relu(x W1^T + b1) -> h2 = relu(h1 W2^T + b2)
--> y = h2 W3^T + b3 (n, n_gamma); loss = mean((y - t)^2) over all entries.
-Parameter vector layout: [W1 (H x 4 n_gamma, row-major), b1, W2 (H x H), b2,
-W3 (n_gamma x H), b3].
+Network: x (n, n_in) -> h1 = relu(x W1^T + b1) -> h2 = relu(h1 W2^T + b2)
+-> y = h2 W3^T + b3 (n, n_out); loss = mean((y - t)^2) over all entries.
+Parameter vector layout: [W1 (H x n_in, row-major), b1, W2 (H x H), b2,
+W3 (n_out x H), b3].
 """
 
 import numpy as np
@@ -28,10 +28,10 @@ def round_bf16(a):
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def unpack(w, n_gamma, hidden):
+def unpack(w, n_in, n_out, hidden):
     """Split the parameter vector into (W1, b1, W2, b2, W3, b3)."""
     w = np.asarray(w, dtype=np.float64)
-    ni, H, ng = 4 * n_gamma, hidden, n_gamma
+    ni, H, ng = n_in, hidden, n_out
     sizes = [H * ni, H, H * H, H, ng * H, ng]
     parts, o = [], 0
     for s in sizes:
@@ -48,9 +48,9 @@ def _mm(a, b, bf16):
     return a @ b
 
 
-def forward(w, x, n_gamma, hidden, bf16=False):
+def forward(w, x, n_in, n_out, hidden, bf16=False):
     """Outputs y and the hidden activations (h1, h2)."""
-    W1, b1, W2, b2, W3, b3 = unpack(w, n_gamma, hidden)
+    W1, b1, W2, b2, W3, b3 = unpack(w, n_in, n_out, hidden)
     x = np.asarray(x, dtype=np.float64)
     h1 = np.maximum(_mm(x, W1.T, bf16) + b1, 0.0)
     h2 = np.maximum(_mm(h1, W2.T, bf16) + b2, 0.0)
@@ -58,12 +58,12 @@ def forward(w, x, n_gamma, hidden, bf16=False):
     return y, (h1, h2)
 
 
-def loss_grad(w, x, t, n_gamma, hidden, bf16=False):
+def loss_grad(w, x, t, n_in, n_out, hidden, bf16=False):
     """Mean squared error and its gradient in the parameter layout."""
-    W1, b1, W2, b2, W3, b3 = unpack(w, n_gamma, hidden)
+    W1, b1, W2, b2, W3, b3 = unpack(w, n_in, n_out, hidden)
     x = np.asarray(x, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)
-    y, (h1, h2) = forward(w, x, n_gamma, hidden, bf16)
+    y, (h1, h2) = forward(w, x, n_in, n_out, hidden, bf16)
     n = y.size
     e = y - t
     loss = float((e * e).sum() / n)

@@ -147,17 +147,25 @@ class SGProblem:
 
     # -- initial state and stepping ------------------------------------------
     def initial_state(self):
-        """U_0 (pulse in mode 0), V_0 = 0, A_0 from M A_0 = -K U_0 - C V_0."""
+        """U_0 (pulse in mode 0), V_0 = 0, A_0 from M A_0 = -K U_0 - C V_0.
+
+        Random initial conditions (Eq. acous_sto: u_0(x, theta) and
+        v_0(x, theta)) are given by their chaos coefficients in the output
+        basis: ``u0_modes`` / ``v0_modes``, arrays of shape (P, (n+1)^2)
+        over all mesh nodes (mode-major), replacing the pulse / zero."""
         prm, mesh = self.prm, self.mesh
-        if "u0" in prm:
-            u0 = np.asarray(prm["u0"], dtype=np.float64)[mesh.free]
+        U = np.zeros((self.N, self.P))
+        if "u0_modes" in prm:
+            U[:] = np.asarray(prm["u0_modes"], dtype=np.float64)[:, mesh.free].T
+        elif "u0" in prm:
+            U[:, 0] = np.asarray(prm["u0"], dtype=np.float64)[mesh.free]
         else:
             r2 = (mesh.x - prm["x0"]) ** 2 + (mesh.y - prm["y0"]) ** 2
-            u0 = (prm.get("amp", 1.0)
-                  * np.exp(-r2 / (prm["width"] ** 2)))[mesh.free]
-        U = np.zeros((self.N, self.P))
-        U[:, 0] = u0
+            U[:, 0] = (prm.get("amp", 1.0)
+                       * np.exp(-r2 / (prm["width"] ** 2)))[mesh.free]
         V = np.zeros_like(U)
+        if "v0_modes" in prm:
+            V[:] = np.asarray(prm["v0_modes"], dtype=np.float64)[:, mesh.free].T
         if self._mlu is None:
             self._mlu = spla.splu(self.M.tocsc())
         A = self._mlu.solve(-self.apply_K(U) - self.apply_C(V))

@@ -17,6 +17,7 @@ SGW_HOST, SGW_DEVICE = 0, 1
 SGW_FP64, SGW_FP32_IR64 = 0, 1
 SGW_GUESS_PREV, SGW_GUESS_NEWMARK, SGW_GUESS_LEARNED = 0, 1, 2
 SGW_INNER_CHOLESKY, SGW_INNER_CHEBYSHEV = 0, 1
+SGW_PRECOND_NN2, SGW_PRECOND_NN1, SGW_PRECOND_LUMPED = 0, 1, 2
 SGW_NOT_CONVERGED = 1
 
 ERRORS = {-1: "SGW_EINVAL", -2: "SGW_ESTATE", -3: "SGW_ENOMEM",
@@ -30,7 +31,8 @@ EXPORTS = ["sgw_create", "sgw_factor", "sgw_set_state", "sgw_get_state",
            "sgw_profile_read", "sgw_autotune", "sgw_mlp_create", "sgw_mlp_destroy",
            "sgw_mlp_last_error", "sgw_mlp_num_params", "sgw_mlp_params", "sgw_mlp_forward",
            "sgw_mlp_loss_grad", "sgw_mlp_train", "sgw_guess_record", "sgw_set_guess_model",
-           "sgw_step_batch", "sgw_set_cheb_tile"]
+           "sgw_step_batch", "sgw_set_cheb_tile", "sgw_set_guess", "sgw_guess_train",
+           "sgw_read_pce"]
 NOT_INT = ("sgw_query", "sgw_last_error", "sgw_mlp_last_error", "sgw_mlp_num_params")
 
 
@@ -50,7 +52,7 @@ class ProblemDesc(ctypes.Structure):
                 ("precond_rtol", ctypes.c_double), ("inner_prec", ctypes.c_int),
                 ("cheb_degree", ctypes.c_int), ("ir_outer_rtol", ctypes.c_double),
                 ("ir_inner_rtol", ctypes.c_double), ("ir_precond_rtol", ctypes.c_double),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -59,6 +61,11 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 class Allocator(ctypes.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class TrainDesc(ctypes.Structure):
+    _fields_ = [("nsteps", ctypes.c_int), ("clear", ctypes.c_int), ("epochs", ctypes.c_int),
+                ("batch", ctypes.c_int), ("lr", ctypes.c_double), ("seed", ctypes.c_ulonglong)]
 
 
 class StepStats(ctypes.Structure):
@@ -103,7 +110,8 @@ def lib():
                                        ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]
         ull, fp = ctypes.c_ulonglong, ctypes.POINTER(ctypes.c_float)
-        L.sgw_mlp_create.argtypes = [ip, ip, ull, ctypes.POINTER(Allocator), ctypes.POINTER(vp)]
+        L.sgw_mlp_create.argtypes = [ip, ip, ip, ull, ctypes.POINTER(Allocator),
+                                     ctypes.POINTER(vp)]
         L.sgw_mlp_destroy.argtypes = [vp]
         L.sgw_mlp_last_error.argtypes = [vp]
         L.sgw_mlp_last_error.restype = ctypes.c_char_p
@@ -115,6 +123,9 @@ def lib():
         L.sgw_mlp_train.argtypes = [vp, vp, vp, ip, ip, ip, dp, ull, vp, fp]
         L.sgw_guess_record.argtypes = [vp, vp, vp, ctypes.c_longlong]
         L.sgw_set_guess_model.argtypes = [vp, vp]
+        L.sgw_set_guess.argtypes = [vp, ip]
+        L.sgw_guess_train.argtypes = [vp, ctypes.POINTER(TrainDesc), vp, fp]
+        L.sgw_read_pce.argtypes = [vp, vp, ip, vp]
         L.sgw_step_batch.argtypes = [ctypes.POINTER(vp), ip, ip, ctypes.POINTER(vp),
                                      ctypes.POINTER(StepStats), ctypes.POINTER(ip)]
         for name in EXPORTS:
@@ -146,7 +157,8 @@ class Solver:
     def __init__(self, prm, rtol=None, inner_rtol=None, max_iter=1000,
                  inner_max_iter=1000, precision=SGW_FP64, guess=SGW_GUESS_PREV,
                  precond_rtol=None, inner_prec=SGW_INNER_CHOLESKY, cheb_degree=0,
-                 graphs=False, ir_rtols=(0.0, 0.0, 0.0), use_torch_allocator=True):
+                 graphs=False, ir_rtols=(0.0, 0.0, 0.0), precond=SGW_PRECOND_NN2,
+                 use_torch_allocator=True):
         import torch
         self.torch = torch
         L = lib()
@@ -171,6 +183,7 @@ class Solver:
         d.precond_rtol = precond_rtol if precond_rtol is not None else 0.0
         d.inner_prec, d.cheb_degree = inner_prec, cheb_degree
         d.graphs = 1 if graphs else 0
+        d.precond = precond
         d.ir_outer_rtol, d.ir_inner_rtol, d.ir_precond_rtol = ir_rtols
         self.desc = d
         self._live = {}
@@ -225,6 +238,13 @@ class Solver:
         ts = [self._dev(x) if x is not None else None for x in (U, V, A)]
         return self._check(lib().sgw_set_state(self.ctx, *[_ptr(t) for t in ts], SGW_DEVICE,
                                                step, self._stream()), "sgw_set_state")
+
+    def read_pce(self):
+        """Chaos coefficients of the current displacement, [P][(n+1)^2]."""
+        U = self.torch.empty(self.P * self.nn, dtype=self.torch.float64, device="cuda")
+        self._check(lib().sgw_read_pce(self.ctx, _ptr(U), SGW_DEVICE, self._stream()),
+                    "sgw_read_pce")
+        return U.view(self.P, self.nn)
 
     def get_state(self):
         out = [self.torch.empty(self.P * self.nn, dtype=self.torch.float64, device="cuda")
@@ -308,13 +328,14 @@ class Solver:
     # -- learned guess ----------------------------------------------------------
     def record_guess_samples(self, X=None, T=None):
         """Record training samples of later steps into the float32 device
-        tensors X [cap, 4 n_gamma] and T [cap, n_gamma]; no arguments stop."""
+        tensors X [cap, 4] and T [cap] (n_gamma x P rows per step); no
+        arguments stop."""
         if X is None:
             self._rec = None
             return self._check(lib().sgw_guess_record(self.ctx, None, None, 0), "sgw_guess_record")
         assert X.dtype == self.torch.float32 and T.dtype == self.torch.float32
         assert X.is_contiguous() and T.is_contiguous() and X.shape[0] == T.shape[0]
-        assert X.shape[1] == 4 * self.ninterface and T.shape[1] == self.ninterface
+        assert X.shape[1] == 4 and T.dim() == 1
         self._rec = (X, T)  # kept alive while recording
         return self._check(lib().sgw_guess_record(self.ctx, _ptr(X), _ptr(T), X.shape[0]),
                            "sgw_guess_record")
@@ -327,6 +348,23 @@ class Solver:
 
     def graph_launches(self):
         return lib().sgw_query(self.ctx, 9)
+
+    def set_guess(self, mode):
+        """Initial guess mode of later steps (SGW_GUESS_*)."""
+        return self._check(lib().sgw_set_guess(self.ctx, mode), "sgw_set_guess")
+
+    def guess_train(self, nsteps, epochs=0, batch=1024, lr=1e-3, seed=0, clear=False):
+        """Record nsteps steps of this trajectory into the context's sample
+        store, then (epochs > 0) train the attached network on the store;
+        returns the last epoch's mean loss (0 without training)."""
+        td = TrainDesc(nsteps, 1 if clear else 0, epochs, batch, lr, seed)
+        loss = ctypes.c_float()
+        self._check(lib().sgw_guess_train(self.ctx, ctypes.byref(td), self._stream(),
+                                          ctypes.byref(loss)), "sgw_guess_train")
+        return loss.value
+
+    def stored_samples(self):
+        return lib().sgw_query(self.ctx, 10)
 
     def set_guess_model(self, model):
         """Network used when the solver runs with guess=SGW_GUESS_LEARNED."""
@@ -369,13 +407,13 @@ def step_batch(solvers, nsteps=1):
 
 
 class GuessModel:
-    """The learned-guess network (see sgw.h): n_gamma interface nodes,
-    ``hidden`` units in each of the two hidden layers."""
+    """A perceptron n_in -> hidden -> hidden -> n_out (see sgw.h); the
+    solver's learned guess uses the default n_in = 4, n_out = 1."""
 
-    def __init__(self, n_gamma, hidden=256, seed=0, use_torch_allocator=True):
+    def __init__(self, n_in=4, n_out=1, hidden=256, seed=0, use_torch_allocator=True):
         import torch
         self.torch = torch
-        self.n_gamma, self.hidden = n_gamma, hidden
+        self.n_in, self.n_out, self.hidden = n_in, n_out, hidden
         self._live = {}
         al = None
         if use_torch_allocator:
@@ -392,7 +430,7 @@ class GuessModel:
             self._afn, self._ffn = ALLOC_FN(_alloc), FREE_FN(_free)
             al = Allocator(self._afn, self._ffn, None)
         self.m = ctypes.c_void_p()
-        rc = lib().sgw_mlp_create(n_gamma, hidden, seed, ctypes.byref(al) if al else None,
+        rc = lib().sgw_mlp_create(n_in, n_out, hidden, seed, ctypes.byref(al) if al else None,
                                   ctypes.byref(self.m))
         self._check(rc, "sgw_mlp_create")
         self.num_params = lib().sgw_mlp_num_params(self.m)
@@ -423,7 +461,7 @@ class GuessModel:
 
     def forward(self, x):
         x = self._f32(x)
-        y = self.torch.empty(x.shape[0], self.n_gamma, dtype=self.torch.float32, device="cuda")
+        y = self.torch.empty(x.shape[0], self.n_out, dtype=self.torch.float32, device="cuda")
         self._check(lib().sgw_mlp_forward(self.m, _ptr(x), _ptr(y), x.shape[0], self._stream()),
                     "sgw_mlp_forward")
         return y

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace sgw {
 namespace k {
@@ -73,20 +74,27 @@ void sg_apply(const DEll<T>& A, const GTab& g, const DHalo* H, int r0, int nrows
 // Once per process before the first sg_apply: LDS attribute of the
 // generated kernels.  0 on success, -1 on a HIP error.
 int sg_apply_prepare();
-// number of generated (unrolled-tensor) kernels for the basis, one per group
-// of output modes; 0 if none is generated
-int sg_apply_generated(int L, int p_in, int p_out);
+// number of generated (unrolled-tensor) kernels for the basis in a precision
+// (wbytes = 4 or 8 bytes per value), one per group of output modes; 0 if
+// none is generated
+int sg_apply_generated(int L, int p_in, int p_out, int wbytes);
+// whether the generated PCG variant of the basis exists for precision T and
+// its LDS (staged tile of the halo, wave partials) fits the halo H
+template <typename T>
+bool sg_apply_pcg_fits(const GTab& g, const DHalo& H);
 // The SG apply of one subdomain PCG iteration on a block-aligned halo (all
 // nrows rows): p = z + beta_b pold (beta_b = new r'z of block b from rzpart
 // over its old r'z in sc[b*8 + 1 - par], 0 if that is infinite; the new r'z
 // goes to sc[b*8 + par]), pnew = p on every row, q = K~ p, and
 // pqg[g*K + k] = p'q over the rows of group g and the output modes of
-// generated kernel k (K = sg_apply_generated(...)).  Returns false (nothing launched) if
+// generated kernel k (K = sg_apply_generated(...)).  With acct != null every
+// active row group adds its rows times bpr (algorithmic bytes per row) to
+// *acct.  Returns false (nothing launched) if
 // no generated kernel fits.
 template <typename T>
 bool sg_apply_pcg(const DEll<T>& A, const GTab& g, const DHalo& H, int nrows, const T* pold,
                   const T* z, T* pnew, int ld, T* q, const double* rzpart, double* sc, int par,
-                  double* pqg, hipStream_t st);
+                  double* pqg, unsigned long long* acct, unsigned bpr, hipStream_t st);
 
 // y[j][r] = beta*y[j][r] + alpha * sum_s M[r, s] x[j][col]  for all P modes.
 template <typename T>
@@ -234,7 +242,6 @@ struct DCoarse {
   const double* cc_val;            // [entry][nk]
   const int *gi_ptr, *gi_k, *gi_j; // Galerkin entries by output mode i
   const double* gi_v;
-  const double* finv;              // dense inverse of F_cc, [(m,c)][(m',c')]
   const int *rem_off, *rem_list;   // remaining torn rows per subdomain
   const int* sc_ptr;               // local corners per subdomain
   const double* phi;               // coarse basis, per subdomain blocks
@@ -247,7 +254,20 @@ struct DCoarse {
 template <typename T>
 void coarse_rhs(const DCoarse& c, const T* r, int ldr, const T* yt, int ldt,
                 double* dc, hipStream_t st);
-void coarse_solve(const DCoarse& c, const double* dc, double* uc, hipStream_t st);
+// Factor of F_cc on the device (see coarse.h): R corner rows, row offsets
+// off (host) in the factor's unknown order w, perm[w] = m * nC + corner of
+// the coarse vectors; per row i the inverse diagonal block linv[i] and its
+// transpose linvT[i] (m_i x m_i), per row i < R-1 the sub-diagonal block
+// b[i] = L_{i+1,i} (m_{i+1} x m_i) and bT[i] = its transpose, all row-major;
+// four work vectors of n.
+struct DCoarseFactor {
+  int R = 0, n = 0;
+  std::vector<int> off;
+  std::vector<const double*> linv, linvT, b, bT;
+  const int* perm = nullptr;
+  double *wd = nullptr, *wy = nullptr, *wt = nullptr, *wx = nullptr;
+};
+void coarse_solve(const DCoarseFactor& f, const double* dc, double* uc, hipStream_t st);
 template <typename T>
 void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt,
                  hipStream_t st);

@@ -7,6 +7,7 @@
 // the Galerkin contraction over the PCE modes runs in registers and LDS of
 // the lane that owns the row.
 #include "kernels.h"
+#include "k1_common.h"
 
 #include <hip/hip_ext.h>
 
@@ -28,31 +29,6 @@ namespace k {
 static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 template <typename T> __device__ __forceinline__ T fmadd(T a, T b, T c) { return fma(a, b, c); }
-
-// Raw buffer access: 128-bit resource (base address, no stride, no range
-// limit) with a per-lane 32-bit byte offset and a wave-uniform byte offset.
-typedef unsigned int sgw_u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xffffffffu,
-                                           0x00020000);
-}
-template <typename T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
-template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-template <> __device__ __forceinline__ int buf_load<int>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-}
-template <typename T> __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int voff, int soff);
-template <> __device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(sgw_u32x2, v), r, voff, soff, 0);
-}
-template <> __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
-}
 
 // ---------------------------------------------------------------------------
 // K1: SG operator apply y_i = sum_k sum_j c_kij K_k x_j (Eq. stok / K_T_Sto).
@@ -131,26 +107,17 @@ __global__ __launch_bounds__(SGW_WAVE) void k_sg_apply(
   }
 }
 
-// Kernels with the Galerkin tensor of a fixed basis unrolled (gen_k1.py).
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i to XCD
-// i % 8), each with its own L2.  This bijection gives XCD x a contiguous
-// range of logical indices, so neighbouring row groups, whose column halos
-// overlap, share an L2.
-__device__ __forceinline__ int xcd_group(int i, int n) {
-  const int nx = 8, x = i % nx, k = i / nx;
-  const int per = n / nx, rem = n % nx;
-  return x * per + min(x, rem) + k;
-}
-
-#include "k1_spec.inc"
+// Kernels with the Galerkin tensor of a fixed basis unrolled (gen_k1.py),
+// compiled in their own translation units (k1_gen_*.hip).
+#include "k1_dispatch.inc"
 
 template <typename T>
 void sg_apply(const DEll<T>& A, const GTab& g, const DHalo* H, int r0, int nrows, const T* x,
               int ldx, T* y, int ldy, T alpha, T beta, int nbatch,
               long long sx, long long sy, hipStream_t st) {
   if (nrows <= 0) return;
+  // the generated kernel when the basis has one and its LDS fits the halo
   if (g.use_spec && H && halo_groups(*H, r0, nrows) > 0 &&
-      (size_t)g.P * H->hmax * sizeof(T) <= 120 * 1024 &&
       sg_apply_specialised<T>(g.L, g.p_in, g.p_out, A, *H, r0, nrows, x, ldx, y, ldy, alpha,
                               beta, nbatch, sx, sy, st))
     return;
@@ -173,19 +140,24 @@ void sg_apply(const DEll<T>& A, const GTab& g, const DHalo* H, int r0, int nrows
 }
 
 int sg_apply_prepare() { return sg_apply_specialised_prepare() ? 0 : -1; }
-int sg_apply_generated(int L, int p_in, int p_out) {
-  return sg_apply_specialised_groups(L, p_in, p_out);
+int sg_apply_generated(int L, int p_in, int p_out, int wbytes) {
+  return sg_apply_specialised_groups(L, p_in, p_out, wbytes);
+}
+
+template <typename T>
+bool sg_apply_pcg_fits(const GTab& g, const DHalo& H) {
+  if (!g.use_spec || H.aligned64 || !H.bgrp) return false;
+  const size_t lds = sg_apply_specialised_lds<T>(g.L, g.p_in, g.p_out, H.hmax, true);
+  return lds > 0 && lds <= 160 * 1024;
 }
 
 template <typename T>
 bool sg_apply_pcg(const DEll<T>& A, const GTab& g, const DHalo& H, int nrows, const T* pold,
                   const T* z, T* pnew, int ld, T* q, const double* rzpart, double* sc, int par,
-                  double* pqg, hipStream_t st) {
-  if (!g.use_spec || H.aligned64 || !H.bgrp || nrows != H.nr ||
-      (size_t)g.P * H.hmax * sizeof(T) > 120 * 1024)
-    return false;
+                  double* pqg, unsigned long long* acct, unsigned bpr, hipStream_t st) {
+  if (!sg_apply_pcg_fits<T>(g, H) || nrows != H.nr) return false;
   return sg_apply_pcg_specialised<T>(g.L, g.p_in, g.p_out, A, H, nrows, pold, z, pnew, ld, q,
-                                     rzpart, sc, par, pqg, st);
+                                     rzpart, sc, par, pqg, acct, bpr, st);
 }
 
 // Deterministic mass apply over all P modes: thread per (row, mode).
@@ -1402,23 +1374,61 @@ void coarse_rhs(const DCoarse& c, const T* r, int ldr, const T* yt, int ldt, dou
     k_coarse_rhs<T><<<(int)((N + wpb - 1) / wpb), SGW_BLOCK, 0, st>>>(c, r, ldr, yt, ldt, dc);
 }
 
-// u_c = F_cc^{-1} d_c: one wave per row; the inverse is symmetric and stored
-// densely, so row `row` is read contiguously by the lanes.
-__global__ __launch_bounds__(SGW_BLOCK) void k_coarse_solve(int n, const double* finv,
-                                                           const double* dc, double* uc) {
+// u_c = F_cc^{-1} d_c with the block-bidiagonal factor F_cc = L L^T of the
+// corner rows (coarse.h): forward y_i = L_ii^{-1} (d_i - B_i y_{i-1}),
+// backward x_i = L_ii^{-T} (y_i - B_{i+1}^T x_{i+1}).  Every step is a dense
+// product with a stored block (the inverse diagonal blocks and their
+// transposes, the sub-diagonal blocks and their transposes, all row-major):
+// one wave per output row, the row read contiguously by the lanes.
+// out[r] = (a ? a[r] : 0) + sign * sum_c M[r][c] v[c], c over the whole row
+// (tri 0), c <= r (tri 1, lower) or c >= r (tri 2, upper).
+__global__ __launch_bounds__(SGW_BLOCK) void k_coarse_gemv(int nr, int nc, const double* M, int ld,
+                                                          const double* v, const double* a,
+                                                          double* out, double sign, int tri) {
   const int row = blockIdx.x * (SGW_BLOCK / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  const double* fr = finv + (size_t)row * n;
+  if (row >= nr) return;
+  const double* mr = M + (size_t)row * ld;
+  const int c0 = tri == 2 ? row : 0, c1 = tri == 1 ? row + 1 : nc;
   double s = 0.0;
-  for (int col = lane; col < n; col += 64) s += fr[col] * dc[col];
+  for (int col = c0 + lane; col < c1; col += 64) s += mr[col] * v[col];
   s = wave_sum(s);
-  if (lane == 0) uc[row] = s;
+  if (lane == 0) out[row] = (a ? a[row] : 0.0) + sign * s;
 }
-void coarse_solve(const DCoarse& c, const double* dc, double* uc, hipStream_t st) {
-  int n = c.nC * c.P;
+__global__ void k_coarse_perm(int n, const int* perm, const double* src, double* dst, int gather) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n) return;
+  if (gather) dst[w] = src[perm[w]];
+  else dst[perm[w]] = src[w];
+}
+void coarse_solve(const DCoarseFactor& f, const double* dc, double* uc, hipStream_t st) {
+  if (f.n <= 0) return;
   const int wpb = SGW_BLOCK / 64;
-  if (n > 0) k_coarse_solve<<<(n + wpb - 1) / wpb, SGW_BLOCK, 0, st>>>(n, c.finv, dc, uc);
+  auto gemv = [&](int nr, int nc, const double* M, const double* v, const double* a, double* out,
+                  double sign, int tri) {
+    k_coarse_gemv<<<(nr + wpb - 1) / wpb, SGW_BLOCK, 0, st>>>(nr, nc, M, nc, v, a, out, sign, tri);
+  };
+  const std::vector<int>& o = f.off;
+  k_coarse_perm<<<(f.n + 255) / 256, 256, 0, st>>>(f.n, f.perm, dc, f.wd, 1);
+  for (int i = 0; i < f.R; ++i) {
+    const int m = o[i + 1] - o[i];
+    const double* t = f.wd + o[i];
+    if (i > 0) {
+      gemv(m, o[i] - o[i - 1], f.b[i - 1], f.wy + o[i - 1], f.wd + o[i], f.wt + o[i], -1.0, 0);
+      t = f.wt + o[i];
+    }
+    gemv(m, m, f.linv[i], t, nullptr, f.wy + o[i], 1.0, 1);
+  }
+  for (int i = f.R - 1; i >= 0; --i) {
+    const int m = o[i + 1] - o[i];
+    const double* t = f.wy + o[i];
+    if (i + 1 < f.R) {
+      gemv(m, o[i + 2] - o[i + 1], f.bT[i], f.wx + o[i + 1], f.wy + o[i], f.wt + o[i], -1.0, 0);
+      t = f.wt + o[i];
+    }
+    gemv(m, m, f.linvT[i], t, nullptr, f.wx + o[i], 1.0, 2);
+  }
+  k_coarse_perm<<<(f.n + 255) / 256, 256, 0, st>>>(f.n, f.perm, f.wx, uc, 0);
 }
 
 // ut[j][rem] += sum_{m, lc} Phi_s[(m, lc)][(j, tr)] uc[m][coarse(lc)]: the
@@ -1490,9 +1500,10 @@ template size_t tri_lds_bytes<float>(const DFactor&, int);
   template void pcg_xr<T>(int, const int*, int, int, double*, T*, int, const T*, int, \
                           T*, int, const T*, int, const double*, double*, int*,            \
                           hipStream_t, const int*, int);                                     \
+  template bool sg_apply_pcg_fits<T>(const GTab&, const DHalo&);                             \
   template bool sg_apply_pcg<T>(const DEll<T>&, const GTab&, const DHalo&, int, const T*,    \
                                 const T*, T*, int, T*, const double*, double*, int, double*, \
-                                hipStream_t);                                                \
+                                unsigned long long*, unsigned, hipStream_t);                 \
   template void pcg_p<T>(int, const int*, int, int, double*, const double*, const T*, int,  \
                          T*, int, hipStream_t);                                              \
   template void fill2d<T>(int, int, T*, int, T, hipStream_t);                               \

@@ -1,13 +1,11 @@
 // Learned initial guess of the interface PCG: a small multilayer perceptron
 // trained on the solver's own trajectories (the C ABI is in sgw.h).
 //
-// One network is shared by all PCE modes: input = the last four interface
-// solutions of one mode (4 x n_gamma values, scaled by the mode's largest
-// magnitude at the latest step), output = the correction to the
-// Newmark-extrapolated guess of the next step, in the same scale.
-// Layers: n_in -> H (ReLU) -> H (ReLU) -> n_gamma.  FP32 master parameters
-// (updated by Adam), BF16 copies of the weight matrices for the matrix
-// products, which run on MFMA with FP32 accumulation.
+// A plain perceptron with two hidden layers: n_in -> H (ReLU) -> H (ReLU) ->
+// n_out, applied to the rows of a batch.  The solver's guess uses n_in = 4,
+// n_out = 1, one row per (PCE mode, interface node) (see sgw.h).  FP32
+// master parameters (updated by Adam), BF16 copies of the weight matrices
+// for the matrix products, which run on MFMA with FP32 accumulation.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,7 +16,7 @@
 #include "sgw.h"
 
 struct sgw_mlp {
-  int ng = 0, nin = 0, H = 0;   // n_gamma, 4 n_gamma, hidden width
+  int ng = 0, nin = 0, H = 0;   // outputs, inputs, hidden width
   long long np = 0;             // number of parameters
   long long off[6] = {0, 0, 0, 0, 0, 0};  // W1 b1 W2 b2 W3 b3 in the parameter vector
   sgw_allocator al{};

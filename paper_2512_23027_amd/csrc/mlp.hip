@@ -238,20 +238,22 @@ int mlp_forward(sgw_mlp* m, const float* x, float* y, int nb, hipStream_t st) {
 
 extern "C" {
 
-int sgw_mlp_create(int n_gamma, int hidden, unsigned long long seed, const sgw_allocator* al,
-                   sgw_mlp** out) {
+int sgw_mlp_create(int n_in, int n_out, int hidden, unsigned long long seed,
+                   const sgw_allocator* al, sgw_mlp** out) {
   if (!out) return SGW_EINVAL;
   *out = nullptr;
-  if (n_gamma <= 0 || hidden <= 0 || hidden > 4096 || n_gamma > (1 << 20)) return SGW_EINVAL;
+  if (n_in <= 0 || n_out <= 0 || hidden <= 0 || hidden > 4096 || n_in > (1 << 22) ||
+      n_out > (1 << 20))
+    return SGW_EINVAL;
   sgw_mlp* m = new sgw_mlp();
   if (al && al->alloc && al->free) {
     m->al = *al;
     m->has_al = true;
   }
-  m->ng = n_gamma;
-  m->nin = 4 * n_gamma;
+  m->ng = n_out;
+  m->nin = n_in;
   m->H = hidden;
-  const long long H = hidden, ni = m->nin, ng = n_gamma;
+  const long long H = hidden, ni = m->nin, ng = n_out;
   const long long sizes[6] = {H * ni, H, H * H, H, ng * H, ng};
   long long o = 0;
   for (int q = 0; q < 6; ++q) {

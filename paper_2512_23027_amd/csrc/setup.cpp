@@ -543,7 +543,9 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
   const int n = d.n;
   if (n < 2 || d.nsx < 1 || d.nsy < 1 || !d.xsplits || !d.ysplits || d.L < 0 ||
       d.p_in < 0 || d.p_out < 0 || !(d.dt > 0) || !(d.zeta > 0) ||
-      (d.L > 0 && (!(d.bx > 0) || !(d.by > 0) || d.sigma < 0))) {
+      (d.L > 0 && (!(d.bx > 0) || !(d.by > 0) || d.sigma < 0)) ||
+      (d.precond != SGW_PRECOND_NN2 && d.precond != SGW_PRECOND_NN1 &&
+       d.precond != SGW_PRECOND_LUMPED)) {
     err = "invalid problem description";
     return SGW_EINVAL;
   }
@@ -637,6 +639,17 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
       mult[i + (n + 1) * j] = (a1 >= 0 ? 2 : 1) * (b1 >= 0 ? 2 : 1);
     }
   auto is_free = [&](int i, int j) { return i > 0 && i < n && j > 0 && j < n; };
+  // corners (cross points of the cut lines) carry the coarse grid of the
+  // two-level preconditioner; the one-level variants have none
+  const bool two_level = d.precond == SGW_PRECOND_NN2;
+  auto is_corner = [&](int v) { return two_level && mult[v] >= 3; };
+  // nodes of a subdomain's local (torn) problem of the preconditioner:
+  // two-level NN every node but the corners, one-level NN all of them,
+  // lumped only the interface nodes (the local interface block K~^s_GG)
+  auto in_torn = [&](int v) {
+    if (d.precond == SGW_PRECOND_LUMPED) return mult[v] >= 2;
+    return !is_corner(v);
+  };
   auto cell_sub = [&](int ci, int cj) {
     int a = int(std::upper_bound(h.xs.begin(), h.xs.end(), ci) - h.xs.begin()) - 1;
     int b = int(std::upper_bound(h.ys.begin(), h.ys.end(), cj) - h.ys.begin()) - 1;
@@ -670,7 +683,7 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
       int gi = (int)h.dd2mesh.size() - h.nI;
       h.mesh2dd[v] = (int)h.dd2mesh.size();
       h.dd2mesh.push_back(v);
-      if (mult[v] >= 3) {
+      if (is_corner(v)) {
         h.g2c.push_back((int)h.c2g.size());
         h.c2g.push_back(gi);
       } else {
@@ -695,7 +708,7 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
       for (int j = h.ys[b]; j <= h.ys[b + 1]; ++j)
         for (int i = h.xs[a]; i <= h.xs[a + 1]; ++i) {
           int v = i + (n + 1) * j;
-          if (is_free(i, j) && mult[v] <= 2) pts.push_back({i, j, v});
+          if (is_free(i, j) && in_torn(v)) pts.push_back({i, j, v});
         }
       std::vector<int> order;
       nested_dissection(pts, 0, order, nsn[s], LEAF);
@@ -735,7 +748,7 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
   std::vector<std::vector<int>> corners(h.nsub);
   for (int v = 0; v < h.nn; ++v) {
     int i = v % (n + 1), j = v / (n + 1);
-    if (!is_free(i, j) || mult[v] < 3) continue;
+    if (!is_free(i, j) || !is_corner(v)) continue;
     for (int s = 0; s < h.nsub; ++s) {
       int a = s % nsx, b = s / nsx;
       if (h.xs[a] <= i && i <= h.xs[a + 1] && h.ys[b] <= j && j <= h.ys[b + 1])
@@ -785,7 +798,7 @@ int build_host(const sgw_problem_desc& d, Host& h, std::string& err) {
             if (ra < h.nI && rb < h.nI) add(h.dir, ra, rb);
             int ta = torn_of(s, ia, ja), tb = torn_of(s, ib, jb);
             if (ta >= 0 && tb >= 0) add(h.neu, ta, tb);
-            if (mult[va] >= 3 && (tb >= 0 || vb == va)) {
+            if (is_corner(va) && (tb >= 0 || vb == va)) {
               int lc = int(std::find(corners[s].begin(), corners[s].end(), va) - corners[s].begin());
               for (int k = 0; k < nk; ++k)
                 crow[s][((size_t)lc * W + sl) * nk + k] +=

@@ -23,6 +23,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "coarse.h"
 #include "kernels.h"
 #include "mlp.h"
 #include "setup.h"
@@ -94,6 +95,7 @@ struct sgw_ctx {
   PrecT<double> d64;
   PrecT<float> f32;
   k::DCoarse co;
+  k::DCoarseFactor cf;  // block-bidiagonal factor of F_cc (sgw_factor)
   double *U = nullptr, *V = nullptr, *A = nullptr, *Um = nullptr, *Uc = nullptr,
          *Wm = nullptr, *F = nullptr, *meshbuf = nullptr, *meshbuf2 = nullptr;
   double *part = nullptr, *part2 = nullptr, *sc = nullptr, *dc = nullptr, *uc = nullptr;
@@ -127,10 +129,11 @@ struct sgw_ctx {
   // algorithmic bytes per kind
   bool prof = false;
   int prof_every = 1;
-  unsigned long long* acct = nullptr;   // device [2]: K3c bytes of timed FP64 / FP32 launches
+  unsigned long long* acct = nullptr;   // device [4]: bytes of timed K3c FP64 / FP32 and
+                                        // fused SG-apply FP64 / FP32 launches (counted by them)
   unsigned long long* acct_h = nullptr; // pinned copy
   bool acct_staged = false;             // acct_h holds the counters (prof_stage)
-  unsigned long long acct_seen[2] = {0, 0};
+  unsigned long long acct_seen[4] = {0, 0, 0, 0};
   long long pseen[6] = {0, 0, 0, 0, 0, 0};
   std::vector<hipEvent_t> ev;
   struct Pend { int a, kind; double bytes; };
@@ -140,7 +143,7 @@ struct sgw_ctx {
   // 64-row group halos of the SG-apply matrices: global system from row 0
   // and from the first interface row, Dirichlet and Neumann systems
   k::DHalo hal_G0, hal_GI, hal_D, hal_N;
-  int k1_generated = 0;        // generated SG-apply kernels of the basis (output groups)
+  int k1_generated[2] = {0, 0};  // generated SG-apply kernels (output groups), FP32 / FP64
   double* pqg = nullptr;       // [groups][P] p'q partials of the fused SG apply
   // learned initial guess: ring of the last 4 converged interface solutions
   // [4][P][nG], the Newmark guess of the current step [P][nG], per-mode
@@ -166,6 +169,9 @@ struct sgw_ctx {
   long long graph_launches = 0;
   float *rec_x = nullptr, *rec_t = nullptr;
   long long rec_cap = 0, rec_n = 0;
+  // sample store of sgw_guess_train: [cap][4] inputs, [cap] targets
+  float *gs_x = nullptr, *gs_t = nullptr;
+  long long gs_cap = 0, gs_n = 0;
   long long guess_fallbacks = 0;  // learned guesses replaced by the Newmark guess
   // subdomain preconditioner: SGW_INNER_* and the Chebyshev degree
   int inner_prec = SGW_INNER_CHOLESKY, cheb_deg = 4;
@@ -202,6 +208,16 @@ static void* dalloc_bytes(sgw_ctx* c, size_t bytes) {
     (void)hipMemset(p, 0, bytes);  // no kernel ever sees uninitialised memory
   }
   return p;
+}
+
+// Releases one allocation of dalloc_bytes before sgw_destroy.
+static void dfree(sgw_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->mem.begin(), c->mem.end(), p);
+  if (it == c->mem.end()) return;
+  c->mem.erase(it);
+  if (c->has_al) c->al.free(p, c->al.user);
+  else (void)hipFree(p);
 }
 
 template <class T>
@@ -341,17 +357,18 @@ static void prof_end(sgw_ctx* c, int a, int kind, double bytes, hipStream_t st,
 // the stream, so the harvest after it needs no copy of its own.
 static void prof_stage(sgw_ctx* c, hipStream_t st) {
   if (c->pend.empty() || !c->acct) return;
-  c->acct_staged = hipMemcpyAsync(c->acct_h, c->acct, 2 * sizeof(unsigned long long),
+  c->acct_staged = hipMemcpyAsync(c->acct_h, c->acct, 4 * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, st) == hipSuccess;
 }
 static void prof_harvest(sgw_ctx* c) {
   if (c->pend.empty()) return;
   const bool staged = c->acct_staged;
   c->acct_staged = false;
-  if (c->acct && (staged || hipMemcpy(c->acct_h, c->acct, 2 * sizeof(unsigned long long),
+  if (c->acct && (staged || hipMemcpy(c->acct_h, c->acct, 4 * sizeof(unsigned long long),
                                       hipMemcpyDeviceToHost) == hipSuccess)) {
-    for (int q = 0; q < 2; ++q) {
-      c->pbytes[q ? 5 : 2] += (double)(c->acct_h[q] - c->acct_seen[q]);
+    static const int kind_of[4] = {2, 5, 0, 3};
+    for (int q = 0; q < 4; ++q) {
+      c->pbytes[kind_of[q]] += (double)(c->acct_h[q] - c->acct_seen[q]);
       c->acct_seen[q] = c->acct_h[q];
     }
   }
@@ -489,8 +506,8 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
   int& predicted = S.last_its[2 * site + (tol >= S.loose_tol ? 1 : 0)];
   // fused iteration: the SG apply also forms p (alternating buffers) and the
   // p'q partial sums (generated kernel on a block-aligned halo)
-  const bool fused = c->gt.use_spec && c->k1_generated > 0 && S.halo && !S.halo->aligned64 &&
-                     (size_t)P * S.halo->hmax * sizeof(T) <= 120 * 1024;
+  const int kgen = c->k1_generated[sizeof(T) == 8];
+  const bool fused = kgen > 0 && S.halo && k::sg_apply_pcg_fits<T>(c->gt, *S.halo);
   k::copy2d<T, T>(P, n, b, ldb, S.r, n, 1.0, st);
   k::fill2d<T>(P, n, S.x, n, T(0), st);
   precond_dot<T>(c, S, neumann, c->part, c->part2, -1, 0.0, st);
@@ -513,13 +530,17 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
     if (fused) {
       T* pold = par ? S.p : S.p2;
       T* pnew = par ? S.p2 : S.p;
+      // timed launches count the algorithmic bytes of the rows they process
+      // (row groups of converged blocks exit at once) on the device:
+      // 7 (M+1) values + 7 column indices + p_old, z in, p, q out per row
       const int a = prof_begin(c, sizeof(T) == 4 ? 3 : 0, s);
+      const unsigned bpr = (unsigned)(7 * c->nk * sizeof(T) + 7 * 4 + 4 * P * sizeof(T));
       (void)k::sg_apply_pcg<T>(S.A, c->gt, *S.halo, n, pold, S.z, pnew, n, S.q, c->part, c->sc,
-                               par, c->pqg, s);
-      prof_end(c, a, sizeof(T) == 4 ? 3 : 0,
-               (7.0 * c->nk * sizeof(T) + 7.0 * 4.0 + 4.0 * P * sizeof(T)) * n, s);
+                               par, c->pqg, a >= 0 ? c->acct + 2 + (sizeof(T) == 4) : nullptr,
+                               bpr, s);
+      prof_end(c, a, sizeof(T) == 4 ? 3 : 0, 0.0, s);
       k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, pnew, n, S.r, n, S.q, n, c->pqg,
-                   c->part2, c->flags, s, S.halo->bgrp, c->k1_generated);
+                   c->part2, c->flags, s, S.halo->bgrp, kgen);
     } else {
       K1<T>(c, S.A, S.halo, 0, n, S.p, n, S.q, n, 1.0, 0.0, s);
       k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr,
@@ -616,7 +637,7 @@ static int precond(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* r, T* z, h
   if (rc < 0) return rc;
   if (c->nC > 0) {
     k::coarse_rhs<T>(c->co, r, NF, pr.Yt, NT, c->dc, st);
-    k::coarse_solve(c->co, c->dc, c->uc, st);
+    k::coarse_solve(c->cf, c->dc, c->uc, st);
     k::coarse_lift<T>(c->co, c->nsub, c->uc, pr.Yt, NT, st);
   }
   k::gather_from_torn<T>(nG, P, c->gam_ptr, c->gam_torn, c->gam_w, c->g2c, pr.Yt, NT, c->uc,
@@ -914,44 +935,6 @@ __global__ void k_basis_store(k::DCoarse co, int lcl, int m, const double* xt, i
     F[(size_t)(m2 * co.maxc + l2) * MP + (m * co.maxc + lcl)] = v;
   }
 }
-
-// dense SPD inverse on the host: Cholesky, then L^{-1}, then L^{-T} L^{-1}
-static bool spd_inverse(std::vector<double>& A, int n) {
-  for (int j = 0; j < n; ++j) {
-    double dsum = A[(size_t)j * n + j];
-    for (int k2 = 0; k2 < j; ++k2) dsum -= A[(size_t)j * n + k2] * A[(size_t)j * n + k2];
-    if (!(dsum > 0.0)) return false;
-    double djj = std::sqrt(dsum);
-    A[(size_t)j * n + j] = djj;
-    for (int i = j + 1; i < n; ++i) {
-      double s = A[(size_t)i * n + j];
-      const double* ai = &A[(size_t)i * n];
-      const double* aj = &A[(size_t)j * n];
-      for (int k2 = 0; k2 < j; ++k2) s -= ai[k2] * aj[k2];
-      A[(size_t)i * n + j] = s / djj;
-    }
-  }
-  // Linv (lower) in place of L
-  std::vector<double> Li((size_t)n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    Li[(size_t)j * n + j] = 1.0 / A[(size_t)j * n + j];
-    for (int i = j + 1; i < n; ++i) {
-      double s = 0.0;
-      for (int k2 = j; k2 < i; ++k2) s -= A[(size_t)i * n + k2] * Li[(size_t)k2 * n + j];
-      Li[(size_t)i * n + j] = s / A[(size_t)i * n + i];
-    }
-  }
-  // Ainv = Li^T Li
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double s = 0.0;
-      for (int k2 = i; k2 < n; ++k2) s += Li[(size_t)k2 * n + i] * Li[(size_t)k2 * n + j];
-      A[(size_t)i * n + j] = s;
-      A[(size_t)j * n + i] = s;
-    }
-  return true;
-}
-
 
 // Device state of one precision: operator values (FP32 copies for the
 // refinement path), system workspaces and interface vectors.
@@ -1331,11 +1314,21 @@ int sgw_guess_record(sgw_ctx* c, float* X, float* T, long long capacity) {
 
 int sgw_set_guess_model(sgw_ctx* c, sgw_mlp* m) {
   if (!c) return SGW_EINVAL;
-  if (m && m->ng != c->nG) {
-    c->err = "the model's n_gamma differs from the number of interface nodes";
+  if (m && (m->nin != 4 || m->ng != 1)) {
+    c->err = "the guess network must map 4 inputs to 1 output";
     return SGW_EINVAL;
   }
   c->mlp = m;
+  return 0;
+}
+
+int sgw_set_guess(sgw_ctx* c, int mode) {
+  if (!c) return SGW_EINVAL;
+  if (mode != SGW_GUESS_PREV && mode != SGW_GUESS_NEWMARK && mode != SGW_GUESS_LEARNED) {
+    c->err = "unknown guess mode";
+    return SGW_EINVAL;
+  }
+  c->h.d.guess = mode;
   return 0;
 }
 
@@ -1352,6 +1345,7 @@ long long sgw_query(const sgw_ctx* c, int what) {
     case 7: return c->rec_n;
     case 8: return c->guess_fallbacks;
     case 9: return c->graph_launches;
+    case 10: return c->gs_n;
     default: return -1;
   }
 }
@@ -1361,11 +1355,9 @@ int sgw_profile(sgw_ctx* c, int enable) {
   prof_harvest(c);
   c->prof = enable != 0;
   c->prof_every = std::max(1, enable);
-  if (c->acct && hipMemcpy(c->acct_h, c->acct, 2 * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost) == hipSuccess) {
-    c->acct_seen[0] = c->acct_h[0];
-    c->acct_seen[1] = c->acct_h[1];
-  }
+  if (c->acct && hipMemcpy(c->acct_h, c->acct, 4 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost) == hipSuccess)
+    for (int q = 0; q < 4; ++q) c->acct_seen[q] = c->acct_h[q];
   for (int k2 = 0; k2 < 6; ++k2) {
     c->pcnt[k2] = 0;
     c->pms[k2] = 0.0;
@@ -1558,6 +1550,7 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   if (!(dd.inner_rtol > 0)) dd.inner_rtol = 1e-3 * dd.rtol;
   if (!(dd.precond_rtol > 0)) dd.precond_rtol = dd.inner_rtol;
   if (dd.cheb_degree <= 0) dd.cheb_degree = 4;
+  if (dd.L == 0) dd.p_in = dd.p_out = 0;  // deterministic medium: one mode, P = 1
   if (!(dd.ir_outer_rtol > 0)) dd.ir_outer_rtol = kIrOuterRtol;
   if (!(dd.ir_inner_rtol > 0)) dd.ir_inner_rtol = kIrInnerRtol;
   if (!(dd.ir_precond_rtol > 0)) dd.ir_precond_rtol = kIrPrecondRtol;
@@ -1608,8 +1601,10 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   c->hal_GI = build_halo(c, h.glob, h.nI);
   c->hal_D = build_halo(c, h.dir, 0, &h.Ioff);
   c->hal_N = build_halo(c, h.neu, 0, &h.Toff);
-  c->k1_generated = k::sg_apply_generated(h.d.L, h.d.p_in, h.d.p_out);
-  c->pqg = dalloc<double>(c, (size_t)P * std::max(c->hal_D.ng, c->hal_N.ng));
+  for (int w = 0; w < 2; ++w)
+    c->k1_generated[w] = k::sg_apply_generated(h.d.L, h.d.p_in, h.d.p_out, w ? 8 : 4);
+  c->pqg = dalloc<double>(c, (size_t)std::max({P, c->k1_generated[0], c->k1_generated[1]}) *
+                                 std::max(c->hal_D.ng, c->hal_N.ng));
   if (k::sg_apply_prepare() != 0) {
     c->err = "hipFuncSetAttribute failed for the SG-apply kernels";
     *out = c;
@@ -1741,8 +1736,8 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     co.max_rem = std::max(co.max_rem, c->rem_off_h[s + 1] - c->rem_off_h[s]);
   c->dc = dalloc<double>(c, (size_t)std::max(1, h.nC * P));
   c->uc = dalloc<double>(c, (size_t)std::max(1, h.nC * P));
-  c->acct = dalloc<unsigned long long>(c, 2);
-  if (hipHostMalloc((void**)&c->acct_h, 2 * sizeof(unsigned long long)) != hipSuccess)
+  c->acct = dalloc<unsigned long long>(c, 4);
+  if (hipHostMalloc((void**)&c->acct_h, 4 * sizeof(unsigned long long)) != hipSuccess)
     c->acct_h = nullptr;
   if (!c->acct_h) c->acct = nullptr;
   if (hipHostMalloc((void**)&c->hflags, 16 * sizeof(int)) != hipSuccess ||
@@ -1799,42 +1794,111 @@ int sgw_factor(sgw_ctx* c, void* stream) {
     std::vector<double> fs((size_t)c->nsub * MP * MP);
     HIPCHK(hipMemcpyAsync(fs.data(), c->fs, fs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    const int n = c->nC * P;
-    std::vector<double> F((size_t)n * n, 0.0);
-    for (int s = 0; s < c->nsub; ++s) {
-      int lc0 = h.sc_ptr[s], ncs = h.sc_ptr[s + 1] - lc0;
-      const double* Fs = &fs[(size_t)s * MP * MP];
+    // coarse unknowns in corner rows (mesh rows of the corners; corners are
+    // numbered in mesh order), inside a row corner by corner with the P
+    // modes of a corner contiguous: F_cc is block tridiagonal over the rows
+    const int nC = c->nC, n1 = h.n + 1;
+    std::vector<int> crow(nC), cpos(nC);
+    CoarseBlocks B;
+    B.off.assign(1, 0);
+    for (int ci = 0, r = -1, last = -1; ci < nC; ++ci) {
+      const int yrow = h.dd2mesh[h.nI + h.c2g[ci]] / n1;
+      if (yrow != last) {
+        if (r >= 0) B.off.push_back(B.off.back() + cpos[ci - 1] * P + P);
+        ++r;
+        last = yrow;
+        cpos[ci] = 0;
+      } else {
+        cpos[ci] = cpos[ci - 1] + 1;
+      }
+      crow[ci] = r;
+      B.R = r + 1;
+    }
+    B.off.push_back(B.off.back() + cpos[nC - 1] * P + P);
+    auto rows_of = [&](int r) { return B.off[r + 1] - B.off[r]; };
+    B.diag.resize(B.R);
+    B.sub.resize(B.R - 1);
+    for (int r = 0; r < B.R; ++r) {
+      B.diag[r].assign((size_t)rows_of(r) * rows_of(r), 0.0);
+      if (r + 1 < B.R) B.sub[r].assign((size_t)rows_of(r + 1) * rows_of(r), 0.0);
+    }
+    // Galerkin entries by (i, j) for the corner self terms K~^s_cc
+    std::vector<std::vector<int>> byij((size_t)P * P);
+    for (size_t e = 0; e < h.g.v.size(); ++e) byij[(size_t)h.g.i[e] * P + h.g.j[e]].push_back((int)e);
+    for (int sd = 0; sd < c->nsub; ++sd) {
+      int lc0 = h.sc_ptr[sd], ncs = h.sc_ptr[sd + 1] - lc0;
+      const double* Fs = &fs[(size_t)sd * MP * MP];
       for (int l2 = 0; l2 < ncs; ++l2)
         for (int m2 = 0; m2 < P; ++m2)
           for (int l1 = 0; l1 < ncs; ++l1)
             for (int m1 = 0; m1 < P; ++m1) {
               double v = Fs[(size_t)(m2 * c->maxc + l2) * MP + (m1 * c->maxc + l1)];
-              if (l2 == l1) {  // K~^s_cc: corners couple only to themselves
-                for (size_t e = 0; e < h.g.v.size(); ++e)
-                  if (h.g.i[e] == m2 && h.g.j[e] == m1)
-                    v += h.g.v[e] * h.cself[(size_t)(lc0 + l2) * c->nk + h.g.k[e]];
+              if (l2 == l1)  // K~^s_cc: corners couple only to themselves
+                for (int e : byij[(size_t)m2 * P + m1])
+                  v += h.g.v[e] * h.cself[(size_t)(lc0 + l2) * c->nk + h.g.k[e]];
+              const int ca = h.sc_coarse[lc0 + l2], cb = h.sc_coarse[lc0 + l1];
+              const int ra = crow[ca], rb = crow[cb];
+              const int wa = cpos[ca] * P + m2, wb = cpos[cb] * P + m1;
+              if (ra == rb) {
+                B.diag[ra][(size_t)wa * rows_of(ra) + wb] += v;
+              } else if (ra == rb + 1) {  // (F + F^T) / 2 of the sub-diagonal block
+                B.sub[rb][(size_t)wa * rows_of(rb) + wb] += 0.5 * v;
+              } else if (rb == ra + 1) {
+                B.sub[ra][(size_t)wb * rows_of(ra) + wa] += 0.5 * v;
+              } else {
+                c->err = "coarse couplings span more than one corner row (not a rectilinear partition)";
+                return SGW_EINVAL;
               }
-              int r = m2 * c->nC + h.sc_coarse[lc0 + l2];
-              int q = m1 * c->nC + h.sc_coarse[lc0 + l1];
-              F[(size_t)r * n + q] += v;
             }
     }
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < i; ++j) {
-        double a = 0.5 * (F[(size_t)i * n + j] + F[(size_t)j * n + i]);
-        F[(size_t)i * n + j] = a;
-        F[(size_t)j * n + i] = a;
-      }
-    if (!spd_inverse(F, n)) {
-      c->err = "coarse matrix F_cc is not positive definite";
-      return SGW_ENOTSPD;
+    for (int r = 0; r < B.R; ++r) {
+      const int m = rows_of(r);
+      std::vector<double>& D = B.diag[r];
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < i; ++j) {
+          const double a = 0.5 * (D[(size_t)i * m + j] + D[(size_t)j * m + i]);
+          D[(size_t)i * m + j] = a;
+          D[(size_t)j * m + i] = a;
+        }
     }
-    double* finv = upload(c, F);
-    if (!finv) {
-      c->err = "device allocation failed (coarse inverse)";
+    std::vector<double>().swap(fs);
+    CoarseFactor CF;
+    const int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (!coarse_factor(B, CF, threads, c->err)) return SGW_ENOTSPD;
+    k::DCoarseFactor& df = c->cf;
+    df.R = CF.R;
+    df.n = nC * P;
+    df.off = CF.off;
+    auto transpose = [](const std::vector<double>& a, int nr, int nc) {
+      std::vector<double> t(a.size());
+      for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nc; ++j) t[(size_t)j * nr + i] = a[(size_t)i * nc + j];
+      return t;
+    };
+    for (int r = 0; r < CF.R; ++r) {
+      const int m = rows_of(r);
+      df.linv.push_back(upload(c, CF.linv[r]));
+      df.linvT.push_back(upload(c, transpose(CF.linv[r], m, m)));
+      if (r + 1 < CF.R) {
+        df.b.push_back(upload(c, CF.b[r]));
+        df.bT.push_back(upload(c, transpose(CF.b[r], rows_of(r + 1), m)));
+      }
+    }
+    std::vector<int> perm(df.n);
+    for (int ci = 0; ci < nC; ++ci)
+      for (int m = 0; m < P; ++m) perm[B.off[crow[ci]] + cpos[ci] * P + m] = m * nC + ci;
+    df.perm = upload(c, perm);
+    df.wd = dalloc<double>(c, df.n);
+    df.wy = dalloc<double>(c, df.n);
+    df.wt = dalloc<double>(c, df.n);
+    df.wx = dalloc<double>(c, df.n);
+    bool ok = df.perm && df.wd && df.wy && df.wt && df.wx;
+    for (auto* v : {&df.linv, &df.linvT, &df.b, &df.bT})
+      for (const double* p : *v) ok = ok && p;
+    if (!ok) {
+      c->err = "device allocation failed (coarse factor)";
       return SGW_ENOMEM;
     }
-    c->co.finv = finv;
     if (c->phif) {  // the FP32 solver's copy of the coarse basis
       const long long tot = c->phi_off_h.back();
       if (tot > 0x7fffffffLL) {
@@ -1850,15 +1914,18 @@ int sgw_factor(sgw_ctx* c, void* stream) {
 }
 
 // ---------------------------------------------------------------------------
-// H3 (learned): the network sees, per PCE mode j, the last four converged
-// interface solutions u_{n-3..n} scaled by s_j = max|u_n^j|; it returns the
-// correction to the Newmark guess g_{n+1} in the same scale.
+// H3 (learned): per PCE mode j and interface node i, the network sees the
+// deviations c_m = u_m - g_m of the last four converged interface values
+// from the Newmark extrapolations made at those steps, scaled by
+// s_j = max_i |c_n^j(i)|, and returns the next deviation in that scale.
 // ---------------------------------------------------------------------------
-__global__ void k_hist_push(int P, int nG, const double* u, int ldu, double* slot) {
+// slot[j][i] = u[j][i] - g[j][i]
+__global__ void k_hist_push(int P, int nG, const double* u, int ldu, const double* g,
+                            double* slot) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (long long)P * nG) return;
   const int j = (int)(q / nG), i = (int)(q % nG);
-  slot[q] = u[(size_t)j * ldu + i];
+  slot[q] = u[(size_t)j * ldu + i] - g[q];
 }
 // s_j = max_i |slot[j][i]| (+ the smallest normal number), one workgroup per mode
 __global__ __launch_bounds__(256) void k_mode_scale(int nG, const double* slot, double* smax) {
@@ -1874,13 +1941,14 @@ __global__ __launch_bounds__(256) void k_mode_scale(int nG, const double* slot, 
   }
   if (threadIdx.x == 0) smax[j] = sh[0] + 2.2250738585072014e-308;
 }
-// x[j][h nG + i] = hist[slot h][j][i] / s_j, h = 0..3 oldest first
+// row (j nG + i) of x: hist[slot h][j][i] / s_j, h = 0..3 oldest first
 __global__ void k_guess_input(int P, int nG, const double* hist, int h0, const double* smax,
                               float* x) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (long long)P * 4 * nG) return;
-  const int j = (int)(q / (4 * nG)), r = (int)(q % (4 * nG));
-  const int h = r / nG, i = r % nG;
+  const long long row = q >> 2;
+  const int h = (int)(q & 3);
+  const int j = (int)(row / nG), i = (int)(row % nG);
   const int slot = (h0 + h) & 3;
   x[q] = (float)(hist[((size_t)slot * P + j) * nG + i] / smax[j]);
 }
@@ -1904,10 +1972,11 @@ __global__ void k_guess_apply(int P, int nG, const double* g, const double* smax
 
 static int grid1(long long n) { return (int)((n + 255) / 256); }
 
-// Appends the interface part of the state u (ld NF) to the history ring.
-static void hist_push(sgw_ctx* c, const double* u, hipStream_t st) {
+// Appends the deviation of the new interface solution (the interface part
+// of u, ld NF) from this step's Newmark guess g to the history ring.
+static void hist_push(sgw_ctx* c, const double* u, const double* g, hipStream_t st) {
   const int P = c->P, nG = c->nG;
-  k_hist_push<<<grid1((long long)P * nG), 256, 0, st>>>(P, nG, u + c->nI, c->NF,
+  k_hist_push<<<grid1((long long)P * nG), 256, 0, st>>>(P, nG, u + c->nI, c->NF, g,
                                                        c->hist + (size_t)c->hist_pos * P * nG);
   c->hist_pos = (c->hist_pos + 1) & 3;
   c->hist_n = std::min(c->hist_n + 1, 4);
@@ -1960,7 +2029,6 @@ int sgw_set_state(sgw_ctx* c, const double* U, const double* V, const double* A,
   // the learned guess starts a new history with this state
   c->hist_n = 0;
   c->hist_pos = 0;
-  hist_push(c, c->U, st);
   HIPCHK(hipStreamSynchronize(st));
   c->stepno = step;
   c->has_state = true;
@@ -2008,13 +2076,14 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
     // correction); the previous solution; or g plus the network's correction
     // (with fewer than 4 past steps or no model attached: g)
     const bool learned = d.guess == SGW_GUESS_LEARNED && c->mlp && c->hist_n >= 4;
-    const bool recording = c->rec_x && c->hist_n >= 4 && c->rec_n + P <= c->rec_cap;
+    const long long rows = (long long)P * nG;  // network rows of a step
+    const bool recording = c->rec_x && c->hist_n >= 4 && c->rec_n + rows <= c->rec_cap;
     k::axpby2d<double>(P, nG, 1.0, c->U + nI, NF, d.dt, c->V + nI, NF, c->gnew, nG, st);
     k::axpby2d<double>(P, nG, 1.0, c->gnew, nG, 0.5 * d.dt * d.dt, c->A + nI, NF, c->gnew, nG,
                        st);
     if (learned || recording) guess_input(c, st);
     if (learned) {
-      int mrc = sgw::mlp_forward(c->mlp, c->mx, c->my, P, st);
+      int mrc = sgw::mlp_forward(c->mlp, c->mx, c->my, (int)rows, st);
       if (mrc < 0) {
         c->err = "learned guess: " + c->mlp->err;
         return mrc;
@@ -2048,13 +2117,13 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
     // H11: training sample (history, correction of the Newmark guess), then
     // the new solution joins the history
     if (recording) {
-      HIPCHK(hipMemcpyAsync(c->rec_x + (size_t)c->rec_n * 4 * nG, c->mx,
-                            (size_t)P * 4 * nG * sizeof(float), hipMemcpyDeviceToDevice, st));
-      k_guess_target<<<grid1((long long)P * nG), 256, 0, st>>>(
-          P, nG, c->d64.X + nI, NF, c->gnew, c->smax, c->rec_t + (size_t)c->rec_n * nG);
-      c->rec_n += P;
+      HIPCHK(hipMemcpyAsync(c->rec_x + (size_t)c->rec_n * 4, c->mx,
+                            (size_t)rows * 4 * sizeof(float), hipMemcpyDeviceToDevice, st));
+      k_guess_target<<<grid1(rows), 256, 0, st>>>(P, nG, c->d64.X + nI, NF, c->gnew, c->smax,
+                                                  c->rec_t + (size_t)c->rec_n);
+      c->rec_n += rows;
     }
-    hist_push(c, c->d64.X, st);
+    hist_push(c, c->d64.X, c->gnew, st);
     // H6: Newmark update
     k::newmark_update(P, NF, NF, c->d64.X, c->Um, c->V, c->A, d.dt, d.zeta, d.gamma, st);
     std::swap(c->U, c->d64.X);
@@ -2109,6 +2178,70 @@ int sgw_step_batch(sgw_ctx** ctx, int n, int nsteps, void** streams, sgw_step_st
     if (rc[i] > 0 && worst == 0) worst = SGW_NOT_CONVERGED;
   }
   return worst;
+}
+
+int sgw_guess_train(sgw_ctx* c, const sgw_train_desc* td, void* stream, float* final_loss) {
+  if (!c || !td || td->nsteps < 0 || td->epochs < 0 || (td->epochs > 0 && td->batch <= 0) ||
+      (td->epochs > 0 && !(td->lr > 0)))
+    return SGW_EINVAL;
+  if (!c->mlp) {
+    c->err = "sgw_guess_train needs a network (sgw_set_guess_model)";
+    return SGW_ESTATE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (td->clear) c->gs_n = 0;
+  const long long rows = (long long)c->P * c->nG;
+  const long long need = c->gs_n + rows * td->nsteps;
+  if (need > c->gs_cap) {  // grow the store, keeping its samples
+    float* nx = dalloc<float>(c, (size_t)need * 4);
+    float* nt = dalloc<float>(c, (size_t)need);
+    if (!nx || !nt) {
+      c->err = "device allocation failed (training samples)";
+      return SGW_ENOMEM;
+    }
+    if (c->gs_n > 0) {
+      HIPCHK(hipMemcpyAsync(nx, c->gs_x, (size_t)c->gs_n * 4 * sizeof(float),
+                            hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(nt, c->gs_t, (size_t)c->gs_n * sizeof(float),
+                            hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    dfree(c, c->gs_x);
+    dfree(c, c->gs_t);
+    c->gs_x = nx;
+    c->gs_t = nt;
+    c->gs_cap = need;
+  }
+  int rc = 0;
+  if (td->nsteps > 0) {
+    c->rec_x = c->gs_x + (size_t)c->gs_n * 4;
+    c->rec_t = c->gs_t + (size_t)c->gs_n;
+    c->rec_cap = c->gs_cap - c->gs_n;
+    c->rec_n = 0;
+    rc = sgw_step(c, td->nsteps, stream, nullptr);
+    c->gs_n += c->rec_n;
+    c->rec_x = c->rec_t = nullptr;
+    c->rec_cap = 0;
+    if (rc < 0) return rc;
+  }
+  if (td->epochs > 0) {
+    if (c->gs_n <= 0 || c->gs_n > 0x7fffffffLL) {
+      c->err = "no training samples (or more than 2^31)";
+      return SGW_EINVAL;
+    }
+    int trc = sgw_mlp_train(c->mlp, c->gs_x, c->gs_t, (int)c->gs_n, td->epochs, td->batch,
+                            td->lr, td->seed, stream, final_loss);
+    if (trc < 0) {
+      c->err = "training failed: " + c->mlp->err;
+      return trc;
+    }
+  }
+  return rc;
+}
+
+int sgw_read_pce(sgw_ctx* c, double* U, int where, void* stream) {
+  if (!c || !U) return SGW_EINVAL;
+  return sgw_get_state(c, U, nullptr, nullptr, where, stream);
 }
 
 int sgw_solve(sgw_ctx* c, const double* F, double* U, void* stream, sgw_step_stats* stats) {

@@ -1,24 +1,30 @@
-"""Generate the specialised SG-apply kernels (csrc/k1_spec.inc).
+"""Generate the specialised SG-apply kernels (csrc/k1_gen_*.hip, csrc/k1_dispatch.inc).
 
 For a fixed Hermite chaos (L variables, input order p_in, output order p_out)
 the sparsity of the Galerkin tensor c_kij = <psi_k psi_i psi_j> and its values
-are known before run time.  This script writes one HIP kernel per such basis
-in which the whole contraction y_i = sum_k sum_j c_kij (K_k x_j) is unrolled:
-the output modes of a lane's row live in registers and every tensor value is
-an immediate, so the inner loop has no table lookups and no LDS traffic.
+are known before run time.  This script writes, per basis and precision, HIP
+kernels in which the whole contraction y_i = sum_k sum_j c_kij (K_k x_j) is
+unrolled: the output modes of a lane's row live in registers and every tensor
+value is an immediate, so the inner loop has no table lookups.
 
 Layout: one lane per matrix row, sliced-ELL values val[(k*7 + s)*nrows + r],
-mode-major vectors.  A workgroup owns 64 consecutive rows; it first copies x
-at the distinct columns its rows reference (the group's "halo", built on the
-host, all P modes) into LDS with independent loads, then contracts from LDS.
-Global accesses are buffer loads/stores: a 32-bit per-lane offset (the row,
-or a halo column) plus a scalar offset (the coefficient matrix and slot, or
-the mode), so no 64-bit address is kept per load.
-The coefficient matrices are split into up to four chunks, one per wave of a
-workgroup, so four waves share the 64 rows of a workgroup (registers per lane:
-7 KC for the chunk, G for G outputs of a group, 14 for the neighbour values
-of the current and the next mode, 7 halo positions); the partial outputs are
-added in a fixed order through LDS.
+mode-major vectors.  A workgroup owns the rows of one row group (at most 64
+consecutive rows).  It copies x at the distinct columns its rows reference
+(the group's "halo", built on the host) into LDS with independent loads, one
+tile of MT modes at a time, and contracts each tile from LDS.  Global
+accesses are buffer loads/stores: a 32-bit per-lane offset (the row, or a
+halo column) plus a scalar offset (the coefficient matrix and slot, or the
+mode), so no 64-bit address is kept per load.
+
+Three parameters per basis and precision keep the registers of a lane
+bounded (about w (7 KC + G + 14) + 7 VGPRs, w = 1 for FP32, 2 for FP64):
+
+* G: output modes per kernel.  P > G splits the outputs over ceil(P/G)
+  kernels (output groups), each of which stages the whole halo again;
+* KC: coefficient matrices per wave.  The nk matrices are split into
+  ceil(nk/KC) chunks, one per wave of a workgroup; the waves' partial
+  outputs are added in a fixed order through LDS (the staging buffer, reused);
+* MT: modes per staging tile.  LDS holds MT x hmax values (and the partials).
 
 Run:  python -m paper_2512_23027_amd.gen_k1   (build.py runs it)
 """
@@ -27,12 +33,19 @@ import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-OUT = os.path.join(HERE, "csrc", "k1_spec.inc")
+CSRC = os.path.join(HERE, "csrc")
+DISPATCH = os.path.join(CSRC, "k1_dispatch.inc")
 
-# (L, p_in, p_out): the bases of the shipped workloads
-BASES = [(2, 2, 2), (4, 2, 3), (6, 2, 3)]
-MAX_GROUP = 42         # output modes per kernel (register budget)
-MAX_WAVES = 2          # waves per workgroup, one per chunk of coefficient matrices
+# (L, p_in, p_out) -> {precision: (G, KC, MT)}: the bases of the shipped
+# workloads and the deterministic case (L = 0, P = 1)
+BASES = {
+    (0, 0, 0): {"float": (1, 1, 1), "double": (1, 1, 1)},
+    (2, 2, 2): {"float": (6, 3, 6), "double": (6, 3, 6)},
+    (4, 2, 3): {"float": (35, 8, 35), "double": (35, 8, 35)},
+    (6, 2, 3): {"float": (42, 7, 28), "double": (21, 7, 21)},
+    (8, 2, 3): {"float": (33, 8, 33), "double": (15, 6, 15)},
+}
+LDS_LIMIT = 160 * 1024
 
 
 def _graded(L, p):
@@ -45,6 +58,8 @@ def _graded(L, p):
         for v in range(rem, -1, -1):
             rec(pos + 1, rem - v, a + [v])
 
+    if L == 0:
+        return [()]
     for deg in range(p + 1):
         rec(0, deg, [])
     return out
@@ -93,44 +108,63 @@ def entries(L, p_in, p_out):
     return len(kin), len(out), ent
 
 
-def kernel_source(L, p_in, p_out, pcg=False):
-    """One kernel per output group; a workgroup = 64 rows x NCH waves.
+def shape(L, p_in, p_out, T):
+    """(nk, P, G, KC, MT, ngroups, nch) of a basis in precision T."""
+    nk, P, _ = entries(L, p_in, p_out)
+    G, KC, MT = BASES[(L, p_in, p_out)][T]
+    ngroups = (P + G - 1) // G
+    G = (P + ngroups - 1) // ngroups
+    nch = (nk + KC - 1) // KC
+    KC = (nk + nch - 1) // nch
+    nch = (nk + KC - 1) // KC
+    MT = min(MT, P)
+    return nk, P, G, KC, MT, ngroups, nch
+
+
+def tag(L, p_in, p_out):
+    return "k1_L%d_%d_%d" % (L, p_in, p_out)
+
+
+def kernel_source(L, p_in, p_out, T, pcg=False):
+    """The output-group kernels of one basis and precision.
 
     pcg=True: the variant for the subdomain PCG iteration (a block whose
     active flag of iteration par is clear is skipped).  It stages
     p = z + beta p_old (beta = the block's new r'z / old r'z, 0 on the first
-    iteration), writes p to pnew for its own rows, applies the operator to it
-    and writes p'q over the group's rows and the kernel's output modes to
-    pqg[group * (output-group kernels) + kernel].
-
-    The workgroup first stages x at the distinct columns of its 64 rows (the
-    group's halo, all P modes) in LDS with independent loads; wave w then
-    contracts coefficient matrices of chunk w reading the neighbour values
-    from LDS.  The partial outputs of the waves are added in a fixed order
-    through LDS (the staging buffer, reused) by wave 0."""
+    iteration), writes p to pnew for its own rows (output group 0), applies
+    the operator to it and writes p'q over the group's rows and the kernel's
+    output modes to pqg[group * (output groups) + kernel]."""
     nk, P, ent = entries(L, p_in, p_out)
-    ngroups = (P + MAX_GROUP - 1) // MAX_GROUP
-    G = (P + ngroups - 1) // ngroups
-    nch = min(MAX_WAVES, nk)
-    KC = (nk + nch - 1) // nch
-    nch = (nk + KC - 1) // KC
+    _, _, G, KC, MT, ngroups, nch = shape(L, p_in, p_out, T)
+    ntile = (P + MT - 1) // MT
     NT = 64 * nch
-    name = "k1_L%d_%d_%d" % (L, p_in, p_out) + ("_pcg" if pcg else "")
+    sz = "(int)sizeof(%s)" % T
+    name = tag(L, p_in, p_out) + ("_pcg" if pcg else "") + ("_f" if T == "float" else "_d")
     lines = []
-    tables = []
     for g in range(ngroups):
         i0, i1 = g * G, min(P, (g + 1) * G)
         gs = i1 - i0
-        lines.append("template <typename T>")
-        extra = (", const T* __restrict__ zs, T* __restrict__ pnew, const double* __restrict__ rzpart, "
-                 "double* __restrict__ sc, int par, double* __restrict__ pqg") if pcg else ""
-        lines.append("__global__ __launch_bounds__(%d, 2) void %s_g%d(DEll<T> A, DHalo H, int r0, int nrows, "
-                     "const T* __restrict__ x, int ldx, T* __restrict__ y, int ldy, T alpha, "
-                     "T beta, long long sx, long long sy%s) {" % (NT, name, g, extra))
+        extra = (", const {T}* __restrict__ zs, {T}* __restrict__ pnew, "
+                 "const double* __restrict__ rzpart, double* __restrict__ sc, int par, "
+                 "double* __restrict__ pqg, unsigned long long* acct, unsigned bpr").format(T=T) if pcg else ""
+        lines.append("__global__ __launch_bounds__(%d) void %s_g%d(DEll<%s> A, DHalo H, int r0, "
+                     "int nrows, const %s* __restrict__ x, int ldx, %s* __restrict__ y, int ldy, "
+                     "%s alpha, %s beta, long long sx, long long sy%s) {"
+                     % (NT, name, g, T, T, T, T, T, extra))
         lines.append("  extern __shared__ unsigned char k1_smem[];")
-        lines.append("  T* xs = reinterpret_cast<T*>(k1_smem);  // [halo][P] staged x")
-        lines.append("  T* part = xs + (size_t)%d * H.hmax;  // partial outputs of waves 1..%d" % (P, nch - 1))
-        lines.append("  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;")
+        if ntile == 1:
+            lines.append("  %s* xs = reinterpret_cast<%s*>(k1_smem);  // [hmax][%d] staged x" % (T, T, MT))
+            lines.append("  %s* part = xs + (size_t)%d * H.hmax;  // partial outputs of waves 1..%d"
+                         % (T, MT, nch - 1))
+        else:
+            lines.append("  %s* xs = reinterpret_cast<%s*>(k1_smem);  // [hmax][%d] staged tile of x;"
+                         " then wave partials" % (T, T, MT))
+            lines.append("  %s* part = xs;" % T)
+            if pcg:
+                lines.append("  %s* pown = xs + max(%d * H.hmax, %d);  // [%d][64] own-row p of the"
+                             " output modes" % (T, MT, (nch - 1) * gs * 64, gs))
+        lines.append("  const int lane = threadIdx.x & 63;")
+        lines.append("  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));")
         lines.append("  const int grp = xcd_group(blockIdx.x, gridDim.x);")
         lines.append("  const int g0 = H.grow[grp], gn = H.grow[grp + 1] - g0;  // rows of this group")
         lines.append("  x += (long long)blockIdx.z * sx;")
@@ -139,8 +173,7 @@ def kernel_source(L, p_in, p_out, pcg=False):
         lines.append("  const int r = g0 + (live ? lane : 0);")
         lines.append("  const int NR = A.nrows;")
         lines.append("  const auto rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y);")
-        lines.append("  const int rb = r * (int)sizeof(T);")
-        # staging: every thread owns halo entries h, loads all P modes at once
+        lines.append("  const int rb = r * %s;" % sz)
         if pcg:
             lines.append("  // beta of this group's block; the block's first group stores the new r'z")
             lines.append("  const int blk = H.gblk[grp];")
@@ -148,207 +181,300 @@ def kernel_source(L, p_in, p_out, pcg=False):
             lines.append("  double rzn = 0.0;")
             lines.append("  for (int j = 0; j < %d; ++j) rzn += rzpart[(size_t)blk * %d + j];" % (P, P))
             lines.append("  const double rzo = sc[(size_t)blk * 8 + 1 - par];")
-            lines.append("  const T bt = (T)(isinf(rzo) ? 0.0 : rzn / rzo);")
-            lines.append("  if (threadIdx.x == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
+            lines.append("  const %s bt = (%s)(isinf(rzo) ? 0.0 : rzn / rzo);" % (T, T))
+            if g == 0:
+                lines.append("  if (threadIdx.x == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
+                lines.append("  // algorithmic bytes of the rows this launch processes (timed launches)")
+                lines.append("  if (acct && threadIdx.x == 0) atomicAdd(acct, (unsigned long long)gn * bpr);")
             lines.append("  const auto rz = buf_rsrc(zs);")
-        lines.append("  {")
-        lines.append("    const int h0 = H.ptr[grp], nh = H.ptr[grp + 1] - h0;")
-        lines.append("    for (int h = threadIdx.x; h < nh; h += %d) {" % NT)
-        lines.append("      const int co = H.idx[h0 + h] * (int)sizeof(T);")
-        if pcg:
-            for j in range(P):
-                lines.append("      T v%d = buf_load<T>(rz, co, %d * ldx * (int)sizeof(T));" % (j, j))
-            lines.append("      if (bt != T(0)) {")
-            for j in range(P):
-                lines.append("        v%d = fma(bt, buf_load<T>(rx, co, %d * ldx * (int)sizeof(T)), v%d);" % (j, j, j))
-            lines.append("      }")
-        else:
-            for j in range(P):
-                lines.append("      const T v%d = buf_load<T>(rx, co, %d * ldx * (int)sizeof(T));" % (j, j))
-        for j in range(P):
-            lines.append("      xs[h * %d + %d] = v%d;" % (P, j, j))
-        lines.append("    }")
-        lines.append("  }")
+        lines.append("  const int h0 = H.ptr[grp], nh = H.ptr[grp + 1] - h0;")
         lines.append("  const int rr = r - H.r0;")
         for q in range(7):
-            lines.append("  const unsigned l%d = (unsigned)H.lcol[%d * H.nr + rr] * %du * (unsigned)sizeof(T);" % (q, q, P))
+            lines.append("  const unsigned l%d = (unsigned)H.lcol[%d * H.nr + rr] * %du * %du;"
+                         % (q, q, MT, 4 if T == "float" else 8))
         for i in range(i0, i1):
-            lines.append("  T y%d = T(0);" % i)
-        lines.append("  __syncthreads();")
-        if pcg and g == 0:
-            lines.append("  if (wv == %d && live) {  // the new direction of the own row" % (nch - 1))
-            lines.append("    const auto rp = buf_rsrc(pnew);")
-            lines.append("    const char* xb0 = reinterpret_cast<const char*>(xs);")
-            for j in range(P):
-                lines.append("    buf_store<T>(*reinterpret_cast<const T*>(xb0 + l0 + %d * sizeof(T)), rp, rb, %d * ldx * (int)sizeof(T));" % (j, j))
-            lines.append("  }")
-        for ch in range(nch):
-            k0, k1 = ch * KC, min(nk, (ch + 1) * KC)
-            mine = [e for e in ent if k0 <= e[0] < k1 and i0 <= e[1] < i1]
-            js = [j for j in range(P) if any(e[2] == j for e in mine)]
-            if not js:
-                continue
-            lines.append("  if (wv == %d) {  // coefficient matrices %d..%d" % (ch, k0, k1 - 1))
-            for k in range(k0, k1):
-                for q in range(7):
-                    lines.append("    const T k%d_%d = buf_load<T>(rv, rb, %d * NR * (int)sizeof(T));"
-                                 % (k, q, k * 7 + q))
-            # The modes of this chunk run as straight-line code.  An empty asm
-            # statement with a memory clobber before the LDS reads of mode
-            # t+1 (issued before mode t's arithmetic, so their latency
-            # overlaps it) keeps them from being hoisted further up, which
-            # keeps the live registers those of two modes.
-            lines.append("    const char* xb = reinterpret_cast<const char*>(xs);")
-            for q in range(7):
-                lines.append("    T n%d = *reinterpret_cast<const T*>(xb + l%d + %d * sizeof(T));" % (q, q, js[0]))
-            for t, j in enumerate(js):
-                lines.append("    {  // mode %d" % j)
-                for q in range(7):
-                    lines.append("      const T u%d = n%d;" % (q, q))
-                if t + 1 < len(js):
-                    lines.append('      asm volatile("" ::: "memory");')
-                    for q in range(7):
-                        lines.append("      n%d = *reinterpret_cast<const T*>(xb + l%d + %d * sizeof(T));"
-                                     % (q, q, js[t + 1]))
-                for k in sorted({e[0] for e in mine if e[2] == j}):
-                    expr = "k%d_0 * u0" % k
-                    for q in range(1, 7):
-                        expr = "fma(k%d_%d, u%d, %s)" % (k, q, q, expr)
-                    lines.append("      { const T w = %s;" % expr)
-                    for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
-                        lines.append("        y%d = fma(T(%.17g), w, y%d);" % (i, v, i))
-                    lines.append("      }")
+            lines.append("  %s y%d = %s(0);" % (T, i, T))
+        for t in range(ntile):
+            j0, j1 = t * MT, min(P, (t + 1) * MT)
+            lines.append("  // ---- tile %d: modes %d..%d" % (t, j0, j1 - 1))
+            if t > 0:
+                lines.append("  __syncthreads();  // every wave is done with the previous tile")
+            lines.append("  for (int h = threadIdx.x; h < nh; h += %d) {" % NT)
+            lines.append("    const int co = H.idx[h0 + h] * %s;" % sz)
+            if pcg:
+                for j in range(j0, j1):
+                    lines.append("    %s v%d = buf_load<%s>(rz, co, %d * ldx * %s);" % (T, j, T, j, sz))
+                lines.append("    if (bt != %s(0)) {" % T)
+                for j in range(j0, j1):
+                    lines.append("      v%d = fma(bt, buf_load<%s>(rx, co, %d * ldx * %s), v%d);"
+                                 % (j, T, j, sz, j))
                 lines.append("    }")
+            else:
+                for j in range(j0, j1):
+                    lines.append("    const %s v%d = buf_load<%s>(rx, co, %d * ldx * %s);" % (T, j, T, j, sz))
+            for j in range(j0, j1):
+                lines.append("    xs[h * %d + %d] = v%d;" % (MT, j - j0, j))
             lines.append("  }")
+            lines.append("  __syncthreads();")
+            lines.append("  const char* xb%d = reinterpret_cast<const char*>(xs);" % t)
+            if pcg:
+                if g == 0:
+                    lines.append("  if (wv == %d && live) {  // the new direction of the own row" % (nch - 1))
+                    lines.append("    const auto rp = buf_rsrc(pnew);")
+                    for j in range(j0, j1):
+                        lines.append("    buf_store<%s>(*reinterpret_cast<const %s*>(xb%d + l0 + %d * sizeof(%s)), "
+                                     "rp, rb, %d * ldx * %s);" % (T, T, t, j - j0, T, j, sz))
+                    lines.append("  }")
+                own = [i for i in range(i0, i1) if j0 <= i < j1]
+                if own and ntile > 1:
+                    lines.append("  if (wv == 0) {  // own-row p of the output modes in this tile")
+                    for i in own:
+                        lines.append("    pown[%d * 64 + lane] = *reinterpret_cast<const %s*>(xb%d + l0 + %d * sizeof(%s));"
+                                     % (i - i0, T, t, i - j0, T))
+                    lines.append("  }")
+            for ch in range(nch):
+                k0, k1 = ch * KC, min(nk, (ch + 1) * KC)
+                mine = [e for e in ent if k0 <= e[0] < k1 and i0 <= e[1] < i1 and j0 <= e[2] < j1]
+                js = sorted({e[2] for e in mine})
+                if not js:
+                    continue
+                ks = sorted({e[0] for e in mine})
+                lines.append("  if (wv == %d) {  // coefficient matrices %d..%d" % (ch, k0, k1 - 1))
+                if ntile > 1:
+                    # an opaque zero offset per tile keeps the compiler from
+                    # reusing the previous tile's loads (which would keep the
+                    # values of every chunk live across the whole kernel)
+                    lines.append("    const int zk = opaque_zero();")
+                for k in ks:
+                    for q in range(7):
+                        lines.append("    const %s k%d_%d = buf_load<%s>(rv, rb, %d * NR * %s%s);"
+                                     % (T, k, q, T, k * 7 + q, sz, " + zk" if ntile > 1 else ""))
+                # straight-line modes; an empty asm statement with a memory
+                # clobber before the LDS reads of mode t+1 (issued before mode
+                # t's arithmetic, so their latency overlaps it) keeps them from
+                # being hoisted further up (live registers of two modes)
+                for q in range(7):
+                    lines.append("    %s n%d = *reinterpret_cast<const %s*>(xb%d + l%d + %d * sizeof(%s));"
+                                 % (T, q, T, t, q, js[0] - j0, T))
+                for u, j in enumerate(js):
+                    lines.append("    {  // mode %d" % j)
+                    for q in range(7):
+                        lines.append("      const %s u%d = n%d;" % (T, q, q))
+                    if u + 1 < len(js):
+                        lines.append('      asm volatile("" ::: "memory");')
+                        for q in range(7):
+                            lines.append("      n%d = *reinterpret_cast<const %s*>(xb%d + l%d + %d * sizeof(%s));"
+                                         % (q, T, t, q, js[u + 1] - j0, T))
+                    for k in sorted({e[0] for e in mine if e[2] == j}):
+                        expr = "k%d_0 * u0" % k
+                        for q in range(1, 7):
+                            expr = "fma(k%d_%d, u%d, %s)" % (k, q, q, expr)
+                        lines.append("      { const %s w = %s;" % (T, expr))
+                        for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
+                            lines.append("        y%d = fma(%s(%.17g), w, y%d);" % (i, T, v, i))
+                        lines.append("      }")
+                    lines.append("    }")
+                lines.append("  }")
         if nch > 1:
+            if ntile > 1:
+                lines.append("  __syncthreads();  // the staging buffer now holds the wave partials")
             lines.append("  if (wv > 0) {")
             for i in range(i0, i1):
                 lines.append("    part[((wv - 1) * %d + %d) * 64 + lane] = y%d;" % (gs, i - i0, i))
             lines.append("  }")
             lines.append("  __syncthreads();")
             lines.append("  if (wv != 0) return;")
-            for i in range(i0, i1):
-                lines.append("  y%d = %s;" % (i, " + ".join(["y%d" % i] + ["part[(%d * %d + %d) * 64 + lane]"
-                                                                       % (w, gs, i - i0)
-                                                                       for w in range(nch - 1)])))
+            # one wave's partials at a time (the asm statement keeps the LDS
+            # reads of all waves from being issued together)
+            for w in range(nch - 1):
+                lines.append('  asm volatile("" ::: "memory");')
+                for i in range(i0, i1):
+                    lines.append("  y%d += part[(%d * %d + %d) * 64 + lane];" % (i, w, gs, i - i0))
         lines.append("  if (live) {")
         for i in range(i0, i1):
-            lines.append("    { T v = alpha * y%d; if (beta != T(0)) v = fma(beta, buf_load<T>(ry, rb, %d * ldy * (int)sizeof(T)), v);"
-                         " buf_store<T>(v, ry, rb, %d * ldy * (int)sizeof(T)); }" % (i, i, i))
+            lines.append("    { %s v = alpha * y%d; if (beta != %s(0)) v = fma(beta, buf_load<%s>(ry, rb, %d * ldy * %s), v);"
+                         " buf_store<%s>(v, ry, rb, %d * ldy * %s); }" % (T, i, T, T, i, sz, T, i, sz))
         lines.append("  }")
         if pcg:
             lines.append("  {  // p'q over this group's rows and this kernel's output modes")
-            lines.append("    const char* xb0 = reinterpret_cast<const char*>(xs);")
             lines.append("    double v = 0.0;")
             lines.append("    if (live) {")
             for i in range(i0, i1):
-                lines.append("      v += (double)(alpha * y%d) * (double)*reinterpret_cast<const T*>(xb0 + l0 + %d * sizeof(T));" % (i, i))
+                if ntile > 1:
+                    lines.append("      v += (double)(alpha * y%d) * (double)pown[%d * 64 + lane];" % (i, i - i0))
+                else:
+                    lines.append("      v += (double)(alpha * y%d) * (double)*reinterpret_cast<const %s*>(xb0 + l0 + %d * sizeof(%s));"
+                                 % (i, T, i, T))
             lines.append("    }")
             lines.append("    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);")
             lines.append("    if (lane == 0) pqg[(size_t)grp * %d + %d] = v;" % (ngroups, g))
             lines.append("  }")
         lines.append("}")
         lines.append("")
-    # dispatcher: one workgroup per row group of the halo that starts at r0
-    xsig = (", const T* zs, T* pnew, const double* rzpart, double* sc, int par, double* pqg"
-            if pcg else "")
-    xarg = ", zs, pnew, rzpart, sc, par, pqg" if pcg else ""
-    lines.append("template <typename T>")
-    lines.append("static void %s_launch(const DEll<T>& A, const DHalo& H, int r0, int nrows, const T* x, "
-                 "int ldx, T* y, int ldy, T alpha, T beta, int nbatch, long long sx, long long sy%s, "
-                 "hipStream_t st) {" % (name, xsig))
-    lines.append("  const int ngrp = halo_groups(H, r0, nrows);")
-    lines.append("  if (ngrp <= 0) return;")
-    lines.append("  dim3 grid(ngrp, 1, nbatch);")
-    for g in range(ngroups):
-        gs = min(P, (g + 1) * G) - g * G
-        lines.append("  {")
-        lines.append("    const size_t sh = sizeof(T) * ((size_t)%d * H.hmax + %d);" % (P, (nch - 1) * gs * 64))
-        lines.append("    %s_g%d<T><<<grid, %d, sh, st>>>(A, H, r0, nrows, x, ldx, y, ldy, alpha, beta, sx, sy%s);"
-                     % (name, g, NT, xarg))
-        lines.append("  }")
-    lines.append("}")
-    lines.append("")
-    # LDS attribute for every kernel of this basis
-    lines.append("static bool %s_prepare() {" % name)
-    lines.append("  bool ok = true;")
-    for g in range(ngroups):
+    return lines, name, (nk, P, G, KC, MT, ngroups, nch, NT)
+
+
+def _lds_expr(P, G, MT, ngroups, nch, T, pcg):
+    """LDS bytes of the largest output-group kernel, as a C expression of hmax."""
+    gs = (P + ngroups - 1) // ngroups
+    w = 4 if T == "float" else 8
+    if MT >= P:  # one tile: the partials follow the staged x
+        return "((size_t)%d * hmax + %d) * %d" % (MT, (nch - 1) * gs * 64, w)
+    base = "std::max<size_t>((size_t)%d * hmax, %d)" % (MT, (nch - 1) * gs * 64)
+    return "(%s + %d) * %d" % (base, gs * 64 if pcg else 0, w)
+
+
+def basis_source(L, p_in, p_out):
+    """One translation unit: the kernels of a basis in both precisions and
+    their host launchers."""
+    t = tag(L, p_in, p_out)
+    nk, P, ent = entries(L, p_in, p_out)
+    out = ["// Generated by gen_k1.py -- SG-apply kernels of the Hermite chaos L=%d, p_in=%d,"
+           " p_out=%d" % (L, p_in, p_out),
+           "// (%d coefficient matrices, P=%d, %d tensor entries), do not edit." % (nk, P, len(ent)),
+           '#include "k1_common.h"', "", "namespace sgw {", "namespace k {", ""]
+    for T in ("float", "double"):
+        for pcg in (False, True):
+            lines, name, (nk_, P_, G, KC, MT, ngroups, nch, NT) = kernel_source(L, p_in, p_out, T, pcg)
+            out.append("// %s%s: %d output group(s) of <= %d modes, %d wave(s) of <= %d coefficient"
+                       " matrices, tiles of %d modes" % (T, " PCG" if pcg else "", ngroups, G, nch,
+                                                          KC, MT))
+            out.extend(lines)
+            lds = _lds_expr(P, G, MT, ngroups, nch, T, pcg)
+            if not pcg:
+                out.append("bool %s_apply(const DEll<%s>& A, const DHalo& H, int r0, int nrows, "
+                           "const %s* x, int ldx, %s* y, int ldy, %s alpha, %s beta, int nbatch, "
+                           "long long sx, long long sy, hipStream_t st) {" % (t, T, T, T, T, T))
+                out.append("  const int ngrp = halo_groups(H, r0, nrows);")
+                out.append("  const size_t hmax = H.hmax;")
+                out.append("  const size_t sh = %s;" % lds)
+                out.append("  if (ngrp <= 0 || sh > %d) return false;" % LDS_LIMIT)
+                out.append("  dim3 grid(ngrp, 1, nbatch);")
+                for g in range(ngroups):
+                    out.append("  %s_g%d<<<grid, %d, sh, st>>>(A, H, r0, nrows, x, ldx, y, ldy, alpha, "
+                               "beta, sx, sy);" % (name, g, NT))
+                out.append("  return true;")
+                out.append("}")
+            else:
+                out.append("bool %s_pcg(const DEll<%s>& A, const DHalo& H, int nrows, const %s* pold, "
+                           "const %s* zs, %s* pnew, int ld, %s* q, const double* rzpart, double* sc, "
+                           "int par, double* pqg, unsigned long long* acct, unsigned bpr, "
+                           "hipStream_t st) {" % (t, T, T, T, T, T))
+                out.append("  const int ngrp = halo_groups(H, H.r0, nrows);")
+                out.append("  const size_t hmax = H.hmax;")
+                out.append("  const size_t sh = %s;" % lds)
+                out.append("  if (ngrp <= 0 || sh > %d) return false;" % LDS_LIMIT)
+                out.append("  dim3 grid(ngrp, 1, 1);")
+                for g in range(ngroups):
+                    out.append("  %s_g%d<<<grid, %d, sh, st>>>(A, H, H.r0, nrows, pold, ld, q, ld, "
+                               "(%s)1, (%s)0, 0, 0, zs, pnew, rzpart, sc, par, pqg, acct, bpr);"
+                               % (name, g, NT, T, T))
+                out.append("  return true;")
+                out.append("}")
+            out.append("size_t %s%s_lds(%s, int hmax_i) { const size_t hmax = hmax_i; return %s; }"
+                       % (t, "_pcg" if pcg else "", T + "*", lds))
+            out.append("")
+    out.append("int %s_groups(int wbytes) { return wbytes == 4 ? %d : %d; }"
+               % (t, shape(L, p_in, p_out, "float")[5], shape(L, p_in, p_out, "double")[5]))
+    out.append("bool %s_prepare() {" % t)
+    out.append("  bool ok = true;")
+    for T in ("float", "double"):
+        for pcg in (False, True):
+            _, _, _, _, _, ngroups, _ = shape(L, p_in, p_out, T)
+            name = t + ("_pcg" if pcg else "") + ("_f" if T == "float" else "_d")
+            for g in range(ngroups):
+                out.append("  ok = ok && hipFuncSetAttribute((const void*)%s_g%d, "
+                           "hipFuncAttributeMaxDynamicSharedMemorySize, %d) == hipSuccess;"
+                           % (name, g, LDS_LIMIT))
+    out.append("  return ok;")
+    out.append("}")
+    out.extend(["", "}  // namespace k", "}  // namespace sgw", ""])
+    return "\n".join(out)
+
+
+def dispatch_source():
+    out = ["// Generated by gen_k1.py -- dispatch to the generated SG-apply kernels, do not edit.",
+           "// Bases (L, p_in, p_out): " + ", ".join(str(b) for b in BASES), ""]
+    for b in BASES:
+        t = tag(*b)
         for T in ("float", "double"):
-            lines.append("  ok = ok && hipFuncSetAttribute((const void*)%s_g%d<%s>, "
-                         "hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;"
-                         % (name, g, T))
-    lines.append("  return ok;")
-    lines.append("}")
-    lines.append("")
-    return "\n".join(tables + [""] + lines), name, nk, P, len(ent)
+            out.append("bool %s_apply(const DEll<%s>&, const DHalo&, int, int, const %s*, int, %s*, "
+                       "int, %s, %s, int, long long, long long, hipStream_t);" % (t, T, T, T, T, T))
+            out.append("bool %s_pcg(const DEll<%s>&, const DHalo&, int, const %s*, const %s*, %s*, "
+                       "int, %s*, const double*, double*, int, double*, unsigned long long*, unsigned, "
+                       "hipStream_t);" % (t, T, T, T, T, T))
+            out.append("size_t %s_lds(%s*, int);" % (t, T))
+            out.append("size_t %s_pcg_lds(%s*, int);" % (t, T))
+        out.append("int %s_groups(int);" % t)
+        out.append("bool %s_prepare();" % t)
+    out.append("")
+    out.append("template <typename T>")
+    out.append("static bool sg_apply_specialised(int L, int p_in, int p_out, const DEll<T>& A, "
+               "const DHalo& H, int r0, int nrows, const T* x, int ldx, T* y, int ldy, T alpha, "
+               "T beta, int nbatch, long long sx, long long sy, hipStream_t st) {")
+    for b in BASES:
+        out.append("  if (L == %d && p_in == %d && p_out == %d)" % b)
+        out.append("    return %s_apply(A, H, r0, nrows, x, ldx, y, ldy, alpha, beta, nbatch, sx, sy, st);"
+                   % tag(*b))
+    out.append("  return false;")
+    out.append("}")
+    out.append("template <typename T>")
+    out.append("static bool sg_apply_pcg_specialised(int L, int p_in, int p_out, const DEll<T>& A, "
+               "const DHalo& H, int nrows, const T* pold, const T* zs, T* pnew, int ld, T* q, "
+               "const double* rzpart, double* sc, int par, double* pqg, unsigned long long* acct, "
+               "unsigned bpr, hipStream_t st) {")
+    for b in BASES:
+        out.append("  if (L == %d && p_in == %d && p_out == %d)" % b)
+        out.append("    return %s_pcg(A, H, nrows, pold, zs, pnew, ld, q, rzpart, sc, par, pqg, acct, bpr, st);"
+                   % tag(*b))
+    out.append("  return false;")
+    out.append("}")
+    out.append("// LDS bytes of the generated kernel (plain or PCG variant) for a halo of")
+    out.append("// hmax columns; 0 if the basis has none")
+    out.append("template <typename T>")
+    out.append("static size_t sg_apply_specialised_lds(int L, int p_in, int p_out, int hmax, bool pcg) {")
+    for b in BASES:
+        out.append("  if (L == %d && p_in == %d && p_out == %d)" % b)
+        out.append("    return pcg ? %s_pcg_lds((T*)nullptr, hmax) : %s_lds((T*)nullptr, hmax);"
+                   % (tag(*b), tag(*b)))
+    out.append("  return 0;")
+    out.append("}")
+    out.append("// number of output-group kernels of the basis in a precision (4 or 8 bytes")
+    out.append("// per value; 0: none generated)")
+    out.append("static int sg_apply_specialised_groups(int L, int p_in, int p_out, int wbytes) {")
+    for b in BASES:
+        out.append("  if (L == %d && p_in == %d && p_out == %d) return %s_groups(wbytes);" % (b + (tag(*b),)))
+    out.append("  return 0;")
+    out.append("}")
+    out.append("// Allows every generated kernel the whole 160 KiB of LDS (they have no")
+    out.append("// static LDS); once per process before the first launch.")
+    out.append("static bool sg_apply_specialised_prepare() {")
+    out.append("  bool ok = true;")
+    for b in BASES:
+        out.append("  ok = ok && %s_prepare();" % tag(*b))
+    out.append("  return ok;")
+    out.append("}")
+    return "\n".join(out) + "\n"
 
 
-def max_lds_modes():
-    """Largest P among the generated bases (the staged x holds P x hmax)."""
-    return max(entries(*b)[1] for b in BASES)
+def sources():
+    """File names of the generated translation units (relative to csrc/)."""
+    return ["k1_gen_L%d_%d_%d.hip" % b for b in BASES]
+
+
+def _write(path, text):
+    old = open(path).read() if os.path.exists(path) else None
+    if old != text:
+        with open(path, "w") as f:
+            f.write(text)
 
 
 def generate():
-    parts = ["// Generated by gen_k1.py -- specialised SG-apply kernels, do not edit.",
-             "// Bases (L, p_in, p_out): " + ", ".join(str(b) for b in BASES), ""]
-    disp = ["template <typename T>",
-            "static bool sg_apply_specialised(int L, int p_in, int p_out, const DEll<T>& A, "
-            "const DHalo& H, int r0, int nrows, const T* x, int ldx, T* y, int ldy, T alpha, "
-            "T beta, int nbatch, long long sx, long long sy, hipStream_t st) {"]
-    prep = ["// Allows every generated kernel the whole 160 KiB of LDS (they have no",
-            "// static LDS); once per process before the first launch.",
-            "static bool sg_apply_specialised_prepare() {",
-            "  bool ok = true;"]
-    dpcg = ["template <typename T>",
-            "static bool sg_apply_pcg_specialised(int L, int p_in, int p_out, const DEll<T>& A, "
-            "const DHalo& H, int nrows, const T* pold, const T* zs, T* pnew, int ld, T* q, "
-            "const double* rzpart, double* sc, int par, double* pqg, hipStream_t st) {"]
-    for (L, pi, po) in BASES:
-        src, name, nk, P, nnz = kernel_source(L, pi, po)
-        srcp, namep, _, _, _ = kernel_source(L, pi, po, pcg=True)
-        parts.append("// L=%d p_in=%d p_out=%d: %d coefficient matrices, P=%d, %d tensor entries"
-                     % (L, pi, po, nk, P, nnz))
-        parts.append(src)
-        parts.append(srcp)
-        disp.append("  if (L == %d && p_in == %d && p_out == %d) {" % (L, pi, po))
-        disp.append("    %s_launch<T>(A, H, r0, nrows, x, ldx, y, ldy, alpha, beta, nbatch, sx, sy, st);"
-                    % name)
-        disp.append("    return true;")
-        disp.append("  }")
-        dpcg.append("  if (L == %d && p_in == %d && p_out == %d) {" % (L, pi, po))
-        dpcg.append("    %s_launch<T>(A, H, H.r0, nrows, pold, ld, q, ld, T(1), T(0), 1, 0, 0, zs, pnew, "
-                    "rzpart, sc, par, pqg, st);" % namep)
-        dpcg.append("    return true;")
-        dpcg.append("  }")
-        prep.append("  ok = ok && %s_prepare();" % name)
-        prep.append("  ok = ok && %s_prepare();" % namep)
-    disp.append("  return false;")
-    disp.append("}")
-    dpcg.append("  return false;")
-    dpcg.append("}")
-    disp.append("")
-    disp.extend(dpcg)
-    disp.append("")
-    disp.append("// number of output-group kernels of the basis (0: none generated)")
-    disp.append("static int sg_apply_specialised_groups(int L, int p_in, int p_out) {")
-    for (L, pi, po) in BASES:
-        P = entries(L, pi, po)[1]
-        ng = (P + MAX_GROUP - 1) // MAX_GROUP
-        disp.append("  if (L == %d && p_in == %d && p_out == %d) return %d;" % (L, pi, po, ng))
-    disp.append("  return 0;")
-    disp.append("}")
-    prep.append("  return ok;")
-    prep.append("}")
-    parts.extend(disp)
-    parts.append("")
-    parts.extend(prep)
-    text = "\n".join(parts) + "\n"
-    old = open(OUT).read() if os.path.exists(OUT) else None
-    if old != text:
-        with open(OUT, "w") as f:
-            f.write(text)
-    return OUT
+    for b, f in zip(BASES, sources()):
+        _write(os.path.join(CSRC, f), basis_source(*b))
+    _write(DISPATCH, dispatch_source())
+    return [DISPATCH] + [os.path.join(CSRC, f) for f in sources()]
 
 
 if __name__ == "__main__":
-    print(generate())
+    print("\n".join(generate()))

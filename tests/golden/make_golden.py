@@ -1,12 +1,18 @@
 """Write oracle reference values for the long-horizon parity tests.
 
-Calls only ``oracle/`` (and the seeded workload definitions).  For the
-256x256, P = 35 workload it runs the oracle (CG with the mean-matrix
-preconditioner to 1e-14 per step) and stores, at the recorded steps, the mean
-and standard-deviation fields on the sub-grid of every 16th mesh node in each
-direction, plus the full-field L2 norms.  Output: cfg2_oracle.txt (text).
+Calls only ``oracle/`` (and the seeded workload definitions): the oracle
+(CG with the mean-matrix preconditioner to a relative residual of 1e-14 per
+step, no domain decomposition) advances the named workload and, at the
+recorded steps, the full mean and standard-deviation fields over all
+(n+1)^2 mesh nodes are stored in FP64 (numpy .npz, compressed).
 
-Usage: python tests/golden/make_golden.py [nsteps]
+* cfg2 (256x256, P = 35, 8x8 subdomains): steps 2, 10, 25, 50, 100, 200,
+  300, 400, 500 -> cfg2_oracle.npz
+* cfg5 (512x512, P = 165, 16x16 subdomains): the first 20 steps, stored at
+  steps 2, 10, 20 -> cfg5_oracle.npz
+The oracle's CG iteration count of every step is stored too (cg_iterations).
+
+Usage: python tests/golden/make_golden.py cfg2|cfg5
 """
 
 import os
@@ -21,35 +27,31 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import workloads  # noqa: E402
 from oracle.sg import SGProblem  # noqa: E402
 
-STRIDE = 16
-
-
-def subgrid(n):
-    idx = np.arange(0, n + 1, STRIDE)
-    return (idx[None, :] + (n + 1) * idx[:, None]).ravel()
+RECORD = {"cfg2": (2, 10, 25, 50, 100, 200, 300, 400, 500),
+          "cfg5": (2, 10, 20)}
 
 
 def main():
-    nsteps = int(sys.argv[1]) if len(sys.argv) > 1 else 500
-    record = {2, 10, 50, 100, 200, 300, 400, 500}
-    prm = workloads.config("cfg2")
+    name = sys.argv[1]
+    record = RECORD[name]
+    prm = workloads.config(name)
     pr = SGProblem(prm, solver="cg")
-    sub = subgrid(prm["n"])
-    out_path = os.path.join(HERE, "cfg2_oracle.txt")
+    out_path = os.path.join(HERE, "%s_oracle.npz" % name)
     U, V, A = pr.initial_state()
-    lines = ["# oracle reference for cfg2 (256x256, P=35, dt 1e-3), written by make_golden.py",
-             "# sub-grid: mesh nodes (16i, 16j); per recorded step: 'step s norm_mean norm_std'",
-             "# then one line per sub-grid node: 'mean std'"]
+    fields = {}
     t0 = time.time()
-    for s in range(1, nsteps + 1):
+    for s in range(1, max(record) + 1):
         U, V, A = pr.step(U, V, A)
+        print("step %d done (%.0f s, %d CG iterations)" % (s, time.time() - t0, pr.cg_iters[-1]),
+              flush=True)
         if s in record:
             mean, std = pr.moments(U)
-            lines.append("step %d %.17e %.17e" % (s, np.linalg.norm(mean), np.linalg.norm(std)))
-            lines.extend("%.17e %.17e" % (mean[v], std[v]) for v in sub)
-            with open(out_path, "w") as f:
-                f.write("\n".join(lines) + "\n")
-            print("step %d written (%.0f s)" % (s, time.time() - t0), flush=True)
+            fields["mean_%d" % s] = mean
+            fields["std_%d" % s] = std
+            np.savez_compressed(out_path, steps=np.array(sorted(int(k[5:]) for k in fields
+                                                                 if k.startswith("mean_"))),
+                                n=np.array(prm["n"]), cg_iterations=np.array(pr.cg_iters),
+                                **fields)
 
 
 if __name__ == "__main__":

@@ -18,30 +18,31 @@ def test_bf16_rounding_known_values():
 
 def test_backward_matches_finite_differences():
     rng = np.random.default_rng(0)
-    ng, H, n = 3, 5, 7
-    npar = H * 4 * ng + H + H * H + H + ng * H + ng
+    ni, ng, H, n = 4, 3, 5, 7
+    npar = H * ni + H + H * H + H + ng * H + ng
     w = rng.standard_normal(npar) * 0.5
-    x = rng.standard_normal((n, 4 * ng))
+    x = rng.standard_normal((n, ni))
     t = rng.standard_normal((n, ng))
-    loss, g = mlp.loss_grad(w, x, t, ng, H)
+    loss, g = mlp.loss_grad(w, x, t, ni, ng, H)
     eps = 1e-6
     fd = np.empty(npar)
     for q in range(npar):
         wp, wm = w.copy(), w.copy()
         wp[q] += eps
         wm[q] -= eps
-        fd[q] = (mlp.loss_grad(wp, x, t, ng, H)[0] - mlp.loss_grad(wm, x, t, ng, H)[0]) / (2 * eps)
+        fd[q] = (mlp.loss_grad(wp, x, t, ni, ng, H)[0]
+                 - mlp.loss_grad(wm, x, t, ni, ng, H)[0]) / (2 * eps)
     assert np.abs(g - fd).max() <= 1e-7 * max(1.0, np.abs(fd).max())
-    assert np.isclose(loss, np.mean((mlp.forward(w, x, ng, H)[0] - t) ** 2))
+    assert np.isclose(loss, np.mean((mlp.forward(w, x, ni, ng, H)[0] - t) ** 2))
 
 
 def test_layout_and_relu():
-    ng, H = 2, 3
-    npar = H * 4 * ng + H + H * H + H + ng * H + ng
+    ni, ng, H = 5, 2, 3
+    npar = H * ni + H + H * H + H + ng * H + ng
     w = np.zeros(npar)
-    W1, b1, W2, b2, W3, b3 = mlp.unpack(w, ng, H)
-    assert W1.shape == (H, 4 * ng) and W3.shape == (ng, H) and b3.shape == (ng,)
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(w, ni, ng, H)
+    assert W1.shape == (H, ni) and W3.shape == (ng, H) and b3.shape == (ng,)
     # only the output bias set: the network returns it for any input
     w[-ng:] = [0.25, -1.5]
-    y, _ = mlp.forward(w, np.ones((4, 4 * ng)), ng, H)
+    y, _ = mlp.forward(w, np.ones((4, ni)), ni, ng, H)
     assert np.all(y == np.array([0.25, -1.5]))

@@ -199,3 +199,94 @@ def test_sg_mean_within_monte_carlo_error():
         U, V, A = sg.step(U, V, A)
     z = np.abs(U[:, 0] - mc_mean) / np.maximum(se, 1e-300)
     assert np.max(z) < 4.5
+
+
+# ---------------------------------------------------------------------------
+# Random initial conditions (Eq. acous_sto: u_0(x, theta), v_0(x, theta)),
+# given by their chaos coefficients u0_modes / v0_modes.
+# ---------------------------------------------------------------------------
+def _pulse(prm, mesh):
+    r2 = (mesh.x - prm["x0"]) ** 2 + (mesh.y - prm["y0"]) ** 2
+    return prm["amp"] * np.exp(-r2 / prm["width"] ** 2)
+
+
+def test_random_initial_condition_sigma_zero_is_linear():
+    # c_s deterministic: every chaos mode evolves on its own, so the modes of
+    # u_0 = (1 + d xi_1) pulse and v_0 = e xi_2 pulse are d and e times
+    # deterministic runs (a transposed or misplaced mode fails)
+    d, e = 0.3, 0.7
+    prm = dict(BASE, sigma=0.0, p_out=2, alpha0=0.5445, alpha1=0.0174)
+    mesh = StructuredMesh(prm["n"])
+    pulse = _pulse(prm, mesh)
+    P = 6
+    u0 = np.zeros((P, mesh.nn))
+    v0 = np.zeros((P, mesh.nn))
+    u0[0], u0[1], v0[2] = pulse, d * pulse, e * pulse  # modes 1, 2 = xi_1, xi_2
+    sg = SGProblem(dict(prm, u0_modes=u0, v0_modes=v0))
+    U, V, A = sg.initial_state()
+    det = SGProblem(dict(prm, L=0, p_in=0, p_out=0))
+    u, v, a = det.initial_state()
+    dv = SGProblem(dict(prm, L=0, p_in=0, p_out=0, u0=0 * pulse, v0_modes=pulse[None, :]))
+    uv, vv, av = dv.initial_state()
+    for _ in range(12):
+        U, V, A = sg.step(U, V, A)
+        u, v, a = det.step(u, v, a)
+        uv, vv, av = dv.step(uv, vv, av)
+    np.testing.assert_allclose(U[:, 0], u[:, 0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(U[:, 1], d * u[:, 0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(U[:, 2], e * uv[:, 0], rtol=0, atol=1e-14)
+    assert np.all(U[:, 3:] == 0.0)
+
+
+def test_random_initial_condition_vs_gauss_hermite():
+    # random medium and random initial pressure and velocity: the SG
+    # moments converge to the tensor Gauss-Hermite moments of deterministic
+    # runs with the exact coefficient exp(g . xi) and the sampled initial
+    # state u_0 = (1 + d xi_1) pulse, v_0 = e xi_2 pulse
+    d, e = 0.4, 2.0
+    prm = dict(BASE, alpha0=0.5445, alpha1=0.0174)
+    nsteps = 25
+    mesh = StructuredMesh(prm["n"])
+    pulse = _pulse(prm, mesh)
+    g = kle_fields(prm["sigma"], prm["bx"], prm["by"], prm["L"], mesh.cx, mesh.cy)
+    f = mesh.free
+    _, Mall = assemble(mesh, np.ones((1, len(mesh.tris))))
+    M = Mall[f][:, f].tocsc()
+    dt, z, gm = prm["dt"], 0.25, 0.5
+    x, w = He.hermegauss(14)
+    w = w / math.sqrt(2 * math.pi)
+    us, wts = [], []
+    for ia, xa in enumerate(x):
+        for ib, xb in enumerate(x):
+            xi = np.array([xa, xb])
+            Kall, _ = assemble(mesh, np.exp(xi @ g)[None, :])
+            K = Kall[0][f][:, f].tocsc()
+            C = (prm["alpha0"] * M + prm["alpha1"] * K).tocsc()
+            lu = spla.splu((M / (z * dt * dt) + gm * C / (z * dt) + K).tocsc())
+            u = (1 + d * xa) * pulse[f]
+            v = e * xb * pulse[f]
+            a = spla.splu(M).solve(-(K @ u) - C @ v)
+            for _ in range(nsteps):
+                u, v, a = newmark_step(u, v, a, dt, lambda q: M @ q, lambda q: C @ q,
+                                       lambda F, _u: lu.solve(F))
+            us.append(u)
+            wts.append(w[ia] * w[ib])
+    us, wts = np.array(us), np.array(wts)
+    mean_ex = wts @ us
+    std_ex = np.sqrt(np.maximum(wts @ (us * us) - mean_ex ** 2, 0.0))
+    errs = []
+    for p in (2, 4):
+        from oracle.pce import pce_size
+        P = pce_size(2, p)
+        u0 = np.zeros((P, mesh.nn))
+        v0 = np.zeros((P, mesh.nn))
+        u0[0], u0[1], v0[2] = pulse, d * pulse, e * pulse
+        sg = SGProblem(dict(prm, p_in=2 * p, p_out=p, u0_modes=u0, v0_modes=v0))
+        U, V, A = sg.initial_state()
+        for _ in range(nsteps):
+            U, V, A = sg.step(U, V, A)
+        errs.append((rel_l2(U[:, 0], mean_ex), rel_l2(np.sqrt(np.sum(U[:, 1:] ** 2, axis=1)),
+                                                       std_ex)))
+    # measured: p = 2: 9.4e-5 / 2.2e-3, p = 4: 4.3e-7 / 2.5e-5 (mean / std)
+    assert errs[1][0] < 2e-6 and errs[1][1] < 1e-4, errs
+    assert errs[1][0] < 0.1 * errs[0][0] and errs[1][1] < 0.1 * errs[0][1], errs
