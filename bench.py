@@ -46,6 +46,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+os.environ.setdefault("SGW_PROGRESS", "1")  # set-up stages on stderr
 
 METRIC = "SG-DD-PCG time-steps/s at ≤1e-6 rel err vs FP64 oracle; PCG iters/step; GB/s"
 HBM_PEAK_GBS = 8000.0
@@ -226,6 +227,56 @@ def run_stack(sgw, prm, opts, warm, steps, golden, log):
             "autotune_us": tune, "prof": prof, "errors": errors}
 
 
+SWEEPS = {
+    # the paper's studies with its mesh sizes (13,472 / 37,267 vertices) on
+    # structured meshes of about the same node counts, the Courant number 0.65
+    # it uses, sigma 0.3, correlation length 0.25, input order 2
+    "subdomains": [dict(n=120, L=7, p_out=3, ns=ns) for ns in (2, 3, 4, 5, 6, 8, 10, 12)],
+    "rvs": [dict(n=192, L=L, p_out=3, ns=8) for L in range(3, 10)],
+    "order": [dict(n=128, L=3, p_out=p, ns=8) for p in range(2, 10)],
+}
+
+
+def sweep(name, steps, warm, log):
+    """One-GPU replica of one of the paper's scaling studies (Sec. 6.3, 6.4):
+    outer (interface) and subdomain PCG iterations per step and time-steps/s
+    of the plain FP64 method against the number of subdomains, the number of
+    random variables or the chaos order."""
+    import torch
+    import paper_2512_23027_amd as sgw
+    import workloads
+    rows = []
+    for c in SWEEPS[name]:
+        n, ns = c["n"], c["ns"]
+        prm = workloads.config("cfg5", n=n, L=c["L"], p_out=c["p_out"], sigma=0.3, bx=0.25,
+                               by=0.25, dt=0.65 / n, xsplits=workloads.uniform_splits(n, ns),
+                               ysplits=workloads.uniform_splits(n, ns), x0=0.5, y0=0.5,
+                               width=0.1)
+        t0 = time.perf_counter()
+        s = sgw.Solver(prm, **solver_settings("fp64"))
+        s.factor()
+        s.autotune()
+        setup = time.perf_counter() - t0
+        s.set_state()
+        s.step(warm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = s.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        row = {"mesh_nodes": (n + 1) ** 2, "subdomains": ns * ns, "L": c["L"],
+               "order": c["p_out"], "P": s.P, "sg_unknowns": s.P * s.nfree,
+               "coarse_unknowns": s.P * s.ncorner,
+               "outer_iters_per_step": st["outer_iters"] / steps,
+               "outer_iters_max": st["outer_iters_max"],
+               "inner_iters_per_step": st["inner_iters"] / steps,
+               "steps_per_s": steps / el, "setup_s": setup}
+        s.close()
+        log("sweep %s: %s" % (name, row))
+        rows.append(row)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +286,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 stack")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--sweep", choices=sorted(SWEEPS), default=None,
+                    help="run one of the scaling studies instead (JSON rows)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -253,6 +306,12 @@ def main():
         print("[bench] " + msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    if args.sweep:
+        rows = sweep(args.sweep, args.steps, args.warmup, log)
+        print(json.dumps({"sweep": args.sweep, "solver": "plain FP64 DD-PCG (two-level NN)",
+                          "steps": args.steps, "warmup": args.warmup, "rows": rows}),
+              flush=True)
+        return
     prm = workloads.config(args.workload)
     golden, gmeta = load_golden(args.workload)
     log("workload %s, stored oracle steps %s" % (args.workload, sorted(golden)))

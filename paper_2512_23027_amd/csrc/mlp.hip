@@ -179,19 +179,24 @@ int ensure_cap(sgw_mlp* m, int nb) {
   return 0;
 }
 
-// forward on rows x[nb][nin]: h1, h2 and y of the work space
-void forward(sgw_mlp* m, const float* x, float* y, int nb, hipStream_t st) {
+// forward on rows x[nb][nin] with the hidden activations in h1, h2
+// ([nb][H] each; the work space's unless given)
+void forward(sgw_mlp* m, const float* x, float* y, int nb, hipStream_t st,
+             float* h1 = nullptr, float* h2 = nullptr) {
   const int H = m->H, ni = m->nin, ng = m->ng;
   const unsigned short* wb = m->wb;
   const float* w = m->w;
+  if (!h1) h1 = m->h1;
+  if (!h2) h2 = m->h2;
   // h = relu(x W^T + b): A(i,k) = x[i][k], B(k,j) = W[j][k]
-  gemm<float, unsigned short>(nb, H, ni, x, ni, 1, wb + m->off[0], 1, ni, m->h1, H,
+  gemm<float, unsigned short>(nb, H, ni, x, ni, 1, wb + m->off[0], 1, ni, h1, H,
                               w + m->off[1], 1, nullptr, st);
-  gemm<float, unsigned short>(nb, H, H, m->h1, H, 1, wb + m->off[2], 1, H, m->h2, H,
+  gemm<float, unsigned short>(nb, H, H, h1, H, 1, wb + m->off[2], 1, H, h2, H,
                               w + m->off[3], 1, nullptr, st);
-  gemm<float, unsigned short>(nb, ng, H, m->h2, H, 1, wb + m->off[4], 1, H, y, ng,
+  gemm<float, unsigned short>(nb, ng, H, h2, H, 1, wb + m->off[4], 1, H, y, ng,
                               w + m->off[5], 0, nullptr, st);
 }
+
 
 // loss and gradient of the mean squared error of rows xb -> tb (work space)
 void backward(sgw_mlp* m, const float* x, const float* t, int nb, hipStream_t st) {
@@ -344,6 +349,7 @@ int sgw_mlp_forward(sgw_mlp* m, const float* x, float* y, int nb, void* stream) 
   if (rc) return rc;
   return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : SGW_EHIP;
 }
+
 
 int sgw_mlp_loss_grad(sgw_mlp* m, const float* x, const float* t, int nb, float* grad,
                       float* loss, void* stream) {

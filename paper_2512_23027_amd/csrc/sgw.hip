@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1782,7 +1783,14 @@ int sgw_factor(sgw_ctx* c, void* stream) {
     }
     HIPCHK(hipMemsetAsync(c->fs, 0, (size_t)c->nsub * MP * MP * sizeof(double), st));
     const double tol = std::min(1e-12, c->h.d.inner_rtol);
-    for (int lcl = 0; lcl < c->maxc; ++lcl)
+    // SGW_PROGRESS=1 reports the stages of this (long, at large P) set-up
+    const char* pe = getenv("SGW_PROGRESS");
+    const bool progress = pe && pe[0] == '1';
+    auto t0 = std::chrono::steady_clock::now();
+    auto secs = [&] {
+      return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    };
+    for (int lcl = 0; lcl < c->maxc; ++lcl) {
       for (int m = 0; m < P; ++m) {
         k::fill2d<double>(P, NT, c->d64.Tt, NT, 0.0, st);
         k_basis_rhs<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->d64.Tt, NT);
@@ -1791,6 +1799,10 @@ int sgw_factor(sgw_ctx* c, void* stream) {
         if (rc < 0) return rc;
         k_basis_store<<<c->nsub, 256, 0, st>>>(c->co, lcl, m, c->d64.Yt, NT, c->fs);
       }
+      if (progress)
+        fprintf(stderr, "[sgw] coarse basis: corner slot %d of %d done (%.1f s)\n", lcl + 1,
+                c->maxc, secs());
+    }
     std::vector<double> fs((size_t)c->nsub * MP * MP);
     HIPCHK(hipMemcpyAsync(fs.data(), c->fs, fs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1865,6 +1877,9 @@ int sgw_factor(sgw_ctx* c, void* stream) {
     CoarseFactor CF;
     const int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     if (!coarse_factor(B, CF, threads, c->err)) return SGW_ENOTSPD;
+    if (progress)
+      fprintf(stderr, "[sgw] coarse factor: %d corner rows, %d unknowns (%.1f s)\n", CF.R,
+              nC * P, secs());
     k::DCoarseFactor& df = c->cf;
     df.R = CF.R;
     df.n = nC * P;
@@ -1899,13 +1914,12 @@ int sgw_factor(sgw_ctx* c, void* stream) {
       c->err = "device allocation failed (coarse factor)";
       return SGW_ENOMEM;
     }
-    if (c->phif) {  // the FP32 solver's copy of the coarse basis
+    if (c->phif) {  // the FP32 solver's copy of the coarse basis, in chunks of 2^30
       const long long tot = c->phi_off_h.back();
-      if (tot > 0x7fffffffLL) {
-        c->err = "coarse basis too large for the FP32 copy";
-        return SGW_EINVAL;
+      for (long long o = 0; o < tot; o += (1LL << 30)) {
+        const int len = (int)std::min<long long>(tot - o, 1LL << 30);
+        k::copy2d<float, double>(1, len, c->phi + o, len, c->phif + o, len, 1.0, st);
       }
-      k::copy2d<float, double>(1, (int)tot, c->phi, (int)tot, c->phif, (int)tot, 1.0, st);
       HIPCHK(hipStreamSynchronize(st));
     }
   }

@@ -121,22 +121,33 @@ def _run(sgw, prm, nsteps, guess, model=None):
     return out
 
 
+def _pulse(prm):
+    """The initial pulse of a workload at every mesh node (its input data)."""
+    n = prm["n"]
+    x = np.tile(np.arange(n + 1) / n, n + 1)
+    y = np.repeat(np.arange(n + 1) / n, n + 1)
+    r2 = (x - prm["x0"]) ** 2 + (y - prm["y0"]) ** 2
+    return prm["amp"] * np.exp(-r2 / prm["width"] ** 2)
+
+
 def test_learned_guess_saves_iterations(sgw):
     train_seeds, test_seeds = workloads.learned_guess_seeds()
     nsteps = 200
     model = sgw.GuessModel(4, 1, 256, seed=7)
+    # one context records the training trajectories (a new initial pulse per
+    # seed through sgw_set_state) into its sample store, then trains
+    s = sgw.Solver(workloads.cfg4(train_seeds[0]), rtol=1e-12, inner_rtol=1e-14,
+                   guess=sgw.SGW_GUESS_NEWMARK)
+    s.factor()
+    s.set_guess_model(model)
     loss = 0.0
-    for q, sd in enumerate(train_seeds):  # record the training trajectories
-        s = sgw.Solver(workloads.cfg4(sd), rtol=1e-12, inner_rtol=1e-14,
-                       guess=sgw.SGW_GUESS_NEWMARK)
-        s.factor()
-        s.set_state()
-        s.set_guess_model(model)
+    for q, sd in enumerate(train_seeds):
+        s.set_state(U=torch.from_numpy(_pulse(workloads.cfg4(sd))[None, :].copy()))
         last = q + 1 == len(train_seeds)
         loss = s.guess_train(nsteps, epochs=30 if last else 0, batch=1024, lr=1e-3, seed=2,
                              clear=q == 0)
         assert s.stored_samples() == (q + 1) * (nsteps - 4) * s.ninterface * s.P
-        s.close()
+    s.close()
     assert np.isfinite(loss)
     print("training: %d samples, final loss %.3e" % (
         len(train_seeds) * (nsteps - 4) * 61 * 6, loss))
