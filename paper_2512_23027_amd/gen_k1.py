@@ -36,14 +36,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 DISPATCH = os.path.join(CSRC, "k1_dispatch.inc")
 
-# (L, p_in, p_out) -> {precision: (G, KC, MT)}: the bases of the shipped
+# (L, p_in, p_out) -> {precision: (G, KC, MT, NW[, RG])}: the bases of the shipped
 # workloads and the deterministic case (L = 0, P = 1)
 BASES = {
-    (0, 0, 0): {"float": (1, 1, 1), "double": (1, 1, 1)},
-    (2, 2, 2): {"float": (6, 3, 6), "double": (6, 3, 6)},
-    (4, 2, 3): {"float": (35, 8, 35), "double": (35, 8, 35)},
-    (6, 2, 3): {"float": (42, 7, 28), "double": (21, 7, 21)},
-    (8, 2, 3): {"float": (33, 8, 33), "double": (15, 6, 15)},
+    (0, 0, 0): {"float": (1, 1, 1, 1), "double": (1, 1, 1, 1)},
+    (2, 2, 2): {"float": (6, 3, 6, 2), "double": (6, 3, 6, 2)},
+    (4, 2, 3): {"float": (35, 8, 35, 2), "double": (35, 8, 35, 2)},
+    (6, 2, 3): {"float": (84, 7, 16, 1), "double": (42, 7, 8, 1)},
+    (8, 2, 3): {"float": (165, 6, 16, 1), "double": (83, 4, 8, 1)},
 }
 LDS_LIMIT = 160 * 1024
 
@@ -109,16 +109,34 @@ def entries(L, p_in, p_out):
 
 
 def shape(L, p_in, p_out, T):
-    """(nk, P, G, KC, MT, ngroups, nch) of a basis in precision T."""
+    """(nk, P, G, KC, MT, ngroups, nch, nw) of a basis in precision T: nch
+    coefficient chunks, nw waves per workgroup (wave w takes the chunks
+    c with c % nw == w, one after the other)."""
     nk, P, _ = entries(L, p_in, p_out)
-    G, KC, MT = BASES[(L, p_in, p_out)][T]
+    G, KC, MT, NW = BASES[(L, p_in, p_out)][T][:4]
     ngroups = (P + G - 1) // G
     G = (P + ngroups - 1) // ngroups
     nch = (nk + KC - 1) // KC
     KC = (nk + nch - 1) // nch
     nch = (nk + KC - 1) // KC
     MT = min(MT, P)
-    return nk, P, G, KC, MT, ngroups, nch
+    return nk, P, G, KC, MT, ngroups, nch, min(NW, nch)
+
+
+def lds_stride(MT):
+    """Values per staged halo entry in LDS: MT rounded up to an odd number,
+    so that the rows of a wave, whose neighbours sit at scattered entries,
+    spread their reads over the LDS banks (an even stride such as 16 maps
+    every entry to one of two banks and serialises the reads 32-fold)."""
+    return MT if MT % 2 else MT + 1
+
+
+def row_groups(L, p_in, p_out, T):
+    """Row groups (64 rows each, one wave each) per workgroup: several waves
+    of one workgroup run the same straight-line code in lockstep (a barrier
+    per staging tile), so they share the instruction cache."""
+    e = BASES[(L, p_in, p_out)][T]
+    return e[4] if len(e) > 4 else 1
 
 
 def tag(L, p_in, p_out):
@@ -135,9 +153,11 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
     the operator to it and writes p'q over the group's rows and the kernel's
     output modes to pqg[group * (output groups) + kernel]."""
     nk, P, ent = entries(L, p_in, p_out)
-    _, _, G, KC, MT, ngroups, nch = shape(L, p_in, p_out, T)
+    _, _, G, KC, MT, ngroups, nch, nw = shape(L, p_in, p_out, T)
+    RG = row_groups(L, p_in, p_out, T)
+    S = lds_stride(MT)
     ntile = (P + MT - 1) // MT
-    NT = 64 * nch
+    NT = 64 * nw * RG
     sz = "(int)sizeof(%s)" % T
     name = tag(L, p_in, p_out) + ("_pcg" if pcg else "") + ("_f" if T == "float" else "_d")
     lines = []
@@ -152,24 +172,34 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
                      "%s alpha, %s beta, long long sx, long long sy%s) {"
                      % (NT, name, g, T, T, T, T, T, extra))
         lines.append("  extern __shared__ unsigned char k1_smem[];")
-        if ntile == 1:
-            lines.append("  %s* xs = reinterpret_cast<%s*>(k1_smem);  // [hmax][%d] staged x" % (T, T, MT))
+        if RG > 1:
+            lines.append("  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));")
+            lines.append("  // wave wv owns row group %d blockIdx + wv and its own [hmax][%d] tile" % (RG, MT))
+            lines.append("  %s* xs = reinterpret_cast<%s*>(k1_smem) + (size_t)wv * %d * H.hmax;"
+                         % (T, T, S))
+        elif ntile == 1:
+            lines.append("  %s* xs = reinterpret_cast<%s*>(k1_smem);  // [hmax][%d] staged x" % (T, T, S))
             lines.append("  %s* part = xs + (size_t)%d * H.hmax;  // partial outputs of waves 1..%d"
-                         % (T, MT, nch - 1))
+                         % (T, S, nw - 1))
         else:
             lines.append("  %s* xs = reinterpret_cast<%s*>(k1_smem);  // [hmax][%d] staged tile of x;"
-                         " then wave partials" % (T, T, MT))
+                         " then wave partials" % (T, T, S))
             lines.append("  %s* part = xs;" % T)
-            if pcg:
-                lines.append("  %s* pown = xs + max(%d * H.hmax, %d);  // [%d][64] own-row p of the"
-                             " output modes" % (T, MT, (nch - 1) * gs * 64, gs))
         lines.append("  const int lane = threadIdx.x & 63;")
-        lines.append("  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));")
-        lines.append("  const int grp = xcd_group(blockIdx.x, gridDim.x);")
+        if RG > 1:
+            lines.append("  const int graw = xcd_group(blockIdx.x, gridDim.x) * %d + wv;" % RG)
+            lines.append("  const bool has = graw < H.ng;  // the last workgroup may be short")
+            lines.append("  const int grp = has ? graw : 0;")
+        else:
+            lines.append("  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));")
+            lines.append("  const int grp = xcd_group(blockIdx.x, gridDim.x);")
         lines.append("  const int g0 = H.grow[grp], gn = H.grow[grp + 1] - g0;  // rows of this group")
         lines.append("  x += (long long)blockIdx.z * sx;")
         lines.append("  y += (long long)blockIdx.z * sy;")
-        lines.append("  const bool live = lane < gn && g0 + lane - r0 < nrows;")
+        if RG > 1:
+            lines.append("  const bool live = has && lane < gn && g0 + lane - r0 < nrows;")
+        else:
+            lines.append("  const bool live = lane < gn && g0 + lane - r0 < nrows;")
         lines.append("  const int r = g0 + (live ? lane : 0);")
         lines.append("  const int NR = A.nrows;")
         lines.append("  const auto rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y);")
@@ -177,21 +207,33 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
         if pcg:
             lines.append("  // beta of this group's block; the block's first group stores the new r'z")
             lines.append("  const int blk = H.gblk[grp];")
-            lines.append("  if (sc[(size_t)blk * 8 + 2 + par] == 0.0) return;  // converged block: frozen")
+            if RG > 1:
+                # waves of a workgroup pass the same barriers, so a frozen
+                # group's wave stays and skips its work instead of returning
+                lines.append("  const bool active = __builtin_amdgcn_readfirstlane("
+                             "(int)(has && sc[(size_t)blk * 8 + 2 + par] != 0.0)) != 0;")
+            else:
+                lines.append("  if (sc[(size_t)blk * 8 + 2 + par] == 0.0) return;  // converged block: frozen")
+                lines.append("  const bool active = true;")
             lines.append("  double rzn = 0.0;")
             lines.append("  for (int j = 0; j < %d; ++j) rzn += rzpart[(size_t)blk * %d + j];" % (P, P))
             lines.append("  const double rzo = sc[(size_t)blk * 8 + 1 - par];")
             lines.append("  const %s bt = (%s)(isinf(rzo) ? 0.0 : rzn / rzo);" % (T, T))
             if g == 0:
-                lines.append("  if (threadIdx.x == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
+                lines.append("  if (active && lane == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
                 lines.append("  // algorithmic bytes of the rows this launch processes (timed launches)")
-                lines.append("  if (acct && threadIdx.x == 0) atomicAdd(acct, (unsigned long long)gn * bpr);")
+                lines.append("  if (acct && active && lane == 0) atomicAdd(acct, (unsigned long long)gn * bpr);")
             lines.append("  const auto rz = buf_rsrc(zs);")
-        lines.append("  const int h0 = H.ptr[grp], nh = H.ptr[grp + 1] - h0;")
+        if RG > 1 and not pcg:
+            lines.append("  const bool active = has;")
+        if RG > 1:
+            lines.append("  const int h0 = H.ptr[grp], nh = active ? H.ptr[grp + 1] - h0 : 0;")
+        else:
+            lines.append("  const int h0 = H.ptr[grp], nh = H.ptr[grp + 1] - h0;")
         lines.append("  const int rr = r - H.r0;")
         for q in range(7):
             lines.append("  const unsigned l%d = (unsigned)H.lcol[%d * H.nr + rr] * %du * %du;"
-                         % (q, q, MT, 4 if T == "float" else 8))
+                         % (q, q, S, 4 if T == "float" else 8))
         for i in range(i0, i1):
             lines.append("  %s y%d = %s(0);" % (T, i, T))
         for t in range(ntile):
@@ -199,7 +241,8 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
             lines.append("  // ---- tile %d: modes %d..%d" % (t, j0, j1 - 1))
             if t > 0:
                 lines.append("  __syncthreads();  // every wave is done with the previous tile")
-            lines.append("  for (int h = threadIdx.x; h < nh; h += %d) {" % NT)
+            lines.append("  for (int h = %s; h < nh; h += %d) {"
+                         % ("lane" if RG > 1 else "threadIdx.x", 64 if RG > 1 else NT))
             lines.append("    const int co = H.idx[h0 + h] * %s;" % sz)
             if pcg:
                 for j in range(j0, j1):
@@ -213,69 +256,76 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
                 for j in range(j0, j1):
                     lines.append("    const %s v%d = buf_load<%s>(rx, co, %d * ldx * %s);" % (T, j, T, j, sz))
             for j in range(j0, j1):
-                lines.append("    xs[h * %d + %d] = v%d;" % (MT, j - j0, j))
+                lines.append("    xs[h * %d + %d] = v%d;" % (S, j - j0, j))
             lines.append("  }")
             lines.append("  __syncthreads();")
             lines.append("  const char* xb%d = reinterpret_cast<const char*>(xs);" % t)
             if pcg:
                 if g == 0:
-                    lines.append("  if (wv == %d && live) {  // the new direction of the own row" % (nch - 1))
+                    if RG > 1:
+                        lines.append("  if (active && live) {  // the new direction of the own row")
+                    else:
+                        lines.append("  if (wv == %d && live) {  // the new direction of the own row" % (nw - 1))
                     lines.append("    const auto rp = buf_rsrc(pnew);")
                     for j in range(j0, j1):
                         lines.append("    buf_store<%s>(*reinterpret_cast<const %s*>(xb%d + l0 + %d * sizeof(%s)), "
                                      "rp, rb, %d * ldx * %s);" % (T, T, t, j - j0, T, j, sz))
                     lines.append("  }")
-                own = [i for i in range(i0, i1) if j0 <= i < j1]
-                if own and ntile > 1:
-                    lines.append("  if (wv == 0) {  // own-row p of the output modes in this tile")
-                    for i in own:
-                        lines.append("    pown[%d * 64 + lane] = *reinterpret_cast<const %s*>(xb%d + l0 + %d * sizeof(%s));"
-                                     % (i - i0, T, t, i - j0, T))
-                    lines.append("  }")
-            for ch in range(nch):
-                k0, k1 = ch * KC, min(nk, (ch + 1) * KC)
-                mine = [e for e in ent if k0 <= e[0] < k1 and i0 <= e[1] < i1 and j0 <= e[2] < j1]
-                js = sorted({e[2] for e in mine})
-                if not js:
-                    continue
-                ks = sorted({e[0] for e in mine})
-                lines.append("  if (wv == %d) {  // coefficient matrices %d..%d" % (ch, k0, k1 - 1))
-                if ntile > 1:
-                    # an opaque zero offset per tile keeps the compiler from
-                    # reusing the previous tile's loads (which would keep the
-                    # values of every chunk live across the whole kernel)
-                    lines.append("    const int zk = opaque_zero();")
-                for k in ks:
-                    for q in range(7):
-                        lines.append("    const %s k%d_%d = buf_load<%s>(rv, rb, %d * NR * %s%s);"
-                                     % (T, k, q, T, k * 7 + q, sz, " + zk" if ntile > 1 else ""))
-                # straight-line modes; an empty asm statement with a memory
-                # clobber before the LDS reads of mode t+1 (issued before mode
-                # t's arithmetic, so their latency overlaps it) keeps them from
-                # being hoisted further up (live registers of two modes)
-                for q in range(7):
-                    lines.append("    %s n%d = *reinterpret_cast<const %s*>(xb%d + l%d + %d * sizeof(%s));"
-                                 % (T, q, T, t, q, js[0] - j0, T))
-                for u, j in enumerate(js):
-                    lines.append("    {  // mode %d" % j)
-                    for q in range(7):
-                        lines.append("      const %s u%d = n%d;" % (T, q, q))
-                    if u + 1 < len(js):
-                        lines.append('      asm volatile("" ::: "memory");')
+            for w in range(nw):
+                chunks = [ch for ch in range(nch) if ch % nw == w]
+                body = []
+                for ch in chunks:
+                    k0, k1 = ch * KC, min(nk, (ch + 1) * KC)
+                    mine = [e for e in ent if k0 <= e[0] < k1 and i0 <= e[1] < i1 and j0 <= e[2] < j1]
+                    js = sorted({e[2] for e in mine})
+                    if not js:
+                        continue
+                    ks = sorted({e[0] for e in mine})
+                    body.append("    {  // coefficient matrices %d..%d" % (k0, k1 - 1))
+                    if ntile > 1:
+                        # an opaque zero offset per tile keeps the compiler from
+                        # reusing the previous tile's loads (which would keep
+                        # the matrix values live across the whole kernel)
+                        body.append("    const int zk = opaque_zero();")
+                    for k in ks:
                         for q in range(7):
-                            lines.append("      n%d = *reinterpret_cast<const %s*>(xb%d + l%d + %d * sizeof(%s));"
-                                         % (q, T, t, q, js[u + 1] - j0, T))
-                    for k in sorted({e[0] for e in mine if e[2] == j}):
-                        expr = "k%d_0 * u0" % k
-                        for q in range(1, 7):
-                            expr = "fma(k%d_%d, u%d, %s)" % (k, q, q, expr)
-                        lines.append("      { const %s w = %s;" % (T, expr))
-                        for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
-                            lines.append("        y%d = fma(%s(%.17g), w, y%d);" % (i, T, v, i))
-                        lines.append("      }")
-                    lines.append("    }")
-                lines.append("  }")
-        if nch > 1:
+                            body.append("    const %s k%d_%d = buf_load<%s>(rv, rb, %d * NR * %s%s);"
+                                        % (T, k, q, T, k * 7 + q, sz, " + zk" if ntile > 1 else ""))
+                    # straight-line modes; an empty asm statement with a memory
+                    # clobber before the LDS reads of mode t+1 (issued before
+                    # mode t's arithmetic, so their latency overlaps it) keeps
+                    # them from being hoisted further up (live registers of two
+                    # modes)
+                    for q in range(7):
+                        body.append("    %s n%d = *reinterpret_cast<const %s*>(xb%d + l%d + %d * sizeof(%s));"
+                                    % (T, q, T, t, q, js[0] - j0, T))
+                    for u, j in enumerate(js):
+                        body.append("    {  // mode %d" % j)
+                        for q in range(7):
+                            body.append("      const %s u%d = n%d;" % (T, q, q))
+                        if u + 1 < len(js):
+                            body.append('      asm volatile("" ::: "memory");')
+                            for q in range(7):
+                                body.append("      n%d = *reinterpret_cast<const %s*>(xb%d + l%d + %d * sizeof(%s));"
+                                            % (q, T, t, q, js[u + 1] - j0, T))
+                        for k in sorted({e[0] for e in mine if e[2] == j}):
+                            expr = "k%d_0 * u0" % k
+                            for q in range(1, 7):
+                                expr = "fma(k%d_%d, u%d, %s)" % (k, q, q, expr)
+                            body.append("      { const %s w = %s;" % (T, expr))
+                            for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
+                                body.append("        y%d = fma(%s(%.17g), w, y%d);" % (i, T, v, i))
+                            body.append("      }")
+                        body.append("    }")
+                    body.append("    }")
+                if body:
+                    if RG > 1:  # one chunk wave; wv numbers the row groups
+                        lines.append("  if (active) {  // chunk(s) %s" % ", ".join(map(str, chunks)))
+                    else:
+                        lines.append("  if (wv == %d) {  // chunk(s) %s" % (w, ", ".join(map(str, chunks))))
+                    lines.extend(body)
+                    lines.append("  }")
+        if nw > 1:
             if ntile > 1:
                 lines.append("  __syncthreads();  // the staging buffer now holds the wave partials")
             lines.append("  if (wv > 0) {")
@@ -286,10 +336,12 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
             lines.append("  if (wv != 0) return;")
             # one wave's partials at a time (the asm statement keeps the LDS
             # reads of all waves from being issued together)
-            for w in range(nch - 1):
+            for w in range(nw - 1):
                 lines.append('  asm volatile("" ::: "memory");')
                 for i in range(i0, i1):
                     lines.append("  y%d += part[(%d * %d + %d) * 64 + lane];" % (i, w, gs, i - i0))
+        if RG > 1:
+            lines.append("  if (!active) return;  // after the last barrier")
         lines.append("  if (live) {")
         for i in range(i0, i1):
             lines.append("    { %s v = alpha * y%d; if (beta != %s(0)) v = fma(beta, buf_load<%s>(ry, rb, %d * ldy * %s), v);"
@@ -300,8 +352,15 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
             lines.append("    double v = 0.0;")
             lines.append("    if (live) {")
             for i in range(i0, i1):
-                if ntile > 1:
-                    lines.append("      v += (double)(alpha * y%d) * (double)pown[%d * 64 + lane];" % (i, i - i0))
+                if ntile > 1 and (i - i0) % 8 == 0 and i > i0:
+                    # eight modes at a time (keeps the loads from all being
+                    # hoisted, which would need 2 x G registers)
+                    lines.append('      asm volatile("" ::: "memory");')
+                if ntile > 1:  # the own row's p, formed again as in the staging
+                    lines.append("      { %s p = buf_load<%s>(rz, rb, %d * ldx * %s); if (bt != %s(0)) "
+                                 "p = fma(bt, buf_load<%s>(rx, rb, %d * ldx * %s), p); "
+                                 "v += (double)(alpha * y%d) * (double)p; }"
+                                 % (T, T, i, sz, T, T, i, sz, i))
                 else:
                     lines.append("      v += (double)(alpha * y%d) * (double)*reinterpret_cast<const %s*>(xb0 + l0 + %d * sizeof(%s));"
                                  % (i, T, i, T))
@@ -311,17 +370,19 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
             lines.append("  }")
         lines.append("}")
         lines.append("")
-    return lines, name, (nk, P, G, KC, MT, ngroups, nch, NT)
+    return lines, name, (nk, P, G, KC, MT, ngroups, nch, nw, NT)
 
 
-def _lds_expr(P, G, MT, ngroups, nch, T, pcg):
+def _lds_expr(P, G, MT, ngroups, nw, T, pcg, RG=1):
     """LDS bytes of the largest output-group kernel, as a C expression of hmax."""
     gs = (P + ngroups - 1) // ngroups
     w = 4 if T == "float" else 8
+    S = lds_stride(MT)
+    if RG > 1:
+        return "(size_t)%d * %d * hmax * %d" % (RG, S, w)
     if MT >= P:  # one tile: the partials follow the staged x
-        return "((size_t)%d * hmax + %d) * %d" % (MT, (nch - 1) * gs * 64, w)
-    base = "std::max<size_t>((size_t)%d * hmax, %d)" % (MT, (nch - 1) * gs * 64)
-    return "(%s + %d) * %d" % (base, gs * 64 if pcg else 0, w)
+        return "((size_t)%d * hmax + %d) * %d" % (S, (nw - 1) * gs * 64, w)
+    return "std::max<size_t>((size_t)%d * hmax, %d) * %d" % (S, (nw - 1) * gs * 64, w)
 
 
 def basis_source(L, p_in, p_out):
@@ -335,12 +396,14 @@ def basis_source(L, p_in, p_out):
            '#include "k1_common.h"', "", "namespace sgw {", "namespace k {", ""]
     for T in ("float", "double"):
         for pcg in (False, True):
-            lines, name, (nk_, P_, G, KC, MT, ngroups, nch, NT) = kernel_source(L, p_in, p_out, T, pcg)
-            out.append("// %s%s: %d output group(s) of <= %d modes, %d wave(s) of <= %d coefficient"
-                       " matrices, tiles of %d modes" % (T, " PCG" if pcg else "", ngroups, G, nch,
-                                                          KC, MT))
+            lines, name, (nk_, P_, G, KC, MT, ngroups, nch, nw, NT) = kernel_source(L, p_in, p_out,
+                                                                                     T, pcg)
+            out.append("// %s%s: %d output group(s) of <= %d modes, %d chunk(s) of <= %d coefficient"
+                       " matrices on %d wave(s), tiles of %d modes"
+                       % (T, " PCG" if pcg else "", ngroups, G, nch, KC, nw, MT))
             out.extend(lines)
-            lds = _lds_expr(P, G, MT, ngroups, nch, T, pcg)
+            RG = row_groups(L, p_in, p_out, T)
+            lds = _lds_expr(P, G, MT, ngroups, nw, T, pcg, RG)
             if not pcg:
                 out.append("bool %s_apply(const DEll<%s>& A, const DHalo& H, int r0, int nrows, "
                            "const %s* x, int ldx, %s* y, int ldy, %s alpha, %s beta, int nbatch, "
@@ -349,7 +412,7 @@ def basis_source(L, p_in, p_out):
                 out.append("  const size_t hmax = H.hmax;")
                 out.append("  const size_t sh = %s;" % lds)
                 out.append("  if (ngrp <= 0 || sh > %d) return false;" % LDS_LIMIT)
-                out.append("  dim3 grid(ngrp, 1, nbatch);")
+                out.append("  dim3 grid((ngrp + %d) / %d, 1, nbatch);" % (RG - 1, RG))
                 for g in range(ngroups):
                     out.append("  %s_g%d<<<grid, %d, sh, st>>>(A, H, r0, nrows, x, ldx, y, ldy, alpha, "
                                "beta, sx, sy);" % (name, g, NT))
@@ -364,7 +427,7 @@ def basis_source(L, p_in, p_out):
                 out.append("  const size_t hmax = H.hmax;")
                 out.append("  const size_t sh = %s;" % lds)
                 out.append("  if (ngrp <= 0 || sh > %d) return false;" % LDS_LIMIT)
-                out.append("  dim3 grid(ngrp, 1, 1);")
+                out.append("  dim3 grid((ngrp + %d) / %d, 1, 1);" % (RG - 1, RG))
                 for g in range(ngroups):
                     out.append("  %s_g%d<<<grid, %d, sh, st>>>(A, H, H.r0, nrows, pold, ld, q, ld, "
                                "(%s)1, (%s)0, 0, 0, zs, pnew, rzpart, sc, par, pqg, acct, bpr);"
@@ -380,7 +443,7 @@ def basis_source(L, p_in, p_out):
     out.append("  bool ok = true;")
     for T in ("float", "double"):
         for pcg in (False, True):
-            _, _, _, _, _, ngroups, _ = shape(L, p_in, p_out, T)
+            ngroups = shape(L, p_in, p_out, T)[5]
             name = t + ("_pcg" if pcg else "") + ("_f" if T == "float" else "_d")
             for g in range(ngroups):
                 out.append("  ok = ok && hipFuncSetAttribute((const void*)%s_g%d, "
