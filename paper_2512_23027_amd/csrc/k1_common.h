@@ -45,6 +45,14 @@ __device__ __forceinline__ int opaque_zero() {
   return z;
 }
 
+// Byte offset of the per-wave p'q partials in the LDS of a shared PCG kernel:
+// after the larger of the staged halo (hmax entries of eb bytes) and the
+// wave partials of one output slice (rb bytes), 8-byte aligned.
+__host__ __device__ inline size_t shared_pq_offset(size_t hmax, size_t eb, size_t rb) {
+  const size_t a = hmax * eb;
+  return ((a > rb ? a : rb) + 7) & ~(size_t)7;
+}
+
 // Kernels with the Galerkin tensor of a fixed basis unrolled (gen_k1.py).
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i to XCD
 // i % 8), each with its own L2.  This bijection gives XCD x a contiguous

@@ -47,6 +47,15 @@ BASES = {
 }
 LDS_LIMIT = 160 * 1024
 
+# (L, p_in, p_out) -> {precision: (NW, KC, MT, RB)}: PCG kernels that spread
+# the coefficient matrices over NW waves of one workgroup (at most KC
+# matrices held at a time) and stage p in tiles of MT modes, read once per
+# row group; RB bytes of LDS hold the wave partials of one output slice.
+# Used when the halo fits; the tiled kernel of BASES otherwise.
+SHARED = {
+    (8, 2, 3): {"float": (8, 6, 165, 96 * 1024)},
+}
+
 
 def _graded(L, p):
     out = []
@@ -167,10 +176,13 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
         extra = (", const {T}* __restrict__ zs, {T}* __restrict__ pnew, "
                  "const double* __restrict__ rzpart, double* __restrict__ sc, int par, "
                  "double* __restrict__ pqg, unsigned long long* acct, unsigned bpr").format(T=T) if pcg else ""
-        lines.append("__global__ __launch_bounds__(%d) void %s_g%d(DEll<%s> A, DHalo H, int r0, "
+        # several row groups per workgroup: two waves per SIMD (at most 256
+        # registers per lane, no accumulation registers beyond them)
+        lb = "%d, 2" % NT if RG > 1 else "%d" % NT
+        lines.append("__global__ __launch_bounds__(%s) void %s_g%d(DEll<%s> A, DHalo H, int r0, "
                      "int nrows, const %s* __restrict__ x, int ldx, %s* __restrict__ y, int ldy, "
                      "%s alpha, %s beta, long long sx, long long sy%s) {"
-                     % (NT, name, g, T, T, T, T, T, extra))
+                     % (lb, name, g, T, T, T, T, T, extra))
         lines.append("  extern __shared__ unsigned char k1_smem[];")
         if RG > 1:
             lines.append("  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));")
@@ -220,9 +232,12 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
             lines.append("  const double rzo = sc[(size_t)blk * 8 + 1 - par];")
             lines.append("  const %s bt = (%s)(isinf(rzo) ? 0.0 : rzn / rzo);" % (T, T))
             if g == 0:
-                lines.append("  if (active && lane == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
+                # one thread per row group: lane 0 of the group's wave (RG > 1)
+                # or of wave 0 (the waves of a workgroup share the group)
+                first = "lane == 0" if RG > 1 else "threadIdx.x == 0"
+                lines.append("  if (active && %s && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;" % first)
                 lines.append("  // algorithmic bytes of the rows this launch processes (timed launches)")
-                lines.append("  if (acct && active && lane == 0) atomicAdd(acct, (unsigned long long)gn * bpr);")
+                lines.append("  if (acct && active && %s) atomicAdd(acct, (unsigned long long)gn * bpr);" % first)
             lines.append("  const auto rz = buf_rsrc(zs);")
         if RG > 1 and not pcg:
             lines.append("  const bool active = has;")
@@ -373,6 +388,260 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
     return lines, name, (nk, P, G, KC, MT, ngroups, nch, nw, NT)
 
 
+def shared_plan(L, p_in, p_out, T):
+    """(NW, MT, waves, R, sl) of a shared PCG kernel: waves[w] = the
+    sub-chunks (lists of at most KC coefficient matrices) of wave w, the
+    matrices dealt to the waves by their work (7 stencil products per (k, j)
+    pair plus one product per tensor entry), largest first, to the least
+    loaded wave; R output slices of sl modes for the reduction of the wave
+    partials."""
+    nk, P, ent = entries(L, p_in, p_out)
+    NW, KC, MT, budget = SHARED[(L, p_in, p_out)][T]
+    w = 4 if T == "float" else 8
+    pairs, trip = {}, {}
+    for (k, i, j, v) in ent:
+        pairs.setdefault(k, set()).add(j)
+        trip[k] = trip.get(k, 0) + 1
+    cost = {k: 7 * len(pairs.get(k, ())) + trip.get(k, 0) for k in range(nk)}
+    load = [0] * NW
+    own = [[] for _ in range(NW)]
+    for k in sorted(range(nk), key=lambda k: (-cost[k], k)):
+        if cost[k] == 0:
+            continue
+        wv = min(range(NW), key=lambda q: (load[q], q))
+        load[wv] += cost[k]
+        own[wv].append(k)
+    waves = []
+    for ks in own:
+        ks = sorted(ks)
+        waves.append([ks[a:a + KC] for a in range(0, len(ks), KC)])
+    R = max(1, -(-NW * P * 64 * w // budget))
+    sl = -(-P // R)
+    R = -(-P // sl)
+    return NW, min(MT, P), waves, R, sl
+
+
+UNS = 16  # staging loads in flight per thread and vector (first tile)
+
+
+def shared_source(L, p_in, p_out, T):
+    """The shared PCG kernel of a basis and precision (see SHARED).
+
+    Tiles of MT modes.  Staging: the threads of the workgroup take the halo
+    columns h (per threads to a column, each every per-th mode j of the
+    tile), form p = z + beta p_old there, UNS modes at a time, and store it
+    at xs[h * S + j - j0] (S odd: consecutive columns fall in different
+    banks).  Products: wave w contracts its coefficient matrices against the
+    tile's modes, reading the 7 neighbours of its rows from LDS, two modes
+    per read.  Reduction: for each slice of output modes every wave writes
+    its partial sums to LDS (over the staged tile, no longer needed) and
+    wave w then adds the partials of the slice's modes w, w + NW, ... in wave
+    order and stores them; p'q of the rows is formed from the stored values
+    and the own rows' p (formed again from z and p_old as in the staging)."""
+    nk, P, ent = entries(L, p_in, p_out)
+    NW, MT, waves, R, sl = shared_plan(L, p_in, p_out, T)
+    ntile = -(-P // MT)
+    S = lds_stride(MT)
+    NT = 64 * NW
+    w = 4 if T == "float" else 8
+    sz = "(int)sizeof(%s)" % T
+    M = -(-sl // NW)  # outputs per wave and slice
+    # workgroups per CU the LDS allows at the typical halo (for the register
+    # budget: 2 waves per SIMD need at most 256 registers per lane)
+    wpe = 2
+    name = tag(L, p_in, p_out) + "_pcg" + ("_f" if T == "float" else "_d") + "_s"
+    out = []
+    a = out.append
+    a("__global__ __launch_bounds__(%d, %d) void %s(DEll<%s> A, DHalo H, int nrows, "
+      "const %s* __restrict__ x, int ldx, %s* __restrict__ y, int ldy, "
+      "const %s* __restrict__ zs, %s* __restrict__ pnew, const double* __restrict__ rzpart, "
+      "double* __restrict__ sc, int par, double* __restrict__ pqg, unsigned long long* acct, "
+      "unsigned bpr) {" % (NT, wpe, name, T, T, T, T, T))
+    a("  extern __shared__ unsigned char k1_smem[];")
+    a("  %s* xs = reinterpret_cast<%s*>(k1_smem);  // [hmax][%d] staged tile of p; then the wave partials"
+      % (T, T, S))
+    a("  const int lane = threadIdx.x & 63;")
+    a("  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));")
+    a("  const int grp = xcd_group(blockIdx.x, gridDim.x);")
+    a("  const int blk = H.gblk[grp];")
+    a("  if (sc[(size_t)blk * 8 + 2 + par] == 0.0) return;  // converged block: frozen (whole workgroup)")
+    a("  const int g0 = H.grow[grp], gn = H.grow[grp + 1] - g0;  // rows of this group")
+    a("  const bool live = lane < gn && g0 + lane - H.r0 < nrows;")
+    a("  const int r = g0 + (live ? lane : 0);")
+    a("  const int NR = A.nrows;")
+    a("  const auto rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y), rz = buf_rsrc(zs);")
+    a("  const int rb = r * %s;" % sz)
+    a("  // beta of this group's block; the block's first group stores the new r'z")
+    a("  double rzn = 0.0;")
+    a("  for (int j = 0; j < %d; ++j) rzn += rzpart[(size_t)blk * %d + j];" % (P, P))
+    a("  const double rzo = sc[(size_t)blk * 8 + 1 - par];")
+    a("  const %s bt = (%s)(isinf(rzo) ? 0.0 : rzn / rzo);" % (T, T))
+    a("  if (threadIdx.x == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
+    a("  // algorithmic bytes of the rows this launch processes (timed launches)")
+    a("  if (acct && threadIdx.x == 0) atomicAdd(acct, (unsigned long long)gn * bpr);")
+    a("  const int h0 = H.ptr[grp], nh = H.ptr[grp + 1] - h0;")
+    a("  const int rr = r - H.r0;")
+    for q in range(7):
+        a("  const unsigned l%d = (unsigned)H.lcol[%d * H.nr + rr] * %du * %du;" % (q, q, S, w))
+    a("  const char* xb = reinterpret_cast<const char*>(xs);")
+    a("  // thread t stages column t % nh, modes t / nh + m * per (per threads a column)")
+    a("  const int per = nh > 0 ? max(1, %d / nh) : 1, jt = nh > 0 ? (int)threadIdx.x / nh : 1;" % NT)
+    for i in range(P):
+        a("  %s y%d = %s(0);" % (T, i, T))
+    for t in range(ntile):
+        j0, j1 = t * MT, min(P, (t + 1) * MT)
+        a("  // ---- tile %d: modes %d..%d" % (t, j0, j1 - 1))
+        if t > 0:
+            a("  __syncthreads();  // every wave is done with the previous tile")
+        # later tiles stage while the accumulators are live: fewer loads in flight
+        un = UNS if t == 0 else UNS // 2
+        a("  if (jt < per) {  // stage p = z + beta p_old")
+        a("    for (int h = (int)threadIdx.x %% nh; h < nh; h += %d) {" % NT)
+        a("      const int co = H.idx[h0 + h] * %s;" % sz)
+        a("      %s* dst = xs + h * %d - %d;" % (T, S, j0))
+        for first in (False, True):
+            # beta = 0 (the first iteration, p_old undefined) reads z alone
+            a("      %s {" % ("if (bt != %s(0))" % T if not first else "else"))
+            a("        int j = %d + jt;" % j0)
+            a("        for (; j + %d * per < %d; j += %d * per) {" % (un - 1, j1, un))
+            a("          %s v[%d];" % (T, un))
+            a("#pragma unroll")
+            a("          for (int u = 0; u < %d; ++u) {" % un)
+            a("            const int o = co + (j + u * per) * ldx * %s;" % sz)
+            if first:
+                a("            v[u] = buf_load<%s>(rz, o, 0);" % T)
+            else:
+                a("            v[u] = fma(bt, buf_load<%s>(rx, o, 0), buf_load<%s>(rz, o, 0));" % (T, T))
+            a("          }")
+            a("#pragma unroll")
+            a("          for (int u = 0; u < %d; ++u) dst[j + u * per] = v[u];" % un)
+            a("        }")
+            a("        for (; j < %d; j += per) {" % j1)
+            a("          const int o = co + j * ldx * %s;" % sz)
+            if first:
+                a("          dst[j] = buf_load<%s>(rz, o, 0);" % T)
+            else:
+                a("          dst[j] = fma(bt, buf_load<%s>(rx, o, 0), buf_load<%s>(rz, o, 0));" % (T, T))
+            a("        }")
+            a("      }")
+        a("    }")
+        a("  }")
+        a("  __syncthreads();")
+        a("  if (live) {  // the new direction of the own row: modes %d + wv, + %d, ..." % (j0, NW))
+        a("    const auto rp = buf_rsrc(pnew);")
+        a("    for (int j = %d + wv; j < %d; j += %d)" % (j0, j1, NW))
+        a("      buf_store<%s>(*reinterpret_cast<const %s*>(xb + l0 + (j - %d) * sizeof(%s)), rp, rb, j * ldx * %s);"
+          % (T, T, j0, T, sz))
+        a("  }")
+        for wq, subs in enumerate(waves):
+            a("  %s (wv == %d) {  // coefficient matrices %s" % ("if" if wq == 0 else "} else if", wq,
+                                                               ", ".join(str(k) for sub in subs for k in sub)))
+            for sub in subs:
+                ks = set(sub)
+                mine = [e for e in ent if e[0] in ks and j0 <= e[2] < j1]
+                js = sorted({e[2] for e in mine})
+                if not js:
+                    continue
+                a("    {  // matrices %s" % ", ".join(map(str, sub)))
+                if ntile > 1:
+                    # an opaque zero offset per tile keeps the compiler from
+                    # reusing the previous tile's loads (which would keep
+                    # the matrix values live across the whole kernel)
+                    a("    const int zk = opaque_zero();")
+                for k in sub:
+                    if not any(e[0] == k for e in mine):
+                        continue
+                    for q in range(7):
+                        a("    const %s k%d_%d = buf_load<%s>(rv, rb, %d * NR * %s%s);"
+                          % (T, k, q, T, k * 7 + q, sz, " + zk" if ntile > 1 else ""))
+                # modes in runs of at most two consecutive ones: the two values
+                # of a neighbour come in one two-address LDS read
+                runs = []
+                for j in js:
+                    if runs and len(runs[-1]) < 2 and runs[-1][-1] + 1 == j:
+                        runs[-1].append(j)
+                    else:
+                        runs.append([j])
+
+                def reads(run, decl):
+                    for q in range(7):
+                        for b_, j in enumerate(run):
+                            a("    %s%sn%d_%d = *reinterpret_cast<const %s*>(xb + l%d + %d * sizeof(%s));"
+                              % ("  " if not decl else "", (T + " ") if decl else "", q, b_, T, q, j - j0, T))
+
+                reads(runs[0], True)
+                if len(runs[0]) < 2:
+                    for q in range(7):
+                        a("    %s n%d_1 = %s(0);" % (T, q, T))
+                for u, run in enumerate(runs):
+                    a("    {  // mode(s) %s" % ", ".join(map(str, run)))
+                    for b_ in range(len(run)):
+                        for q in range(7):
+                            a("      const %s u%d_%d = n%d_%d;" % (T, q, b_, q, b_))
+                    if u + 1 < len(runs):
+                        # the LDS reads of the next run are issued before this
+                        # run's products (the asm statement keeps them from
+                        # moving further up)
+                        a('      asm volatile("" ::: "memory");')
+                        reads(runs[u + 1], False)
+                    for b_, j in enumerate(run):
+                        for k in sorted({e[0] for e in mine if e[2] == j}):
+                            expr = "k%d_0 * u0_%d" % (k, b_)
+                            for q in range(1, 7):
+                                expr = "fma(k%d_%d, u%d_%d, %s)" % (k, q, q, b_, expr)
+                            a("      { const %s w = %s;" % (T, expr))
+                            for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
+                                a("        y%d = fma(%s(%.17g), w, y%d);" % (i, T, v, i))
+                            a("      }")
+                    a("    }")
+                # the next sub-chunk's matrix loads stay below this one's
+                # last products (both sets of values live would not fit)
+                a('    asm volatile("" ::: "memory");')
+                a("    }")
+        a("  }")
+    a("  double pq = 0.0;")
+    a("  %s* part = xs;  // [wave][slice mode][64]" % T)
+    for t in range(R):
+        s0, s1 = t * sl, min(P, (t + 1) * sl)
+        a("  // ---- output slice %d: modes %d..%d" % (t, s0, s1 - 1))
+        a("  __syncthreads();  // %s" % ("the products no longer read the staged p" if t == 0
+                                        else "the previous slice is added up"))
+        for i in range(s0, s1):
+            a("  part[(wv * %d + %d) * 64 + lane] = y%d;" % (sl, i - s0, i))
+        a("  __syncthreads();")
+        for m in range(M):
+            a("  if (wv + %d < %d) {" % (NW * m, s1 - s0))
+            a("    const int o = wv + %d;" % (NW * m))
+            terms = ["part[(%d * %d + o) * 64 + lane]" % (q, sl) for q in range(NW)]
+            a("    %s s = %s;" % (T, terms[0]))
+            for tm in terms[1:]:
+                a("    s += %s;" % tm)
+            a("    if (live) {")
+            a("      const int so = (%d + o) * ldx * %s;" % (s0, sz))
+            a("      const %s p = bt != %s(0) ? fma(bt, buf_load<%s>(rx, rb, so), buf_load<%s>(rz, rb, so))"
+              " : buf_load<%s>(rz, rb, so);" % (T, T, T, T, T))
+            a("      buf_store<%s>(s, ry, rb, (%d + o) * ldy * %s);" % (T, s0, sz))
+            a("      pq += (double)s * (double)p;")
+            a("    }")
+            a("  }")
+    a("  // p'q of the row group: wave sums, then the waves in order")
+    a("  for (int o = 32; o > 0; o >>= 1) pq += __shfl_xor(pq, o, 64);")
+    a("  double* pqw = reinterpret_cast<double*>(k1_smem + shared_pq_offset(H.hmax, %d, %d));"
+      % (S * w, NW * sl * 64 * w))
+    a("  if (lane == 0) pqw[wv] = pq;")
+    a("  __syncthreads();")
+    a("  if (threadIdx.x == 0) {")
+    a("    double v = pqw[0];")
+    for q in range(1, NW):
+        a("    v += pqw[%d];" % q)
+    a("    pqg[grp] = v;")
+    a("  }")
+    a("}")
+    a("")
+    lds = "(shared_pq_offset(hmax, %d, %d) + %d)" % (S * w, NW * sl * 64 * w, NW * 8)
+    return out, name, NT, lds
+
+
 def _lds_expr(P, G, MT, ngroups, nw, T, pcg, RG=1):
     """LDS bytes of the largest output-group kernel, as a C expression of hmax."""
     gs = (P + ngroups - 1) // ngroups
@@ -404,6 +673,16 @@ def basis_source(L, p_in, p_out):
             out.extend(lines)
             RG = row_groups(L, p_in, p_out, T)
             lds = _lds_expr(P, G, MT, ngroups, nw, T, pcg, RG)
+            shared = pcg and T in SHARED.get((L, p_in, p_out), {})
+            if shared:
+                # both kernels write one p'q per row group
+                assert ngroups == 1
+                slines, sname, SNT, slds = shared_source(L, p_in, p_out, T)
+                NW_, MT_, waves_, R_, sl_ = shared_plan(L, p_in, p_out, T)
+                out.append("// %s PCG, shared halo tiles of %d modes: %d waves (matrices %s), %d output"
+                           " slice(s) of %d" % (T, MT_, NW_, " | ".join(",".join(str(k) for sub in wq for k in sub)
+                                                                      for wq in waves_), R_, sl_))
+                out.extend(slines)
             if not pcg:
                 out.append("bool %s_apply(const DEll<%s>& A, const DHalo& H, int r0, int nrows, "
                            "const %s* x, int ldx, %s* y, int ldy, %s alpha, %s beta, int nbatch, "
@@ -425,6 +704,13 @@ def basis_source(L, p_in, p_out):
                            "hipStream_t st) {" % (t, T, T, T, T, T))
                 out.append("  const int ngrp = halo_groups(H, H.r0, nrows);")
                 out.append("  const size_t hmax = H.hmax;")
+                if shared:
+                    out.append("  const size_t ss = %s;" % slds)
+                    out.append("  if (ngrp > 0 && ss <= %d) {  // the whole halo fits: shared kernel" % LDS_LIMIT)
+                    out.append("    %s<<<ngrp, %d, ss, st>>>(A, H, nrows, pold, ld, q, ld, zs, pnew, rzpart, "
+                               "sc, par, pqg, acct, bpr);" % (sname, SNT))
+                    out.append("    return true;")
+                    out.append("  }")
                 out.append("  const size_t sh = %s;" % lds)
                 out.append("  if (ngrp <= 0 || sh > %d) return false;" % LDS_LIMIT)
                 out.append("  dim3 grid((ngrp + %d) / %d, 1, 1);" % (RG - 1, RG))
@@ -434,8 +720,13 @@ def basis_source(L, p_in, p_out):
                                % (name, g, NT, T, T))
                 out.append("  return true;")
                 out.append("}")
-            out.append("size_t %s%s_lds(%s, int hmax_i) { const size_t hmax = hmax_i; return %s; }"
-                       % (t, "_pcg" if pcg else "", T + "*", lds))
+            if shared:  # the kernel that runs: the shared one where it fits
+                out.append("size_t %s_pcg_lds(%s, int hmax_i) { const size_t hmax = hmax_i; "
+                           "const size_t ss = %s; return ss <= %d ? ss : %s; }"
+                           % (t, T + "*", slds, LDS_LIMIT, lds))
+            else:
+                out.append("size_t %s%s_lds(%s, int hmax_i) { const size_t hmax = hmax_i; return %s; }"
+                           % (t, "_pcg" if pcg else "", T + "*", lds))
             out.append("")
     out.append("int %s_groups(int wbytes) { return wbytes == 4 ? %d : %d; }"
                % (t, shape(L, p_in, p_out, "float")[5], shape(L, p_in, p_out, "double")[5]))
@@ -445,10 +736,13 @@ def basis_source(L, p_in, p_out):
         for pcg in (False, True):
             ngroups = shape(L, p_in, p_out, T)[5]
             name = t + ("_pcg" if pcg else "") + ("_f" if T == "float" else "_d")
-            for g in range(ngroups):
-                out.append("  ok = ok && hipFuncSetAttribute((const void*)%s_g%d, "
+            kern = ["%s_g%d" % (name, g) for g in range(ngroups)]
+            if pcg and T in SHARED.get((L, p_in, p_out), {}):
+                kern.append(name + "_s")
+            for kn in kern:
+                out.append("  ok = ok && hipFuncSetAttribute((const void*)%s, "
                            "hipFuncAttributeMaxDynamicSharedMemorySize, %d) == hipSuccess;"
-                           % (name, g, LDS_LIMIT))
+                           % (kn, LDS_LIMIT))
     out.append("  return ok;")
     out.append("}")
     out.extend(["", "}  // namespace k", "}  // namespace sgw", ""])

@@ -1,31 +1,34 @@
-"""The stored oracle values of the 256x256, P = 35 workload are what the
-oracle computes now: the first recorded step is recomputed (CPU, ~10 s)."""
+"""The stored oracle runs are what the oracle computes now: their layout is
+checked, and the first stored step of the 256x256, P = 35 workload is
+recomputed here (CPU, ~15 s) and compared over every node."""
 
 import numpy as np
+import pytest
 
-import golden_cfg2
+import golden_io
 import workloads
 from oracle.sg import SGProblem
 
 
 def test_golden_file_layout():
-    g = golden_cfg2.load()
-    assert sorted(g) == [2, 10, 50, 100, 200, 300, 400, 500]
-    for nm, ns, m, s in g.values():
-        assert m.shape == s.shape == (17 * 17,)
-        assert nm > 0 and ns > 0 and np.all(s >= 0)
+    for name, n, steps, dtype_ok in (("cfg2", 256, [2, 10, 25, 100, 200, 500], True),
+                                     ("cfg5", 512, [2, 10, 20], True)):
+        g, nn = golden_io.load(name)
+        if name == "cfg5" and not g:
+            pytest.skip("cfg5 oracle run not stored")
+        assert nn == n and sorted(g) == steps, (name, sorted(g))
+        for m, s in g.values():
+            assert m.shape == s.shape == ((n + 1) ** 2,)
+            assert np.all(s >= 0) and np.linalg.norm(m) > 0 and np.linalg.norm(s) > 0
 
 
 def test_golden_step2_matches_oracle():
-    g = golden_cfg2.load()
+    g, _ = golden_io.load("cfg2")
     pr = SGProblem(workloads.config("cfg2"), solver="cg")
     U, V, A = pr.initial_state()
     for _ in range(2):
         U, V, A = pr.step(U, V, A)
     m, s = pr.moments(U)
-    nm, ns, gm, gs = g[2]
-    sub = golden_cfg2.subgrid(256)
-    assert np.allclose(m[sub], gm, rtol=1e-10, atol=1e-14 * np.abs(gm).max())
-    assert np.allclose(s[sub], gs, rtol=1e-10, atol=1e-14 * np.abs(gs).max())
-    assert abs(np.linalg.norm(m) - nm) <= 1e-10 * nm
-    assert abs(np.linalg.norm(s) - ns) <= 1e-10 * ns
+    gm, gs = g[2]
+    assert np.linalg.norm(m - gm) <= 1e-10 * np.linalg.norm(gm)
+    assert np.linalg.norm(s - gs) <= 1e-10 * np.linalg.norm(gs)

@@ -5,7 +5,7 @@ SGW_GUESS_LEARNED on the learned-guess workload (the 32x32, P = 6 problem
 with seeded pulse centres): trained with sgw_guess_train on 200-step
 trajectories of the 10 training seeds, then run for 200 steps on each of the
 5 held-out seeds.  Its results match the oracle to the same bound as the
-other guesses (1e-10 at rtol 1e-12, the FP64 bound), and it must save outer
+other guesses (1e-10 after 200 steps at rtol 1e-13, the FP64 bound), and it must save outer
 PCG iterations against the Newmark-extrapolated guess it corrects on every
 held-out seed (at least 10 % of them); iterations and time per step of the
 three guesses are printed.
@@ -104,8 +104,8 @@ def test_recording_layout(sgw):
     s.close()
 
 
-def _run(sgw, prm, nsteps, guess, model=None):
-    s = sgw.Solver(prm, rtol=1e-12, inner_rtol=1e-14, guess=guess)
+def _run(sgw, prm, nsteps, guess, model=None, rtol=1e-12):
+    s = sgw.Solver(prm, rtol=rtol, inner_rtol=1e-14, guess=guess)
     s.factor()
     s.set_state()
     if model is not None:
@@ -142,7 +142,9 @@ def test_learned_guess_saves_iterations(sgw):
     s.set_guess_model(model)
     loss = 0.0
     for q, sd in enumerate(train_seeds):
-        s.set_state(U=torch.from_numpy(_pulse(workloads.cfg4(sd))[None, :].copy()))
+        U0 = np.zeros((s.P, s.nn))
+        U0[0] = _pulse(workloads.cfg4(sd))
+        s.set_state(U=torch.from_numpy(U0))
         last = q + 1 == len(train_seeds)
         loss = s.guess_train(nsteps, epochs=30 if last else 0, batch=1024, lr=1e-3, seed=2,
                              clear=q == 0)
@@ -162,7 +164,8 @@ def test_learned_guess_saves_iterations(sgw):
         res = {}
         for name, g in (("prev", sgw.SGW_GUESS_PREV), ("newmark", sgw.SGW_GUESS_NEWMARK),
                         ("learned", sgw.SGW_GUESS_LEARNED)):
-            st, m, sd_, ms, fb = _run(sgw, prm, nsteps, g, model=model)
+            # rtol 1e-13: 200 steps accumulate the per-step solve errors
+            st, m, sd_, ms, fb = _run(sgw, prm, nsteps, g, model=model, rtol=1e-13)
             assert st["status"] == 0
             assert rel_l2(m, mo) < 1e-10 and rel_l2(sd_, so) < 1e-10, (name, sd)
             res[name] = (st["outer_iters"] / nsteps, ms, fb)
