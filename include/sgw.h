@@ -292,6 +292,15 @@ int sgw_mlp_params(sgw_mlp* m, float* w, int set, int where, void* stream);
 /* y[nb][n_out] = network(x[nb][n_in]), device arrays; waits for the
  * stream. */
 int sgw_mlp_forward(sgw_mlp* m, const float* x, float* y, int nb, void* stream);
+/* Allocation-free variant of sgw_mlp_forward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same kernels, with the two
+ * hidden activations in a static device scratch array of 16 MiB, one per
+ * GPU, held until the process ends (nb x 2 x hidden at most 4 Mi floats,
+ * else SGW_EINVAL).  Calls no allocator and does not wait: the work is
+ * enqueued on the stream.  Calls that overlap on one GPU share that scratch
+ * and race. */
+int sgw_mlp_forward_noalloc(sgw_mlp* m, const float* x, float* y, int nb, void* stream);
 /* Mean squared error of the network on (x[nb][n_in], t[nb][n_out])
  * (host *loss) and its gradient with respect to the parameters (device
  * grad[num_params], may be NULL); waits for the stream. */

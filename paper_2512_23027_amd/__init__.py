@@ -32,7 +32,7 @@ EXPORTS = ["sgw_create", "sgw_factor", "sgw_set_state", "sgw_get_state",
            "sgw_mlp_last_error", "sgw_mlp_num_params", "sgw_mlp_params", "sgw_mlp_forward",
            "sgw_mlp_loss_grad", "sgw_mlp_train", "sgw_guess_record", "sgw_set_guess_model",
            "sgw_step_batch", "sgw_set_cheb_tile", "sgw_set_guess", "sgw_guess_train",
-           "sgw_read_pce"]
+           "sgw_read_pce", "sgw_mlp_forward_noalloc"]
 NOT_INT = ("sgw_query", "sgw_last_error", "sgw_mlp_last_error", "sgw_mlp_num_params")
 
 
@@ -119,6 +119,7 @@ def lib():
         L.sgw_mlp_num_params.restype = ctypes.c_longlong
         L.sgw_mlp_params.argtypes = [vp, vp, ip, ip, vp]
         L.sgw_mlp_forward.argtypes = [vp, vp, vp, ip, vp]
+        L.sgw_mlp_forward_noalloc.argtypes = [vp, vp, vp, ip, vp]
         L.sgw_mlp_loss_grad.argtypes = [vp, vp, vp, ip, vp, fp, vp]
         L.sgw_mlp_train.argtypes = [vp, vp, vp, ip, ip, ip, dp, ull, vp, fp]
         L.sgw_guess_record.argtypes = [vp, vp, vp, ctypes.c_longlong]

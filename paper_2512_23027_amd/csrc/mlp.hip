@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mlp.h"
@@ -197,6 +198,27 @@ void forward(sgw_mlp* m, const float* x, float* y, int nb, hipStream_t st,
                               w + m->off[5], 0, nullptr, st);
 }
 
+// Scratch of the allocation-free forward pass (sgw_mlp_forward_noalloc):
+// the two hidden activations, nb x H floats each.  Every GPU that runs the
+// library holds its own copy until the process ends; host code reaches it
+// only through the per-device address from hipGetSymbolAddress.
+#define SGW_MLP_SCRATCH_FLOATS (4 << 20)  // 16 MiB
+static __device__ __align__(256) float scratch[SGW_MLP_SCRATCH_FLOATS];
+#define SGW_MAX_DEVICES 64
+static float* scratch_ptr[SGW_MAX_DEVICES] = {};
+static std::mutex scratch_mu;
+
+// device address of this device's scratch (looked up once per device, with
+// that device current); nullptr on a HIP error
+float* scratch_address(int dev) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    scratch_ptr[dev] = reinterpret_cast<float*>(p);
+  }
+  return scratch_ptr[dev];
+}
 
 // loss and gradient of the mean squared error of rows xb -> tb (work space)
 void backward(sgw_mlp* m, const float* x, const float* t, int nb, hipStream_t st) {
@@ -350,6 +372,25 @@ int sgw_mlp_forward(sgw_mlp* m, const float* x, float* y, int nb, void* stream) 
   return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : SGW_EHIP;
 }
 
+int sgw_mlp_forward_noalloc(sgw_mlp* m, const float* x, float* y, int nb, void* stream) {
+  if (!m || !x || !y || nb <= 0) return SGW_EINVAL;
+  if ((long long)nb * 2 * m->H > SGW_MLP_SCRATCH_FLOATS) {
+    m->err = "batch too large for the static scratch (nb x 2 x hidden above 4 Mi floats)";
+    return SGW_EINVAL;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SGW_MAX_DEVICES) {
+    m->err = "no usable HIP device";
+    return SGW_EHIP;
+  }
+  float* p = scratch_address(dev);
+  if (!p) {
+    m->err = "hipGetSymbolAddress failed for the scratch array";
+    return SGW_EHIP;
+  }
+  forward(m, x, y, nb, (hipStream_t)stream, p, p + (size_t)nb * m->H);
+  return launch_check(m);
+}
 
 int sgw_mlp_loss_grad(sgw_mlp* m, const float* x, const float* t, int nb, float* grad,
                       float* loss, void* stream) {
