@@ -145,8 +145,10 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* alloc,
 /* Coarse-grid setup on the device: for every subdomain and every local
  * corner degree of freedom, the SG Neumann solve that gives the coarse
  * basis and the local coarse matrix; assembly of F_cc (Eq. Fcc_2) and its
- * Cholesky factor in FP64.  stream may be 0.  Errors: SGW_ESTATE,
- * SGW_ENOTSPD, SGW_EHIP. */
+ * Cholesky factor in FP64 (with FP32 copies of the factor's blocks and an
+ * FP16 copy of the coarse basis for the FP32 solver's preconditioner).
+ * Once per context.  stream may be 0.  Errors: SGW_ESTATE (already
+ * factored), SGW_ENOTSPD, SGW_EHIP. */
 int sgw_factor(sgw_ctx* ctx, void* stream);
 
 /* Set the state (U, V, A), each mode-major [P][(n+1)^2] in memory `where`.

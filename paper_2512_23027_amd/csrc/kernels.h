@@ -198,6 +198,8 @@ void copy2d(int P, int n, const TS* src, int lds, TD* dst, int ldd, double a,
             hipStream_t st);
 template <typename T>
 void fill2d(int P, int n, T* dst, int ldd, T v, hipStream_t st);
+// dst[i] = the FP16 bit pattern of src[i] rounded to nearest (via FP32)
+void to_half(long long n, const double* src, unsigned short* dst, hipStream_t st);
 // dst = a*x + b*y (elementwise over [P][n])
 template <typename T>
 void axpby2d(int P, int n, double a, const T* x, int ldx, double b, const T* y,
@@ -245,7 +247,7 @@ struct DCoarse {
   const int *rem_off, *rem_list;   // remaining torn rows per subdomain
   const int* sc_ptr;               // local corners per subdomain
   const double* phi;               // coarse basis, per subdomain blocks
-  const float* phif;               // its FP32 copy (FP32 solver only)
+  const unsigned short* phih;      // its FP16 copy (bit patterns; FP32 solver only)
   const long long* phi_off;
   int max_rem = 0;                 // largest number of remaining rows
 };
@@ -259,15 +261,18 @@ void coarse_rhs(const DCoarse& c, const T* r, int ldr, const T* yt, int ldt,
 // the coarse vectors; per row i the inverse diagonal block linv[i] and its
 // transpose linvT[i] (m_i x m_i), per row i < R-1 the sub-diagonal block
 // b[i] = L_{i+1,i} (m_{i+1} x m_i) and bT[i] = its transpose, all row-major;
-// four work vectors of n.
+// four work vectors of n; FP32 copies of the blocks for the FP32 solver
+// (single = true: the same sweeps read them, accumulating in FP64).
 struct DCoarseFactor {
   int R = 0, n = 0;
   std::vector<int> off;
   std::vector<const double*> linv, linvT, b, bT;
+  std::vector<const float*> linvf, linvTf, bf, bTf;
   const int* perm = nullptr;
   double *wd = nullptr, *wy = nullptr, *wt = nullptr, *wx = nullptr;
 };
-void coarse_solve(const DCoarseFactor& f, const double* dc, double* uc, hipStream_t st);
+void coarse_solve(const DCoarseFactor& f, const double* dc, double* uc, bool single,
+                  hipStream_t st);
 template <typename T>
 void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt,
                  hipStream_t st);

@@ -1382,17 +1382,26 @@ void coarse_rhs(const DCoarse& c, const T* r, int ldr, const T* yt, int ldt, dou
 // one wave per output row, the row read contiguously by the lanes.
 // out[r] = (a ? a[r] : 0) + sign * sum_c M[r][c] v[c], c over the whole row
 // (tri 0), c <= r (tri 1, lower) or c >= r (tri 2, upper).
-__global__ __launch_bounds__(SGW_BLOCK) void k_coarse_gemv(int nr, int nc, const double* M, int ld,
+template <typename TM>
+__global__ __launch_bounds__(SGW_BLOCK) void k_coarse_gemv(int nr, int nc, const TM* M, int ld,
                                                           const double* v, const double* a,
                                                           double* out, double sign, int tri) {
   const int row = blockIdx.x * (SGW_BLOCK / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= nr) return;
-  const double* mr = M + (size_t)row * ld;
+  const TM* mr = M + (size_t)row * ld;
   const int c0 = tri == 2 ? row : 0, c1 = tri == 1 ? row + 1 : nc;
-  double s = 0.0;
-  for (int col = c0 + lane; col < c1; col += 64) s += mr[col] * v[col];
-  s = wave_sum(s);
+  // four independent partial sums: four row loads in flight per lane
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int col = c0 + lane;
+  for (; col + 192 < c1; col += 256) {
+    s0 += (double)mr[col] * v[col];
+    s1 += (double)mr[col + 64] * v[col + 64];
+    s2 += (double)mr[col + 128] * v[col + 128];
+    s3 += (double)mr[col + 192] * v[col + 192];
+  }
+  for (; col < c1; col += 64) s0 += (double)mr[col] * v[col];
+  const double s = wave_sum((s0 + s1) + (s2 + s3));
   if (lane == 0) out[row] = (a ? a[row] : 0.0) + sign * s;
 }
 __global__ void k_coarse_perm(int n, const int* perm, const double* src, double* dst, int gather) {
@@ -1401,12 +1410,16 @@ __global__ void k_coarse_perm(int n, const int* perm, const double* src, double*
   if (gather) dst[w] = src[perm[w]];
   else dst[perm[w]] = src[w];
 }
-void coarse_solve(const DCoarseFactor& f, const double* dc, double* uc, hipStream_t st) {
-  if (f.n <= 0) return;
+template <typename TM>
+static void coarse_sweeps(const DCoarseFactor& f, const std::vector<const TM*>& linv,
+                          const std::vector<const TM*>& linvT, const std::vector<const TM*>& b,
+                          const std::vector<const TM*>& bT, const double* dc, double* uc,
+                          hipStream_t st) {
   const int wpb = SGW_BLOCK / 64;
-  auto gemv = [&](int nr, int nc, const double* M, const double* v, const double* a, double* out,
+  auto gemv = [&](int nr, int nc, const TM* M, const double* v, const double* a, double* out,
                   double sign, int tri) {
-    k_coarse_gemv<<<(nr + wpb - 1) / wpb, SGW_BLOCK, 0, st>>>(nr, nc, M, nc, v, a, out, sign, tri);
+    k_coarse_gemv<TM><<<(nr + wpb - 1) / wpb, SGW_BLOCK, 0, st>>>(nr, nc, M, nc, v, a, out, sign,
+                                                                  tri);
   };
   const std::vector<int>& o = f.off;
   k_coarse_perm<<<(f.n + 255) / 256, 256, 0, st>>>(f.n, f.perm, dc, f.wd, 1);
@@ -1414,27 +1427,37 @@ void coarse_solve(const DCoarseFactor& f, const double* dc, double* uc, hipStrea
     const int m = o[i + 1] - o[i];
     const double* t = f.wd + o[i];
     if (i > 0) {
-      gemv(m, o[i] - o[i - 1], f.b[i - 1], f.wy + o[i - 1], f.wd + o[i], f.wt + o[i], -1.0, 0);
+      gemv(m, o[i] - o[i - 1], b[i - 1], f.wy + o[i - 1], f.wd + o[i], f.wt + o[i], -1.0, 0);
       t = f.wt + o[i];
     }
-    gemv(m, m, f.linv[i], t, nullptr, f.wy + o[i], 1.0, 1);
+    gemv(m, m, linv[i], t, nullptr, f.wy + o[i], 1.0, 1);
   }
   for (int i = f.R - 1; i >= 0; --i) {
     const int m = o[i + 1] - o[i];
     const double* t = f.wy + o[i];
     if (i + 1 < f.R) {
-      gemv(m, o[i + 2] - o[i + 1], f.bT[i], f.wx + o[i + 1], f.wy + o[i], f.wt + o[i], -1.0, 0);
+      gemv(m, o[i + 2] - o[i + 1], bT[i], f.wx + o[i + 1], f.wy + o[i], f.wt + o[i], -1.0, 0);
       t = f.wt + o[i];
     }
-    gemv(m, m, f.linvT[i], t, nullptr, f.wx + o[i], 1.0, 2);
+    gemv(m, m, linvT[i], t, nullptr, f.wx + o[i], 1.0, 2);
   }
   k_coarse_perm<<<(f.n + 255) / 256, 256, 0, st>>>(f.n, f.perm, f.wx, uc, 0);
+}
+void coarse_solve(const DCoarseFactor& f, const double* dc, double* uc, bool single,
+                  hipStream_t st) {
+  if (f.n <= 0) return;
+  if (single && !f.linvf.empty())
+    coarse_sweeps<float>(f, f.linvf, f.linvTf, f.bf, f.bTf, dc, uc, st);
+  else
+    coarse_sweeps<double>(f, f.linv, f.linvT, f.b, f.bT, dc, uc, st);
 }
 
 // ut[j][rem] += sum_{m, lc} Phi_s[(m, lc)][(j, tr)] uc[m][coarse(lc)]: the
 // subdomain's coarse values go to LDS, each thread owns one output and
 // streams its column of Phi_s (contiguous across the threads).  The FP32
-// path reads an FP32 copy of Phi.
+// path reads an FP16 copy of Phi (half the bytes of this bandwidth-bound
+// product; the lift belongs to the preconditioner, whose Neumann solves in
+// that path stop at a relative residual of 1e-2, far above FP16 rounding).
 template <typename T>
 __global__ __launch_bounds__(SGW_BLOCK) void k_coarse_lift(DCoarse c, const double* uc, T* ut,
                                                           int ldt) {
@@ -1452,9 +1475,10 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_coarse_lift(DCoarse c, const doub
   if (o >= nout) return;
   double acc = 0.0;
   if constexpr (sizeof(T) == 4) {
-    const float* ph = c.phif + c.phi_off[s] + o;
+    const unsigned short* ph = c.phih + c.phi_off[s] + o;
 #pragma unroll 8
-    for (int q = 0; q < nq; ++q) acc += (double)ph[(size_t)q * nout] * ucl[q];
+    for (int q = 0; q < nq; ++q)
+      acc += (double)(float)__builtin_bit_cast(_Float16, ph[(size_t)q * nout]) * ucl[q];
   } else {
     const double* ph = c.phi + c.phi_off[s] + o;
 #pragma unroll 8
@@ -1464,6 +1488,14 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_coarse_lift(DCoarse c, const doub
   T* dst = ut + (size_t)j * ldt + c.rem_list[c.rem_off[s] + tr];
   *dst = (T)((double)*dst + acc);
 }
+__global__ void k_to_half(long long n, const double* src, unsigned short* dst) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = __builtin_bit_cast(unsigned short, (_Float16)(float)src[i]);
+}
+void to_half(long long n, const double* src, unsigned short* dst, hipStream_t st) {
+  if (n > 0) k_to_half<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, src, dst);
+}
+
 template <typename T>
 void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt, hipStream_t st) {
   if (c.nC == 0) return;

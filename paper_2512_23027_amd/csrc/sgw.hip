@@ -120,7 +120,7 @@ struct sgw_ctx {
   std::vector<int> rem_off_h, rem_list_h;
   std::vector<long long> phi_off_h;
   double* phi = nullptr;
-  float* phif = nullptr;
+  unsigned short* phih = nullptr;  // FP16 copy of phi (FP32 solver)
   double* fs = nullptr;   // local coarse matrices during factor
   bool factored = false, has_state = false;
   long long stepno = 0;
@@ -532,10 +532,12 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
       T* pold = par ? S.p : S.p2;
       T* pnew = par ? S.p2 : S.p;
       // timed launches count the algorithmic bytes of the rows they process
-      // (row groups of converged blocks exit at once) on the device:
-      // 7 (M+1) values + 7 column indices + p_old, z in, p, q out per row
+      // (row groups of converged blocks exit at once) on the device: those
+      // of one SG apply, 7 (M+1) values + 7 column indices + one vector in
+      // and one out per row (the fused p update moves two more vectors,
+      // reported apart from these)
       const int a = prof_begin(c, sizeof(T) == 4 ? 3 : 0, s);
-      const unsigned bpr = (unsigned)(7 * c->nk * sizeof(T) + 7 * 4 + 4 * P * sizeof(T));
+      const unsigned bpr = (unsigned)(7 * c->nk * sizeof(T) + 7 * 4 + 2 * P * sizeof(T));
       (void)k::sg_apply_pcg<T>(S.A, c->gt, *S.halo, n, pold, S.z, pnew, n, S.q, c->part, c->sc,
                                par, c->pqg, a >= 0 ? c->acct + 2 + (sizeof(T) == 4) : nullptr,
                                bpr, s);
@@ -638,7 +640,7 @@ static int precond(sgw_ctx* c, PrecT<T>& pr, const Tols& tl, const T* r, T* z, h
   if (rc < 0) return rc;
   if (c->nC > 0) {
     k::coarse_rhs<T>(c->co, r, NF, pr.Yt, NT, c->dc, st);
-    k::coarse_solve(c->cf, c->dc, c->uc, st);
+    k::coarse_solve(c->cf, c->dc, c->uc, sizeof(T) == 4, st);
     k::coarse_lift<T>(c->co, c->nsub, c->uc, pr.Yt, NT, st);
   }
   k::gather_from_torn<T>(nG, P, c->gam_ptr, c->gam_torn, c->gam_w, c->g2c, pr.Yt, NT, c->uc,
@@ -1290,7 +1292,7 @@ static bool check_pointers(sgw_ctx* c) {
       return false;
     }
   if (!prec_complete(c->d64, false) ||
-      (c->h.d.precision == SGW_FP32_IR64 && (!prec_complete(c->f32, true) || !c->phif))) {
+      (c->h.d.precision == SGW_FP32_IR64 && (!prec_complete(c->f32, true) || !c->phih))) {
     c->err = "internal error: a device array of a solver precision was not allocated";
     return false;
   }
@@ -1729,8 +1731,8 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   c->phi = dalloc<double>(c, (size_t)std::max<long long>(1, c->phi_off_h.back()));
   co.phi = c->phi;
   if (dd.precision == SGW_FP32_IR64) {
-    c->phif = dalloc<float>(c, (size_t)std::max<long long>(1, c->phi_off_h.back()));
-    co.phif = c->phif;
+    c->phih = dalloc<unsigned short>(c, (size_t)std::max<long long>(1, c->phi_off_h.back()));
+    co.phih = c->phih;
   }
   co.max_rem = 0;
   for (int s = 0; s < h.nsub; ++s)
@@ -1771,6 +1773,10 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
 
 int sgw_factor(sgw_ctx* c, void* stream) {
   if (!c) return SGW_EINVAL;
+  if (c->factored) {
+    c->err = "the coarse grid is already factored";
+    return SGW_ESTATE;
+  }
   hipStream_t st = (hipStream_t)stream;
   const Host& h = c->h;
   const int P = c->P, NT = c->NT;
@@ -1890,13 +1896,27 @@ int sgw_factor(sgw_ctx* c, void* stream) {
         for (int j = 0; j < nc; ++j) t[(size_t)j * nr + i] = a[(size_t)i * nc + j];
       return t;
     };
+    // the FP32 solver's coarse solves read FP32 copies (a preconditioner:
+    // its Neumann solves stop far above FP32 rounding)
+    const bool single = c->h.d.precision == SGW_FP32_IR64;
+    auto to_f = [](const std::vector<double>& a) { return std::vector<float>(a.begin(), a.end()); };
     for (int r = 0; r < CF.R; ++r) {
       const int m = rows_of(r);
+      const std::vector<double> lt = transpose(CF.linv[r], m, m);
       df.linv.push_back(upload(c, CF.linv[r]));
-      df.linvT.push_back(upload(c, transpose(CF.linv[r], m, m)));
+      df.linvT.push_back(upload(c, lt));
+      if (single) {
+        df.linvf.push_back(upload(c, to_f(CF.linv[r])));
+        df.linvTf.push_back(upload(c, to_f(lt)));
+      }
       if (r + 1 < CF.R) {
+        const std::vector<double> bt = transpose(CF.b[r], rows_of(r + 1), m);
         df.b.push_back(upload(c, CF.b[r]));
-        df.bT.push_back(upload(c, transpose(CF.b[r], rows_of(r + 1), m)));
+        df.bT.push_back(upload(c, bt));
+        if (single) {
+          df.bf.push_back(upload(c, to_f(CF.b[r])));
+          df.bTf.push_back(upload(c, to_f(bt)));
+        }
       }
     }
     std::vector<int> perm(df.n);
@@ -1910,16 +1930,14 @@ int sgw_factor(sgw_ctx* c, void* stream) {
     bool ok = df.perm && df.wd && df.wy && df.wt && df.wx;
     for (auto* v : {&df.linv, &df.linvT, &df.b, &df.bT})
       for (const double* p : *v) ok = ok && p;
+    for (auto* v : {&df.linvf, &df.linvTf, &df.bf, &df.bTf})
+      for (const float* p : *v) ok = ok && p;
     if (!ok) {
       c->err = "device allocation failed (coarse factor)";
       return SGW_ENOMEM;
     }
-    if (c->phif) {  // the FP32 solver's copy of the coarse basis, in chunks of 2^30
-      const long long tot = c->phi_off_h.back();
-      for (long long o = 0; o < tot; o += (1LL << 30)) {
-        const int len = (int)std::min<long long>(tot - o, 1LL << 30);
-        k::copy2d<float, double>(1, len, c->phi + o, len, c->phif + o, len, 1.0, st);
-      }
+    if (c->phih) {  // the FP32 solver's FP16 copy of the coarse basis
+      k::to_half(c->phi_off_h.back(), c->phi, c->phih, st);
       HIPCHK(hipStreamSynchronize(st));
     }
   }

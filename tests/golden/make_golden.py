@@ -8,14 +8,16 @@ recorded steps, the full mean and standard-deviation fields over all
 
 * cfg2 (256x256, P = 35, 8x8 subdomains): steps 2, 10, 25, 100, 200, 500
   -> cfg2_oracle.npz (FP64)
-* cfg5 (512x512, P = 165, 16x16 subdomains): the first 20 steps, stored at
-  steps 2, 10, 20 -> cfg5_oracle.npz (rounded to FP32: its parity bound is
-  1e-6 and FP32 keeps the stored fields within 6e-8 of the oracle's)
+* cfg5 (512x512, P = 165, 16x16 subdomains): the first 30 steps, stored at
+  steps 2, 10, 20, 30 -> cfg5_oracle.npz (rounded to FP32: its parity bound
+  is 1e-6 and FP32 keeps the stored fields within 6e-8 of the oracle's)
 The oracle's CG iteration count of every step is stored too (cg_iterations).
 
-Usage: python tests/golden/make_golden.py cfg2|cfg5
+Usage: python tests/golden/make_golden.py cfg2|cfg5 [--out PATH]
        python tests/golden/make_golden.py cfg2|cfg5 --repack   (keep only the
        stored steps and precision above from a file written with more)
+The file is rewritten after every recorded step (so a long run can be
+inspected); --out writes elsewhere, to be moved into place when complete.
 """
 
 import os
@@ -31,7 +33,7 @@ import workloads  # noqa: E402
 from oracle.sg import SGProblem  # noqa: E402
 
 RECORD = {"cfg2": (2, 10, 25, 100, 200, 500),
-          "cfg5": (2, 10, 20)}
+          "cfg5": (2, 10, 20, 30)}
 DTYPE = {"cfg2": np.float64, "cfg5": np.float32}
 
 
@@ -60,6 +62,8 @@ def main():
     prm = workloads.config(name)
     pr = SGProblem(prm, solver="cg")
     out_path = os.path.join(HERE, "%s_oracle.npz" % name)
+    if "--out" in sys.argv:
+        out_path = sys.argv[sys.argv.index("--out") + 1]
     U, V, A = pr.initial_state()
     fields = {}
     t0 = time.time()

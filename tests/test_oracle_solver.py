@@ -19,6 +19,11 @@
   (the exact exp(sum g_l xi_l), no PCE), and agree with Monte Carlo within
   its standard error.
 * Direct and mean-preconditioned CG solves agree.
+* The premise of the forced-failure GPU test: on a 16x16 mesh (L = 2, input
+  order 2) the SG transient matrix is positive definite at sigma = 0.2, and
+  indefinite at sigma = 3, dt = 1, where the second-order truncation of
+  exp(sigma xi), e^(sigma^2/2) (1 + sigma xi + sigma^2 (xi^2 - 1) / 2), is
+  negative near xi = -1/sigma and the stiffness outweighs the mass term.
 """
 
 import math
@@ -290,3 +295,19 @@ def test_random_initial_condition_vs_gauss_hermite():
     # measured: p = 2: 9.4e-5 / 2.2e-3, p = 4: 4.3e-7 / 2.5e-5 (mean / std)
     assert errs[1][0] < 2e-6 and errs[1][1] < 1e-4, errs
     assert errs[1][0] < 0.1 * errs[0][0] and errs[1][1] < 0.1 * errs[0][1], errs
+
+
+def test_truncated_pce_indefinite_premise():
+    import workloads
+    # the 1-D truncation takes the value (1 - sigma^2) / 2 e^(sigma^2/2) at its minimum
+    sig = 3.0
+    xi = -1.0 / sig
+    f = math.exp(sig * sig / 2) * (1 + sig * xi + sig * sig * (xi * xi - 1) / 2)
+    assert f < 0 and abs(f - (1 - sig * sig) / 2 * math.exp(sig * sig / 2)) < 1e-9 * abs(f)
+    lo = {}
+    for sigma, dt in ((0.2, 0.005), (3.0, 1.0)):
+        prm = workloads.config("cfg1", n=16, xsplits=workloads.uniform_splits(16, 2),
+                               ysplits=workloads.uniform_splits(16, 2), sigma=sigma, dt=dt)
+        K = SGProblem(prm).assembled_Kt()
+        lo[sigma] = float(spla.eigsh(K, k=1, which="SA", return_eigenvectors=False)[0])
+    assert lo[0.2] > 0 and lo[3.0] < -10, lo
