@@ -73,6 +73,10 @@ WORKLOADS = {
             "corr. length 0.25, PCE order 3 (P=165, 43.1M SG unknowns), dt 1e-3, pulse seed 5",
     "cfg2": "cfg2: 256x256 P1 mesh (66,049 nodes), 8x8 subdomains, KLE 4 terms, sigma 0.3, "
             "corr. length 0.3, PCE order 3 (P=35, 2.28M SG unknowns), dt 1e-3, pulse seed 2",
+    "cfg3": "cfg3: 8 independent 384x384 problems (148,225 nodes each), seeded uneven "
+            "rectilinear splits (8-10 strips per side), sigma ~ U[0.1, 0.4], corr. length ~ "
+            "U[0.2, 0.6], KLE 6 terms, PCE order 3 (P=84, 12.3M SG unknowns each), dt 1e-3, "
+            "seeds 300-307, advanced together by sgw_step_batch",
 }
 
 
@@ -343,6 +347,70 @@ def run_stack(sgw, prm, opts, warm, steps, golden, log):
             "autotune_us": tune, "prof": prof, "errors": errors}
 
 
+def run_batch(sgw, names, opts, warm, steps, log):
+    """The batched workload: every problem set up, then advanced together
+    (sgw_step_batch: one stream and host thread per problem); the timed
+    region covers `steps` batched steps.  Problems with stored oracle values
+    are compared after the timed steps (the trajectory run on to the stored
+    steps beyond them) and, for stored steps it passed, after a rerun of the
+    batch from the initial states."""
+    import numpy as np
+    import torch
+    from oracle.sg import rel_l2
+    import workloads
+    t0 = time.perf_counter()
+    ss = []
+    for nm in names:
+        s = sgw.Solver(workloads.config(nm), **opts)
+        s.factor()
+        s.autotune()
+        s.set_state()
+        ss.append(s)
+        log("%s set up (%.1f s)" % (nm, time.perf_counter() - t0))
+    setup_s = time.perf_counter() - t0
+    if warm:
+        sgw.step_batch(ss, warm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sgw.step_batch(ss, steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    log("timed %d batched steps: %.3f s" % (steps, elapsed))
+    goldens = {i: load_golden(nm)[0] for i, nm in enumerate(names)}
+    errors = []
+
+    def compare(i, step, after):
+        m, v = ss[i].moments()
+        gm, gs = goldens[i][step]
+        errors.append({"problem": names[i], "step": step, "after_timing": after,
+                       "mean": rel_l2(m.cpu().numpy(), gm),
+                       "std": rel_l2(np.sqrt(v.cpu().numpy()), gs)})
+
+    done = warm + steps
+    for i in goldens:
+        d = done
+        for step in [g for g in sorted(goldens[i]) if g >= done]:
+            ss[i].step(step - d)
+            d = step
+            compare(i, step, True)
+        earlier = [g for g in sorted(goldens[i]) if g < done]
+        if earlier:
+            ss[i].set_state()
+            d = 0
+            for step in earlier:
+                ss[i].step(step - d)
+                d = step
+                compare(i, step, False)
+    log("accuracy: %s" % errors)
+    for s in ss:
+        s.close()
+    return {"problem_steps_per_s": len(names) * steps / elapsed,
+            "ms_per_batched_step": 1e3 * elapsed / steps,
+            "pcg_iters_per_step": [x["outer_iters"] / steps for x in st],
+            "inner_iters_per_step": [x["inner_iters"] / steps for x in st],
+            "setup_s": setup_s, "errors": errors}
+
+
 SWEEPS = {
     # the paper's studies with its mesh sizes (13,472 / 37,267 vertices) on
     # structured meshes of about the same node counts, the Courant number 0.65
@@ -438,6 +506,24 @@ def main():
         print(json.dumps({"sweep": args.sweep, "solver": "plain FP64 DD-PCG (two-level NN)",
                           "steps": args.steps, "warmup": args.warmup, "rows": rows}),
               flush=True)
+        return
+    if args.workload == "cfg3":
+        names = ["cfg3-%d" % p for p in range(8)]
+        res = run_batch(sgw, names, solver_settings("mixed"), args.warmup, args.steps, log)
+        errs = res["errors"]
+        ok = any(e["after_timing"] for e in errs) and all(max(e["mean"], e["std"]) <= 1e-6
+                                                          for e in errs)
+        print(json.dumps({
+            "metric": METRIC, "value": res["problem_steps_per_s"],
+            "unit": "problem time-steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res["ms_per_batched_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64-refinement", "data": "synthetic",
+            "config": {"workload": WORKLOADS["cfg3"] + "; full stack as for cfg5",
+                       "global_batch": len(names)},
+            "pcg_iters_per_step": res["pcg_iters_per_step"],
+            "inner_iters_per_step": res["inner_iters_per_step"], "setup_s": res["setup_s"],
+            "rel_err_vs_oracle": errs, "accuracy_ok": ok}), flush=True)
         return
     prm = workloads.config(args.workload)
     golden, gmeta = load_golden(args.workload)

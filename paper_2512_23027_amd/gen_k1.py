@@ -47,13 +47,17 @@ BASES = {
 }
 LDS_LIMIT = 160 * 1024
 
-# (L, p_in, p_out) -> {precision: (NW, KC, MT, RB)}: PCG kernels that spread
-# the coefficient matrices over NW waves of one workgroup (at most KC
-# matrices held at a time) and stage p in tiles of MT modes, read once per
-# row group; RB bytes of LDS hold the wave partials of one output slice.
-# Used when the halo fits; the tiled kernel of BASES otherwise.
+# (L, p_in, p_out) -> {precision: configuration} of the shared-halo kernels:
+# every row group stages its halo in tiles of MT modes once and NW waves of
+# one workgroup share it, each contracting its own coefficient matrices (at
+# most KC held at a time); output groups of at most G modes are separate
+# kernels (the tiled kernel of the same precision must have as many for the
+# PCG variant: both write one p'q per output group); RB bytes of LDS hold
+# the wave partials of one output slice.  apply: also the plain SG apply
+# (else the PCG variant only).  Used when the halo fits; the tiled kernels
+# of BASES otherwise.
 SHARED = {
-    (8, 2, 3): {"float": (8, 6, 165, 96 * 1024)},
+    (8, 2, 3): {"float": dict(NW=8, KC=6, MT=165, RB=96 * 1024, G=165, apply=False)},
 }
 
 
@@ -388,20 +392,36 @@ def kernel_source(L, p_in, p_out, T, pcg=False):
     return lines, name, (nk, P, G, KC, MT, ngroups, nch, nw, NT)
 
 
-def shared_plan(L, p_in, p_out, T):
-    """(NW, MT, waves, R, sl) of a shared PCG kernel: waves[w] = the
-    sub-chunks (lists of at most KC coefficient matrices) of wave w, the
-    matrices dealt to the waves by their work (7 stencil products per (k, j)
-    pair plus one product per tensor entry), largest first, to the least
-    loaded wave; R output slices of sl modes for the reduction of the wave
-    partials."""
+def shared_cfg(L, p_in, p_out, T):
+    """The shared-kernel configuration of a basis and precision, or None."""
+    return SHARED.get((L, p_in, p_out), {}).get(T)
+
+
+def shared_groups(L, p_in, p_out, T):
+    """Output groups [(i0, i1)] of the shared kernels of a basis and precision."""
+    _, P, _ = entries(L, p_in, p_out)
+    G = shared_cfg(L, p_in, p_out, T)["G"]
+    ng = -(-P // G)
+    G = -(-P // ng)
+    return [(g * G, min(P, (g + 1) * G)) for g in range(ng)]
+
+
+def shared_plan(L, p_in, p_out, T, i0, i1):
+    """(NW, MT, waves, R, sl) of the shared kernel of output modes [i0, i1):
+    waves[w] = the sub-chunks (lists of at most KC coefficient matrices) of
+    wave w, the matrices dealt to the waves by their work on these outputs
+    (7 stencil products per (k, j) pair plus one product per tensor entry),
+    largest first, to the least loaded wave; R output slices of sl modes for
+    the reduction of the wave partials (at most RB bytes of LDS)."""
     nk, P, ent = entries(L, p_in, p_out)
-    NW, KC, MT, budget = SHARED[(L, p_in, p_out)][T]
+    c = shared_cfg(L, p_in, p_out, T)
+    NW, KC, MT, budget = c["NW"], c["KC"], c["MT"], c["RB"]
     w = 4 if T == "float" else 8
     pairs, trip = {}, {}
     for (k, i, j, v) in ent:
-        pairs.setdefault(k, set()).add(j)
-        trip[k] = trip.get(k, 0) + 1
+        if i0 <= i < i1:
+            pairs.setdefault(k, set()).add(j)
+            trip[k] = trip.get(k, 0) + 1
     cost = {k: 7 * len(pairs.get(k, ())) + trip.get(k, 0) for k in range(nk)}
     load = [0] * NW
     own = [[] for _ in range(NW)]
@@ -415,70 +435,94 @@ def shared_plan(L, p_in, p_out, T):
     for ks in own:
         ks = sorted(ks)
         waves.append([ks[a:a + KC] for a in range(0, len(ks), KC)])
-    R = max(1, -(-NW * P * 64 * w // budget))
-    sl = -(-P // R)
-    R = -(-P // sl)
+    gs = i1 - i0
+    R = max(1, -(-NW * gs * 64 * w // budget))
+    sl = -(-gs // R)
+    R = -(-gs // sl)
     return NW, min(MT, P), waves, R, sl
 
 
 UNS = 16  # staging loads in flight per thread and vector (first tile)
 
 
-def shared_source(L, p_in, p_out, T):
-    """The shared PCG kernel of a basis and precision (see SHARED).
+def shared_source(L, p_in, p_out, T, pcg, i0, i1, g):
+    """The shared kernel of output modes [i0, i1) (output group g) of a
+    basis and precision: the SG apply y = alpha K x + beta y over a row range,
+    or (pcg) the subdomain-PCG variant that forms p = z + beta p_old while
+    staging, writes p (group 0), q and the group's p'q.
 
     Tiles of MT modes.  Staging: the threads of the workgroup take the halo
     columns h (per threads to a column, each every per-th mode j of the
-    tile), form p = z + beta p_old there, UNS modes at a time, and store it
-    at xs[h * S + j - j0] (S odd: consecutive columns fall in different
-    banks).  Products: wave w contracts its coefficient matrices against the
-    tile's modes, reading the 7 neighbours of its rows from LDS, two modes
-    per read.  Reduction: for each slice of output modes every wave writes
-    its partial sums to LDS (over the staged tile, no longer needed) and
-    wave w then adds the partials of the slice's modes w, w + NW, ... in wave
-    order and stores them; p'q of the rows is formed from the stored values
-    and the own rows' p (formed again from z and p_old as in the staging)."""
+    tile), form the staged value there (x, or z + beta p_old), UNS modes at
+    a time, and store it at xs[h * S + j - j0] (S odd: consecutive columns
+    fall in different banks).  Products: wave w contracts its coefficient
+    matrices against the tile's modes, reading the 7 neighbours of its rows
+    from LDS, two modes per read.  With several tiles each wave's whole tile
+    loop sits in one branch (every branch passes the same barriers).
+    Reduction: for each slice of output modes every wave writes its partial
+    sums to LDS (over the staged tile, no longer needed) and wave w then adds
+    the partials of the slice's modes w, w + NW, ... in wave order and
+    stores them; p'q of the rows is formed from the stored values and the
+    own rows' p (read from LDS with one tile, else formed again from z and
+    p_old as in the staging)."""
     nk, P, ent = entries(L, p_in, p_out)
-    NW, MT, waves, R, sl = shared_plan(L, p_in, p_out, T)
+    NW, MT, waves, R, sl = shared_plan(L, p_in, p_out, T, i0, i1)
+    ent = [e for e in ent if i0 <= e[1] < i1]
     ntile = -(-P // MT)
     S = lds_stride(MT)
     NT = 64 * NW
     w = 4 if T == "float" else 8
     sz = "(int)sizeof(%s)" % T
+    gs = i1 - i0
     M = -(-sl // NW)  # outputs per wave and slice
-    # workgroups per CU the LDS allows at the typical halo (for the register
-    # budget: 2 waves per SIMD need at most 256 registers per lane)
-    wpe = 2
-    name = tag(L, p_in, p_out) + "_pcg" + ("_f" if T == "float" else "_d") + "_s"
+    # modes per run of LDS reads: two consecutive modes of a neighbour in one
+    # two-address read (FP32); one in FP64, whose registers are twice as wide
+    RUN = 2 if T == "float" else 1
+    name = tag(L, p_in, p_out) + ("_pcg" if pcg else "") + ("_f" if T == "float" else "_d") \
+        + "_s%d" % g
     out = []
     a = out.append
-    a("__global__ __launch_bounds__(%d, %d) void %s(DEll<%s> A, DHalo H, int nrows, "
-      "const %s* __restrict__ x, int ldx, %s* __restrict__ y, int ldy, "
-      "const %s* __restrict__ zs, %s* __restrict__ pnew, const double* __restrict__ rzpart, "
-      "double* __restrict__ sc, int par, double* __restrict__ pqg, unsigned long long* acct, "
-      "unsigned bpr) {" % (NT, wpe, name, T, T, T, T, T))
+    if pcg:
+        sig = ("DEll<%s> A, DHalo H, int nrows, const %s* __restrict__ x, int ldx, "
+               "%s* __restrict__ y, int ldy, const %s* __restrict__ zs, %s* __restrict__ pnew, "
+               "const double* __restrict__ rzpart, double* __restrict__ sc, int par, "
+               "double* __restrict__ pqg, int ngq, unsigned long long* acct, unsigned bpr"
+               % (T, T, T, T, T))
+    else:
+        sig = ("DEll<%s> A, DHalo H, int r0, int nrows, const %s* __restrict__ x, int ldx, "
+               "%s* __restrict__ y, int ldy, %s alpha, %s beta, long long sx, long long sy"
+               % (T, T, T, T, T))
+    a("__global__ __launch_bounds__(%d, %d) void %s(%s) {" % (NT, max(1, 8 // NW), name, sig))
     a("  extern __shared__ unsigned char k1_smem[];")
-    a("  %s* xs = reinterpret_cast<%s*>(k1_smem);  // [hmax][%d] staged tile of p; then the wave partials"
+    a("  %s* xs = reinterpret_cast<%s*>(k1_smem);  // [hmax][%d] staged tile; then the wave partials"
       % (T, T, S))
     a("  const int lane = threadIdx.x & 63;")
     a("  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));")
     a("  const int grp = xcd_group(blockIdx.x, gridDim.x);")
-    a("  const int blk = H.gblk[grp];")
-    a("  if (sc[(size_t)blk * 8 + 2 + par] == 0.0) return;  // converged block: frozen (whole workgroup)")
+    if pcg:
+        a("  const int r0 = H.r0;")
+        a("  const int blk = H.gblk[grp];")
+        a("  if (sc[(size_t)blk * 8 + 2 + par] == 0.0) return;  // converged block: frozen (whole workgroup)")
+    else:
+        a("  x += (long long)blockIdx.z * sx;")
+        a("  y += (long long)blockIdx.z * sy;")
     a("  const int g0 = H.grow[grp], gn = H.grow[grp + 1] - g0;  // rows of this group")
-    a("  const bool live = lane < gn && g0 + lane - H.r0 < nrows;")
+    a("  const bool live = lane < gn && g0 + lane - r0 < nrows;")
     a("  const int r = g0 + (live ? lane : 0);")
     a("  const int NR = A.nrows;")
-    a("  const auto rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y), rz = buf_rsrc(zs);")
+    a("  const auto rv = buf_rsrc(A.val), rx = buf_rsrc(x), ry = buf_rsrc(y);")
     a("  const int rb = r * %s;" % sz)
-    a("  // beta of this group's block; the block's first group stores the new r'z")
-    a("  double rzn = 0.0;")
-    a("  for (int j = 0; j < %d; ++j) rzn += rzpart[(size_t)blk * %d + j];" % (P, P))
-    a("  const double rzo = sc[(size_t)blk * 8 + 1 - par];")
-    a("  const %s bt = (%s)(isinf(rzo) ? 0.0 : rzn / rzo);" % (T, T))
-    a("  if (threadIdx.x == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
-    a("  // algorithmic bytes of the rows this launch processes (timed launches)")
-    a("  if (acct && threadIdx.x == 0) atomicAdd(acct, (unsigned long long)gn * bpr);")
+    if pcg:
+        a("  const auto rz = buf_rsrc(zs);")
+        a("  // beta of this group's block; the block's first group stores the new r'z")
+        a("  double rzn = 0.0;")
+        a("  for (int j = 0; j < %d; ++j) rzn += rzpart[(size_t)blk * %d + j];" % (P, P))
+        a("  const double rzo = sc[(size_t)blk * 8 + 1 - par];")
+        a("  const %s bt = (%s)(isinf(rzo) ? 0.0 : rzn / rzo);" % (T, T))
+        if g == 0:
+            a("  if (threadIdx.x == 0 && grp == H.bgrp[blk]) sc[(size_t)blk * 8 + par] = rzn;")
+            a("  // algorithmic bytes of the rows this launch processes (timed launches)")
+            a("  if (acct && threadIdx.x == 0) atomicAdd(acct, (unsigned long long)gn * bpr);")
     a("  const int h0 = H.ptr[grp], nh = H.ptr[grp + 1] - h0;")
     a("  const int rr = r - H.r0;")
     for q in range(7):
@@ -486,29 +530,34 @@ def shared_source(L, p_in, p_out, T):
     a("  const char* xb = reinterpret_cast<const char*>(xs);")
     a("  // thread t stages column t % nh, modes t / nh + m * per (per threads a column)")
     a("  const int per = nh > 0 ? max(1, %d / nh) : 1, jt = nh > 0 ? (int)threadIdx.x / nh : 1;" % NT)
-    for i in range(P):
+    for i in range(i0, i1):
         a("  %s y%d = %s(0);" % (T, i, T))
-    for t in range(ntile):
+
+    def stage(t):
+        """stage tile t in LDS (every thread of the workgroup)"""
         j0, j1 = t * MT, min(P, (t + 1) * MT)
-        a("  // ---- tile %d: modes %d..%d" % (t, j0, j1 - 1))
-        if t > 0:
-            a("  __syncthreads();  // every wave is done with the previous tile")
         # later tiles stage while the accumulators are live: fewer loads in flight
-        un = UNS if t == 0 else UNS // 2
-        a("  if (jt < per) {  // stage p = z + beta p_old")
+        un = UNS if t == 0 else UNS // (2 if T == "float" else 4)
+        a("  if (jt < per) {  // stage modes %d..%d" % (j0, j1 - 1))
         a("    for (int h = (int)threadIdx.x %% nh; h < nh; h += %d) {" % NT)
         a("      const int co = H.idx[h0 + h] * %s;" % sz)
         a("      %s* dst = xs + h * %d - %d;" % (T, S, j0))
-        for first in (False, True):
-            # beta = 0 (the first iteration, p_old undefined) reads z alone
-            a("      %s {" % ("if (bt != %s(0))" % T if not first else "else"))
+        variants = (False, True) if pcg else (None,)
+        for first in variants:
+            # PCG: beta = 0 (the first iteration, p_old undefined) reads z alone
+            if first is not None:
+                a("      %s {" % ("if (bt != %s(0))" % T if not first else "else"))
+            else:
+                a("      {")
             a("        int j = %d + jt;" % j0)
             a("        for (; j + %d * per < %d; j += %d * per) {" % (un - 1, j1, un))
             a("          %s v[%d];" % (T, un))
             a("#pragma unroll")
             a("          for (int u = 0; u < %d; ++u) {" % un)
             a("            const int o = co + (j + u * per) * ldx * %s;" % sz)
-            if first:
+            if first is None:
+                a("            v[u] = buf_load<%s>(rx, o, 0);" % T)
+            elif first:
                 a("            v[u] = buf_load<%s>(rz, o, 0);" % T)
             else:
                 a("            v[u] = fma(bt, buf_load<%s>(rx, o, 0), buf_load<%s>(rz, o, 0));" % (T, T))
@@ -518,7 +567,9 @@ def shared_source(L, p_in, p_out, T):
             a("        }")
             a("        for (; j < %d; j += per) {" % j1)
             a("          const int o = co + j * ldx * %s;" % sz)
-            if first:
+            if first is None:
+                a("          dst[j] = buf_load<%s>(rx, o, 0);" % T)
+            elif first:
                 a("          dst[j] = buf_load<%s>(rz, o, 0);" % T)
             else:
                 a("          dst[j] = fma(bt, buf_load<%s>(rx, o, 0), buf_load<%s>(rz, o, 0));" % (T, T))
@@ -526,88 +577,130 @@ def shared_source(L, p_in, p_out, T):
             a("      }")
         a("    }")
         a("  }")
-        a("  __syncthreads();")
+
+    def pnew_store(t):
+        if not (pcg and g == 0):
+            return
+        j0, j1 = t * MT, min(P, (t + 1) * MT)
         a("  if (live) {  // the new direction of the own row: modes %d + wv, + %d, ..." % (j0, NW))
         a("    const auto rp = buf_rsrc(pnew);")
         a("    for (int j = %d + wv; j < %d; j += %d)" % (j0, j1, NW))
         a("      buf_store<%s>(*reinterpret_cast<const %s*>(xb + l0 + (j - %d) * sizeof(%s)), rp, rb, j * ldx * %s);"
           % (T, T, j0, T, sz))
         a("  }")
-        for wq, subs in enumerate(waves):
-            a("  %s (wv == %d) {  // coefficient matrices %s" % ("if" if wq == 0 else "} else if", wq,
-                                                               ", ".join(str(k) for sub in subs for k in sub)))
-            for sub in subs:
-                ks = set(sub)
-                mine = [e for e in ent if e[0] in ks and j0 <= e[2] < j1]
-                js = sorted({e[2] for e in mine})
-                if not js:
+
+    def products(wq, t):
+        """wave wq's contraction of its coefficient matrices with tile t"""
+        j0, j1 = t * MT, min(P, (t + 1) * MT)
+        for sub in waves[wq]:
+            ks = set(sub)
+            mine = [e for e in ent if e[0] in ks and j0 <= e[2] < j1]
+            js = sorted({e[2] for e in mine})
+            if not js:
+                continue
+            a("    {  // matrices %s, modes %d..%d" % (", ".join(map(str, sub)), j0, j1 - 1))
+            if ntile > 1:
+                # an opaque zero offset per tile keeps the compiler from
+                # reusing the previous tile's loads (which would keep the
+                # matrix values live across the whole kernel)
+                a("    const int zk = opaque_zero();")
+            for k in sub:
+                if not any(e[0] == k for e in mine):
                     continue
-                a("    {  // matrices %s" % ", ".join(map(str, sub)))
-                if ntile > 1:
-                    # an opaque zero offset per tile keeps the compiler from
-                    # reusing the previous tile's loads (which would keep
-                    # the matrix values live across the whole kernel)
-                    a("    const int zk = opaque_zero();")
-                for k in sub:
-                    if not any(e[0] == k for e in mine):
-                        continue
-                    for q in range(7):
-                        a("    const %s k%d_%d = buf_load<%s>(rv, rb, %d * NR * %s%s);"
-                          % (T, k, q, T, k * 7 + q, sz, " + zk" if ntile > 1 else ""))
-                # modes in runs of at most two consecutive ones: the two values
-                # of a neighbour come in one two-address LDS read
-                runs = []
-                for j in js:
-                    if runs and len(runs[-1]) < 2 and runs[-1][-1] + 1 == j:
-                        runs[-1].append(j)
-                    else:
-                        runs.append([j])
+                for q in range(7):
+                    a("    const %s k%d_%d = buf_load<%s>(rv, rb, %d * NR * %s%s);"
+                      % (T, k, q, T, k * 7 + q, sz, " + zk" if ntile > 1 else ""))
+            # modes in runs of at most RUN consecutive ones
+            runs = []
+            for j in js:
+                if runs and len(runs[-1]) < RUN and runs[-1][-1] + 1 == j:
+                    runs[-1].append(j)
+                else:
+                    runs.append([j])
 
-                def reads(run, decl):
-                    for q in range(7):
-                        for b_, j in enumerate(run):
-                            a("    %s%sn%d_%d = *reinterpret_cast<const %s*>(xb + l%d + %d * sizeof(%s));"
-                              % ("  " if not decl else "", (T + " ") if decl else "", q, b_, T, q, j - j0, T))
-
-                reads(runs[0], True)
-                if len(runs[0]) < 2:
-                    for q in range(7):
-                        a("    %s n%d_1 = %s(0);" % (T, q, T))
-                for u, run in enumerate(runs):
-                    a("    {  // mode(s) %s" % ", ".join(map(str, run)))
-                    for b_ in range(len(run)):
-                        for q in range(7):
-                            a("      const %s u%d_%d = n%d_%d;" % (T, q, b_, q, b_))
-                    if u + 1 < len(runs):
-                        # the LDS reads of the next run are issued before this
-                        # run's products (the asm statement keeps them from
-                        # moving further up)
-                        a('      asm volatile("" ::: "memory");')
-                        reads(runs[u + 1], False)
+            def reads(run, decl):
+                for q in range(7):
                     for b_, j in enumerate(run):
-                        for k in sorted({e[0] for e in mine if e[2] == j}):
-                            expr = "k%d_0 * u0_%d" % (k, b_)
-                            for q in range(1, 7):
-                                expr = "fma(k%d_%d, u%d_%d, %s)" % (k, q, q, b_, expr)
-                            a("      { const %s w = %s;" % (T, expr))
-                            for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
-                                a("        y%d = fma(%s(%.17g), w, y%d);" % (i, T, v, i))
-                            a("      }")
-                    a("    }")
-                # the next sub-chunk's matrix loads stay below this one's
-                # last products (both sets of values live would not fit)
-                a('    asm volatile("" ::: "memory");')
+                        a("    %s%sn%d_%d = *reinterpret_cast<const %s*>(xb + l%d + %d * sizeof(%s));"
+                          % ("  " if not decl else "", (T + " ") if decl else "", q, b_, T, q, j - j0, T))
+
+            reads(runs[0], True)
+            if RUN > 1 and len(runs[0]) < 2:
+                for q in range(7):
+                    a("    %s n%d_1 = %s(0);" % (T, q, T))
+            for u, run in enumerate(runs):
+                a("    {  // mode(s) %s" % ", ".join(map(str, run)))
+                for b_ in range(len(run)):
+                    for q in range(7):
+                        a("      const %s u%d_%d = n%d_%d;" % (T, q, b_, q, b_))
+                if u + 1 < len(runs):
+                    # the LDS reads of the next run are issued before this
+                    # run's products (the asm statement keeps them from
+                    # moving further up)
+                    a('      asm volatile("" ::: "memory");')
+                    reads(runs[u + 1], False)
+                for b_, j in enumerate(run):
+                    for k in sorted({e[0] for e in mine if e[2] == j}):
+                        expr = "k%d_0 * u0_%d" % (k, b_)
+                        for q in range(1, 7):
+                            expr = "fma(k%d_%d, u%d_%d, %s)" % (k, q, q, b_, expr)
+                        a("      { const %s w = %s;" % (T, expr))
+                        for (_, i, _, v) in [e for e in mine if e[0] == k and e[2] == j]:
+                            a("        y%d = fma(%s(%.17g), w, y%d);" % (i, T, v, i))
+                        a("      }")
                 a("    }")
+            # the next sub-chunk's matrix loads stay below this one's last
+            # products (both sets of values live would not fit)
+            a('    asm volatile("" ::: "memory");')
+            a("    }")
+
+    def head(wq):
+        return "  %s (wv == %d) {  // coefficient matrices %s" % (
+            "if" if wq == 0 else "} else if", wq,
+            ", ".join(str(k) for sub in waves[wq] for k in sub))
+
+    if ntile == 1:
+        stage(0)
+        a("  __syncthreads();")
+        pnew_store(0)
+        for wq in range(NW):
+            a(head(wq))
+            products(wq, 0)
         a("  }")
-    a("  double pq = 0.0;")
+    else:
+        # several tiles: each wave's whole tile loop sits in its own branch
+        # (the accumulators stay in one set of registers).  Every branch
+        # passes the same barriers: one after each staging, one before each
+        # later staging.
+        for wq in range(NW):
+            a(head(wq))
+            for t in range(ntile):
+                if t > 0:
+                    a("  __syncthreads();  // every wave is done with the previous tile")
+                stage(t)
+                a("  __syncthreads();")
+                pnew_store(t)
+                products(wq, t)
+        a("  }")
+    if pcg and ntile == 1:
+        a("  __syncthreads();  // the products no longer read the staged p")
+        a("  // own-row p of the modes this wave finalises: slice t, mode %d + t * %d + wv + %d m"
+          % (i0, sl, NW))
+        for t in range(R):
+            s0, s1 = t * sl, min(gs, (t + 1) * sl)
+            for m in range(M):
+                a("  const %s po%d_%d = (wv + %d < %d) ? *reinterpret_cast<const %s*>(xb + l0 + (%d + wv + %d) * sizeof(%s)) : %s(0);"
+                  % (T, t, m, NW * m, s1 - s0, T, i0 + s0, NW * m, T, T))
+    if pcg:
+        a("  double pq = 0.0;")
     a("  %s* part = xs;  // [wave][slice mode][64]" % T)
     for t in range(R):
-        s0, s1 = t * sl, min(P, (t + 1) * sl)
-        a("  // ---- output slice %d: modes %d..%d" % (t, s0, s1 - 1))
-        a("  __syncthreads();  // %s" % ("the products no longer read the staged p" if t == 0
+        s0, s1 = t * sl, min(gs, (t + 1) * sl)
+        a("  // ---- output slice %d: modes %d..%d" % (t, i0 + s0, i0 + s1 - 1))
+        a("  __syncthreads();  // %s" % ("the products no longer read the staged tile" if t == 0
                                         else "the previous slice is added up"))
-        for i in range(s0, s1):
-            a("  part[(wv * %d + %d) * 64 + lane] = y%d;" % (sl, i - s0, i))
+        for i in range(i0 + s0, i0 + s1):
+            a("  part[(wv * %d + %d) * 64 + lane] = y%d;" % (sl, i - i0 - s0, i))
         a("  __syncthreads();")
         for m in range(M):
             a("  if (wv + %d < %d) {" % (NW * m, s1 - s0))
@@ -617,28 +710,38 @@ def shared_source(L, p_in, p_out, T):
             for tm in terms[1:]:
                 a("    s += %s;" % tm)
             a("    if (live) {")
-            a("      const int so = (%d + o) * ldx * %s;" % (s0, sz))
-            a("      const %s p = bt != %s(0) ? fma(bt, buf_load<%s>(rx, rb, so), buf_load<%s>(rz, rb, so))"
-              " : buf_load<%s>(rz, rb, so);" % (T, T, T, T, T))
-            a("      buf_store<%s>(s, ry, rb, (%d + o) * ldy * %s);" % (T, s0, sz))
-            a("      pq += (double)s * (double)p;")
+            if pcg:
+                if ntile == 1:
+                    a("      const %s p = po%d_%d;" % (T, t, m))
+                else:
+                    a("      const int so = (%d + o) * ldx * %s;" % (i0 + s0, sz))
+                    a("      const %s p = bt != %s(0) ? fma(bt, buf_load<%s>(rx, rb, so), buf_load<%s>(rz, rb, so))"
+                      " : buf_load<%s>(rz, rb, so);" % (T, T, T, T, T))
+                a("      buf_store<%s>(s, ry, rb, (%d + o) * ldy * %s);" % (T, i0 + s0, sz))
+                a("      pq += (double)s * (double)p;")
+            else:
+                a("      const int so = (%d + o) * ldy * %s;" % (i0 + s0, sz))
+                a("      %s v = alpha * s;" % T)
+                a("      if (beta != %s(0)) v = fma(beta, buf_load<%s>(ry, rb, so), v);" % (T, T))
+                a("      buf_store<%s>(v, ry, rb, so);" % T)
             a("    }")
             a("  }")
-    a("  // p'q of the row group: wave sums, then the waves in order")
-    a("  for (int o = 32; o > 0; o >>= 1) pq += __shfl_xor(pq, o, 64);")
-    a("  double* pqw = reinterpret_cast<double*>(k1_smem + shared_pq_offset(H.hmax, %d, %d));"
-      % (S * w, NW * sl * 64 * w))
-    a("  if (lane == 0) pqw[wv] = pq;")
-    a("  __syncthreads();")
-    a("  if (threadIdx.x == 0) {")
-    a("    double v = pqw[0];")
-    for q in range(1, NW):
-        a("    v += pqw[%d];" % q)
-    a("    pqg[grp] = v;")
-    a("  }")
+    if pcg:
+        a("  // p'q of the row group and this output group: wave sums, then the waves in order")
+        a("  for (int o = 32; o > 0; o >>= 1) pq += __shfl_xor(pq, o, 64);")
+        a("  double* pqw = reinterpret_cast<double*>(k1_smem + shared_pq_offset(H.hmax, %d, %d));"
+          % (S * w, NW * sl * 64 * w))
+        a("  if (lane == 0) pqw[wv] = pq;")
+        a("  __syncthreads();")
+        a("  if (threadIdx.x == 0) {")
+        a("    double v = pqw[0];")
+        for q in range(1, NW):
+            a("    v += pqw[%d];" % q)
+        a("    pqg[(size_t)grp * ngq + %d] = v;" % g)
+        a("  }")
     a("}")
     a("")
-    lds = "(shared_pq_offset(hmax, %d, %d) + %d)" % (S * w, NW * sl * 64 * w, NW * 8)
+    lds = "(shared_pq_offset(hmax, %d, %d) + %d)" % (S * w, NW * sl * 64 * w, NW * 8 if pcg else 0)
     return out, name, NT, lds
 
 
@@ -673,22 +776,37 @@ def basis_source(L, p_in, p_out):
             out.extend(lines)
             RG = row_groups(L, p_in, p_out, T)
             lds = _lds_expr(P, G, MT, ngroups, nw, T, pcg, RG)
-            shared = pcg and T in SHARED.get((L, p_in, p_out), {})
+            cfg = shared_cfg(L, p_in, p_out, T)
+            shared = cfg is not None and (pcg or cfg["apply"])
+            skern = []  # (name, threads, LDS expression) per output group
             if shared:
-                # both kernels write one p'q per row group
-                assert ngroups == 1
-                slines, sname, SNT, slds = shared_source(L, p_in, p_out, T)
-                NW_, MT_, waves_, R_, sl_ = shared_plan(L, p_in, p_out, T)
-                out.append("// %s PCG, shared halo tiles of %d modes: %d waves (matrices %s), %d output"
-                           " slice(s) of %d" % (T, MT_, NW_, " | ".join(",".join(str(k) for sub in wq for k in sub)
-                                                                      for wq in waves_), R_, sl_))
-                out.extend(slines)
+                sgroups = shared_groups(L, p_in, p_out, T)
+                if pcg:  # both kernels write one p'q per (row group, output group)
+                    assert len(sgroups) == ngroups, (L, T, len(sgroups), ngroups)
+                for g, (i0, i1) in enumerate(sgroups):
+                    slines, sname, SNT, slds = shared_source(L, p_in, p_out, T, pcg, i0, i1, g)
+                    NW_, MT_, waves_, R_, sl_ = shared_plan(L, p_in, p_out, T, i0, i1)
+                    out.append("// %s%s, shared halo, output modes %d..%d, tiles of %d modes: %d waves "
+                               "(matrices %s), %d output slice(s) of %d"
+                               % (T, " PCG" if pcg else "", i0, i1 - 1, MT_, NW_,
+                                  " | ".join(",".join(str(k) for sub in wq for k in sub)
+                                             for wq in waves_), R_, sl_))
+                    out.extend(slines)
+                    skern.append((sname, SNT, slds))
+            smax = "std::max<size_t>({%s})" % ", ".join(k[2] for k in skern) if skern else None
             if not pcg:
                 out.append("bool %s_apply(const DEll<%s>& A, const DHalo& H, int r0, int nrows, "
                            "const %s* x, int ldx, %s* y, int ldy, %s alpha, %s beta, int nbatch, "
                            "long long sx, long long sy, hipStream_t st) {" % (t, T, T, T, T, T))
                 out.append("  const int ngrp = halo_groups(H, r0, nrows);")
                 out.append("  const size_t hmax = H.hmax;")
+                if shared:
+                    out.append("  if (ngrp > 0 && %s <= %d) {  // the halo fits: shared kernels" % (smax, LDS_LIMIT))
+                    for sname, SNT, slds in skern:
+                        out.append("    %s<<<dim3(ngrp, 1, nbatch), %d, %s, st>>>(A, H, r0, nrows, x, ldx, "
+                                   "y, ldy, alpha, beta, sx, sy);" % (sname, SNT, slds))
+                    out.append("    return true;")
+                    out.append("  }")
                 out.append("  const size_t sh = %s;" % lds)
                 out.append("  if (ngrp <= 0 || sh > %d) return false;" % LDS_LIMIT)
                 out.append("  dim3 grid((ngrp + %d) / %d, 1, nbatch);" % (RG - 1, RG))
@@ -705,10 +823,10 @@ def basis_source(L, p_in, p_out):
                 out.append("  const int ngrp = halo_groups(H, H.r0, nrows);")
                 out.append("  const size_t hmax = H.hmax;")
                 if shared:
-                    out.append("  const size_t ss = %s;" % slds)
-                    out.append("  if (ngrp > 0 && ss <= %d) {  // the whole halo fits: shared kernel" % LDS_LIMIT)
-                    out.append("    %s<<<ngrp, %d, ss, st>>>(A, H, nrows, pold, ld, q, ld, zs, pnew, rzpart, "
-                               "sc, par, pqg, acct, bpr);" % (sname, SNT))
+                    out.append("  if (ngrp > 0 && %s <= %d) {  // the halo fits: shared kernels" % (smax, LDS_LIMIT))
+                    for sname, SNT, slds in skern:
+                        out.append("    %s<<<ngrp, %d, %s, st>>>(A, H, nrows, pold, ld, q, ld, zs, pnew, "
+                                   "rzpart, sc, par, pqg, %d, acct, bpr);" % (sname, SNT, slds, ngroups))
                     out.append("    return true;")
                     out.append("  }")
                 out.append("  const size_t sh = %s;" % lds)
@@ -720,10 +838,10 @@ def basis_source(L, p_in, p_out):
                                % (name, g, NT, T, T))
                 out.append("  return true;")
                 out.append("}")
-            if shared:  # the kernel that runs: the shared one where it fits
-                out.append("size_t %s_pcg_lds(%s, int hmax_i) { const size_t hmax = hmax_i; "
+            if shared:  # the kernels that run: the shared ones where they fit
+                out.append("size_t %s%s_lds(%s, int hmax_i) { const size_t hmax = hmax_i; "
                            "const size_t ss = %s; return ss <= %d ? ss : %s; }"
-                           % (t, T + "*", slds, LDS_LIMIT, lds))
+                           % (t, "_pcg" if pcg else "", T + "*", smax, LDS_LIMIT, lds))
             else:
                 out.append("size_t %s%s_lds(%s, int hmax_i) { const size_t hmax = hmax_i; return %s; }"
                            % (t, "_pcg" if pcg else "", T + "*", lds))
@@ -737,8 +855,9 @@ def basis_source(L, p_in, p_out):
             ngroups = shape(L, p_in, p_out, T)[5]
             name = t + ("_pcg" if pcg else "") + ("_f" if T == "float" else "_d")
             kern = ["%s_g%d" % (name, g) for g in range(ngroups)]
-            if pcg and T in SHARED.get((L, p_in, p_out), {}):
-                kern.append(name + "_s")
+            cfg = shared_cfg(L, p_in, p_out, T)
+            if cfg is not None and (pcg or cfg["apply"]):
+                kern += ["%s_s%d" % (name, g) for g in range(len(shared_groups(L, p_in, p_out, T)))]
             for kn in kern:
                 out.append("  ok = ok && hipFuncSetAttribute((const void*)%s, "
                            "hipFuncAttributeMaxDynamicSharedMemorySize, %d) == hipSuccess;"

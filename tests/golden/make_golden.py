@@ -11,9 +11,12 @@ recorded steps, the full mean and standard-deviation fields over all
 * cfg5 (512x512, P = 165, 16x16 subdomains): the first 30 steps, stored at
   steps 2, 10, 20, 30 -> cfg5_oracle.npz (rounded to FP32: its parity bound
   is 1e-6 and FP32 keeps the stored fields within 6e-8 of the oracle's)
+* cfg3-0, cfg3-1 (384x384, P = 84, seeded uneven splits; two of the eight
+  problems of the batched workload): the first 10 steps, stored at steps 5
+  and 10 -> cfg3-<p>_oracle.npz (FP32 as above)
 The oracle's CG iteration count of every step is stored too (cg_iterations).
 
-Usage: python tests/golden/make_golden.py cfg2|cfg5 [--out PATH]
+Usage: python tests/golden/make_golden.py cfg2|cfg5|cfg3-0|cfg3-1 [--out PATH]
        python tests/golden/make_golden.py cfg2|cfg5 --repack   (keep only the
        stored steps and precision above from a file written with more)
 The file is rewritten after every recorded step (so a long run can be
@@ -33,8 +36,8 @@ import workloads  # noqa: E402
 from oracle.sg import SGProblem  # noqa: E402
 
 RECORD = {"cfg2": (2, 10, 25, 100, 200, 500),
-          "cfg5": (2, 10, 20, 30)}
-DTYPE = {"cfg2": np.float64, "cfg5": np.float32}
+          "cfg5": (2, 10, 20, 30), "cfg3-0": (5, 10), "cfg3-1": (5, 10)}
+DTYPE = {"cfg2": np.float64, "cfg5": np.float32, "cfg3-0": np.float32, "cfg3-1": np.float32}
 
 
 def save(path, name, n, fields, cg):
