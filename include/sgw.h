@@ -97,7 +97,8 @@ typedef struct sgw_problem_desc {
                             the interface PCG is the flexible (Polak-Ribiere) variant */
   int inner_prec;        /* preconditioner I_P (x) (K~_0^s)^-1 of the subdomain SG PCG:
                             SGW_INNER_CHOLESKY applies the mean-matrix inverse exactly
-                            (supernodal Cholesky factors), SGW_INNER_CHEBYSHEV
+                            (supernodal Cholesky factors; every nested-dissection level
+                            of a subdomain <= 2048 rows), SGW_INNER_CHEBYSHEV
                             approximates it by a Chebyshev polynomial in the
                             Jacobi-scaled mean matrix (blocks of <= 4096 rows) */
   int cheb_degree;       /* degree of that polynomial (<= 0: 4; at most 64) */

@@ -1595,8 +1595,10 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   };
   c->factor_bytes_D = fbytes(h.fD);
   c->factor_bytes_N = fbytes(h.fN);
-  if (h.fD.max_level_rows > 2048 || h.fN.max_level_rows > 2048) {
-    c->err = "a nested-dissection level holds more than 2048 rows";
+  // the exact triangular solves hold one nested-dissection level per workgroup
+  if (dd.inner_prec == SGW_INNER_CHOLESKY &&
+      (h.fD.max_level_rows > 2048 || h.fN.max_level_rows > 2048)) {
+    c->err = "a nested-dissection level holds more than 2048 rows (exact subdomain preconditioner)";
     *out = c;
     return SGW_EINVAL;
   }

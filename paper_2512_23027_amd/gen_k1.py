@@ -42,8 +42,8 @@ BASES = {
     (0, 0, 0): {"float": (1, 1, 1, 1), "double": (1, 1, 1, 1)},
     (2, 2, 2): {"float": (6, 3, 6, 2), "double": (6, 3, 6, 2)},
     (4, 2, 3): {"float": (35, 8, 35, 2), "double": (35, 8, 35, 2)},
-    (6, 2, 3): {"float": (84, 7, 16, 1), "double": (42, 7, 8, 1)},
-    (8, 2, 3): {"float": (165, 6, 16, 1), "double": (83, 4, 8, 1)},
+    (6, 2, 3): {"float": (84, 7, 32, 1), "double": (42, 7, 16, 1)},
+    (8, 2, 3): {"float": (165, 6, 32, 1), "double": (83, 4, 16, 1)},
 }
 LDS_LIMIT = 160 * 1024
 
@@ -57,6 +57,7 @@ LDS_LIMIT = 160 * 1024
 # (else the PCG variant only).  Used when the halo fits; the tiled kernels
 # of BASES otherwise.
 SHARED = {
+    (6, 2, 3): {"float": dict(NW=4, KC=7, MT=84, RB=40 * 1024, G=84, apply=False)},
     (8, 2, 3): {"float": dict(NW=8, KC=6, MT=165, RB=96 * 1024, G=165, apply=False)},
 }
 

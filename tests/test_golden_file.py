@@ -1,9 +1,10 @@
 """The stored oracle runs are what the oracle computes now: their layout is
-checked, and the first stored step of the 256x256, P = 35 workload is
-recomputed here (CPU, ~15 s) and compared over every node."""
+checked (the 256x256 run to step 500, the 512x512 run to step 20, two
+384x384 problems of the batched set to step 10), and the first stored step
+of the 256x256, P = 35 workload is recomputed here (CPU, ~15 s) and
+compared over every node."""
 
 import numpy as np
-import pytest
 
 import golden_io
 import workloads
@@ -12,10 +13,10 @@ from oracle.sg import SGProblem
 
 def test_golden_file_layout():
     for name, n, steps, dtype_ok in (("cfg2", 256, [2, 10, 25, 100, 200, 500], True),
-                                     ("cfg5", 512, [2, 10, 20], True)):
+                                     ("cfg5", 512, [2, 10, 20], True),
+                                     ("cfg3-0", 384, [5, 10], True),
+                                     ("cfg3-1", 384, [5, 10], True)):
         g, nn = golden_io.load(name)
-        if name == "cfg5" and not g:
-            pytest.skip("cfg5 oracle run not stored")
         assert nn == n and sorted(g) == steps, (name, sorted(g))
         for m, s in g.values():
             assert m.shape == s.shape == ((n + 1) ** 2,)
