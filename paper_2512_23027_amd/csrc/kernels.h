@@ -198,8 +198,7 @@ void copy2d(int P, int n, const TS* src, int lds, TD* dst, int ldd, double a,
             hipStream_t st);
 template <typename T>
 void fill2d(int P, int n, T* dst, int ldd, T v, hipStream_t st);
-// dst[i] = the FP16 bit pattern of src[i] rounded to nearest (via FP32)
-void to_half(long long n, const double* src, unsigned short* dst, hipStream_t st);
+
 // dst = a*x + b*y (elementwise over [P][n])
 template <typename T>
 void axpby2d(int P, int n, double a, const T* x, int ldx, double b, const T* y,
@@ -247,8 +246,10 @@ struct DCoarse {
   const int *rem_off, *rem_list;   // remaining torn rows per subdomain
   const int* sc_ptr;               // local corners per subdomain
   const double* phi;               // coarse basis, per subdomain blocks
-  const unsigned short* phih;      // its FP16 copy (bit patterns; FP32 solver only)
+  const unsigned short* phih;      // its FP16 copy (bit patterns; FP32 solver only), each
+                                   // subdomain's rows padded to a multiple of 4 values
   const long long* phi_off;
+  const long long* phih_off;
   int max_rem = 0;                 // largest number of remaining rows
 };
 // local coarse unknowns (P x corners) of one subdomain held in LDS by the lift
@@ -276,6 +277,10 @@ void coarse_solve(const DCoarseFactor& f, const double* dc, double* uc, bool sin
 template <typename T>
 void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt,
                  hipStream_t st);
+// c.phih = FP16 (round to nearest, via FP32) copy of c.phi in its padded layout;
+// nq[s], nout[s]: coarse unknowns and outputs of subdomain s (device arrays)
+void coarse_basis_to_half(const DCoarse& c, int nsub, const int* nq, const long long* nout,
+                          hipStream_t st);
 
 }  // namespace k
 }  // namespace sgw

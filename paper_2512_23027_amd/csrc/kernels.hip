@@ -1471,35 +1471,66 @@ __global__ __launch_bounds__(SGW_BLOCK) void k_coarse_lift(DCoarse c, const doub
     ucl[q] = uc[(size_t)(q / ncs) * c.nC + c.sc_coarse[lc0 + q % ncs]];
   __syncthreads();
   const long long nout = (long long)c.P * nrem;
-  const long long o = (long long)blockIdx.y * SGW_BLOCK + threadIdx.x;
-  if (o >= nout) return;
-  double acc = 0.0;
   if constexpr (sizeof(T) == 4) {
-    const unsigned short* ph = c.phih + c.phi_off[s] + o;
-#pragma unroll 8
-    for (int q = 0; q < nq; ++q)
-      acc += (double)(float)__builtin_bit_cast(_Float16, ph[(size_t)q * nout]) * ucl[q];
+    // four consecutive outputs per thread: one 8-byte load of four FP16
+    // values per coarse unknown (rows padded to a multiple of 4)
+    const long long npad = (nout + 3) / 4 * 4;
+    const long long o = 4 * ((long long)blockIdx.y * SGW_BLOCK + threadIdx.x);
+    if (o >= nout) return;
+    const uint2* ph = reinterpret_cast<const uint2*>(c.phih + c.phih_off[s] + o);
+    const long long stride = npad / 4;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+    for (int q = 0; q < nq; ++q) {
+      const uint2 v = ph[(size_t)q * stride];
+      const double u = ucl[q];
+      a0 += (double)(float)__builtin_bit_cast(_Float16, (unsigned short)(v.x & 0xffffu)) * u;
+      a1 += (double)(float)__builtin_bit_cast(_Float16, (unsigned short)(v.x >> 16)) * u;
+      a2 += (double)(float)__builtin_bit_cast(_Float16, (unsigned short)(v.y & 0xffffu)) * u;
+      a3 += (double)(float)__builtin_bit_cast(_Float16, (unsigned short)(v.y >> 16)) * u;
+    }
+    const double acc[4] = {a0, a1, a2, a3};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (o + e >= nout) break;
+      const int j = (int)((o + e) / nrem), tr = (int)((o + e) % nrem);
+      T* dst = ut + (size_t)j * ldt + c.rem_list[c.rem_off[s] + tr];
+      *dst = (T)((double)*dst + acc[e]);
+    }
   } else {
+    const long long o = (long long)blockIdx.y * SGW_BLOCK + threadIdx.x;
+    if (o >= nout) return;
+    double acc = 0.0;
     const double* ph = c.phi + c.phi_off[s] + o;
 #pragma unroll 8
     for (int q = 0; q < nq; ++q) acc += ph[(size_t)q * nout] * ucl[q];
+    const int j = (int)(o / nrem), tr = (int)(o % nrem);
+    T* dst = ut + (size_t)j * ldt + c.rem_list[c.rem_off[s] + tr];
+    *dst = (T)((double)*dst + acc);
   }
-  const int j = (int)(o / nrem), tr = (int)(o % nrem);
-  T* dst = ut + (size_t)j * ldt + c.rem_list[c.rem_off[s] + tr];
-  *dst = (T)((double)*dst + acc);
 }
-__global__ void k_to_half(long long n, const double* src, unsigned short* dst) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = __builtin_bit_cast(unsigned short, (_Float16)(float)src[i]);
+// per subdomain: rows of nout values of phi -> rows of npad FP16 values (zeros after nout)
+__global__ void k_basis_to_half(DCoarse c, const int* nq_s, const long long* nout_s) {
+  const int s = blockIdx.y;
+  const long long nout = nout_s[s], npad = (nout + 3) / 4 * 4;
+  const long long tot = (long long)nq_s[s] * npad;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long q = i / npad, o = i - q * npad;
+    const float v = o < nout ? (float)c.phi[c.phi_off[s] + q * nout + o] : 0.0f;
+    const_cast<unsigned short*>(c.phih)[c.phih_off[s] + i] = __builtin_bit_cast(unsigned short, (_Float16)v);
+  }
 }
-void to_half(long long n, const double* src, unsigned short* dst, hipStream_t st) {
-  if (n > 0) k_to_half<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, src, dst);
+void coarse_basis_to_half(const DCoarse& c, int nsub, const int* nq, const long long* nout,
+                          hipStream_t st) {
+  if (c.nC == 0 || nsub <= 0) return;
+  k_basis_to_half<<<dim3(256, nsub), 256, 0, st>>>(c, nq, nout);
 }
-
 template <typename T>
 void coarse_lift(const DCoarse& c, int nsub, const double* uc, T* ut, int ldt, hipStream_t st) {
   if (c.nC == 0) return;
-  const int gy = (int)((c.P * (long long)c.max_rem + SGW_BLOCK - 1) / SGW_BLOCK);
+  const long long per = sizeof(T) == 4 ? 4 : 1;  // outputs per thread
+  const int gy = (int)((c.P * (long long)c.max_rem + per * SGW_BLOCK - 1) / (per * SGW_BLOCK));
   k_coarse_lift<T><<<dim3(nsub, std::max(gy, 1)), SGW_BLOCK, 0, st>>>(c, uc, ut, ldt);
 }
 

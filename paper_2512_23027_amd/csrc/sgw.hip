@@ -118,7 +118,7 @@ struct sgw_ctx {
   const double *torn_w = nullptr, *gam_w = nullptr;
   int maxc = 0;
   std::vector<int> rem_off_h, rem_list_h;
-  std::vector<long long> phi_off_h;
+  std::vector<long long> phi_off_h, phih_off_h;
   double* phi = nullptr;
   unsigned short* phih = nullptr;  // FP16 copy of phi (FP32 solver)
   double* fs = nullptr;   // local coarse matrices during factor
@@ -1719,6 +1719,7 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   }
   c->rem_off_h.assign(1, 0);
   c->phi_off_h.assign(1, 0);
+  c->phih_off_h.assign(1, 0);
   for (int s = 0; s < h.nsub; ++s) {
     for (int t = h.Toff[s]; t < h.Toff[s + 1]; ++t)
       if (h.torn_gidx[t] >= 0) c->rem_list_h.push_back(t);
@@ -1726,6 +1727,8 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     long long nrem = c->rem_off_h[s + 1] - c->rem_off_h[s];
     int ncs = h.sc_ptr[s + 1] - h.sc_ptr[s];
     c->phi_off_h.push_back(c->phi_off_h.back() + (long long)P * ncs * P * nrem);
+    // the FP16 copy pads each row of outputs to a multiple of 4 (8-byte loads)
+    c->phih_off_h.push_back(c->phih_off_h.back() + (long long)P * ncs * ((P * nrem + 3) / 4 * 4));
   }
   co.rem_off = upload(c, c->rem_off_h);
   co.rem_list = upload(c, c->rem_list_h.empty() ? std::vector<int>{0} : c->rem_list_h);
@@ -1733,8 +1736,9 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
   c->phi = dalloc<double>(c, (size_t)std::max<long long>(1, c->phi_off_h.back()));
   co.phi = c->phi;
   if (dd.precision == SGW_FP32_IR64) {
-    c->phih = dalloc<unsigned short>(c, (size_t)std::max<long long>(1, c->phi_off_h.back()));
+    c->phih = dalloc<unsigned short>(c, (size_t)std::max<long long>(4, c->phih_off_h.back()));
     co.phih = c->phih;
+    co.phih_off = upload(c, c->phih_off_h);
   }
   co.max_rem = 0;
   for (int s = 0; s < h.nsub; ++s)
@@ -1939,7 +1943,19 @@ int sgw_factor(sgw_ctx* c, void* stream) {
       return SGW_ENOMEM;
     }
     if (c->phih) {  // the FP32 solver's FP16 copy of the coarse basis
-      k::to_half(c->phi_off_h.back(), c->phi, c->phih, st);
+      std::vector<int> nq(c->nsub);
+      std::vector<long long> nout(c->nsub);
+      for (int s = 0; s < c->nsub; ++s) {
+        nq[s] = P * (h.sc_ptr[s + 1] - h.sc_ptr[s]);
+        nout[s] = (long long)P * (c->rem_off_h[s + 1] - c->rem_off_h[s]);
+      }
+      const int* dnq = upload(c, nq);
+      const long long* dno = upload(c, nout);
+      if (!dnq || !dno) {
+        c->err = "device allocation failed (coarse basis copy)";
+        return SGW_ENOMEM;
+      }
+      k::coarse_basis_to_half(c->co, c->nsub, dnq, dno, st);
       HIPCHK(hipStreamSynchronize(st));
     }
   }
