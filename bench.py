@@ -282,9 +282,30 @@ def load_golden(name):
     return out, meta
 
 
-def run_stack(sgw, prm, opts, warm, steps, golden, log):
+def pulse_modes(prm, P, seed):
+    """Initial displacement chaos coefficients [P][(n+1)^2] of the workload's
+    problem with its pulse centred where `seed` draws it (mode 0 only): the
+    input of a training trajectory of the learned guess."""
+    import numpy as np
+    import workloads
+    n = prm["n"]
+    x0, y0 = workloads.pulse_centre(seed)
+    x = np.tile(np.arange(n + 1) / n, n + 1)
+    y = np.repeat(np.arange(n + 1) / n, n + 1)
+    u = np.zeros((P, (n + 1) ** 2))
+    u[0] = prm["amp"] * np.exp(-((x - x0) ** 2 + (y - y0) ** 2) / prm["width"] ** 2)
+    return u
+
+
+# learned guess of the full stack: trained, after the set-up, on trajectories
+# of the same problem with the pulse elsewhere (seeds other than the timed one)
+LEARN = dict(seeds=(51, 52), nsteps=10, epochs=1, batch=16384, lr=1e-3)
+
+
+def run_stack(sgw, prm, opts, warm, steps, golden, log, learn=None):
     """Set up one solver stack, time `steps` steps after `warm` warm-up steps,
-    then rerun from the initial state to the stored oracle steps."""
+    then rerun from the initial state to the stored oracle steps.  learn: train
+    the learned guess first (LEARN) and time the stack with it."""
     import numpy as np
     import torch
     from oracle.sg import rel_l2
@@ -297,6 +318,26 @@ def run_stack(sgw, prm, opts, warm, steps, golden, log):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log("autotuned; set-up %.1f s" % setup_s)
+    train = None
+    if learn:
+        t2 = time.perf_counter()
+        model = sgw.GuessModel(4, 1, 256, seed=7)
+        s.set_guess_model(model)
+        s.set_guess(sgw.SGW_GUESS_NEWMARK)
+        loss = 0.0
+        for q, sd in enumerate(learn["seeds"]):
+            s.set_state(U=torch.from_numpy(pulse_modes(prm, s.P, sd)))
+            last = q + 1 == len(learn["seeds"])
+            loss = s.guess_train(learn["nsteps"], epochs=learn["epochs"] if last else 0,
+                                 batch=learn["batch"], lr=learn["lr"], seed=2, clear=q == 0)
+            log("learned guess: trajectory %d recorded%s (%.1f s)"
+                % (q + 1, ", network trained" if last else "", time.perf_counter() - t2))
+        s.set_guess(sgw.SGW_GUESS_LEARNED)
+        torch.cuda.synchronize()
+        train = {"trajectories": len(learn["seeds"]), "steps_each": learn["nsteps"],
+                 "samples": s.stored_samples(), "epochs": learn["epochs"],
+                 "final_loss": loss, "seconds": time.perf_counter() - t2}
+        log("learned guess trained: %s" % train)
     s.set_state()
     if warm:
         s.step(warm)
@@ -339,8 +380,10 @@ def run_stack(sgw, prm, opts, warm, steps, golden, log):
                 done = step
                 compare(step, False)
         log("accuracy: %s" % errors)
+    fallbacks = s.guess_fallbacks() if learn else None
     s.close()
     return {"steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+            "learned_guess": train, "guess_fallbacks": fallbacks,
             "pcg_iters_per_step": st["outer_iters"] / st["steps"],
             "inner_iters_per_step": st["inner_iters"] / st["steps"],
             "ir_sweeps_per_step": st["ir_sweeps"] / st["steps"], "setup_s": setup_s,
@@ -469,6 +512,9 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cfg5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 stack")
+    ap.add_argument("--guess", choices=("newmark", "learned"), default="newmark",
+                    help="initial guess of the full stack (learned: trained after the set-up "
+                         "on trajectories of other pulse positions)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--trace-window", metavar="KERNEL_TRACE_CSV", default=None,
                     help="per-step kernel times of the first timed region of a kernel trace")
@@ -528,7 +574,8 @@ def main():
     prm = workloads.config(args.workload)
     golden, gmeta = load_golden(args.workload)
     log("workload %s, stored oracle steps %s" % (args.workload, sorted(golden)))
-    full = run_stack(sgw, prm, solver_settings("mixed"), args.warmup, args.steps, golden, log)
+    full = run_stack(sgw, prm, solver_settings("mixed"), args.warmup, args.steps, golden, log,
+                     learn=LEARN if args.guess == "learned" else None)
     plain = None
     if not args.no_fp64:
         plain = run_stack(sgw, prm, solver_settings("fp64"), args.warmup, args.steps, golden,
@@ -592,8 +639,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload] + "; full stack: FP32 DD-PCG in FP64 "
                    "iterative refinement to SG residual 1e-8, batched Chebyshev-preconditioned "
-                   "subdomain solves, autotuned tiles, Newmark-extrapolated guess",
+                   "subdomain solves, autotuned tiles, " + (
+                       "learned guess (trained after the set-up on %d trajectories of %d steps "
+                       "with the pulse elsewhere)" % (len(LEARN["seeds"]), LEARN["nsteps"])
+                       if args.guess == "learned" else "Newmark-extrapolated guess"),
                    "global_batch": 1},
+        "learned_guess_training": full["learned_guess"],
+        "guess_fallbacks": full["guess_fallbacks"],
         "pcg_iters_per_step": full["pcg_iters_per_step"],
         "inner_iters_per_step": full["inner_iters_per_step"],
         "ir_sweeps_per_step": full["ir_sweeps_per_step"],
