@@ -66,7 +66,9 @@ KERNEL_NAMES = {0: "k1 SG operator apply, FP64 (K1)",
                 3: "k1 SG operator apply, FP32 (K1)",
                 4: "k_tri_solve batched supernodal triangular solves, FP32 (K3)",
                 5: "k_cheb Chebyshev subdomain preconditioner, FP32 (K3c)"}
-PROFILE_EVERY = 1    # time every launch of each kind (a sample can miss the slower early iterations)
+PROFILE_EVERY = 7    # time every 7th launch of each kind: a prime, so that the sample rotates
+                     # over the positions of a step (50 SG applies per step at 512x512; every
+                     # 5th launch saw the same 10 positions in every step)
 
 WORKLOADS = {
     "cfg5": "cfg5: 512x512 P1 mesh (263,169 nodes), 16x16 subdomains, KLE 8 terms, sigma 0.3, "
@@ -655,7 +657,7 @@ def main():
                                       "avg_launch_us": 1e3 * v[1] / v[0],
                                       "GB/s": (v[2] / (v[1] * 1e-3)) / 1e9}
                     for k, v in prof.items() if v[0] > 0},
-        "kernel_timing": "HIP events around every launch (1 in %d) of each kind in the timed steps "
+        "kernel_timing": "HIP events around every %dth launch of each kind in the timed steps "
                          "(the Chebyshev launches have theirs recorded with their dispatch); "
                          "bytes of the fused SG-apply and Chebyshev launches counted on the "
                          "device over the rows they process" % PROFILE_EVERY,
