@@ -152,21 +152,25 @@ def cpu_baseline(prm, golden_steps):
     U, V, A = pr.initial_state()
     import scipy.sparse.linalg as spla
     lu = spla.splu(pr.Kt[0].tocsc())
-    its, t0 = 0, time.perf_counter()
+    its, t0, c0 = 0, time.perf_counter(), time.process_time()
     while True:  # the two operations of a CG iteration on the step's vectors
         Q = pr.apply_Kt(U)
         lu.solve(Q)
         its += 1
         if time.perf_counter() - t0 > 20.0:
             break
-    per_it = (time.perf_counter() - t0) / its
+    wall = time.perf_counter() - t0
+    per_it = wall / its
+    busy = (time.process_time() - c0) / wall  # cores kept busy on average
     cg_per_step = golden_steps.get("cg_iterations_per_step")
     if not cg_per_step:
         return None
-    return {"value": 1.0 / (per_it * cg_per_step), "unit": "time-steps/s", "cores": threads,
-            "kind": "oracle", "cpu_model": cpu_model(),
-            "threads_note": "%d BLAS threads in the dense Galerkin contractions; scipy's sparse "
-                            "products and triangular solves run on one thread" % threads,
+    return {"value": 1.0 / (per_it * cg_per_step), "unit": "time-steps/s",
+            "cores": max(1, int(round(busy))), "kind": "oracle", "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
+            "threads_note": "cores = process CPU time / wall time over the sample (%.2f): %d BLAS "
+                            "threads in the dense Galerkin contractions, scipy's sparse products "
+                            "and triangular solves on one thread" % (busy, threads),
             "sample": "%d CG iterations (SG operator apply + mean-matrix preconditioner solve, "
                       "%.2f s each) of the oracle's first time step, scaled by the %.1f CG "
                       "iterations per step the oracle takes on this workload"

@@ -1,5 +1,5 @@
 """The stored oracle runs are what the oracle computes now: their layout is
-checked (the 256x256 run to step 500, the 512x512 run to step 20, two
+checked (the 256x256 run to step 500, the 512x512 run to step 30, two
 384x384 problems of the batched set to step 10), and the first stored step
 of the 256x256, P = 35 workload is recomputed here (CPU, ~15 s) and
 compared over every node."""
@@ -13,7 +13,7 @@ from oracle.sg import SGProblem
 
 def test_golden_file_layout():
     for name, n, steps, dtype_ok in (("cfg2", 256, [2, 10, 25, 100, 200, 500], True),
-                                     ("cfg5", 512, [2, 10, 20], True),
+                                     ("cfg5", 512, [2, 10, 20, 30], True),
                                      ("cfg3-0", 384, [5, 10], True),
                                      ("cfg3-1", 384, [5, 10], True)):
         g, nn = golden_io.load(name)
