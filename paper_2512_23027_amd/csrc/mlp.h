@@ -29,8 +29,10 @@ struct sgw_mlp {
   long long adam_t = 0;
   // work space for batches of up to cap rows
   int cap = 0;
-  float *xb = nullptr, *tb = nullptr, *h1 = nullptr, *h2 = nullptr, *y = nullptr,
-        *d2 = nullptr, *d1 = nullptr, *dy = nullptr, *loss = nullptr;
+  float *xb = nullptr, *tb = nullptr, *y = nullptr, *d2 = nullptr, *d1 = nullptr, *dy = nullptr,
+        *loss = nullptr;
+  unsigned short *h1 = nullptr, *h2 = nullptr;  // hidden activations, BF16
+  float* part = nullptr;        // partial sums of the gradient reductions
   int* perm = nullptr;          // sample permutation of an epoch
   int perm_cap = 0;
   float* hloss = nullptr;       // pinned

@@ -1,6 +1,8 @@
 // Learned initial guess: the MLP, its training (Adam) and inference kernels.
-// Matrix products run on MFMA (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32
-// accumulation); everything else is FP32 elementwise or reduction work.
+// Matrix products run on MFMA (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
+// accumulation); the hidden activations are kept in BF16, the precision the
+// products read them in; everything else is FP32 elementwise or reduction
+// work.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,7 +17,11 @@
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16;  // BF16 bits
 
 // FP32 -> BF16, round to nearest even (finite inputs).
 __host__ __device__ inline unsigned short f2bf(float f) {
@@ -24,24 +30,33 @@ __host__ __device__ inline unsigned short f2bf(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (unsigned short)(u >> 16);
 }
+__device__ inline float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ inline short ld_bf(const float* p) { return (short)f2bf(*p); }
-__device__ inline short ld_bf(const unsigned short* p) { return (short)*p; }
+__device__ inline short ld_bf(const bf16* p) { return (short)*p; }
+__device__ inline float ld_f(const float* p) { return *p; }
+__device__ inline float ld_f(const bf16* p) { return bf2f(*p); }
+__device__ inline void st_c(float* p, float x) { *p = x; }
+__device__ inline void st_c(bf16* p, float x) { *p = f2bf(x); }
+// eight FP32 values -> eight BF16 (round to nearest even)
+__device__ inline bf16x8 to_bf8(f32x8 f) { return __builtin_convertvector(f, bf16x8); }
 
+// ---------------------------------------------------------------------------
+// Fallback GEMM for contraction lengths above 256 (hidden widths above 256):
 // C[i][j] = epilogue(sum_k A(i,k) B(k,j)) with A(i,k) = A[i*sai + k*sak] and
-// B(k,j) = B[k*sbk + j*sbj] (so transposed operands are plain strides).
-// Epilogue: + bias[j] (if bias), ReLU (if relu), times [gate[i][j] > 0] (if
-// gate).  A workgroup = 4 waves = a 32x32 tile of C, one 16x16 tile per wave;
+// B(k,j) = B[k*sbk + j*sbj] (BF16 weights).  Epilogue: + bias[j] (if bias),
+// ReLU (if relu), times [gate[i][j] > 0] (if gate, BF16, leading dimension
+// ldc).  A workgroup = 4 waves = a 32x32 tile of C, one 16x16 tile per wave;
 // each lane loads its 4-value slices of A and B for every 16-wide k step
 // (lane l: A rows l%16, B columns l%16, k = 4*(l/16) .. +3), out-of-range
 // entries read as zero.  Result of the MFMA: lane l holds rows 4*(l/16) ..
 // +3 of column l%16.
-template <typename TA, typename TB>
+template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __restrict__ A,
                                               long long sai, long long sak,
-                                              const TB* __restrict__ B, long long sbk,
-                                              long long sbj, float* __restrict__ C, int ldc,
+                                              const bf16* __restrict__ B, long long sbk,
+                                              long long sbj, TC* __restrict__ C, int ldc,
                                               const float* __restrict__ bias, int relu,
-                                              const float* __restrict__ gate) {
+                                              const bf16* __restrict__ gate) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int i0 = (blockIdx.y * 2 + (w >> 1)) * 16, j0 = (blockIdx.x * 2 + (w & 1)) * 16;
   if (i0 >= M || j0 >= N) return;  // uniform per wave
@@ -65,37 +80,418 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
     float x = acc[v];
     if (bias) x += bias[j];
     if (relu) x = fmaxf(x, 0.f);
-    if (gate && !(gate[(size_t)i * ldc + j] > 0.f)) x = 0.f;
-    C[(size_t)i * ldc + j] = x;
+    if (gate && !(bf2f(gate[(size_t)i * ldc + j]) > 0.f)) x = 0.f;
+    st_c(C + (size_t)i * ldc + j, x);
   }
 }
 
-template <typename TA, typename TB>
-void gemm(int M, int N, int K, const TA* A, long long sai, long long sak, const TB* B,
-          long long sbk, long long sbj, float* C, int ldc, const float* bias, int relu,
-          const float* gate, hipStream_t st) {
-  dim3 grid((N + 31) / 32, (M + 31) / 32);
-  k_gemm<TA, TB><<<grid, 256, 0, st>>>(M, N, K, A, sai, sak, B, sbk, sbj, C, ldc, bias, relu,
-                                       gate);
+// ---------------------------------------------------------------------------
+// Dense layer with the weight panel resident in LDS (contraction length
+// K <= 32*KS <= 256):
+//   C[i][j] = epilogue(sum_k A[i][k] W(k,j)),  A row-major [M][K] (FP32 or
+//   BF16), W(k,j) = W[k*sbk + j*sbj] (BF16), C row-major with leading
+//   dimension ldc (FP32 or BF16); epilogue as in k_gemm.
+// blockIdx.y picks a panel of NB output columns; the workgroup (8 waves)
+// stages W(k, panel) transposed, Wt[j][k], in LDS once (rows padded to
+// 32*KS + 8 values so that the 16-byte fragment reads of 16 lanes hit
+// distinct banks) with the panel's bias behind it, then each wave walks
+// 16-row tiles of A: the tile's BF16 fragments for all k sit in registers
+// (lane l: row l%16, k = 32 s + 8 (l/16) .. +7 of k step s) while the next
+// tile's are loaded, and are contracted with the panel's 16-column tiles,
+// four at a time with independent accumulators, by v_mfma_f32_16x16x32_bf16
+// with the weight tile as the first operand, so the accumulator of lane l
+// holds output row l%16, columns 4 (l/16) .. +3: four adjacent values,
+// stored with one vector store.
+// wmode: how the panel is staged: 1 = 16-byte loads along k (sbk == 1),
+// 2 = 16-byte loads along j (sbj == 1), 0 = element by element.
+template <typename TA>
+struct RawA {  // one k step of a lane's A fragment as loaded
+  typedef f32x8 T;
+};
+template <>
+struct RawA<bf16> {
+  typedef u32x4 T;
+};
+
+template <int KS, typename TA>
+__device__ inline void load_a(typename RawA<TA>::T (&r)[KS], const TA* __restrict__ row,
+                              bool valid, int K, int vecA, int lq) {
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k0 = 32 * s + 8 * lq;
+    if constexpr (sizeof(TA) == 4) {
+      f32x8 f = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (valid) {
+        if (vecA && k0 + 8 <= K) {
+          const float4 lo = *reinterpret_cast<const float4*>(row + k0);
+          const float4 hi = *reinterpret_cast<const float4*>(row + k0 + 4);
+          f = f32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (k0 + u < K) f[u] = row[k0 + u];
+        }
+      }
+      r[s] = f;
+    } else {
+      u32x4 q = {0u, 0u, 0u, 0u};
+      if (valid) {
+        if (vecA && k0 + 8 <= K) {
+          const uint4 v = *reinterpret_cast<const uint4*>(row + k0);
+          q = u32x4{v.x, v.y, v.z, v.w};
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (k0 + u < K) q[u >> 1] |= (uint32_t)row[k0 + u] << (16 * (u & 1));
+        }
+      }
+      r[s] = q;
+    }
+  }
 }
 
-// out[j] = sum_i X[i][j] (column sums, fixed order)
-__global__ void k_colsum(int rows, int cols, const float* X, float* out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+template <int KS, typename TA>
+__device__ inline void to_frag(const typename RawA<TA>::T (&r)[KS], bf16x8 (&a)[KS]) {
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    if constexpr (sizeof(TA) == 4) a[s] = to_bf8(r[s]);
+    else a[s] = __builtin_bit_cast(bf16x8, r[s]);
+  }
+}
+
+template <int KS, typename TA, typename TC>
+__global__ __launch_bounds__(512) void k_dense(int M, int N, int K, const TA* __restrict__ A,
+                                               int vecA, const bf16* __restrict__ W,
+                                               long long sbk, long long sbj, int wmode,
+                                               TC* __restrict__ C, int ldc, int vecC,
+                                               const float* __restrict__ bias, int relu,
+                                               const bf16* __restrict__ gate, int vg, int NB) {
+  extern __shared__ __align__(16) bf16 wt[];
+  constexpr int KP = 32 * KS, S = KP + 8, U = 8;
+  const int jb = blockIdx.y * NB;
+  const int nbc = min(NB, N - jb);          // columns of this panel
+  const int ncp = (nbc + 15) & ~15;         // ... in whole 16-column tiles
+  float* bs = reinterpret_cast<float*>(wt + (size_t)((min(NB, N) + 15) & ~15) * S);
+  // stage the panel, U 16-byte loads in flight per thread
+  if (wmode == 1) {
+    constexpr int KV = KP / 8;
+    const int n = ncp * KV;
+    for (int e0 = threadIdx.x; e0 < n; e0 += 512 * U) {
+      uint4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 512 * u, j = e / KV, k = (e % KV) * 8;
+        v[u] = uint4{0u, 0u, 0u, 0u};
+        if (e < n && j < nbc && k < K)
+          v[u] = *reinterpret_cast<const uint4*>(W + k + (size_t)(jb + j) * sbj);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 512 * u;
+        if (e < n) *reinterpret_cast<uint4*>(wt + (e / KV) * S + (e % KV) * 8) = v[u];
+      }
+    }
+  } else if (wmode == 2) {
+    const int jv = ncp / 8, n = KP * jv;
+    for (int e0 = threadIdx.x; e0 < n; e0 += 512 * U) {
+      uint4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 512 * u, k = e / jv, j = (e % jv) * 8;
+        v[u] = uint4{0u, 0u, 0u, 0u};
+        if (e < n && j < nbc && k < K)
+          v[u] = *reinterpret_cast<const uint4*>(W + (size_t)k * sbk + jb + j);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 512 * u, k = e / jv, j = (e % jv) * 8;
+        if (e >= n) continue;
+        const uint32_t q[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (int h = 0; h < 8; ++h) wt[(j + h) * S + k] = (bf16)(q[h >> 1] >> (16 * (h & 1)));
+      }
+    }
+  } else {
+    const int n = ncp * KP;
+    for (int e0 = threadIdx.x; e0 < n; e0 += 512 * U) {
+      bf16 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 512 * u, j = e / KP, k = e % KP;
+        v[u] = (e < n && j < nbc && k < K) ? W[(size_t)k * sbk + (size_t)(jb + j) * sbj] : (bf16)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 512 * u;
+        if (e < n) wt[(e / KP) * S + e % KP] = v[u];
+      }
+    }
+  }
+  for (int j = threadIdx.x; j < ncp; j += 512) bs[j] = (bias && j < nbc) ? bias[jb + j] : 0.f;
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  const int ntm = (M + 15) / 16, nct = ncp / 16, stride = gridDim.x * 8;
+  int tm = blockIdx.x * 8 + w;  // uniform per wave
+  typename RawA<TA>::T raw[KS];
+  if (tm < ntm) load_a<KS, TA>(raw, A + (size_t)(tm * 16 + lr) * K, tm * 16 + lr < M, K, vecA, lq);
+  for (; tm < ntm; tm += stride) {
+    bf16x8 a[KS];
+    to_frag<KS, TA>(raw, a);
+    const int i = tm * 16 + lr;
+    const int tn = tm + stride;
+    if (tn < ntm) load_a<KS, TA>(raw, A + (size_t)(tn * 16 + lr) * K, tn * 16 + lr < M, K, vecA, lq);
+    for (int jt = 0; jt < nct; jt += 4) {
+      uint2 gv[4];  // gate values of the four tiles (BF16 pairs)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        gv[u] = uint2{0u, 0u};
+        const int j = jb + 4 * lq + 16 * (jt + u);
+        if (vg && i < M && j + 4 <= N)
+          gv[u] = *reinterpret_cast<const uint2*>(gate + (size_t)i * ldc + j);
+      }
+      f32x4 acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (jt + u >= nct) continue;
+          const bf16x8 b =
+              *reinterpret_cast<const bf16x8*>(wt + ((jt + u) * 16 + lr) * S + 32 * s + 8 * lq);
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[s], acc[u], 0, 0, 0);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jl = 16 * (jt + u) + 4 * lq, j = jb + jl;  // panel column, output column
+        if (jt + u >= nct || i >= M || j >= N) continue;
+        float x[4] = {acc[u][0], acc[u][1], acc[u][2], acc[u][3]};
+        const bool full = j + 4 <= N;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          x[v] += bs[jl + v];
+          if (relu) x[v] = fmaxf(x[v], 0.f);
+          if (gate) {
+            const bf16 gh = (vg && full) ? (bf16)((v < 2 ? gv[u].x : gv[u].y) >> (16 * (v & 1)))
+                            : (j + v < N ? gate[(size_t)i * ldc + j + v] : (bf16)0);
+            if (!(bf2f(gh) > 0.f)) x[v] = 0.f;
+          }
+        }
+        TC* out = C + (size_t)i * ldc + j;
+        if (vecC && full) {
+          if constexpr (sizeof(TC) == 4) {
+            *reinterpret_cast<float4*>(out) = float4{x[0], x[1], x[2], x[3]};
+          } else {
+            *reinterpret_cast<uint2*>(out) =
+                uint2{(uint32_t)f2bf(x[0]) | ((uint32_t)f2bf(x[1]) << 16),
+                      (uint32_t)f2bf(x[2]) | ((uint32_t)f2bf(x[3]) << 16)};
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (j + v < N) st_c(out + v, x[v]);
+        }
+      }
+    }
+  }
+}
+
+constexpr int kDenseLds = 160 * 1024;  // LDS of one CU
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+template <int KS, typename TA, typename TC>
+void dense_launch(int M, int N, int K, const TA* A, const bf16* W, long long sbk, long long sbj,
+                  TC* C, int ldc, const float* bias, int relu, const bf16* gate, hipStream_t st) {
+  constexpr int KP = 32 * KS, S = KP + 8;
+  const int ncmax = (kDenseLds / (2 * S + 4)) & ~15;
+  const int NB = std::min((N + 15) & ~15, ncmax);
+  const int ny = (N + NB - 1) / NB;
+  const int ncp0 = (std::min(NB, N) + 15) & ~15;
+  const int lds = ncp0 * S * 2 + ncp0 * 4;  // panel, then its bias
+  int wmode = 0;
+  if (sbk == 1 && K % 8 == 0 && sbj % 8 == 0 && aligned16(W)) wmode = 1;
+  else if (sbj == 1 && N % 8 == 0 && sbk % 8 == 0 && aligned16(W)) wmode = 2;
+  const int vecA = K % 8 == 0 && aligned16(A);
+  const int vecC = ldc % 4 == 0 && (reinterpret_cast<uintptr_t>(C) % (4 * sizeof(TC))) == 0;
+  const int per_cu = std::max(1, std::min(4, kDenseLds / std::max(lds, 1)));
+  const int ntm = (M + 15) / 16;
+  const int nx = std::max(1, std::min((ntm + 7) / 8, 256 * per_cu / ny));
+  auto* f = &k_dense<KS, TA, TC>;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const int vg = gate && ldc % 4 == 0 && reinterpret_cast<uintptr_t>(gate) % 8 == 0;
+  f<<<dim3(nx, ny), 512, lds, st>>>(M, N, K, A, vecA, W, sbk, sbj, wmode, C, ldc, vecC, bias, relu,
+                                    gate, vg, NB);
+}
+
+// C = epilogue(A W) for A row-major [M][K]; the dense kernel for K <= 256,
+// else the fallback GEMM.
+template <typename TA, typename TC>
+void dense(int M, int N, int K, const TA* A, const bf16* W, long long sbk, long long sbj, TC* C,
+           int ldc, const float* bias, int relu, const bf16* gate, hipStream_t st) {
+  if (K <= 32) dense_launch<1>(M, N, K, A, W, sbk, sbj, C, ldc, bias, relu, gate, st);
+  else if (K <= 64) dense_launch<2>(M, N, K, A, W, sbk, sbj, C, ldc, bias, relu, gate, st);
+  else if (K <= 128) dense_launch<4>(M, N, K, A, W, sbk, sbj, C, ldc, bias, relu, gate, st);
+  else if (K <= 256) dense_launch<8>(M, N, K, A, W, sbk, sbj, C, ldc, bias, relu, gate, st);
+  else {
+    dim3 grid((N + 31) / 32, (M + 31) / 32);
+    k_gemm<TA, TC><<<grid, 256, 0, st>>>(M, N, K, A, K, 1, W, sbk, sbj, C, ldc, bias, relu, gate);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient, split over the rows r (the batch):
+//   part[c][i][j] = sum_{r in chunk c} D[r][i] X[r][j]   (i < M, j < N)
+// with D [R][M] FP32 and X [R][N] (FP32 or BF16), and, in the workgroups of
+// the first column tile, cpart[c][i] = sum_{r in chunk c} D[r][i] in FP32
+// (the bias gradient).  A workgroup (4 waves) owns a 64x64 tile of the
+// output and a chunk of rows; per stage of 64 rows each thread loads column
+// t%64 of rows 8 g .. 8 g + 7 of two row groups g (coalesced along the
+// columns), converts them to BF16 and writes them as one 16-byte row segment
+// of the transposed tiles Dt[i][r], Xt[j][r] in LDS; each wave then
+// contracts a 32x32 quarter of the tile with v_mfma_f32_16x16x32_bf16.  The
+// next stage's loads are issued before the current stage's products.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_wgrad(int R, int M, int N, const float* __restrict__ D,
+                                               const TX* __restrict__ X, int rows_per_chunk,
+                                               float* __restrict__ part,
+                                               float* __restrict__ cpart) {
+  constexpr int S = 72;  // 64 rows + 8: 16-byte row segments on distinct banks
+  __shared__ __align__(16) bf16 dt[64 * S], xt[64 * S];
+  __shared__ float cs[4][64];
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64, c = blockIdx.z;
+  const int rb = c * rows_per_chunk, re = min(R, rb + rows_per_chunk);
+  const int t = threadIdx.x, col = t & 63, g = t >> 6;
+  const int l = t & 63, lr = l & 15, lq = l >> 4;
+  const int wi = (g >> 1) * 32, wj = (g & 1) * 32;
+  const bool di = i0 + col < M, xj = j0 + col < N;
+  float dv[16], xv[16];
+  auto load = [&](int r0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = r0 + 8 * (g + 4 * (u >> 3)) + (u & 7);
+      dv[u] = (di && r < re) ? D[(size_t)r * M + i0 + col] : 0.f;
+      xv[u] = (xj && r < re) ? ld_f(X + (size_t)r * N + j0 + col) : 0.f;
+    }
+  };
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float csum = 0.f;
+  if (rb < re) load(rb);
+  for (int r0 = rb; r0 < re; r0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) csum += dv[u];
+    __syncthreads();  // the previous stage's fragment reads are done
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rr = 8 * (g + 4 * h);
+      *reinterpret_cast<bf16x8*>(dt + col * S + rr) =
+          to_bf8(f32x8{dv[8 * h], dv[8 * h + 1], dv[8 * h + 2], dv[8 * h + 3], dv[8 * h + 4],
+                       dv[8 * h + 5], dv[8 * h + 6], dv[8 * h + 7]});
+      *reinterpret_cast<bf16x8*>(xt + col * S + rr) =
+          to_bf8(f32x8{xv[8 * h], xv[8 * h + 1], xv[8 * h + 2], xv[8 * h + 3], xv[8 * h + 4],
+                       xv[8 * h + 5], xv[8 * h + 6], xv[8 * h + 7]});
+    }
+    __syncthreads();
+    if (r0 + 64 < re) load(r0 + 64);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        a[p] = *reinterpret_cast<const bf16x8*>(dt + (wi + 16 * p + lr) * S + 32 * s + 8 * lq);
+        b[p] = *reinterpret_cast<const bf16x8*>(xt + (wj + 16 * p + lr) * S + 32 * s + 8 * lq);
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[p], b[q], acc[p][q], 0, 0, 0);
+    }
+  }
+  // lane l holds rows 4 (l/16) .. +3, column l%16 of each 16x16 product
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = j0 + wj + 16 * q + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wi + 16 * p + 4 * lq + v;
+        if (i < M && j < N) part[((size_t)c * M + i) * N + j] = acc[p][q][v];
+      }
+    }
+  if (blockIdx.y == 0) {
+    cs[g][col] = csum;
+    __syncthreads();
+    if (t < 64 && i0 + t < M)
+      cpart[(size_t)c * M + i0 + t] = ((cs[0][t] + cs[1][t]) + cs[2][t]) + cs[3][t];
+  }
+}
+
+// out[e] = sum_{c < nc} part[c n + e], summed in the order of c
+__global__ void k_sum_parts(long long n, int nc, const float* __restrict__ part,
+                            float* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
   float s = 0.f;
-  for (int i = 0; i < rows; ++i) s += X[(size_t)i * cols + j];
-  out[j] = s;
+  int c = 0;
+  for (; c + 8 <= nc; c += 8) {  // eight loads in flight, added in order
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(c + u) * n + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; c < nc; ++c) s += part[(size_t)c * n + e];
+  out[e] = s;
 }
 
-// dy = 2 (y - t) / n and loss = mean((y - t)^2), n = rows * cols; one
-// workgroup, fixed reduction order.
+// chunks of the weight-gradient split for R rows and an M x N output: about
+// 1024 workgroups, at least 64 rows per chunk
+void wgrad_split(int R, int M, int N, int* nchunk, int* rows) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int nc = std::max(1, std::min((1024 + tiles - 1) / tiles, (R + 63) / 64));
+  int rc = (((R + nc - 1) / nc) + 63) / 64 * 64;
+  *rows = rc;
+  *nchunk = (R + rc - 1) / rc;
+}
+
+// partial-sum floats of wgrad for R rows: products, then column sums
+long long wgrad_part_floats(int R, int M, int N) {
+  int nc, rc;
+  wgrad_split(R, M, N, &nc, &rc);
+  return (long long)nc * M * N + (long long)nc * M;
+}
+
+// dW[i][j] = sum_r D[r][i] X[r][j] and db[i] = sum_r D[r][i], through the
+// partial-sum buffer part
+template <typename TX>
+void wgrad(int R, int M, int N, const float* D, const TX* X, float* dW, float* db, float* part,
+           hipStream_t st) {
+  int nc, rc;
+  wgrad_split(R, M, N, &nc, &rc);
+  float* cpart = part + (size_t)nc * M * N;
+  k_wgrad<TX><<<dim3((M + 63) / 64, (N + 63) / 64, nc), 256, 0, st>>>(R, M, N, D, X, rc, part,
+                                                                    cpart);
+  const long long n = (long long)M * N;
+  k_sum_parts<<<(int)((n + 255) / 256), 256, 0, st>>>(n, nc, part, dW);
+  k_sum_parts<<<(M + 255) / 256, 256, 0, st>>>(M, nc, cpart, db);
+}
+
+// dy = 2 (y - t) / n and the block's share of loss = mean((y - t)^2),
+// n = rows * cols: part[b] = sum over the elements b*256 + t + q*gridDim*256
+// of (y - t)^2 / n (fixed reduction order); k_sum_parts adds the shares.
 __global__ __launch_bounds__(256) void k_mse(int n, const float* y, const float* t, float* dy,
-                                             float* loss) {
+                                             float* part) {
   __shared__ float sh[256];
   float s = 0.f;
   const float inv = 1.f / (float)n;
-  for (int q = threadIdx.x; q < n; q += 256) {
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256) {
     const float e = y[q] - t[q];
     dy[q] = 2.f * e * inv;
     s += e * e;
@@ -106,8 +502,9 @@ __global__ __launch_bounds__(256) void k_mse(int n, const float* y, const float*
     if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *loss = sh[0] * inv;
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] * inv;
 }
+constexpr int kMseBlocks = 256;
 
 // Adam (Kingma & Ba, 2015) on the FP32 master parameters, then the BF16 copy.
 __global__ void k_adam(long long n, float* w, unsigned short* wb, const float* g, float* m,
@@ -164,15 +561,19 @@ double unif(uint64_t& s) { return (splitmix64(s) >> 11) * (1.0 / 900719925474099
 int ensure_cap(sgw_mlp* m, int nb) {
   if (nb <= m->cap) return 0;
   const int c = std::max(nb, 256);
-  m->xb = dalloc<float>(m, (size_t)c * m->nin);
-  m->tb = dalloc<float>(m, (size_t)c * m->ng);
-  m->h1 = dalloc<float>(m, (size_t)c * m->H);
-  m->h2 = dalloc<float>(m, (size_t)c * m->H);
-  m->y = dalloc<float>(m, (size_t)c * m->ng);
-  m->dy = dalloc<float>(m, (size_t)c * m->ng);
-  m->d2 = dalloc<float>(m, (size_t)c * m->H);
-  m->d1 = dalloc<float>(m, (size_t)c * m->H);
-  if (!m->xb || !m->tb || !m->h1 || !m->h2 || !m->y || !m->dy || !m->d2 || !m->d1) {
+  const int H = m->H, ni = m->nin, ng = m->ng;
+  const long long np = std::max({wgrad_part_floats(c, ng, H), wgrad_part_floats(c, H, H),
+                                 wgrad_part_floats(c, H, ni), (long long)kMseBlocks});
+  m->xb = dalloc<float>(m, (size_t)c * ni);
+  m->tb = dalloc<float>(m, (size_t)c * ng);
+  m->h1 = dalloc<bf16>(m, (size_t)c * H);
+  m->h2 = dalloc<bf16>(m, (size_t)c * H);
+  m->y = dalloc<float>(m, (size_t)c * ng);
+  m->dy = dalloc<float>(m, (size_t)c * ng);
+  m->d2 = dalloc<float>(m, (size_t)c * H);
+  m->d1 = dalloc<float>(m, (size_t)c * H);
+  m->part = dalloc<float>(m, (size_t)np);
+  if (!m->xb || !m->tb || !m->h1 || !m->h2 || !m->y || !m->dy || !m->d2 || !m->d1 || !m->part) {
     m->err = "device allocation failed (MLP work space)";
     return SGW_ENOMEM;
   }
@@ -180,27 +581,26 @@ int ensure_cap(sgw_mlp* m, int nb) {
   return 0;
 }
 
-// forward on rows x[nb][nin] with the hidden activations in h1, h2
-// ([nb][H] each; the work space's unless given)
-void forward(sgw_mlp* m, const float* x, float* y, int nb, hipStream_t st,
-             float* h1 = nullptr, float* h2 = nullptr) {
+// forward on rows x[nb][nin] with the hidden activations (BF16, the operands
+// of the next layer's products) in h1, h2 ([nb][H] each; the work space's
+// unless given)
+void forward(sgw_mlp* m, const float* x, float* y, int nb, hipStream_t st, bf16* h1 = nullptr,
+             bf16* h2 = nullptr) {
   const int H = m->H, ni = m->nin, ng = m->ng;
-  const unsigned short* wb = m->wb;
+  const bf16* wb = m->wb;
   const float* w = m->w;
   if (!h1) h1 = m->h1;
   if (!h2) h2 = m->h2;
-  // h = relu(x W^T + b): A(i,k) = x[i][k], B(k,j) = W[j][k]
-  gemm<float, unsigned short>(nb, H, ni, x, ni, 1, wb + m->off[0], 1, ni, h1, H,
-                              w + m->off[1], 1, nullptr, st);
-  gemm<float, unsigned short>(nb, H, H, h1, H, 1, wb + m->off[2], 1, H, h2, H,
-                              w + m->off[3], 1, nullptr, st);
-  gemm<float, unsigned short>(nb, ng, H, h2, H, 1, wb + m->off[4], 1, H, y, ng,
-                              w + m->off[5], 0, nullptr, st);
+  // h = relu(x W^T + b): W(k,j) = W[j][k]
+  dense<float, bf16>(nb, H, ni, x, wb + m->off[0], 1, ni, h1, H, w + m->off[1], 1, nullptr, st);
+  dense<bf16, bf16>(nb, H, H, h1, wb + m->off[2], 1, H, h2, H, w + m->off[3], 1, nullptr, st);
+  dense<bf16, float>(nb, ng, H, h2, wb + m->off[4], 1, H, y, ng, w + m->off[5], 0, nullptr, st);
 }
 
 // Scratch of the allocation-free forward pass (sgw_mlp_forward_noalloc):
-// the two hidden activations, nb x H floats each.  Every GPU that runs the
-// library holds its own copy until the process ends; host code reaches it
+// the two hidden activations, nb x H BF16 values each (nb x 2 x H is limited
+// to 4 Mi, the array's length in floats).  Every GPU that runs the library
+// holds its own copy until the process ends; host code reaches it
 // only through the per-device address from hipGetSymbolAddress.
 #define SGW_MLP_SCRATCH_FLOATS (4 << 20)  // 16 MiB
 static __device__ __align__(256) float scratch[SGW_MLP_SCRATCH_FLOATS];
@@ -224,23 +624,20 @@ float* scratch_address(int dev) {
 void backward(sgw_mlp* m, const float* x, const float* t, int nb, hipStream_t st) {
   const int H = m->H, ni = m->nin, ng = m->ng;
   float* g = m->g;
-  const unsigned short* wb = m->wb;
+  const bf16* wb = m->wb;
   forward(m, x, m->y, nb, st);
-  k_mse<<<1, 256, 0, st>>>(nb * ng, m->y, t, m->dy, m->loss);
+  const int n = nb * ng;
+  const int nmb = std::max(1, std::min(kMseBlocks, (n + 1023) / 1024));
+  k_mse<<<nmb, 256, 0, st>>>(n, m->y, t, m->dy, m->part);
+  k_sum_parts<<<1, 256, 0, st>>>(1, nmb, m->part, m->loss);
   // layer 3: dW3 = dy^T h2, db3 = colsum(dy), d2 = (dy W3) * [h2 > 0]
-  gemm<float, float>(ng, H, nb, m->dy, 1, ng, m->h2, H, 1, g + m->off[4], H, nullptr, 0, nullptr,
-                     st);
-  k_colsum<<<(ng + 255) / 256, 256, 0, st>>>(nb, ng, m->dy, g + m->off[5]);
-  gemm<float, unsigned short>(nb, H, ng, m->dy, ng, 1, wb + m->off[4], H, 1, m->d2, H, nullptr, 0,
-                              m->h2, st);
+  wgrad<bf16>(nb, ng, H, m->dy, m->h2, g + m->off[4], g + m->off[5], m->part, st);
+  dense<float, float>(nb, H, ng, m->dy, wb + m->off[4], H, 1, m->d2, H, nullptr, 0, m->h2, st);
   // layer 2
-  gemm<float, float>(H, H, nb, m->d2, 1, H, m->h1, H, 1, g + m->off[2], H, nullptr, 0, nullptr, st);
-  k_colsum<<<(H + 255) / 256, 256, 0, st>>>(nb, H, m->d2, g + m->off[3]);
-  gemm<float, unsigned short>(nb, H, H, m->d2, H, 1, wb + m->off[2], H, 1, m->d1, H, nullptr, 0,
-                              m->h1, st);
+  wgrad<bf16>(nb, H, H, m->d2, m->h1, g + m->off[2], g + m->off[3], m->part, st);
+  dense<float, float>(nb, H, H, m->d2, wb + m->off[2], H, 1, m->d1, H, nullptr, 0, m->h1, st);
   // layer 1
-  gemm<float, float>(H, ni, nb, m->d1, 1, H, x, ni, 1, g + m->off[0], ni, nullptr, 0, nullptr, st);
-  k_colsum<<<(H + 255) / 256, 256, 0, st>>>(nb, H, m->d1, g + m->off[1]);
+  wgrad<float>(nb, H, ni, m->d1, x, g + m->off[0], g + m->off[1], m->part, st);
 }
 
 int launch_check(sgw_mlp* m) {
@@ -388,7 +785,8 @@ int sgw_mlp_forward_noalloc(sgw_mlp* m, const float* x, float* y, int nb, void* 
     m->err = "hipGetSymbolAddress failed for the scratch array";
     return SGW_EHIP;
   }
-  forward(m, x, y, nb, (hipStream_t)stream, p, p + (size_t)nb * m->H);
+  bf16* h1 = reinterpret_cast<bf16*>(p);  // two BF16 activations, the second 16-byte aligned
+  forward(m, x, y, nb, (hipStream_t)stream, h1, h1 + (((size_t)nb * m->H + 7) & ~(size_t)7));
   return launch_check(m);
 }
 

@@ -63,6 +63,32 @@ def test_forward_and_gradient_match_reference(sgw, ni, no, H, nb):
     m.close()
 
 
+def test_large_batches_match_reference(sgw):
+    """Batches the size of a solver's guess: the forward pass over 70,001
+    rows (4,376 row tiles, several per wave of the dense kernel, and a
+    ragged last tile) and the gradient over 20,011 rows (the weight-gradient
+    split into 63 row chunks of five 64-row stages, the last one ragged)."""
+    ni, no, H = 4, 1, 256
+    m = sgw.GuessModel(ni, no, H, seed=5)
+    w = m.params().cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(70001)
+    x = rng.standard_normal((70001, ni)).astype(np.float32)
+    y = m.forward(torch.from_numpy(x)).cpu().numpy()
+    yr, _ = ref.forward(w, x, ni, no, H, bf16=True)
+    assert _rel(y, yr) <= 2e-3
+    worst = np.abs(y - yr).max() / np.abs(yr).max()
+    assert worst <= 2e-2, worst  # no row left out or misplaced
+    xs, t = x[:20011], (0.1 * rng.standard_normal((20011, no))).astype(np.float32)
+    loss, g = m.loss_grad(torch.from_numpy(xs), torch.from_numpy(t))
+    lr_, gr = ref.loss_grad(w, xs, t, ni, no, H, bf16=True)
+    assert abs(loss - lr_) <= 2e-3 * lr_
+    g = g.cpu().numpy()
+    for part in ref.unpack(np.arange(w.size), ni, no, H):
+        idx = part.ravel().astype(np.int64)
+        assert _rel(g[idx], gr[idx]) <= 2e-3
+    m.close()
+
+
 def test_params_roundtrip_and_training_reduces_loss(sgw):
     ni, no, H = 16, 4, 64
     m = sgw.GuessModel(ni, no, H, seed=3)
