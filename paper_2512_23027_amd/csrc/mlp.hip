@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
 //   C[i][j] = epilogue(sum_k A[i][k] W(k,j)),  A row-major [M][K] (FP32 or
 //   BF16), W(k,j) = W[k*sbk + j*sbj] (BF16), C row-major with leading
 //   dimension ldc (FP32 or BF16); epilogue as in k_gemm.
-// blockIdx.y picks a panel of NB output columns; the workgroup (8 waves)
+// blockIdx.y picks a panel of NB output columns; the workgroup (NT/64 waves)
 // stages W(k, panel) transposed, Wt[j][k], in LDS once (rows padded to
 // 32*KS + 8 values so that the 16-byte fragment reads of 16 lanes hit
 // distinct banks) with the panel's bias behind it, then each wave walks
@@ -159,8 +159,8 @@ __device__ inline void to_frag(const typename RawA<TA>::T (&r)[KS], bf16x8 (&a)[
   }
 }
 
-template <int KS, typename TA, typename TC>
-__global__ __launch_bounds__(512) void k_dense(int M, int N, int K, const TA* __restrict__ A,
+template <int KS, typename TA, typename TC, int NT>
+__global__ __launch_bounds__(NT) void k_dense(int M, int N, int K, const TA* __restrict__ A,
                                                int vecA, const bf16* __restrict__ W,
                                                long long sbk, long long sbj, int wmode,
                                                TC* __restrict__ C, int ldc, int vecC,
@@ -176,35 +176,35 @@ __global__ __launch_bounds__(512) void k_dense(int M, int N, int K, const TA* __
   if (wmode == 1) {
     constexpr int KV = KP / 8;
     const int n = ncp * KV;
-    for (int e0 = threadIdx.x; e0 < n; e0 += 512 * U) {
+    for (int e0 = threadIdx.x; e0 < n; e0 += NT * U) {
       uint4 v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = e0 + 512 * u, j = e / KV, k = (e % KV) * 8;
+        const int e = e0 + NT * u, j = e / KV, k = (e % KV) * 8;
         v[u] = uint4{0u, 0u, 0u, 0u};
         if (e < n && j < nbc && k < K)
           v[u] = *reinterpret_cast<const uint4*>(W + k + (size_t)(jb + j) * sbj);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = e0 + 512 * u;
+        const int e = e0 + NT * u;
         if (e < n) *reinterpret_cast<uint4*>(wt + (e / KV) * S + (e % KV) * 8) = v[u];
       }
     }
   } else if (wmode == 2) {
     const int jv = ncp / 8, n = KP * jv;
-    for (int e0 = threadIdx.x; e0 < n; e0 += 512 * U) {
+    for (int e0 = threadIdx.x; e0 < n; e0 += NT * U) {
       uint4 v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = e0 + 512 * u, k = e / jv, j = (e % jv) * 8;
+        const int e = e0 + NT * u, k = e / jv, j = (e % jv) * 8;
         v[u] = uint4{0u, 0u, 0u, 0u};
         if (e < n && j < nbc && k < K)
           v[u] = *reinterpret_cast<const uint4*>(W + (size_t)k * sbk + jb + j);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = e0 + 512 * u, k = e / jv, j = (e % jv) * 8;
+        const int e = e0 + NT * u, k = e / jv, j = (e % jv) * 8;
         if (e >= n) continue;
         const uint32_t q[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
@@ -213,25 +213,25 @@ __global__ __launch_bounds__(512) void k_dense(int M, int N, int K, const TA* __
     }
   } else {
     const int n = ncp * KP;
-    for (int e0 = threadIdx.x; e0 < n; e0 += 512 * U) {
+    for (int e0 = threadIdx.x; e0 < n; e0 += NT * U) {
       bf16 v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = e0 + 512 * u, j = e / KP, k = e % KP;
+        const int e = e0 + NT * u, j = e / KP, k = e % KP;
         v[u] = (e < n && j < nbc && k < K) ? W[(size_t)k * sbk + (size_t)(jb + j) * sbj] : (bf16)0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = e0 + 512 * u;
+        const int e = e0 + NT * u;
         if (e < n) wt[(e / KP) * S + e % KP] = v[u];
       }
     }
   }
-  for (int j = threadIdx.x; j < ncp; j += 512) bs[j] = (bias && j < nbc) ? bias[jb + j] : 0.f;
+  for (int j = threadIdx.x; j < ncp; j += NT) bs[j] = (bias && j < nbc) ? bias[jb + j] : 0.f;
   __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
-  const int ntm = (M + 15) / 16, nct = ncp / 16, stride = gridDim.x * 8;
-  int tm = blockIdx.x * 8 + w;  // uniform per wave
+  const int ntm = (M + 15) / 16, nct = ncp / 16, stride = gridDim.x * (NT / 64);
+  int tm = blockIdx.x * (NT / 64) + w;  // uniform per wave
   typename RawA<TA>::T raw[KS];
   if (tm < ntm) load_a<KS, TA>(raw, A + (size_t)(tm * 16 + lr) * K, tm * 16 + lr < M, K, vecA, lq);
   for (; tm < ntm; tm += stride) {
@@ -316,12 +316,15 @@ void dense_launch(int M, int N, int K, const TA* A, const bf16* W, long long sbk
   const int vecC = ldc % 4 == 0 && (reinterpret_cast<uintptr_t>(C) % (4 * sizeof(TC))) == 0;
   const int per_cu = std::max(1, std::min(4, kDenseLds / std::max(lds, 1)));
   const int ntm = (M + 15) / 16;
-  const int nx = std::max(1, std::min((ntm + 7) / 8, 256 * per_cu / ny));
-  auto* f = &k_dense<KS, TA, TC>;
+  // 16 waves a workgroup where the registers stay within 128 a lane (BF16
+  // operands, or FP32 ones with K <= 128), else 8
+  constexpr int NT = (sizeof(TA) == 2 || KS <= 4) ? 1024 : 512, NW = NT / 64;
+  const int nx = std::max(1, std::min((ntm + NW - 1) / NW, 256 * per_cu / ny));
+  auto* f = &k_dense<KS, TA, TC, NT>;
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   const int vg = gate && ldc % 4 == 0 && reinterpret_cast<uintptr_t>(gate) % 8 == 0;
-  f<<<dim3(nx, ny), 512, lds, st>>>(M, N, K, A, vecA, W, sbk, sbj, wmode, C, ldc, vecC, bias, relu,
+  f<<<dim3(nx, ny), NT, lds, st>>>(M, N, K, A, vecA, W, sbk, sbj, wmode, C, ldc, vecC, bias, relu,
                                     gate, vg, NB);
 }
 
