@@ -225,6 +225,19 @@ void newmark_predict(int P, int n, int ld, const double* U, const double* V,
 void newmark_update(int P, int n, int ld, const double* U1, const double* Um,
                     double* V, double* A, double dt, double zeta, double gamma,
                     hipStream_t st);
+// The same two steps with the images of the state under the SG operator K~
+// carried along (both steps are linear, so K~ of each combination is the
+// combination of GU = K~ U, GV = K~ V, GA = K~ A).  Predictor: Um and Wm as
+// above, and F = c1 K~ Uc (the stiffness-damping share of the force).
+// Update: V, A as above, and GU = F - R (K~ U1, with R = F - K~ U1 the
+// final residual of the step's solve), GA, GV by the update's formulas.
+void newmark_predict_g(int P, int ld, const double* U, const double* V, const double* A,
+                       const double* GU, const double* GV, const double* GA, double dt,
+                       double zeta, double gamma, double wc, double c1, double* Um, double* Wm,
+                       double* F, hipStream_t st);
+void newmark_update_g(int P, int ld, const double* U1, const double* Um, const double* F,
+                      const double* R, double* V, double* A, double* GU, double* GV, double* GA,
+                      double dt, double zeta, double gamma, hipStream_t st);
 
 // Interface <-> torn maps (D_s R_s and sum_s R_s^T D_s) and the coarse grid.
 template <typename T>

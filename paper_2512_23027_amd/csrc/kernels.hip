@@ -858,6 +858,57 @@ void newmark_update(int P, int n, int ld, const double* U1, const double* Um, do
   k_newmark_update<<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(N, U1, Um, V, A, dt, zeta, gamma);
 }
 
+__global__ void k_newmark_predict_g(long long N, const double* U, const double* V,
+                                    const double* A, const double* GU, const double* GV,
+                                    const double* GA, double dt, double zeta, double gamma,
+                                    double wc, double c1, double* Um, double* Wm, double* F) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double um = (U[t] + dt * V[t]) / (zeta * dt * dt) + (1.0 - 2.0 * zeta) * A[t] / (2.0 * zeta);
+  const double uc = gamma * dt * um - V[t] - (1.0 - gamma) * dt * A[t];
+  const double gum =
+      (GU[t] + dt * GV[t]) / (zeta * dt * dt) + (1.0 - 2.0 * zeta) * GA[t] / (2.0 * zeta);
+  const double guc = gamma * dt * gum - GV[t] - (1.0 - gamma) * dt * GA[t];
+  Um[t] = um;
+  Wm[t] = um + wc * uc;
+  F[t] = c1 * guc;
+}
+void newmark_predict_g(int P, int ld, const double* U, const double* V, const double* A,
+                       const double* GU, const double* GV, const double* GA, double dt,
+                       double zeta, double gamma, double wc, double c1, double* Um, double* Wm,
+                       double* F, hipStream_t st) {
+  long long N = (long long)P * ld;
+  k_newmark_predict_g<<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(N, U, V, A, GU, GV, GA, dt,
+                                                                     zeta, gamma, wc, c1, Um, Wm,
+                                                                     F);
+}
+
+__global__ void k_newmark_update_g(long long N, const double* U1, const double* Um,
+                                   const double* F, const double* R, double* V, double* A,
+                                   double* GU, double* GV, double* GA, double dt, double zeta,
+                                   double gamma) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double a1 = U1[t] / (zeta * dt * dt) - Um[t];
+  V[t] = V[t] + dt * ((1.0 - gamma) * A[t] + gamma * a1);
+  A[t] = a1;
+  // K~ Um from the images of the old state, as in the predictor
+  const double gum =
+      (GU[t] + dt * GV[t]) / (zeta * dt * dt) + (1.0 - 2.0 * zeta) * GA[t] / (2.0 * zeta);
+  const double gu1 = F[t] - R[t];
+  const double ga1 = gu1 / (zeta * dt * dt) - gum;
+  GV[t] = GV[t] + dt * ((1.0 - gamma) * GA[t] + gamma * ga1);
+  GA[t] = ga1;
+  GU[t] = gu1;
+}
+void newmark_update_g(int P, int ld, const double* U1, const double* Um, const double* F,
+                      const double* R, double* V, double* A, double* GU, double* GV, double* GA,
+                      double dt, double zeta, double gamma, hipStream_t st) {
+  long long N = (long long)P * ld;
+  k_newmark_update_g<<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(N, U1, Um, F, R, V, A, GU, GV,
+                                                                    GA, dt, zeta, gamma);
+}
+
 // ---------------------------------------------------------------------------
 // K6: interface restriction with partition-of-unity weights (D_s R_s,
 // Eq. det_scaling) into the torn Neumann vectors, and the weighted

@@ -99,6 +99,11 @@ struct sgw_ctx {
   k::DCoarseFactor cf;  // block-bidiagonal factor of F_cc (sgw_factor)
   double *U = nullptr, *V = nullptr, *A = nullptr, *Um = nullptr, *Uc = nullptr,
          *Wm = nullptr, *F = nullptr, *meshbuf = nullptr, *meshbuf2 = nullptr;
+  // K~ U, K~ V, K~ A (refinement path with stiffness damping): the damping
+  // share of the force follows from them without an SG apply; g_valid once
+  // they belong to the current state
+  double *GU = nullptr, *GV = nullptr, *GA = nullptr;
+  bool g_valid = false;
   double *part = nullptr, *part2 = nullptr, *sc = nullptr, *dc = nullptr, *uc = nullptr;
   double* osc = nullptr;   // interface PCG: G'G and r'r partials, device scalars
   double* hosc = nullptr;  // pinned copy of osc
@@ -1204,6 +1209,14 @@ static int fdot(sgw_ctx* c, const T* a, const T* b, double& out, hipStream_t st,
   return 0;
 }
 
+// Whether a step carries the images K~ U, K~ V, K~ A along with the state:
+// in the refinement path with stiffness damping, where the effective force
+// needs K~ Uc (Eq. fparts) and the solve's final FP64 residual R = F - K~ U1
+// already holds K~ of the new state.
+static bool carry_images(const sgw_problem_desc& d) {
+  return d.precision == SGW_FP32_IR64 && d.alpha1 != 0.0;
+}
+
 // H7: FP64 iterative refinement around the FP32 DD-PCG.  The residual
 // R = F - K~ X and the update X += D are FP64 on the global SG system; each
 // correction K~ D = R is solved by the whole DD method in FP32 (coarse grid
@@ -1291,6 +1304,10 @@ static bool check_pointers(sgw_ctx* c) {
       c->err = "internal error: a device array was not allocated";
       return false;
     }
+  if (carry_images(c->h.d) && (!c->GU || !c->GV || !c->GA)) {
+    c->err = "internal error: a device array was not allocated";
+    return false;
+  }
   if (!prec_complete(c->d64, false) ||
       (c->h.d.precision == SGW_FP32_IR64 && (!prec_complete(c->f32, true) || !c->phih))) {
     c->err = "internal error: a device array of a solver precision was not allocated";
@@ -1633,6 +1650,8 @@ int sgw_create(const sgw_problem_desc* d, const sgw_allocator* al, sgw_ctx** out
     size_t nv = (size_t)P * h.NF;
     for (double** v : {&c->U, &c->V, &c->A, &c->Um, &c->Uc, &c->Wm, &c->F})
       *v = dalloc<double>(c, nv);
+    if (carry_images(h.d))
+      for (double** v : {&c->GU, &c->GV, &c->GA}) *v = dalloc<double>(c, nv);
     c->hist = dalloc<double>(c, (size_t)4 * P * h.nG);
     c->gnew = dalloc<double>(c, (size_t)P * h.nG);
     c->smax = dalloc<double>(c, (size_t)P);
@@ -2076,6 +2095,7 @@ int sgw_set_state(sgw_ctx* c, const double* U, const double* V, const double* A,
     int rc = mass_solve(c, c->F, c->A, st);
     if (rc) return rc;
   }
+  c->g_valid = false;  // K~ of the new state not formed yet
   // the learned guess starts a new history with this state
   c->hist_n = 0;
   c->hist_pos = 0;
@@ -2116,11 +2136,25 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
   for (int n = 0; n < nsteps; ++n) {
     // H1: predictor and effective force F~ = M (Um + wc Uc) + (a1/s) K~ Uc
     const double wc = d.alpha0 - d.alpha1 * h.a_m / h.s_k;
-    k::newmark_predict(P, NF, NF, c->U, c->V, c->A, d.dt, d.zeta, d.gamma, wc, c->Um, c->Uc,
-                       c->Wm, st);
-    k::mass_apply<double>(c->d64.G, 0, NF, P, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
-    if (d.alpha1 != 0.0)
-      K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0, st);
+    const bool images = carry_images(d);
+    if (images) {
+      if (!c->g_valid) {  // first step from this state: K~ U, K~ V, K~ A
+        K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, c->U, NF, c->GU, NF, 1.0, 0.0, st);
+        K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, c->V, NF, c->GV, NF, 1.0, 0.0, st);
+        K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, c->A, NF, c->GA, NF, 1.0, 0.0, st);
+        c->g_valid = true;
+      }
+      k::newmark_predict_g(P, NF, c->U, c->V, c->A, c->GU, c->GV, c->GA, d.dt, d.zeta, d.gamma,
+                           wc, d.alpha1 / h.s_k, c->Um, c->Wm, c->F, st);
+      k::mass_apply<double>(c->d64.G, 0, NF, P, c->Wm, NF, c->F, NF, 1.0, 1.0, st);
+    } else {
+      k::newmark_predict(P, NF, NF, c->U, c->V, c->A, d.dt, d.zeta, d.gamma, wc, c->Um, c->Uc,
+                         c->Wm, st);
+      k::mass_apply<double>(c->d64.G, 0, NF, P, c->Wm, NF, c->F, NF, 1.0, 0.0, st);
+      if (d.alpha1 != 0.0)
+        K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, c->Uc, NF, c->F, NF, d.alpha1 / h.s_k, 1.0,
+                   st);
+    }
     // H3: initial interface guess.  Newmark extrapolation g = U + dt V +
     // dt^2/2 A on the interface (also the reference of the learned
     // correction); the previous solution; or g plus the network's correction
@@ -2162,7 +2196,10 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
       Tols tl{d.rtol, d.inner_rtol, d.precond_rtol, d.max_iter, d.inner_max_iter};
       rc = dd_solve<double>(c, c->d64, tl, c->F, c->d64.X, st, its, rel, fallback);
     }
-    if (rc < 0) return rc;
+    if (rc < 0) {
+      c->g_valid = false;
+      return rc;
+    }
     warn |= rc;
     // H11: training sample (history, correction of the Newmark guess), then
     // the new solution joins the history
@@ -2175,7 +2212,11 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
     }
     hist_push(c, c->d64.X, c->gnew, st);
     // H6: Newmark update
-    k::newmark_update(P, NF, NF, c->d64.X, c->Um, c->V, c->A, d.dt, d.zeta, d.gamma, st);
+    if (images)  // ir_solve leaves R = F - K~ X of the accepted X
+      k::newmark_update_g(P, NF, c->d64.X, c->Um, c->F, c->d64.R, c->V, c->A, c->GU, c->GV,
+                          c->GA, d.dt, d.zeta, d.gamma, st);
+    else
+      k::newmark_update(P, NF, NF, c->d64.X, c->Um, c->V, c->A, d.dt, d.zeta, d.gamma, st);
     std::swap(c->U, c->d64.X);
     s.steps++;
     s.outer_iters += its;

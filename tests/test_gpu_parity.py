@@ -239,6 +239,32 @@ def test_resume_from_state_is_bitwise(sgw):
     b.close()
 
 
+def test_resume_refinement_path_with_carried_images(sgw):
+    """Refinement path with stiffness damping: a step takes the damping share
+    of the force, K~ Uc, from the images K~ U, K~ V, K~ A carried along with
+    the state (the first step after set_state forms them by SG applies).  A
+    run resumed from a mid-run state (images formed afresh) and the continued
+    run (images carried) agree to far below the refinement tolerance."""
+    prm = workloads.config("cfg1")
+    kw = dict(rtol=1e-10, precision=sgw.SGW_FP32_IR64)
+    a = sgw.Solver(prm, **kw)
+    a.factor()
+    a.set_state()
+    assert a.step(5)["status"] == 0
+    U, V, A = [x.clone() for x in a.get_state()]
+    assert a.step(5)["status"] == 0
+    ua = a.get_state()[0].clone()
+    b = sgw.Solver(prm, **kw)
+    b.factor()
+    b.set_state(U, V, A, step=5)
+    assert b.step(5)["status"] == 0
+    ub = b.get_state()[0]
+    err = float((ua - ub).norm() / ua.norm())
+    assert err < 1e-8, err
+    a.close()
+    b.close()
+
+
 def test_sg_apply_fp32_kernel(sgw):
     """FP32 operator of the refinement path: relative error ~ FP32 rounding."""
     prm = workloads.config("cfg2", n=64, xsplits=workloads.uniform_splits(64, 4),
