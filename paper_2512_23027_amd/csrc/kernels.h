@@ -235,6 +235,10 @@ void newmark_predict_g(int P, int ld, const double* U, const double* V, const do
                        const double* GU, const double* GV, const double* GA, double dt,
                        double zeta, double gamma, double wc, double c1, double* Um, double* Wm,
                        double* F, hipStream_t st);
+// R = F - (GU + cv GV + ca GA): the residual of X0 = U + cv V + ca A from the
+// images of the state.
+void residual_images(int P, int ld, const double* F, const double* GU, const double* GV,
+                     const double* GA, double cv, double ca, double* R, hipStream_t st);
 void newmark_update_g(int P, int ld, const double* U1, const double* Um, const double* F,
                       const double* R, double* V, double* A, double* GU, double* GV, double* GA,
                       double dt, double zeta, double gamma, hipStream_t st);

@@ -883,6 +883,19 @@ void newmark_predict_g(int P, int ld, const double* U, const double* V, const do
                                                                      F);
 }
 
+__global__ void k_residual_images(long long N, const double* F, const double* GU,
+                                  const double* GV, const double* GA, double cv, double ca,
+                                  double* R) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  R[t] = F[t] - ((GU[t] + cv * GV[t]) + ca * GA[t]);
+}
+void residual_images(int P, int ld, const double* F, const double* GU, const double* GV,
+                     const double* GA, double cv, double ca, double* R, hipStream_t st) {
+  long long N = (long long)P * ld;
+  k_residual_images<<<ceil_div(N, SGW_BLOCK), SGW_BLOCK, 0, st>>>(N, F, GU, GV, GA, cv, ca, R);
+}
+
 __global__ void k_newmark_update_g(long long N, const double* U1, const double* Um,
                                    const double* F, const double* R, double* V, double* A,
                                    double* GU, double* GV, double* GA, double dt, double zeta,

@@ -1221,8 +1221,13 @@ static bool carry_images(const sgw_problem_desc& d) {
 // R = F - K~ X and the update X += D are FP64 on the global SG system; each
 // correction K~ D = R is solved by the whole DD method in FP32 (coarse grid
 // FP64) to the relative tolerances below.  Stops when ||R|| <= rtol ||F||.
+//
+// x0 (optional): X holds U + x0[0] V + x0[1] A of the carried state, whose
+// images give the first residual without an SG apply; every later residual,
+// and so the accepted one, is formed by the FP64 apply.
 static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int& outer_total,
-                    int& sweeps, double& relres, const double* fallback = nullptr) {
+                    int& sweeps, double& relres, const double* fallback = nullptr,
+                    const double* x0 = nullptr) {
   const sgw_problem_desc& d = c->h.d;
   const int P = c->P, NF = c->NF;
   PrecT<float>& pr = c->f32;
@@ -1234,8 +1239,12 @@ static int ir_solve(sgw_ctx* c, const double* F, double* X, hipStream_t st, int&
   outer_total = 0;
   sweeps = 0;
   for (bool first = true;; first = false) {
-    k::copy2d<double, double>(P, NF, F, NF, R, NF, 1.0, st);
-    K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, X, NF, R, NF, -1.0, 1.0, st);
+    if (first && x0) {
+      k::residual_images(P, NF, F, c->GU, c->GV, c->GA, x0[0], x0[1], R, st);
+    } else {
+      k::copy2d<double, double>(P, NF, F, NF, R, NF, 1.0, st);
+      K1<double>(c, c->d64.G, &c->hal_G0, 0, NF, X, NF, R, NF, -1.0, 1.0, st);
+    }
     double rr;
     if (first) rc = fdot<double>(c, R, R, rr, st, F, F, &ff);  // with F'F
     else rc = fdot<double>(c, R, R, rr, st);
@@ -2190,7 +2199,12 @@ int sgw_step(sgw_ctx* c, int nsteps, void* stream, sgw_step_stats* stats) {
         k::axpby2d<double>(P, nI, 1.0, c->U, NF, d.dt, c->V, NF, c->d64.X, NF, st);
         k::axpby2d<double>(P, nI, 1.0, c->d64.X, NF, 0.5 * d.dt * d.dt, c->A, NF, c->d64.X, NF, st);
       }
-      rc = ir_solve(c, c->F, c->d64.X, st, its, sweeps, rel, fallback);
+      // X = U + cv V + ca A everywhere unless the learned correction moved
+      // the interface: then the first residual needs the apply
+      const double x0[2] = {d.guess == SGW_GUESS_PREV ? 0.0 : d.dt,
+                            d.guess == SGW_GUESS_PREV ? 0.0 : 0.5 * d.dt * d.dt};
+      rc = ir_solve(c, c->F, c->d64.X, st, its, sweeps, rel, fallback,
+                    images && !learned ? x0 : nullptr);
       s.ir_sweeps += sweeps;
     } else {
       Tols tl{d.rtol, d.inner_rtol, d.precond_rtol, d.max_iter, d.inner_max_iter};
