@@ -298,8 +298,8 @@ int sgw_mlp_forward(sgw_mlp* m, const float* x, float* y, int nb, void* stream);
 /* Allocation-free variant of sgw_mlp_forward, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): the same kernels, with the two
- * hidden activations in a static device scratch array of 16 MiB, one per
- * GPU, held until the process ends (nb x 2 x hidden at most 4 Mi floats,
+ * hidden activations (BF16) in a static device scratch array of 16 MiB,
+ * one per GPU, held until the process ends (nb x 2 x hidden at most 4 Mi,
  * else SGW_EINVAL).  Calls no allocator and does not wait: the work is
  * enqueued on the stream.  Calls that overlap on one GPU share that scratch
  * and race. */
