@@ -514,8 +514,12 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
   // p'q partial sums (generated kernel on a block-aligned halo)
   const int kgen = c->k1_generated[sizeof(T) == 8];
   const bool fused = kgen > 0 && S.halo && k::sg_apply_pcg_fits<T>(c->gt, *S.halo);
+  // the iterate lives in the caller's output, except under graph replay,
+  // whose captured launches keep the system's own array
+  T* const x = c->use_graphs ? S.x : out;
+  const int ldx = c->use_graphs ? n : ldo;
   k::copy2d<T, T>(P, n, b, ldb, S.r, n, 1.0, st);
-  k::fill2d<T>(P, n, S.x, n, T(0), st);
+  k::fill2d<T>(P, n, x, ldx, T(0), st);
   precond_dot<T>(c, S, neumann, c->part, c->part2, -1, 0.0, st);
   if (!fused) k::copy2d<T, T>(P, n, S.z, n, S.p, n, 1.0, st);
   k::pcg_start(nb, P, c->part, c->part2, c->sc, tol2, NegligibleBlock<T>::value, c->flags, st);
@@ -547,13 +551,13 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
                                par, c->pqg, a >= 0 ? c->acct + 2 + (sizeof(T) == 4) : nullptr,
                                bpr, s);
       prof_end(c, a, sizeof(T) == 4 ? 3 : 0, 0.0, s);
-      k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, pnew, n, S.r, n, S.q, n, c->pqg,
+      k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, x, ldx, pnew, n, S.r, n, S.q, n, c->pqg,
                    c->part2, c->flags, s, S.halo->bgrp, kgen);
     } else {
       K1<T>(c, S.A, S.halo, 0, n, S.p, n, S.q, n, 1.0, 0.0, s);
       k::seg_dot<T>(nb, S.row_off, P, S.p, n, S.q, n, c->part, nullptr, 0, nullptr, 0, nullptr,
                     s);
-      k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, S.x, n, S.p, n, S.r, n, S.q, n, c->part,
+      k::pcg_xr<T>(nb, S.row_off, P, par, c->sc, x, ldx, S.p, n, S.r, n, S.q, n, c->part,
                    c->part2, c->flags, s);
     }
     precond_dot<T>(c, S, neumann, c->part, nullptr, par, tol2, s);
@@ -607,7 +611,7 @@ static int inner_solve(sgw_ctx* c, SysT<T>& S, bool neumann, const T* b, int ldb
     }
     second_half(par, st);
   }
-  k::copy2d<T, T>(P, n, S.x, n, out, ldo, 1.0, st);
+  if (x != out) k::copy2d<T, T>(P, n, x, n, out, ldo, 1.0, st);
   predicted = done;
   c->inner_its += done;
   c->inner_solves += 1;
