@@ -49,3 +49,41 @@ def test_bench_counts_follow_the_oracle_tensor():
     assert fpr == 2 * (7 * kj + int(nz.sum()))
     assert fused == 2 * P * 4
     assert (nk, P, kj, int(nz.sum())) == (45, 165, 3701, 4413)
+
+
+SHARED = [(b, T) for b in sorted(gen_k1.SHARED) for T in sorted(gen_k1.SHARED[b])]
+
+
+@pytest.mark.parametrize("basis,T", SHARED)
+def test_shared_kernel_plan_covers_every_product_once(basis, T):
+    """Work plan of the shared-halo SG-apply kernels: over the output groups,
+    every coefficient matrix with products on a group's outputs is owned by
+    exactly one wave in sub-chunks of at most KC matrices; the greedy deal
+    leaves the waves' loads within one matrix's work of each other; the
+    reduction slices cover the group within the LDS budget; the groups
+    cover every output mode once."""
+    L, p_in, p_out = basis
+    cfg = gen_k1.shared_cfg(L, p_in, p_out, T)
+    nk, P, ent = gen_k1.entries(L, p_in, p_out)
+    w = 4 if T == "float" else 8
+    groups = gen_k1.shared_groups(L, p_in, p_out, T)
+    assert groups[0][0] == 0 and groups[-1][1] == P
+    assert all(a[1] == b[0] for a, b in zip(groups, groups[1:]))
+    for i0, i1 in groups:
+        NW, MT, waves, R, sl = gen_k1.shared_plan(L, p_in, p_out, T, i0, i1)
+        cost = {}
+        pairs = {}
+        for k, i, j, _ in ent:
+            if i0 <= i < i1:
+                pairs.setdefault(k, set()).add(j)
+                cost[k] = cost.get(k, 0) + 1
+        cost = {k: cost[k] + 7 * len(pairs[k]) for k in cost}
+        owned = [k for wave in waves for chunk in wave for k in chunk]
+        assert sorted(owned) == sorted(cost)  # each matrix with work, once
+        assert all(len(chunk) <= cfg["KC"] for wave in waves for chunk in wave)
+        loads = [sum(cost[k] for chunk in wave for k in chunk) for wave in waves]
+        assert len(waves) == NW
+        assert max(loads) - min(loads) <= max(cost.values())
+        assert R * sl >= i1 - i0 and (R - 1) * sl < i1 - i0
+        assert NW * sl * 64 * w <= cfg["RB"] or R == i1 - i0
+        assert MT == min(cfg["MT"], P)
