@@ -42,7 +42,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("ni,no,H,nb", [(4, 1, 256, 366), (4, 1, 256, 1000), (7, 3, 40, 33),
-                                        (61, 61, 64, 6)])
+                                        (61, 61, 64, 6), (4, 1, 320, 150), (300, 2, 40, 20)])
 def test_forward_and_gradient_match_reference(sgw, ni, no, H, nb):
     m = sgw.GuessModel(ni, no, H, seed=11)
     w = m.params().cpu().numpy().astype(np.float64)
