@@ -1,4 +1,4 @@
-"""Host-side tables of the HIP path against the oracle, without a GPU.
+"""Host-side tables and host logic of the HIP path, without a GPU.
 
 The generated SG-apply kernels carry the Galerkin tensor
 c_kij = <psi_k psi_i psi_j> (Eq. galerproject_chap2 with the normalised
@@ -7,7 +7,8 @@ chaos order of the solver's coefficient and solution arrays.  Every basis the
 library generates code for is compared entry by entry with the oracle's dense
 tensor: the same multi-index order, the same nonzero pattern, the same values.
 The roofline accounting of bench.py (bytes and flops per row of one SG
-apply) is checked against counts taken from the oracle's tensor.
+apply) is checked against counts taken from the oracle's tensor, and its
+refusal of more than one GPU.
 """
 
 import numpy as np
@@ -87,3 +88,16 @@ def test_shared_kernel_plan_covers_every_product_once(basis, T):
         assert R * sl >= i1 - i0 and (R - 1) * sl < i1 - i0
         assert NW * sl * 64 * w <= cfg["RB"] or R == i1 - i0
         assert MT == min(cfg["MT"], P)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 ends with a message and exit
+    status 2 before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
